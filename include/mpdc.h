@@ -1,0 +1,221 @@
+/*
+ * mpdc -- mixed-precision icosahedral C-grid dynamical core for AMD MI355X.
+ *
+ * C ABI of the GPU hot path of the mixed-precision GRIST dynamical core
+ * (Chen, Zhang, Wang, Liu, Li, Xue: "Mixed-Precision Computing in the GRIST
+ * Dynamical Core for Weather and Climate Modelling", arXiv 2404.08849).
+ *
+ * What the calls compute (paper anchors):
+ *  - mpdc_mesh_create: operator tables of the hexagonal/pentagonal
+ *    Arakawa-C grid (Section 2.1, Table 1);
+ *  - mpdc_dycore_step: the dry dynamical core -- continuity (Eq. 3),
+ *    theta_m transport (Eq. 4), momentum (Eq. 5), and for the
+ *    non-hydrostatic model the w/phi equations with the equation of state
+ *    and an implicit vertical column solve (Eqs. 6-9, HEVI, Section 2.1);
+ *    shallow water is the single-layer special case;
+ *  - mpdc_tracer_step: flux-form tracer transport (Eq. 10) with a third-order
+ *    upwind flux and an FCT limiter (Section 2.1), double-precision mass
+ *    continuity (Section 2.3);
+ *  - mpdc_diagnostics: global sums and the L1/L2/Linf error norms of
+ *    Section 2.2 (Eqs. 1-2).
+ * Precision policies (Section 2.3): MPDC_POLICY_DBL computes everything in
+ * FP64; MPDC_POLICY_MIX computes the advective terms, the tracer fluxes and
+ * the limiter in FP32 and keeps the pressure-gradient force, gravity and
+ * geopotential, the vertex mass in the potential vorticity, the implicit
+ * vertical solve and the mass sums in FP64.  The prognostic state stays FP64
+ * (tracers are FP32 under MIX); initial states are always written in FP64.
+ *
+ * Conventions
+ *  - Every function returning int returns MPDC_OK (0) or a negative error
+ *    code; on error no output is modified and mpdc_last_error() (per thread)
+ *    describes the failure.  No C++ exception crosses this boundary.
+ *  - The library never allocates device memory: the caller passes device
+ *    workspaces (pointer + size in bytes) that must outlive the handle that
+ *    uses them.  Host arrays in descriptors are only read during the call.
+ *  - Streams are hipStream_t passed as void*; NULL is the default stream.
+ *    Calls are asynchronous on that stream unless stated otherwise.
+ *  - Layouts are level-innermost SoA: cell fields [N][K][M], edge fields
+ *    [E][K][M], interface fields [N][K+1][M], tracers [N][K][T]; level 0 is
+ *    the model top; M is the ensemble member count.
+ *  - Indices are int32, zero based.
+ */
+#ifndef MPDC_H
+#define MPDC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define MPDC_OK 0
+#define MPDC_E_INVAL (-1)        /* null pointer or bad argument                          */
+#define MPDC_E_MESH (-2)         /* invalid mesh (index, Euler number, degree, orientation, area) */
+#define MPDC_E_NOMEM (-3)        /* caller workspace too small                            */
+#define MPDC_E_DEVICE (-4)       /* HIP runtime error                                     */
+#define MPDC_E_NUMERIC (-5)      /* NaN/Inf found by diagnostics                          */
+#define MPDC_E_UNSUPPORTED (-6)  /* unsupported combination of options                    */
+#define MPDC_E_STATE (-7)        /* call-order error                                      */
+
+/* ---- models and policies ---- */
+#define MPDC_MODEL_SW 0          /* single-layer shallow water (h, u)                     */
+#define MPDC_MODEL_HDC 1         /* hydrostatic dry dycore (pi_s, Theta, u)               */
+#define MPDC_MODEL_NDC 2         /* non-hydrostatic dry dycore (pi_s, Theta, u, w, phi)   */
+#define MPDC_MODEL_TRACER 3      /* tracer transport with a prescribed FP64 mass flux     */
+
+#define MPDC_POLICY_DBL 0        /* all FP64                                               */
+#define MPDC_POLICY_MIX 1        /* the paper's term split (see above)                     */
+
+/* ---- state fields for mpdc_state_write / mpdc_state_read (FP64 in and out) ---- */
+#define MPDC_FIELD_H 0           /* SW fluid depth h          [N][M]        */
+#define MPDC_FIELD_PS 1          /* surface pressure pi_s     [N][M]        */
+#define MPDC_FIELD_THETA 2       /* Theta = dpi theta_m       [N][K][M]     */
+#define MPDC_FIELD_U 3           /* normal velocity u         [E][K][M]     */
+#define MPDC_FIELD_W 4           /* vertical velocity w       [N][K+1][M]   */
+#define MPDC_FIELD_PHI 5         /* geopotential phi          [N][K+1][M]   */
+#define MPDC_FIELD_B 6           /* SW bottom height b        [N]           */
+#define MPDC_FIELD_TR_FLUX 7     /* tracer mass flux F        [E][K]        */
+#define MPDC_FIELD_TR_DPI 8      /* tracer layer mass dpi     [N][K]        */
+#define MPDC_FIELD_TR_Q 9        /* tracer mixing ratios q    [N][K][T]     */
+
+/* ---- mesh tables exported for checks (mpdc_mesh_get_table) ---- */
+#define MPDC_TABLE_CELLS_ON_CELL 0   /* int32 [2E], aligned with edges_on_cell            */
+#define MPDC_TABLE_EDGE_SIGN 1       /* double [2E], s_{e,i} = +1 if i = c1(e) else -1    */
+#define MPDC_TABLE_VERTEX_SIGN 2     /* double [V][3], s'_{e,v} = +1 if v = v2(e) else -1 */
+#define MPDC_TABLE_TRISK_OFFSET 3    /* int32 [E+1]                                        */
+#define MPDC_TABLE_TRISK_EDGE 4      /* int32 [n], n = TRISK_OFFSET[E]                     */
+#define MPDC_TABLE_TRISK_WEIGHT 5    /* double [n], w_{e,e'}                              */
+#define MPDC_TABLE_HESSIAN 6         /* double [2E][6], directional 2nd-derivative weights */
+
+typedef struct {
+    int32_t nCells, nEdges, nVertices;
+    const int32_t *cells_on_edge;     /* [E][2]  c1, c2; the normal n_e points c1 -> c2          */
+    const int32_t *vertices_on_edge;  /* [E][2]  v1, v2; t_e = k x n_e points v1 -> v2           */
+    const int32_t *eoc_offset;        /* [N+1]   CSR offsets into the two lists below             */
+    const int32_t *edges_on_cell;     /* [2E]    counter-clockwise                                */
+    const int32_t *vertices_on_cell;  /* [2E]    vertex j lies between edges j-1 and j            */
+    const int32_t *cells_on_vertex;   /* [V][3]  counter-clockwise                                */
+    const int32_t *edges_on_vertex;   /* [V][3]  edge j joins cells j and j+1                     */
+    const double *xCell, *xVertex, *xEdge;  /* unit position vectors [..][3]                     */
+    const double *dEdge;              /* [E] cell-to-cell arc length (m)                          */
+    const double *lEdge;              /* [E] vertex-to-vertex arc length (m)                      */
+    const double *areaCell;           /* [N] (m^2)                                                */
+    const double *areaVertex;         /* [V] (m^2)                                                */
+    const double *kiteArea;           /* [V][3] area shared by vertex v and cell cells_on_vertex[v][j] */
+    const double *fVertex;            /* [V] Coriolis parameter (1/s)                             */
+    double radius;                    /* sphere radius (m)                                        */
+} mpdc_mesh_desc;
+
+typedef struct {
+    int32_t model;        /* MPDC_MODEL_*                                                   */
+    int32_t policy;       /* MPDC_POLICY_*                                                  */
+    int32_t K;            /* layers (1 for SW; >= 2 for NDC)                                */
+    int32_t M;            /* ensemble members batched member-innermost (>= 1)               */
+    int32_t T;            /* tracers (TRACER model)                                         */
+    int32_t fct;          /* tracer limiter: 1 on (default), 0 off (bounds +-inf)           */
+    double dt;            /* time step (s)                                                  */
+    double grav, rd, cp, p0, ptop;  /* g, R_d, c_p, reference and model-top pressure       */
+    const double *sigma;  /* [K+1] sigma at interfaces, 0 at the top, 1 at the surface      */
+    int32_t reserved[8];  /* must be zero                                                   */
+} mpdc_config;
+
+typedef struct {
+    double mass;          /* sum_i A_i h_i (SW) or sum_i A_i (pi_s - pi_t) summed over members */
+    double mass_tracer[16];/* sum A dpi q per tracer (first 16 tracers)                    */
+    double min, max;      /* of the field named in mpdc_diagnostics                         */
+    double l1, l2, linf;  /* area-weighted normalised errors vs the reference (if given)    */
+    int64_t nonfinite;    /* NaN/Inf count over every prognostic field                      */
+} mpdc_diag;
+
+typedef struct mpdc_mesh mpdc_mesh;
+typedef struct mpdc_state mpdc_state;
+
+/* Bytes of device workspace mpdc_mesh_create needs for this mesh (0 if the
+ * descriptor is unusable). */
+size_t mpdc_mesh_workspace_bytes(const mpdc_mesh_desc *d);
+
+/* Validate the mesh (index ranges, N - E + V = 2, cell degree 5/6, degree-3
+ * vertices, counter-clockwise orientation, positive lengths and areas),
+ * derive its operator tables in FP64 on the host (signs, cells-on-cell, TRiSK
+ * lists and weights, quadratic-fit second-derivative weights) with FP32
+ * copies, and upload them into dev_ws (ws_bytes >= mpdc_mesh_workspace_bytes)
+ * on stream s.  *out receives a handle; the descriptor may be freed after the
+ * call returns.  Errors: INVAL, MESH, NOMEM, DEVICE. */
+int mpdc_mesh_create(const mpdc_mesh_desc *d, void *dev_ws, size_t ws_bytes, void *stream,
+                     mpdc_mesh **out);
+
+/* Copy one derived table (MPDC_TABLE_*) to host memory; synchronous.
+ * bytes must equal the table size (errors: INVAL). */
+int mpdc_mesh_get_table(const mpdc_mesh *m, int table_id, void *host_dst, size_t bytes);
+size_t mpdc_mesh_table_bytes(const mpdc_mesh *m, int table_id);
+void mpdc_mesh_destroy(mpdc_mesh *m);
+
+/* Device workspace needed by a state of this configuration (0 if unsupported). */
+size_t mpdc_state_workspace_bytes(const mpdc_mesh *m, const mpdc_config *c);
+
+/* Create a state (fields zero-initialised asynchronously on the mesh's stream).
+ * The mesh must outlive the state.  Errors: INVAL, UNSUPPORTED, NOMEM, DEVICE. */
+int mpdc_state_create(const mpdc_mesh *m, const mpdc_config *c, void *dev_ws, size_t ws_bytes,
+                      mpdc_state **out);
+
+/* Write a field (MPDC_FIELD_*) from FP64 data on the host (src_on_device = 0)
+ * or device; the library converts to its storage precision and regenerates
+ * the FP32 shadows.  bytes must equal the field's FP64 size. */
+int mpdc_state_write(mpdc_state *st, int field_id, const void *src, int src_on_device, size_t bytes,
+                     void *stream);
+
+/* Read a field back as FP64 into host (dst_on_device = 0; synchronous) or
+ * device memory (asynchronous). */
+int mpdc_state_read(mpdc_state *st, int field_id, void *dst, int dst_on_device, size_t bytes,
+                    void *stream);
+
+/* Advance the dycore (SW, HDC or NDC) by nsteps RK3 steps of dt.  Each stage
+ * updates the mass and Theta first and uses them in the pressure-gradient
+ * term (forward-backward).  Asynchronous.  Errors: INVAL, STATE, DEVICE. */
+int mpdc_dycore_step(mpdc_state *st, int nsteps, void *stream);
+
+/* Advance the tracers (TRACER model) by nsteps RK3 steps with the FCT limiter
+ * applied in every stage.  Asynchronous.  Errors: INVAL, STATE, DEVICE. */
+int mpdc_tracer_step(mpdc_state *st, int nsteps, void *stream);
+
+/* Deterministic FP64 reductions over the state: global mass, tracer masses,
+ * NaN/Inf count, min/max of field_id, and (if ref_dev is not NULL) the
+ * area-weighted normalised L1/L2/Linf errors of field_id against the FP64
+ * device array ref_dev of the same layout.  Synchronous.  Returns
+ * MPDC_E_NUMERIC (with *out filled) if a NaN/Inf is present. */
+int mpdc_diagnostics(mpdc_state *st, int field_id, const void *ref_dev, mpdc_diag *out, void *stream);
+
+/* Capture one dycore or tracer step into a HIP graph and replay it for later
+ * steps (enable != 0), or go back to direct launches (enable == 0).  Results
+ * are bitwise identical either way.  The stream passed to the step calls must
+ * not be the legacy default stream while graphs are enabled. */
+int mpdc_set_graph(mpdc_state *st, int enable);
+
+/* Launch shape of the state's kernels: cells per work-group for the column
+ * kernels and threads per work-group for the flat kernels (0 = default).
+ * Any legal shape gives bitwise identical results. */
+int mpdc_set_launch(mpdc_state *st, int cells_per_block, int flat_block);
+
+/* Time nreps launches of one kernel class (0 = first cell kernel, 1 = vertex,
+ * 2 = second cell kernel, 3 = edge/momentum kernel; tracer: 0..2 its three
+ * passes) of stage 1 on stream with HIP events; *ms_avg receives the mean
+ * duration.  The state is advanced by nothing (inputs are not modified).  */
+int mpdc_time_kernel(mpdc_state *st, int kernel_id, int nreps, void *stream, double *ms_avg);
+
+/* Algorithmic HBM bytes of one launch of a kernel class (same ids) and of one
+ * whole step, from the arrays each kernel must read and write once. */
+double mpdc_kernel_bytes(const mpdc_state *st, int kernel_id);
+double mpdc_step_bytes(const mpdc_state *st);
+
+void mpdc_state_destroy(mpdc_state *st);
+
+const char *mpdc_strerror(int code);
+const char *mpdc_last_error(void);
+const char *mpdc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

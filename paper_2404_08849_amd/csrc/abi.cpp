@@ -1,0 +1,937 @@
+// C ABI of the mpdc library: handles, workspace layout, stepping, graphs,
+// diagnostics.  See include/mpdc.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "dycore_kernels.h"
+#include "mpdc_internal.h"
+
+namespace mpdc {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+int fail(int code, const std::string &msg) {
+    set_error(msg);
+    return code;
+}
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Carves typed arrays out of one device workspace (or only measures it).
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base((char *)b) {}
+    template <typename T> T *take(size_t n) {
+        size_t o = off;
+        off = align_up(off + n * sizeof(T));
+        return base ? (T *)(base + o) : nullptr;
+    }
+};
+
+int hip_fail(hipError_t e, const char *where) {
+    std::ostringstream o;
+    o << where << ": " << hipGetErrorString(e);
+    return fail(MPDC_E_DEVICE, o.str());
+}
+#define HIP_TRY(call)                                   \
+    do {                                                \
+        hipError_t _e = (call);                         \
+        if (_e != hipSuccess) return hip_fail(_e, #call); \
+    } while (0)
+
+// ---------------- mesh workspace layout ----------------
+struct MeshLayout {
+    int *c_edge, *c_nbr;
+    double *c_div, *c_ke, *c_hess, *c_area;
+    float *c_div32, *c_ke32, *c_hess32;
+    int *e_cell, *e_vert, *e_tk;
+    double *e_dinv, *e_d2, *e_hdir, *e_tkw;
+    float *e_dinv32, *e_d2_32, *e_hdir32, *e_tkw32;
+    int *v_edge, *v_cell;
+    double *v_curl, *v_kite, *v_f;
+    float *v_curl32;
+    size_t bytes;
+};
+
+MeshLayout mesh_layout(void *base, long N, long E, long V) {
+    Carver c(base);
+    MeshLayout L;
+    const int S = kCellSlots;
+    L.c_edge = c.take<int>(N * S);
+    L.c_nbr = c.take<int>(N * S);
+    L.c_div = c.take<double>(N * S);
+    L.c_ke = c.take<double>(N * S);
+    L.c_hess = c.take<double>(N * 3 * S);
+    L.c_area = c.take<double>(N);
+    L.c_div32 = c.take<float>(N * S);
+    L.c_ke32 = c.take<float>(N * S);
+    L.c_hess32 = c.take<float>(N * 3 * S);
+    L.e_cell = c.take<int>(2 * E);
+    L.e_vert = c.take<int>(2 * E);
+    L.e_tk = c.take<int>(E * kTriskSlots);
+    L.e_dinv = c.take<double>(E);
+    L.e_d2 = c.take<double>(E);
+    L.e_hdir = c.take<double>(6 * E);
+    L.e_tkw = c.take<double>(E * kTriskSlots);
+    L.e_dinv32 = c.take<float>(E);
+    L.e_d2_32 = c.take<float>(E);
+    L.e_hdir32 = c.take<float>(6 * E);
+    L.e_tkw32 = c.take<float>(E * kTriskSlots);
+    L.v_edge = c.take<int>(3 * V);
+    L.v_cell = c.take<int>(3 * V);
+    L.v_curl = c.take<double>(3 * V);
+    L.v_kite = c.take<double>(3 * V);
+    L.v_f = c.take<double>(V);
+    L.v_curl32 = c.take<float>(3 * V);
+    L.bytes = c.off;
+    return L;
+}
+
+template <typename T> void put(std::vector<char> &host, void *dev_base, T *dev_ptr, const std::vector<T> &src) {
+    size_t off = (char *)dev_ptr - (char *)dev_base;
+    std::memcpy(host.data() + off, src.data(), src.size() * sizeof(T));
+}
+template <typename T> void put32(std::vector<char> &host, void *dev_base, float *dev_ptr, const std::vector<T> &src) {
+    size_t off = (char *)dev_ptr - (char *)dev_base;
+    float *h = (float *)(host.data() + off);
+    for (size_t i = 0; i < src.size(); i++) h[i] = (float)src[i];
+}
+
+}  // namespace
+}  // namespace mpdc
+
+using namespace mpdc;
+
+// =====================================================================
+// state
+// =====================================================================
+struct StateSet {
+    double *ps = nullptr, *Th = nullptr, *u = nullptr, *w = nullptr, *phi = nullptr;
+    float *u32 = nullptr, *th32 = nullptr;
+};
+
+struct mpdc_state {
+    const mpdc_mesh *mesh;
+    mpdc_config cfg;
+    std::vector<double> sigma;
+    int model, policy, K, M, T;
+    long N, E, V;
+    // dycore
+    StateSet set[3];
+    double *b = nullptr, *dsig = nullptr, *sig = nullptr, *dps = nullptr, *mdot = nullptr;
+    void *ke = nullptr, *hth = nullptr, *qv = nullptr;
+    double *alpha = nullptr, *phim = nullptr, *pm = nullptr, *mum = nullptr, *wstar = nullptr, *phistar = nullptr;
+    // tracer
+    double *F = nullptr, *dpi[2] = {nullptr, nullptr};
+    void *q[3] = {nullptr, nullptr, nullptr};
+    void *qtd = nullptr, *hq = nullptr, *rp = nullptr, *rm = nullptr;
+    int parity = 0;
+    // diagnostics scratch
+    double *partial = nullptr;
+    unsigned long long *nfpartial = nullptr;
+    // launch shape, graphs
+    Launch launch;
+    bool use_graph = false;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    hipStream_t graph_stream[2] = {nullptr, nullptr};
+    size_t ws_bytes = 0;
+};
+
+namespace {
+
+constexpr int kDiagBlocks = 1024;
+
+size_t rsize(int policy) { return policy == MPDC_POLICY_DBL ? sizeof(double) : sizeof(float); }
+
+// lay out (or measure) a state's workspace
+size_t state_layout(mpdc_state *st, void *base) {
+    Carver c(base);
+    const long N = st->N, E = st->E, V = st->V, K = st->K, M = st->M, T = st->T;
+    const long KM = K * M, K1M = (K + 1) * M;
+    const bool mix = st->policy == MPDC_POLICY_MIX;
+    const size_t r = rsize(st->policy);
+    st->partial = c.take<double>((size_t)kDiagBlocks * 9);
+    st->nfpartial = c.take<unsigned long long>(kDiagBlocks);
+    st->dsig = c.take<double>(K);
+    st->sig = c.take<double>(K + 1);
+    if (st->model == MPDC_MODEL_TRACER) {
+        st->F = c.take<double>(E * K);
+        st->dpi[0] = c.take<double>(N * K);
+        st->dpi[1] = c.take<double>(N * K);
+        for (int j = 0; j < 3; j++) st->q[j] = c.take<char>(N * K * T * r);
+        st->qtd = c.take<char>(N * K * T * r);
+        st->hq = c.take<char>(3 * N * K * T * r);
+        st->rp = c.take<char>(N * K * T * r);
+        st->rm = c.take<char>(N * K * T * r);
+        return c.off;
+    }
+    const bool sw = st->model == MPDC_MODEL_SW, nh = st->model == MPDC_MODEL_NDC;
+    for (int j = 0; j < 3; j++) {
+        StateSet &s = st->set[j];
+        s.ps = c.take<double>(N * M);
+        s.u = c.take<double>(E * KM);
+        if (!sw) s.Th = c.take<double>(N * KM);
+        if (nh) {
+            s.w = c.take<double>(N * K1M);
+            s.phi = c.take<double>(N * K1M);
+        }
+        if (mix) {
+            s.u32 = c.take<float>(E * KM);
+            if (!sw) s.th32 = c.take<float>(N * KM);
+        }
+    }
+    if (sw) st->b = c.take<double>(N);
+    st->dps = c.take<double>(N * M);
+    if (!sw) st->mdot = c.take<double>(N * K1M);
+    st->ke = c.take<char>(N * KM * r);
+    if (!sw) st->hth = c.take<char>(3 * N * KM * r);
+    st->qv = c.take<char>(V * KM * r);
+    if (!sw) {
+        st->alpha = c.take<double>(N * KM);
+        st->phim = c.take<double>(N * KM);
+    }
+    if (nh) {
+        st->pm = c.take<double>(N * KM);
+        st->mum = c.take<double>(N * KM);
+        st->wstar = c.take<double>(N * K1M);
+        st->phistar = c.take<double>(N * K1M);
+    }
+    return c.off;
+}
+
+int auto_cpb(const mpdc_state *st) {
+    const int KM = st->K * st->M;
+    int c = std::max(1, 256 / KM);
+    while (c > 1 && c * KM > 1024) c--;
+    return c;
+}
+
+int cpb_of(const mpdc_state *st) {
+    if (st->model == MPDC_MODEL_TRACER) return st->launch.flat_block;
+    return st->launch.cells_per_block > 0 ? st->launch.cells_per_block : auto_cpb(st);
+}
+
+StageArgs stage_args(const mpdc_state *st, int s) {
+    StageArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.mesh = st->mesh->dev;
+    a.K = st->K;
+    a.M = st->M;
+    a.cpb = cpb_of(st);
+    a.flat_block = st->launch.flat_block;
+    static const double frac[3] = {1.0 / 3.0, 0.5, 1.0};
+    a.dts = frac[s] * st->cfg.dt;
+    a.grav = st->cfg.grav;
+    a.rd = st->cfg.rd;
+    a.cp = st->cfg.cp;
+    a.p0 = st->cfg.p0;
+    a.ptop = st->cfg.ptop;
+    a.kappa = st->cfg.rd / st->cfg.cp;
+    a.gamma = st->cfg.cp / (st->cfg.cp - st->cfg.rd);
+    a.dsig = st->dsig;
+    a.sig = st->sig;
+    const StateSet &n = st->set[0];
+    const StateSet &in = st->set[s];             // y^(s-1): set0 for the first stage
+    const StateSet &out = st->set[(s + 1) % 3];  // the last stage writes set0 in place
+    a.ps_n = n.ps; a.Th_n = n.Th; a.u_n = n.u; a.w_n = n.w; a.phi_n = n.phi;
+    a.ps_s = in.ps; a.Th_s = in.Th; a.u_s = in.u; a.w_s = in.w; a.phi_s = in.phi;
+    a.u32_s = in.u32; a.th32_s = in.th32;
+    a.ps_o = out.ps; a.Th_o = out.Th; a.u_o = out.u; a.w_o = out.w; a.phi_o = out.phi;
+    a.u32_o = out.u32; a.th32_o = out.th32;
+    a.b = st->b;
+    a.dps = st->dps;
+    a.mdot = st->mdot;
+    a.ke = st->ke;
+    a.hth = st->hth;
+    a.qv = st->qv;
+    a.alpha = st->alpha; a.phim = st->phim; a.pm = st->pm; a.mum = st->mum;
+    a.wstar = st->wstar; a.phistar = st->phistar;
+    return a;
+}
+
+TracerArgs tracer_args(const mpdc_state *st, int s, int parity) {
+    TracerArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.mesh = st->mesh->dev;
+    a.K = st->K;
+    a.T = st->T;
+    a.cpb = st->launch.flat_block;
+    a.fct = st->cfg.fct;
+    static const double frac[3] = {1.0 / 3.0, 0.5, 1.0};
+    a.dts = frac[s] * st->cfg.dt;
+    a.F = st->F;
+    a.dpi_n = st->dpi[parity];
+    a.dpi_o = st->dpi[1 - parity];
+    void *qn = st->q[parity], *qo = st->q[1 - parity], *q2 = st->q[2];
+    a.q_n = qn;
+    a.q_s = (s == 0) ? qn : (s == 1) ? qo : q2;
+    a.q_o = (s == 0) ? qo : (s == 1) ? q2 : qo;
+    a.qtd = st->qtd;
+    a.hq = st->hq;
+    a.rp = st->rp;
+    a.rm = st->rm;
+    a.last_stage = (s == 2);
+    return a;
+}
+
+int run_dycore_step(mpdc_state *st, hipStream_t s) {
+    for (int stage = 0; stage < 3; stage++) {
+        StageArgs a = stage_args(st, stage);
+        for (int k = KERNEL_CELL_A; k <= KERNEL_EDGE; k++) {
+            hipError_t e = launch_stage_kernel(st->model, st->policy, a, k, s);
+            if (e != hipSuccess) return hip_fail(e, "dycore kernel launch");
+        }
+    }
+    return MPDC_OK;
+}
+
+int run_tracer_step(mpdc_state *st, int parity, hipStream_t s) {
+    for (int stage = 0; stage < 3; stage++) {
+        TracerArgs a = tracer_args(st, stage, parity);
+        for (int k = TKERNEL_LOW; k <= TKERNEL_UPDATE; k++) {
+            hipError_t e = launch_tracer_kernel(st->policy, a, k, s);
+            if (e != hipSuccess) return hip_fail(e, "tracer kernel launch");
+        }
+    }
+    return MPDC_OK;
+}
+
+void drop_graphs(mpdc_state *st) {
+    for (int j = 0; j < 2; j++) {
+        if (st->graph[j]) (void)hipGraphExecDestroy(st->graph[j]);
+        st->graph[j] = nullptr;
+        st->graph_stream[j] = nullptr;
+    }
+}
+
+// capture one step (for the given tracer parity) on stream s
+int capture_step(mpdc_state *st, int parity, hipStream_t s) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    int rc = (st->model == MPDC_MODEL_TRACER) ? run_tracer_step(st, parity, s) : run_dycore_step(st, s);
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc != MPDC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    st->graph[parity] = ex;
+    st->graph_stream[parity] = s;
+    return MPDC_OK;
+}
+
+long field_count(const mpdc_state *st, int f) {
+    const long N = st->N, E = st->E, K = st->K, M = st->M, T = st->T;
+    const int mdl = st->model;
+    switch (f) {
+    case MPDC_FIELD_H: return mdl == MPDC_MODEL_SW ? N * M : -1;
+    case MPDC_FIELD_PS: return (mdl == MPDC_MODEL_HDC || mdl == MPDC_MODEL_NDC) ? N * M : -1;
+    case MPDC_FIELD_THETA: return (mdl == MPDC_MODEL_HDC || mdl == MPDC_MODEL_NDC) ? N * K * M : -1;
+    case MPDC_FIELD_U: return (mdl != MPDC_MODEL_TRACER) ? E * K * M : -1;
+    case MPDC_FIELD_W:
+    case MPDC_FIELD_PHI: return mdl == MPDC_MODEL_NDC ? N * (K + 1) * M : -1;
+    case MPDC_FIELD_B: return mdl == MPDC_MODEL_SW ? N : -1;
+    case MPDC_FIELD_TR_FLUX: return mdl == MPDC_MODEL_TRACER ? E * K : -1;
+    case MPDC_FIELD_TR_DPI: return mdl == MPDC_MODEL_TRACER ? N * K : -1;
+    case MPDC_FIELD_TR_Q: return mdl == MPDC_MODEL_TRACER ? N * K * T : -1;
+    default: return -1;
+    }
+}
+
+// device pointer of an FP64 field of the current state (null for tracer q under MIX)
+double *field_ptr(mpdc_state *st, int f) {
+    StateSet &s = st->set[0];
+    switch (f) {
+    case MPDC_FIELD_H:
+    case MPDC_FIELD_PS: return s.ps;
+    case MPDC_FIELD_THETA: return s.Th;
+    case MPDC_FIELD_U: return s.u;
+    case MPDC_FIELD_W: return s.w;
+    case MPDC_FIELD_PHI: return s.phi;
+    case MPDC_FIELD_B: return st->b;
+    case MPDC_FIELD_TR_FLUX: return st->F;
+    case MPDC_FIELD_TR_DPI: return st->dpi[st->parity];
+    case MPDC_FIELD_TR_Q: return st->policy == MPDC_POLICY_DBL ? (double *)st->q[st->parity] : nullptr;
+    default: return nullptr;
+    }
+}
+
+__global__ void k_f64_to_f32(const double *src, float *dst, long n) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (float)src[i];
+}
+__global__ void k_f32_to_f64(const float *src, double *dst, long n) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (double)src[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mpdc_version(void) { return "mpdc 0.1 (gfx950)"; }
+
+const char *mpdc_strerror(int code) {
+    switch (code) {
+    case MPDC_OK: return "ok";
+    case MPDC_E_INVAL: return "invalid argument";
+    case MPDC_E_MESH: return "invalid mesh";
+    case MPDC_E_NOMEM: return "workspace too small";
+    case MPDC_E_DEVICE: return "HIP runtime error";
+    case MPDC_E_NUMERIC: return "non-finite values";
+    case MPDC_E_UNSUPPORTED: return "unsupported configuration";
+    case MPDC_E_STATE: return "call-order error";
+    default: return "unknown error";
+    }
+}
+
+const char *mpdc_last_error(void) { return g_last_error.c_str(); }
+
+size_t mpdc_mesh_workspace_bytes(const mpdc_mesh_desc *d) {
+    if (!d || d->nCells <= 0 || d->nEdges <= 0 || d->nVertices <= 0) return 0;
+    return mesh_layout(nullptr, d->nCells, d->nEdges, d->nVertices).bytes;
+}
+
+int mpdc_mesh_create(const mpdc_mesh_desc *d, void *dev_ws, size_t ws_bytes, void *stream, mpdc_mesh **out) {
+    if (!d || !out) return fail(MPDC_E_INVAL, "null descriptor or output handle");
+    if (!dev_ws) return fail(MPDC_E_INVAL, "null device workspace");
+    try {
+        std::string err = validate_mesh(d);
+        if (!err.empty()) return fail(MPDC_E_MESH, err);
+        const long N = d->nCells, E = d->nEdges, V = d->nVertices;
+        MeshLayout L = mesh_layout(dev_ws, N, E, V);
+        if (ws_bytes < L.bytes) return fail(MPDC_E_NOMEM, "mesh workspace too small");
+        HostTables t;
+        err = derive_tables(d, t);
+        if (!err.empty()) return fail(MPDC_E_MESH, err);
+        std::vector<char> host(L.bytes, 0);
+        put(host, dev_ws, L.c_edge, t.c_edge);
+        put(host, dev_ws, L.c_nbr, t.c_nbr);
+        put(host, dev_ws, L.c_div, t.c_div);
+        put(host, dev_ws, L.c_ke, t.c_ke);
+        put(host, dev_ws, L.c_hess, t.c_hess);
+        put(host, dev_ws, L.c_area, t.c_area);
+        put32(host, dev_ws, L.c_div32, t.c_div);
+        put32(host, dev_ws, L.c_ke32, t.c_ke);
+        put32(host, dev_ws, L.c_hess32, t.c_hess);
+        put(host, dev_ws, L.e_cell, t.e_cell);
+        put(host, dev_ws, L.e_vert, t.e_vert);
+        put(host, dev_ws, L.e_tk, t.e_tk);
+        put(host, dev_ws, L.e_dinv, t.e_dinv);
+        put(host, dev_ws, L.e_d2, t.e_d2);
+        put(host, dev_ws, L.e_hdir, t.e_hdir);
+        put(host, dev_ws, L.e_tkw, t.e_tkw);
+        put32(host, dev_ws, L.e_dinv32, t.e_dinv);
+        put32(host, dev_ws, L.e_d2_32, t.e_d2);
+        put32(host, dev_ws, L.e_hdir32, t.e_hdir);
+        put32(host, dev_ws, L.e_tkw32, t.e_tkw);
+        put(host, dev_ws, L.v_edge, t.v_edge);
+        put(host, dev_ws, L.v_cell, t.v_cell);
+        put(host, dev_ws, L.v_curl, t.v_curl);
+        put(host, dev_ws, L.v_kite, t.v_kite);
+        put(host, dev_ws, L.v_f, t.v_f);
+        put32(host, dev_ws, L.v_curl32, t.v_curl);
+        hipStream_t s = (hipStream_t)stream;
+        HIP_TRY(hipMemcpyAsync(dev_ws, host.data(), L.bytes, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+
+        mpdc_mesh *m = new mpdc_mesh();
+        m->N = (int)N; m->E = (int)E; m->V = (int)V;
+        m->radius = d->radius;
+        m->stream = s;
+        DevMesh &D = m->dev;
+        D.N = (int)N; D.E = (int)E; D.V = (int)V;
+        D.c_edge = L.c_edge; D.c_nbr = L.c_nbr; D.c_div = L.c_div; D.c_div32 = L.c_div32;
+        D.c_ke = L.c_ke; D.c_ke32 = L.c_ke32; D.c_hess = L.c_hess; D.c_hess32 = L.c_hess32; D.c_area = L.c_area;
+        D.e_cell = L.e_cell; D.e_vert = L.e_vert; D.e_dinv = L.e_dinv; D.e_dinv32 = L.e_dinv32;
+        D.e_d2 = L.e_d2; D.e_d2_32 = L.e_d2_32; D.e_hdir = L.e_hdir; D.e_hdir32 = L.e_hdir32;
+        D.e_tk = L.e_tk; D.e_tkw = L.e_tkw; D.e_tkw32 = L.e_tkw32;
+        D.v_edge = L.v_edge; D.v_cell = L.v_cell; D.v_curl = L.v_curl; D.v_curl32 = L.v_curl32;
+        D.v_kite = L.v_kite; D.v_f = L.v_f;
+        m->cells_on_cell = std::move(t.cells_on_cell);
+        m->edge_sign = std::move(t.edge_sign);
+        m->vertex_sign = std::move(t.vertex_sign);
+        m->trisk_off = std::move(t.trisk_off);
+        m->trisk_edge = std::move(t.trisk_edge);
+        m->trisk_w = std::move(t.trisk_w);
+        m->hessian = std::move(t.hessian);
+        m->area_cell = std::move(t.c_area);
+        *out = m;
+        return MPDC_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(MPDC_E_INVAL, "host allocation failed while deriving mesh tables");
+    } catch (...) {
+        return fail(MPDC_E_INVAL, "unexpected host error in mpdc_mesh_create");
+    }
+}
+
+size_t mpdc_mesh_table_bytes(const mpdc_mesh *m, int id) {
+    if (!m) return 0;
+    switch (id) {
+    case MPDC_TABLE_CELLS_ON_CELL: return m->cells_on_cell.size() * sizeof(int);
+    case MPDC_TABLE_EDGE_SIGN: return m->edge_sign.size() * sizeof(double);
+    case MPDC_TABLE_VERTEX_SIGN: return m->vertex_sign.size() * sizeof(double);
+    case MPDC_TABLE_TRISK_OFFSET: return m->trisk_off.size() * sizeof(int);
+    case MPDC_TABLE_TRISK_EDGE: return m->trisk_edge.size() * sizeof(int);
+    case MPDC_TABLE_TRISK_WEIGHT: return m->trisk_w.size() * sizeof(double);
+    case MPDC_TABLE_HESSIAN: return m->hessian.size() * sizeof(double);
+    default: return 0;
+    }
+}
+
+int mpdc_mesh_get_table(const mpdc_mesh *m, int id, void *dst, size_t bytes) {
+    if (!m || !dst) return fail(MPDC_E_INVAL, "null mesh or destination");
+    size_t need = mpdc_mesh_table_bytes(m, id);
+    if (need == 0) return fail(MPDC_E_INVAL, "unknown table id");
+    if (bytes != need) return fail(MPDC_E_INVAL, "destination size does not match the table");
+    const void *src = nullptr;
+    switch (id) {
+    case MPDC_TABLE_CELLS_ON_CELL: src = m->cells_on_cell.data(); break;
+    case MPDC_TABLE_EDGE_SIGN: src = m->edge_sign.data(); break;
+    case MPDC_TABLE_VERTEX_SIGN: src = m->vertex_sign.data(); break;
+    case MPDC_TABLE_TRISK_OFFSET: src = m->trisk_off.data(); break;
+    case MPDC_TABLE_TRISK_EDGE: src = m->trisk_edge.data(); break;
+    case MPDC_TABLE_TRISK_WEIGHT: src = m->trisk_w.data(); break;
+    case MPDC_TABLE_HESSIAN: src = m->hessian.data(); break;
+    }
+    std::memcpy(dst, src, bytes);
+    return MPDC_OK;
+}
+
+void mpdc_mesh_destroy(mpdc_mesh *m) { delete m; }
+
+static int check_config(const mpdc_mesh *m, const mpdc_config *c) {
+    if (!m || !c) return fail(MPDC_E_INVAL, "null mesh or config");
+    if (c->model < MPDC_MODEL_SW || c->model > MPDC_MODEL_TRACER) return fail(MPDC_E_INVAL, "unknown model");
+    if (c->policy != MPDC_POLICY_DBL && c->policy != MPDC_POLICY_MIX) return fail(MPDC_E_INVAL, "unknown policy");
+    if (c->K < 1 || c->M < 1 || c->K > 512 || c->M > 64) return fail(MPDC_E_INVAL, "K must be 1..512 and M 1..64");
+    if (c->model == MPDC_MODEL_SW && c->K != 1) return fail(MPDC_E_UNSUPPORTED, "shallow water needs K = 1");
+    if (c->model == MPDC_MODEL_NDC && c->K < 2) return fail(MPDC_E_UNSUPPORTED, "the NH column solve needs K >= 2");
+    if (c->model == MPDC_MODEL_TRACER && (c->T < 1 || c->M != 1))
+        return fail(MPDC_E_UNSUPPORTED, "tracer transport needs T >= 1 and M = 1");
+    if ((long)c->K * c->M > 1024 && c->model != MPDC_MODEL_TRACER)
+        return fail(MPDC_E_UNSUPPORTED, "a column (K*M) must fit one work-group of 1024 lanes");
+    if (!(c->dt > 0)) return fail(MPDC_E_INVAL, "dt must be positive");
+    if (c->model != MPDC_MODEL_SW) {
+        if (!c->sigma) return fail(MPDC_E_INVAL, "sigma interfaces required");
+        if (c->sigma[0] != 0.0 || c->sigma[c->K] != 1.0) return fail(MPDC_E_INVAL, "sigma must run from 0 to 1");
+        for (int k = 0; k < c->K; k++)
+            if (!(c->sigma[k + 1] > c->sigma[k])) return fail(MPDC_E_INVAL, "sigma must increase");
+    }
+    for (int j = 0; j < 8; j++)
+        if (c->reserved[j]) return fail(MPDC_E_INVAL, "reserved config fields must be zero");
+    return MPDC_OK;
+}
+
+static mpdc_state *new_state(const mpdc_mesh *m, const mpdc_config *c) {
+    mpdc_state *st = new mpdc_state();
+    st->mesh = m;
+    st->cfg = *c;
+    st->model = c->model;
+    st->policy = c->policy;
+    st->K = c->K;
+    st->M = c->M;
+    st->T = c->model == MPDC_MODEL_TRACER ? c->T : 0;
+    st->N = m->N;
+    st->E = m->E;
+    st->V = m->V;
+    if (c->model == MPDC_MODEL_SW) {
+        st->sigma = {0.0, 1.0};
+    } else {
+        st->sigma.assign(c->sigma, c->sigma + c->K + 1);
+    }
+    st->cfg.sigma = st->sigma.data();
+    return st;
+}
+
+size_t mpdc_state_workspace_bytes(const mpdc_mesh *m, const mpdc_config *c) {
+    if (check_config(m, c) != MPDC_OK) return 0;
+    mpdc_state *st = new_state(m, c);
+    size_t b = state_layout(st, nullptr);
+    delete st;
+    return b;
+}
+
+int mpdc_state_create(const mpdc_mesh *m, const mpdc_config *c, void *dev_ws, size_t ws_bytes, mpdc_state **out) {
+    int rc = check_config(m, c);
+    if (rc != MPDC_OK) return rc;
+    if (!dev_ws || !out) return fail(MPDC_E_INVAL, "null workspace or output handle");
+    mpdc_state *st = new_state(m, c);
+    size_t need = state_layout(st, nullptr);
+    if (ws_bytes < need) {
+        delete st;
+        return fail(MPDC_E_NOMEM, "state workspace too small");
+    }
+    state_layout(st, dev_ws);
+    st->ws_bytes = need;
+    hipStream_t s = m->stream;
+    std::vector<double> dsig(st->K);
+    for (int k = 0; k < st->K; k++) dsig[k] = st->sigma[k + 1] - st->sigma[k];
+    hipError_t e = hipMemsetAsync(dev_ws, 0, need, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(st->dsig, dsig.data(), dsig.size() * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(st->sig, st->sigma.data(), st->sigma.size() * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete st;
+        return hip_fail(e, "state initialisation");
+    }
+    *out = st;
+    return MPDC_OK;
+}
+
+void mpdc_state_destroy(mpdc_state *st) {
+    if (!st) return;
+    drop_graphs(st);
+    delete st;
+}
+
+int mpdc_state_write(mpdc_state *st, int f, const void *src, int src_on_device, size_t bytes, void *stream) {
+    if (!st || !src) return fail(MPDC_E_INVAL, "null state or source");
+    long n = field_count(st, f);
+    if (n < 0) return fail(MPDC_E_INVAL, "field not part of this model");
+    if (bytes != (size_t)n * sizeof(double)) return fail(MPDC_E_INVAL, "byte count does not match the field");
+    hipStream_t s = (hipStream_t)stream;
+    hipMemcpyKind kind = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    double *dst = field_ptr(st, f);
+    if (dst) {
+        HIP_TRY(hipMemcpyAsync(dst, src, bytes, kind, s));
+    } else {
+        // tracer q under the mixed policy is stored in FP32; stage the FP64 copy in the
+        // second-derivative scratch (3 floats per value >= one double)
+        double *tmp = (double *)st->hq;
+        HIP_TRY(hipMemcpyAsync(tmp, src, bytes, kind, s));
+        hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tmp,
+                           (float *)st->q[st->parity], n);
+        HIP_TRY(hipGetLastError());
+    }
+    if (st->policy == MPDC_POLICY_MIX && st->model != MPDC_MODEL_TRACER) {
+        StageArgs a = stage_args(st, 0);
+        // regenerate the FP32 shadows of the current state (set 0)
+        a.u_o = st->set[0].u;
+        a.Th_o = st->set[0].Th;
+        a.ps_o = st->set[0].ps;
+        a.u32_o = st->set[0].u32;
+        a.th32_o = st->set[0].th32;
+        HIP_TRY(launch_shadows(st->model, a, s));
+    }
+    if (!src_on_device) HIP_TRY(hipStreamSynchronize(s));
+    return MPDC_OK;
+}
+
+int mpdc_state_read(mpdc_state *st, int f, void *dst, int dst_on_device, size_t bytes, void *stream) {
+    if (!st || !dst) return fail(MPDC_E_INVAL, "null state or destination");
+    long n = field_count(st, f);
+    if (n < 0) return fail(MPDC_E_INVAL, "field not part of this model");
+    if (bytes != (size_t)n * sizeof(double)) return fail(MPDC_E_INVAL, "byte count does not match the field");
+    hipStream_t s = (hipStream_t)stream;
+    hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    double *srcp = field_ptr(st, f);
+    if (srcp) {
+        HIP_TRY(hipMemcpyAsync(dst, srcp, bytes, kind, s));
+    } else {
+        double *tmp = (double *)st->hq;
+        hipLaunchKernelGGL(k_f32_to_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           (const float *)st->q[st->parity], tmp, n);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(dst, tmp, bytes, kind, s));
+    }
+    if (!dst_on_device) HIP_TRY(hipStreamSynchronize(s));
+    return MPDC_OK;
+}
+
+int mpdc_set_graph(mpdc_state *st, int enable) {
+    if (!st) return fail(MPDC_E_INVAL, "null state");
+    drop_graphs(st);
+    st->use_graph = enable != 0;
+    return MPDC_OK;
+}
+
+int mpdc_set_launch(mpdc_state *st, int cells_per_block, int flat_block) {
+    if (!st) return fail(MPDC_E_INVAL, "null state");
+    if (flat_block == 0) flat_block = 256;
+    if (flat_block < 64 || flat_block > 1024 || flat_block % 64) return fail(MPDC_E_INVAL, "flat block must be 64..1024, a multiple of 64");
+    if (cells_per_block < 0 || (long)cells_per_block * st->K * st->M > 1024)
+        return fail(MPDC_E_INVAL, "cells per block times K*M must be at most 1024");
+    if (st->model == MPDC_MODEL_NDC && cells_per_block > 0 &&
+        stage_lds_bytes(st->model, KERNEL_CELL_B, cells_per_block, st->K, st->M) > 65536)
+        return fail(MPDC_E_INVAL, "column kernel would need more than 64 KiB of LDS");
+    drop_graphs(st);
+    st->launch.cells_per_block = cells_per_block;
+    st->launch.flat_block = flat_block;
+    return MPDC_OK;
+}
+
+static int step_common(mpdc_state *st, int nsteps, void *stream, bool tracer) {
+    if (!st) return fail(MPDC_E_INVAL, "null state");
+    if (nsteps < 0) return fail(MPDC_E_INVAL, "negative step count");
+    if (tracer != (st->model == MPDC_MODEL_TRACER))
+        return fail(MPDC_E_STATE, tracer ? "tracer_step on a dycore state" : "dycore_step on a tracer state");
+    hipStream_t s = (hipStream_t)stream;
+    if (st->model == MPDC_MODEL_NDC &&
+        stage_lds_bytes(st->model, KERNEL_CELL_B, cpb_of(st), st->K, st->M) > 65536)
+        return fail(MPDC_E_UNSUPPORTED, "column too tall for the LDS of one work-group");
+    for (int n = 0; n < nsteps; n++) {
+        int parity = tracer ? st->parity : 0;
+        if (st->use_graph && s != nullptr) {
+            if (!st->graph[parity] || st->graph_stream[parity] != s) {
+                if (st->graph[parity]) (void)hipGraphExecDestroy(st->graph[parity]);
+                st->graph[parity] = nullptr;
+                int rc = capture_step(st, parity, s);
+                if (rc != MPDC_OK) return rc;
+            }
+            HIP_TRY(hipGraphLaunch(st->graph[parity], s));
+        } else {
+            int rc = tracer ? run_tracer_step(st, parity, s) : run_dycore_step(st, s);
+            if (rc != MPDC_OK) return rc;
+        }
+        if (tracer) st->parity = 1 - st->parity;
+    }
+    return MPDC_OK;
+}
+
+int mpdc_dycore_step(mpdc_state *st, int nsteps, void *stream) { return step_common(st, nsteps, stream, false); }
+int mpdc_tracer_step(mpdc_state *st, int nsteps, void *stream) { return step_common(st, nsteps, stream, true); }
+
+int mpdc_time_kernel(mpdc_state *st, int kernel_id, int nreps, void *stream, double *ms_avg) {
+    if (!st || !ms_avg || nreps < 1) return fail(MPDC_E_INVAL, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    const bool tr = st->model == MPDC_MODEL_TRACER;
+    const int nk = tr ? 3 : 4;
+    if (kernel_id < 0 || kernel_id >= nk) return fail(MPDC_E_INVAL, "kernel id out of range");
+    // run the kernels of the first stage that precede the timed one, so its inputs exist
+    if (tr) {
+        TracerArgs a = tracer_args(st, 0, st->parity);
+        a.last_stage = 0;
+        for (int k = 0; k < kernel_id; k++) HIP_TRY(launch_tracer_kernel(st->policy, a, k, s));
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int r = 0; r < nreps; r++) HIP_TRY(launch_tracer_kernel(st->policy, a, kernel_id, s));
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *ms_avg = ms / nreps;
+        return MPDC_OK;
+    }
+    StageArgs a = stage_args(st, 0);
+    for (int k = 0; k < kernel_id; k++) HIP_TRY(launch_stage_kernel(st->model, st->policy, a, k, s));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < nreps; r++) HIP_TRY(launch_stage_kernel(st->model, st->policy, a, kernel_id, s));
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_avg = ms / nreps;
+    return MPDC_OK;
+}
+
+// Algorithmic bytes: every array a kernel must touch, read or written once.
+static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
+    const double N = st->N, E = st->E, V = st->V, K = st->K, M = st->M;
+    const double KM = K * M, K1M = (K + 1) * M;
+    const double r = (double)rsize(st->policy);
+    const bool mix = st->policy == MPDC_POLICY_MIX;
+    const bool first = (stage == 0);
+    if (st->model == MPDC_MODEL_TRACER) {
+        const double T = st->T, nq = N * K * T;
+        const double tabc = N * kCellSlots * (4 + 4 + r);              // c_edge, c_nbr, c_div
+        const double Fb = E * K * 8 + N * K * 8;                        // F, dpi_n
+        switch (id) {
+        case TKERNEL_LOW:   // q_n, q_s, hess table, e_cell -> qtd, hq
+            return Fb + tabc + N * 3 * kCellSlots * r + E * 8 + nq * r * (first ? 1 : 2) + nq * r * 4;
+        case TKERNEL_LIMIT: // q_n, qtd, q_s, hq, hdir, d2 -> rp, rm
+            return Fb + tabc + E * 8 + E * 6 * r + E * r + nq * r * (first ? 5 : 6) + nq * r * 2;
+        case TKERNEL_UPDATE:// q_n, q_s, hq, rp, rm -> q_o (+ dpi_o)
+            return Fb + tabc + E * 8 + E * 6 * r + E * r + nq * r * (first ? 6 : 7) + nq * r +
+                   (stage == 2 ? N * K * 8 : 0);
+        }
+        return 0;
+    }
+    const bool sw = st->model == MPDC_MODEL_SW, nh = st->model == MPDC_MODEL_NDC;
+    const double cellI = N * kCellSlots * 8;                            // c_edge + c_nbr
+    const double u_s = E * KM * r, ps = N * M * 8;
+    const double th_s = sw ? 0 : N * KM * (mix ? 4 : 8);
+    switch (id) {
+    case KERNEL_CELL_A: {
+        double b = cellI + N * kCellSlots * (8 + r) + u_s + ps + th_s + N * KM * r /*ke*/;
+        if (sw) return b + ps /*h_n*/ + ps /*h_o*/;
+        b += N * 3 * kCellSlots * r + 3 * N * KM * r /*hth*/ + N * K1M * 8 /*mdot*/ + ps /*dps*/;
+        if (nh) b += 4 * N * K1M * 8 /*w_s, phi_s (+ w_n, phi_n)*/ + 2 * N * K1M * 8 /*w*, phi* */ -
+                     (first ? 2 * N * K1M * 8 : 0);
+        return b;
+    }
+    case KERNEL_VERTEX:
+        return V * 3 * 8 + V * 3 * (r + 8) + V * 8 + u_s + ps + V * KM * r;
+    case KERNEL_CELL_B: {
+        if (sw) return 0;
+        double b = cellI + N * kCellSlots * r + E * 8 + E * 6 * r + E * r + ps + th_s + 3 * N * KM * r + u_s +
+                   N * K1M * 8 + ps /*dps*/;
+        b += (first && !mix) ? 0 : N * KM * 8 + ps;       // Th_n, ps_n (stage 1 FP64: same arrays as _s)
+        b += N * KM * 8 + ps + 2 * N * KM * 8 + (mix ? N * KM * 4 : 0);   // Th_o, ps_o, alpha, phim, th32_o
+        if (nh) b += 2 * N * K1M * 8 /*w*, phi* */ + 2 * N * K1M * 8 /*w_o, phi_o*/ + 2 * N * KM * 8 /*pm, mum*/;
+        return b;
+    }
+    case KERNEL_EDGE: {
+        double b = E * (2 * 4 + 2 * 4 + kTriskSlots * (4 + r) + 8 + (mix ? 4 : 0)) + V * KM * r + ps + u_s +
+                   N * KM * r /*ke*/;
+        b += (first && !mix) ? 0 : E * KM * 8;             // u_n
+        b += E * KM * 8 + (mix ? E * KM * 4 : 0);           // u_o, u32_o
+        if (sw) return b + ps /*h_o*/ + N * 8 /*b*/;
+        b += N * K1M * 8 + 2 * N * KM * 8 + ps;             // mdot, alpha, phim, ps_o
+        if (nh) b += 2 * N * KM * 8;                         // pm, mum
+        return b;
+    }
+    }
+    return 0;
+}
+
+double mpdc_kernel_bytes(const mpdc_state *st, int id) {
+    if (!st) return 0;
+    return kernel_bytes_stage(st, id, 0);
+}
+
+double mpdc_step_bytes(const mpdc_state *st) {
+    if (!st) return 0;
+    double b = 0;
+    const int nk = st->model == MPDC_MODEL_TRACER ? 3 : 4;
+    for (int s = 0; s < 3; s++)
+        for (int k = 0; k < nk; k++) b += kernel_bytes_stage(st, k, s);
+    return b;
+}
+
+int mpdc_diagnostics(mpdc_state *st, int f, const void *ref_dev, mpdc_diag *out, void *stream) {
+    if (!st || !out) return fail(MPDC_E_INVAL, "null state or output");
+    long nf = field_count(st, f);
+    if (nf < 0) return fail(MPDC_E_INVAL, "field not part of this model");
+    hipStream_t s = (hipStream_t)stream;
+    mpdc_diag d;
+    std::memset(&d, 0, sizeof(d));
+    std::vector<double> part((size_t)kDiagBlocks * 9);
+    auto reduce = [&](DiagArgs a, double r9[9]) -> int {
+        a.partial = st->partial;
+        HIP_TRY(launch_diag(a, kDiagBlocks, s));
+        HIP_TRY(hipMemcpyAsync(part.data(), st->partial, part.size() * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        r9[0] = 0; r9[1] = INFINITY; r9[2] = -INFINITY;
+        for (int v = 3; v < 9; v++) r9[v] = 0;
+        for (int b = 0; b < kDiagBlocks; b++) {       // fixed order
+            const double *p = &part[(size_t)b * 9];
+            r9[0] += p[0];
+            r9[1] = std::min(r9[1], p[1]);
+            r9[2] = std::max(r9[2], p[2]);
+            for (int v = 3; v < 7; v++) r9[v] += p[v];
+            r9[7] = std::max(r9[7], p[7]);
+            r9[8] = std::max(r9[8], p[8]);
+        }
+        return MPDC_OK;
+    };
+    const double *area = st->mesh->dev.c_area;
+    const long N = st->N, K = st->K, M = st->M, T = st->T;
+    double r9[9];
+    // mass
+    if (st->model == MPDC_MODEL_TRACER) {
+        for (int t = 0; t < T && t < 16; t++) {
+            DiagArgs a{};
+            a.area = area;
+            a.n = N; a.inner = K; a.xs = (int)T; a.xo = t;
+            if (st->policy == MPDC_POLICY_DBL) a.x = (const double *)st->q[st->parity];
+            else a.x32 = (const float *)st->q[st->parity];
+            a.w = st->dpi[st->parity];
+            int rc = reduce(a, r9);
+            if (rc) return rc;
+            d.mass_tracer[t] = r9[0];
+        }
+        DiagArgs a{};
+        a.area = area; a.n = N; a.inner = K; a.xs = 1; a.xo = 0; a.x = st->dpi[st->parity];
+        int rc = reduce(a, r9);
+        if (rc) return rc;
+        d.mass = r9[0];
+    } else {
+        DiagArgs a{};
+        a.area = area; a.n = N; a.inner = M; a.xs = 1; a.xo = 0; a.x = st->set[0].ps;
+        a.offset = st->model == MPDC_MODEL_SW ? 0.0 : st->cfg.ptop;
+        int rc = reduce(a, r9);
+        if (rc) return rc;
+        d.mass = r9[0];
+    }
+    // field statistics and norms: cell fields area-weighted, edge fields unweighted
+    {
+        DiagArgs a{};
+        const bool edge = (f == MPDC_FIELD_U || f == MPDC_FIELD_TR_FLUX);
+        a.area = edge ? nullptr : area;
+        a.n = edge ? st->E : N;
+        a.inner = nf / a.n;
+        a.xs = 1;
+        a.xo = 0;
+        double *fp = field_ptr(st, f);
+        if (fp) a.x = fp;
+        else a.x32 = (const float *)st->q[st->parity];
+        a.ref = (const double *)ref_dev;
+        int rc = reduce(a, r9);
+        if (rc) return rc;
+        d.min = r9[1];
+        d.max = r9[2];
+        if (ref_dev) {
+            d.l1 = r9[3] / r9[4];
+            d.l2 = std::sqrt(r9[5] / r9[6]);
+            d.linf = r9[7] / r9[8];
+        }
+    }
+    // non-finite count over the prognostic fields
+    {
+        std::vector<unsigned long long> nfp(kDiagBlocks);
+        auto count = [&](const double *x, const float *x32, long n) -> int {
+            if ((!x && !x32) || n <= 0) return MPDC_OK;
+            HIP_TRY(launch_nonfinite(x, x32, n, st->nfpartial, kDiagBlocks, s));
+            HIP_TRY(hipMemcpyAsync(nfp.data(), st->nfpartial, nfp.size() * 8, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            for (auto v : nfp) d.nonfinite += (int64_t)v;
+            return MPDC_OK;
+        };
+        int rc = MPDC_OK;
+        if (st->model == MPDC_MODEL_TRACER) {
+            rc = count(st->dpi[st->parity], nullptr, N * K);
+            if (!rc) {
+                if (st->policy == MPDC_POLICY_DBL) rc = count((const double *)st->q[st->parity], nullptr, N * K * T);
+                else rc = count(nullptr, (const float *)st->q[st->parity], N * K * T);
+            }
+        } else {
+            const StateSet &s0 = st->set[0];
+            rc = count(s0.ps, nullptr, N * M);
+            if (!rc) rc = count(s0.u, nullptr, st->E * K * M);
+            if (!rc && s0.Th) rc = count(s0.Th, nullptr, N * K * M);
+            if (!rc && s0.w) rc = count(s0.w, nullptr, N * (K + 1) * M);
+            if (!rc && s0.phi) rc = count(s0.phi, nullptr, N * (K + 1) * M);
+        }
+        if (rc) return rc;
+    }
+    *out = d;
+    if (d.nonfinite > 0) return fail(MPDC_E_NUMERIC, "non-finite values in the state");
+    return MPDC_OK;
+}
+
+}  // extern "C"

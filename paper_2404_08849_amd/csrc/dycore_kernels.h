@@ -1,0 +1,91 @@
+// Kernel arguments and launchers of the dycore and tracer kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "mpdc_internal.h"
+
+namespace mpdc {
+
+enum { MODEL_SW = MPDC_MODEL_SW, MODEL_HDC = MPDC_MODEL_HDC, MODEL_NDC = MPDC_MODEL_NDC };
+enum { POLICY_DBL = MPDC_POLICY_DBL, POLICY_MIX = MPDC_POLICY_MIX };
+enum { KERNEL_CELL_A = 0, KERNEL_VERTEX = 1, KERNEL_CELL_B = 2, KERNEL_EDGE = 3 };
+
+// Everything one dycore stage reads and writes.  Pointers of another model
+// or policy are null.  "_n": state at the start of the step; "_s": state of
+// the previous stage; "_o": output state of this stage.
+struct StageArgs {
+    DevMesh mesh;
+    int K, M;
+    int cpb;          // cells per work-group of the column kernels
+    int flat_block;   // threads per work-group of the flat kernels
+    double dts, grav, rd, cp, p0, ptop, kappa, gamma;
+    const double *dsig;  // [K]
+    const double *sig;   // [K+1]
+    const double *ps_n, *Th_n, *u_n, *w_n, *phi_n;
+    const double *ps_s, *Th_s, *u_s, *w_s, *phi_s;
+    const float *u32_s, *th32_s;
+    double *ps_o, *Th_o, *u_o, *w_o, *phi_o;
+    float *u32_o, *th32_o;
+    const double *b;     // SW bottom height [N]
+    // stage intermediates
+    double *dps;         // [N][M]
+    double *mdot;        // [N][K+1][M]
+    void *ke;            // [N][K][M]      (R)
+    void *hth;           // [N][3][K][M]   (R)
+    void *qv;            // [V][K][M]      (R)
+    double *alpha, *phim, *pm, *mum;   // [N][K][M]
+    double *wstar, *phistar;           // [N][K+1][M]
+
+    template <typename R> __device__ R *ke_out() const { return (R *)ke; }
+    template <typename R> __device__ const R *ke_in() const { return (const R *)ke; }
+    template <typename R> __device__ R *hth_out() const { return (R *)hth; }
+    template <typename R> __device__ const R *hth_in() const { return (const R *)hth; }
+    template <typename R> __device__ R *qv_out() const { return (R *)qv; }
+    template <typename R> __device__ const R *qv_in() const { return (const R *)qv; }
+};
+
+hipError_t launch_stage_kernel(int model, int policy, const StageArgs &a, int which, hipStream_t s);
+hipError_t launch_shadows(int model, const StageArgs &a, hipStream_t s);
+size_t stage_lds_bytes(int model, int which, int cpb, int K, int M);
+
+// ---- tracer transport ----
+enum { TKERNEL_LOW = 0, TKERNEL_LIMIT = 1, TKERNEL_UPDATE = 2 };
+
+struct TracerArgs {
+    DevMesh mesh;
+    int K, T;
+    int cpb;           // cells per work-group
+    int fct;
+    double dts;
+    const double *F;       // [E][K]   prescribed FP64 mass flux
+    const double *dpi_n;   // [N][K]   layer mass at the start of the step
+    double *dpi_o;         // [N][K]   layer mass after the step (written by the last stage)
+    const void *q_n;       // [N][K][T] (R)
+    const void *q_s;       // previous stage (R)
+    void *q_o;             // this stage (R)
+    void *qtd;             // [N][K][T] low-order solution (R)
+    void *hq;              // [N][3][K][T] second-derivative coefficients of q_s (R)
+    void *rp, *rm;         // [N][K][T] limiter ratios R+ / R- (R)
+    int last_stage;
+};
+
+hipError_t launch_tracer_kernel(int policy, const TracerArgs &a, int which, hipStream_t s);
+
+// ---- diagnostics ----
+struct DiagArgs {
+    const double *area;   // [N]
+    const double *x;      // field [n][inner]   FP64 (or null)
+    const float *x32;     // field [n][inner]   FP32 (or null)
+    const double *ref;    // reference, same layout (or null)
+    const double *w;      // optional second factor [n][inner] (tracer mass: dpi), or null
+    long n, inner;        // entities and values per entity
+    int xs, xo;           // x/ref index = (i*inner + j)*xs + xo (tracer t of T: xs = T, xo = t)
+    double offset;        // subtracted from x before the mass sum (pi_t)
+    double *partial;      // [nblocks][8]
+};
+hipError_t launch_diag(const DiagArgs &a, int nblocks, hipStream_t s);
+hipError_t launch_nonfinite(const double *x, const float *x32, long n, unsigned long long *partial, int nblocks,
+                            hipStream_t s);
+
+}  // namespace mpdc

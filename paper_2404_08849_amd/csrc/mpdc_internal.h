@@ -1,0 +1,109 @@
+// Internal structures of the mpdc library (host + device).
+//
+// Device tables are fixed-width per entity so that a kernel thread reaches
+// its stencil with one multiply-add: cells carry 6 slots (pentagons pad the
+// sixth with -1 and zero weights), edges carry 10 TRiSK slots, vertices 3.
+// Geometry weights come in FP64 (every policy's FP64 terms) and FP32 (the
+// FP32 advective terms of the mixed policy); both are derived in FP64 on the
+// host and the FP32 copy is a rounding of the FP64 value.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mpdc.h"
+
+namespace mpdc {
+
+constexpr int kCellSlots = 6;
+constexpr int kTriskSlots = 10;
+
+// Device view of the mesh tables (pointers into the caller's workspace).
+struct DevMesh {
+    int N, E, V;
+    // cells
+    const int *c_edge;      // [N][6] edge of slot j (-1 pad)
+    const int *c_nbr;       // [N][6] neighbour across slot j (self for pads)
+    const double *c_div;    // [N][6] s_{e,i} l_e / A_i
+    const float *c_div32;
+    const double *c_ke;     // [N][6] l_e d_e / (4 A_i)
+    const float *c_ke32;
+    const double *c_hess;   // [N][3][6] slot differences -> (Hxx, Hxy, Hyy)
+    const float *c_hess32;
+    const double *c_area;   // [N]
+    // edges
+    const int *e_cell;      // [E][2]
+    const int *e_vert;      // [E][2]
+    const double *e_dinv;   // [E] 1/d_e
+    const float *e_dinv32;
+    const double *e_d2;     // [E] d_e^2/12
+    const float *e_d2_32;
+    const double *e_hdir;   // [E][2][3] (c^2, 2cs, s^2) of the neighbour direction in c1's / c2's frame
+    const float *e_hdir32;
+    const int *e_tk;        // [E][10] TRiSK edges (-1 pad)
+    const double *e_tkw;    // [E][10] w_{e,e'} l_{e'} / d_e
+    const float *e_tkw32;
+    // vertices
+    const int *v_edge;      // [V][3]
+    const int *v_cell;      // [V][3]
+    const double *v_curl;   // [V][3] s'_{e,v} d_e / A_v
+    const float *v_curl32;
+    const double *v_kite;   // [V][3] R_{i,v} / A_v
+    const double *v_f;      // [V]
+};
+
+}  // namespace mpdc
+
+struct mpdc_mesh {
+    int N, E, V;
+    double radius;
+    mpdc::DevMesh dev;
+    hipStream_t stream;
+    // FP64 host copies of the exported tables
+    std::vector<int> cells_on_cell;
+    std::vector<double> edge_sign, vertex_sign;
+    std::vector<int> trisk_off, trisk_edge;
+    std::vector<double> trisk_w;
+    std::vector<double> hessian;   // [2E][6]
+    std::vector<double> area_cell; // host copy for diagnostics weights
+};
+
+namespace mpdc {
+
+// Layout helpers
+struct Dims {
+    int N, E, V, K, M, T;
+    long long KM() const { return (long long)K * M; }
+};
+
+// Kernel launch shape
+struct Launch {
+    int cells_per_block = 0;   // column kernels: cells per work-group (0 = auto)
+    int flat_block = 256;      // flat kernels: threads per work-group
+};
+
+// Thread-local error message
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+// Table derivation (host, FP64); returns "" or an error message.
+struct HostTables {
+    std::vector<int> c_edge, c_nbr;
+    std::vector<double> c_div, c_ke, c_hess, c_area;
+    std::vector<int> e_cell, e_vert;
+    std::vector<double> e_dinv, e_d2, e_hdir, e_tkw;
+    std::vector<int> e_tk;
+    std::vector<int> v_edge, v_cell;
+    std::vector<double> v_curl, v_kite, v_f;
+    // exported (reference-form) tables
+    std::vector<int> cells_on_cell, trisk_off, trisk_edge;
+    std::vector<double> edge_sign, vertex_sign, trisk_w, hessian;
+};
+std::string validate_mesh(const mpdc_mesh_desc *d);
+std::string derive_tables(const mpdc_mesh_desc *d, HostTables &t);
+
+}  // namespace mpdc

@@ -1,0 +1,227 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars (stated in the workload definitions): the all-FP64 path within 1e-12
+normalised L2 of the oracle on every prognostic field; the mixed path within
+1e-5 normalised L2 on h / surface pressure after 10 steps (every other field
+reported and bounded loosely); integer mesh tables bit-exact.
+"""
+import numpy as np
+import pytest
+
+from paper_2404_08849_amd.inputs import initial as ic
+from gpu_helpers import gpu_hdc, gpu_ndc, gpu_sw, gpu_tracer, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+DBL_TOL = 1e-12
+MIX_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def mpdc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_08849_amd.mpdc as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def oracle_mod():
+    import oracle
+    return oracle
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def test_mesh_tables_match_oracle(mpdc, oracle_mod, mesh_cache):
+    for lev in (2, 4):
+        m = mesh_cache(lev)
+        g = mpdc.Mesh(m)
+        o = oracle_mod.OracleMesh(m).tables()
+        assert np.array_equal(g.table(mpdc.TABLE_CELLS_ON_CELL), o["cells_on_cell"])
+        assert np.array_equal(g.table(mpdc.TABLE_EDGE_SIGN), o["edge_sign"])
+        assert np.array_equal(g.table(mpdc.TABLE_VERTEX_SIGN), o["vertex_sign"].ravel())
+        assert np.array_equal(g.table(mpdc.TABLE_TRISK_OFFSET), o["trisk_offset"])
+        assert np.array_equal(g.table(mpdc.TABLE_TRISK_EDGE), o["trisk_edge"])
+        assert np.abs(g.table(mpdc.TABLE_TRISK_WEIGHT) - o["trisk_weight"]).max() <= 1e-14
+        hg = g.table(mpdc.TABLE_HESSIAN).reshape(-1, 6)
+        scale = np.abs(o["hessian"]).max()
+        assert np.abs(hg - o["hessian"]).max() <= 1e-9 * scale
+
+
+@pytest.mark.parametrize("policy", ["DBL", "MIX"])
+def test_sw_parity_g5(mpdc, oracle_mod, mesh_cache, policy):
+    m = mesh_cache(5)
+    s = ic.sw_geostrophic(m, seed=1000)
+    om = oracle_mod.OracleMesh(m)
+    h_o, u_o = om.sw_run(s["h"], s["u"], s["b"], 600.0, 10)
+    g = mpdc.Mesh(m)
+    pol = getattr(mpdc, "POLICY_" + policy)
+    _say("sw G5 10 steps", policy)
+    st, h, u = gpu_sw(mpdc, g, s, 600.0, 10, pol)
+    eh, eu = rel_l2(h, h_o, m["areaCell"]), rel_l2(u, u_o)
+    # the bump's signal (h - h0) must also agree, not only the mean depth
+    eb = rel_l2(h - s["h"], h_o - s["h"], m["areaCell"])
+    _say("  h %.3e  u %.3e  dh %.3e" % (eh, eu, eb))
+    if policy == "DBL":
+        assert eh <= DBL_TOL and eu <= DBL_TOL and eb <= 1e-9
+    else:
+        assert eh <= MIX_TOL and eu <= 1e-3 and eb <= 1e-2
+
+
+@pytest.mark.parametrize("policy", ["DBL", "MIX"])
+def test_hdc_parity_g4(mpdc, oracle_mod, mesh_cache, policy):
+    m = mesh_cache(4)
+    K = 30
+    s = ic.hdc_jet(m, K, seed=2000)
+    om = oracle_mod.OracleMesh(m)
+    ps_o, Th_o, u_o = om.hdc_run(s["ps"], s["Theta"], s["u"], 600.0, 10)
+    g = mpdc.Mesh(m)
+    pol = getattr(mpdc, "POLICY_" + policy)
+    _say("hdc G4x30 10 steps", policy)
+    st, (ps, Th, u) = gpu_hdc(mpdc, g, s, K, 600.0, 10, pol)
+    e = (rel_l2(ps, ps_o, m["areaCell"]), rel_l2(Th, Th_o, m["areaCell"]), rel_l2(u, u_o))
+    du = rel_l2(u - s["u"], u_o - s["u"])
+    _say("  ps %.3e  Theta %.3e  u %.3e  du %.3e" % (e + (du,)))
+    if policy == "DBL":
+        assert max(e) <= DBL_TOL and du <= 1e-9
+    else:
+        assert e[0] <= MIX_TOL and e[1] <= MIX_TOL and e[2] <= 1e-3
+
+
+@pytest.mark.parametrize("policy", ["DBL", "MIX"])
+def test_ndc_parity_g4(mpdc, oracle_mod, mesh_cache, policy):
+    m = mesh_cache(4)
+    K = 20
+    s = ic.nh_warm_bubble(m, K, rh=6.0e5, seed=4000)
+    om = oracle_mod.OracleMesh(m)
+    ref = om.ndc_run(s["ps"], s["Theta"], s["u"], s["w"], s["phi"], 60.0, 10)
+    g = mpdc.Mesh(m)
+    pol = getattr(mpdc, "POLICY_" + policy)
+    _say("ndc G4x20 10 steps", policy)
+    st, out = gpu_ndc(mpdc, g, s, K, 60.0, 10, pol)
+    names = ["ps", "Theta", "u", "w", "phi"]
+    errs = {}
+    for n, x, r in zip(names, out, ref):
+        errs[n] = rel_l2(x, r)
+    errs["dphi"] = rel_l2(out[4] - s["phi"], ref[4] - s["phi"])
+    _say("  " + "  ".join("%s %.3e" % kv for kv in errs.items()))
+    assert np.abs(ref[3]).max() > 1e-4          # the bubble produces vertical motion
+    if policy == "DBL":
+        # w and u are small residuals of cancelling FP64 terms (the acoustic
+        # balance g dt (dp/dpi - 1)); their bar is the oracle's own sensitivity
+        # to a 1e-15 relative perturbation of Theta (a few ulps), times 10
+        r = np.random.default_rng(9)
+        Thp = s["Theta"] * (1.0 + 1e-15 * r.standard_normal(s["Theta"].shape))
+        refp = om.ndc_run(s["ps"], Thp, s["u"], s["w"], s["phi"], 60.0, 10)
+        sens = {n: rel_l2(a, b) for n, a, b in zip(names, refp, ref)}
+        _say("  oracle sensitivity " + "  ".join("%s %.3e" % kv for kv in sens.items()))
+        for n in names:
+            assert errs[n] <= max(DBL_TOL, 10.0 * sens[n]), n
+    else:
+        assert errs["ps"] <= MIX_TOL and errs["Theta"] <= MIX_TOL and errs["phi"] <= MIX_TOL
+        assert rel_l2(out[3], ref[3]) <= 1e-2
+
+
+@pytest.mark.parametrize("policy", ["DBL", "MIX"])
+def test_tracer_parity_g4(mpdc, oracle_mod, mesh_cache, policy):
+    m = mesh_cache(4)
+    tr = ic.tracer_solid_body(m, 5, 4, seed=3000)
+    om = oracle_mod.OracleMesh(m)
+    dt = 3000.0
+    dpi_o, q_o = om.tracer_run(tr["F"], tr["dpi"], tr["q"], dt, 6)
+    g = mpdc.Mesh(m)
+    pol = getattr(mpdc, "POLICY_" + policy)
+    _say("tracer G4x5x4 6 steps", policy)
+    st, dpi, q = gpu_tracer(mpdc, g, tr, dt, 6, pol)
+    eq = max(rel_l2(q[:, :, t], q_o[:, :, t], m["areaCell"]) for t in range(q.shape[2]))
+    ed = rel_l2(dpi, dpi_o, m["areaCell"])
+    _say("  q %.3e  dpi %.3e  min %.3e max %.3e" % (eq, ed, q.min(), q.max()))
+    assert ed <= DBL_TOL
+    if policy == "DBL":
+        assert eq <= DBL_TOL
+    else:
+        assert eq <= MIX_TOL
+        assert q.min() >= -1e-6 and q.max() <= 1.0 + 1e-6
+
+
+def test_hdc_ensemble_members_match_single_runs(mpdc, oracle_mod, mesh_cache):
+    m = mesh_cache(3)
+    K, M = 8, 3
+    base = ic.hdc_jet(m, K, seed=5000)
+    ens = ic.ensemble(base, M, sigma=0.1, seed=5000)
+    g = mpdc.Mesh(m)
+    om = oracle_mod.OracleMesh(m)
+    _say("hdc ensemble G3x8x3 5 steps DBL")
+    st, (ps, Th, u) = gpu_hdc(mpdc, g, ens, K, 900.0, 5, mpdc.POLICY_DBL, M=M)
+    for j in range(M):
+        ps_o, Th_o, u_o = om.hdc_run(ens["ps"][:, j], ens["Theta"][:, :, j], ens["u"][:, :, j], 900.0, 5)
+        assert rel_l2(ps[:, j], ps_o) <= DBL_TOL
+        assert rel_l2(Th[:, :, j], Th_o) <= DBL_TOL
+        assert rel_l2(u[:, :, j], u_o) <= DBL_TOL
+
+
+def test_graph_replay_and_launch_shapes_are_bitwise_identical(mpdc, mesh_cache):
+    m = mesh_cache(4)
+    K = 10
+    s = ic.hdc_jet(m, K, seed=2000)
+    g = mpdc.Mesh(m)
+    ref = None
+    for graph, launch in [(False, None), (True, None), (False, (1, 64)), (True, (3, 512)), (False, (25, 128))]:
+        _say("hdc G4x10 graph=%s launch=%s" % (graph, launch))
+        st, out = gpu_hdc(mpdc, g, s, K, 600.0, 4, mpdc.POLICY_MIX, graph=graph, launch=launch)
+        if ref is None:
+            ref = out
+        for a, b in zip(out, ref):
+            assert np.array_equal(a, b)
+    tr = ic.tracer_solid_body(m, 3, 2, seed=3000)
+    tref = None
+    for graph, launch in [(False, None), (True, None), (True, (0, 128))]:
+        _say("tracer G4 graph=%s launch=%s" % (graph, launch))
+        st, dpi, q = gpu_tracer(mpdc, g, tr, 3000.0, 3, mpdc.POLICY_MIX, graph=graph, launch=launch)
+        if tref is None:
+            tref = (dpi, q)
+        assert np.array_equal(dpi, tref[0]) and np.array_equal(q, tref[1])
+
+
+def test_diagnostics_match_oracle(mpdc, oracle_mod, mesh_cache):
+    import torch
+    m = mesh_cache(4)
+    K = 10
+    s = ic.hdc_jet(m, K, seed=2000)
+    g = mpdc.Mesh(m)
+    _say("diagnostics G4x10")
+    st, (ps, Th, u) = gpu_hdc(mpdc, g, s, K, 600.0, 3, mpdc.POLICY_DBL)
+    ref = torch.from_numpy(s["Theta"][:, :, None].copy()).cuda()
+    d = st.diagnostics(mpdc.FIELD_THETA, ref)
+    n = oracle_mod.norms(m["areaCell"], Th, s["Theta"])
+    assert np.allclose([d["l1"], d["l2"], d["linf"]], n, rtol=1e-10)
+    mass = oracle_mod.area_sum(m["areaCell"], ps - 1000.0)
+    assert abs(d["mass"] - mass) <= 1e-12 * mass
+    assert d["min"] == Th.min() and d["max"] == Th.max()
+    assert d["nonfinite"] == 0
+    # mass conservation of the GPU path at FP64 level in both policies
+    for pol in (mpdc.POLICY_DBL, mpdc.POLICY_MIX):
+        st, (ps, Th, u) = gpu_hdc(mpdc, g, s, K, 600.0, 10, pol)
+        m0 = oracle_mod.area_sum(m["areaCell"], s["ps"] - 1000.0)
+        m1 = oracle_mod.area_sum(m["areaCell"], ps - 1000.0)
+        assert abs(m1 - m0) <= 1e-13 * m0
+
+
+def test_diagnostics_flag_nonfinite(mpdc, mesh_cache):
+    m = mesh_cache(3)
+    s = ic.sw_geostrophic(m)
+    g = mpdc.Mesh(m)
+    st = mpdc.State(g, mpdc.MODEL_SW, mpdc.POLICY_DBL, dt=600.0)
+    h = s["h"].copy()
+    h[7] = np.nan
+    st.state_write(mpdc.FIELD_H, h[:, None])
+    st.state_write(mpdc.FIELD_U, s["u"][:, None, None])
+    st.state_write(mpdc.FIELD_B, s["b"])
+    d = st.diagnostics(mpdc.FIELD_H, check=False)
+    assert d["rc"] == -5 and d["nonfinite"] == 1
+    with pytest.raises(mpdc.MpdcError):
+        st.diagnostics(mpdc.FIELD_H)

@@ -1,0 +1,286 @@
+"""Benchmark of the mixed-precision icosahedral dycore on one MI355X.
+
+Default workload: the hydrostatic dry dycore (continuity, theta_m transport,
+momentum with TRiSK Coriolis and FP64 pressure gradient; RK3 forward-backward)
+on the G6 icosahedral mesh (40,962 cells) x 30 sigma levels, isothermal jet
+plus a seeded wind perturbation, dt = 300 s -- run in the mixed policy (the
+paper's term split) and in all-FP64.  One "step" is one full RK3 dycore step
+(three stages, four kernels each) replayed from a HIP graph.
+
+Prints ONE JSON line: value = mixed-policy cell-level-steps/s with inputs
+resident in HBM; the all-FP64 rate, the mixed/FP64 speedup, the accuracy gate
+(mixed vs FP64 oracle, normalised L2 of surface pressure after the workload's
+20 steps), the roofline of the dominant kernel (algorithmic bytes / HIP-event
+duration) and the FP64 oracle timed on the host cores.
+
+Other workloads (--workload): sw-g5, hdc-g6 (default), tracer-g8, ndc-g8,
+ens-g7 (16 members), hdc-g9.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_NAMES = {
+    "dycore": ["k_cell_a", "k_vertex", "k_cell_b", "k_edge"],
+    "tracer": ["k_tr_low", "k_tr_limit", "k_tr_update"],
+}
+
+WORKLOADS = {
+    "sw-g5": dict(model="SW", level=5, K=1, M=1, T=0, dt=600.0, steps=10,
+                  desc="shallow water G5 (10242 cells), geostrophic flow + bump, dt=600 s"),
+    "hdc-g6": dict(model="HDC", level=6, K=30, M=1, T=0, dt=300.0, steps=20,
+                   desc="hydrostatic dycore G6 (40962 cells) x 30 levels, jet + wind bump, dt=300 s"),
+    "tracer-g8": dict(model="TRACER", level=8, K=30, M=1, T=8, dt=300.0, steps=10,
+                      desc="tracer FCT transport G8 (655362 cells) x 30 levels x 8 tracers, solid-body rotation, dt=300 s"),
+    "ndc-g8": dict(model="NDC", level=8, K=60, M=1, T=0, dt=60.0, steps=10,
+                   desc="non-hydrostatic dycore G8 (655362 cells) x 60 levels, warm bubble, dt=60 s"),
+    "ens-g7": dict(model="HDC", level=7, K=30, M=16, T=0, dt=150.0, steps=20,
+                   desc="hydrostatic dycore ensemble G7 (163842 cells) x 30 levels x 16 members, dt=150 s"),
+    "hdc-g9": dict(model="HDC", level=9, K=30, M=1, T=0, dt=37.5, steps=10,
+                   desc="hydrostatic dycore G9 (2621442 cells) x 30 levels, jet, dt=37.5 s"),
+}
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--workload", default="hdc-g6", choices=sorted(WORKLOADS))
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-dbl", action="store_true", help="skip the all-FP64 timing")
+    p.add_argument("--profile-steps", type=int, default=20,
+                   help="steps run with HIP events between launches for per-kernel durations")
+    p.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                   help="only run a plain device copy of this many MiB (HBM counter calibration)")
+    return p.parse_args()
+
+
+def build_inputs(w):
+    from paper_2404_08849_amd.inputs import initial as ic
+    from paper_2404_08849_amd.inputs.meshgen import icosahedral_mesh
+    mesh = icosahedral_mesh(w["level"])
+    K, M, T = w["K"], w["M"], w["T"]
+    if w["model"] == "SW":
+        st = ic.sw_geostrophic(mesh, seed=1000)
+    elif w["model"] == "HDC":
+        base = ic.hdc_jet(mesh, K, seed=2000)
+        st = ic.ensemble(base, M, sigma=0.1, seed=5000) if M > 1 else base
+    elif w["model"] == "NDC":
+        st = ic.nh_warm_bubble(mesh, K, seed=4000)
+    else:
+        st = ic.tracer_solid_body(mesh, K, T, seed=3000)
+    return mesh, st
+
+
+def make_state(mpdc, g, w, st, policy):
+    from paper_2404_08849_amd.inputs import initial as ic
+    K, M, T = w["K"], w["M"], w["T"]
+    model = getattr(mpdc, "MODEL_" + w["model"])
+    s = mpdc.State(g, model, policy, K=K, M=M, T=T, dt=w["dt"],
+                   sigma=ic.sigma_interfaces(K) if w["model"] != "SW" else None)
+    if w["model"] == "SW":
+        s.state_write(mpdc.FIELD_H, st["h"])
+        s.state_write(mpdc.FIELD_U, st["u"])
+        s.state_write(mpdc.FIELD_B, st["b"])
+    elif w["model"] == "TRACER":
+        s.state_write(mpdc.FIELD_TR_FLUX, st["F"])
+        s.state_write(mpdc.FIELD_TR_DPI, st["dpi"])
+        s.state_write(mpdc.FIELD_TR_Q, st["q"])
+    else:
+        exp = (lambda a: a) if M > 1 else (lambda a: a[..., None])
+        s.state_write(mpdc.FIELD_PS, exp(st["ps"]))
+        s.state_write(mpdc.FIELD_THETA, exp(st["Theta"]))
+        s.state_write(mpdc.FIELD_U, exp(st["u"]))
+        if w["model"] == "NDC":
+            s.state_write(mpdc.FIELD_W, st["w"][..., None])
+            s.state_write(mpdc.FIELD_PHI, st["phi"][..., None])
+    return s
+
+
+def step(s, w, n, stream):
+    if w["model"] == "TRACER":
+        s.tracer_step(n, stream=stream)
+    else:
+        s.dycore_step(n, stream=stream)
+
+
+def key_field(mpdc, w):
+    return {"SW": mpdc.FIELD_H, "TRACER": mpdc.FIELD_TR_Q}.get(w["model"], mpdc.FIELD_PS)
+
+
+def timed_run(torch, mpdc, g, w, st, policy, steps, warmup, stream):
+    s = make_state(mpdc, g, w, st, policy)
+    s.set_graph(True)
+    with torch.cuda.stream(stream):
+        step(s, w, warmup, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step(s, w, steps, stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    return s, (t1 - t0) / max(steps, 1)
+
+
+def kernel_times(torch, s, w, nsteps, stream):
+    """Per-kernel mean launch duration from HIP events recorded between the
+    launches of nsteps real steps on the launch stream (continuing the timed
+    run's state), with the algorithmic bytes of one launch."""
+    kind = "tracer" if w["model"] == "TRACER" else "dycore"
+    with torch.cuda.stream(stream):
+        prof = s.profile_steps(nsteps, stream=stream)
+    out = {}
+    for kid, (ms, n) in prof.items():
+        out[KERNEL_NAMES[kind][kid]] = dict(ms=ms / n, launches=n, bytes=s.kernel_bytes(kid))
+    return out
+
+
+def accuracy_run(torch, mpdc, g, w, st, stream):
+    """Both policies for the workload's own step count from the same input."""
+    res = {}
+    for name, pol in (("DBL", mpdc.POLICY_DBL), ("MIX", mpdc.POLICY_MIX)):
+        s = make_state(mpdc, g, w, st, pol)
+        with torch.cuda.stream(stream):
+            step(s, w, w["steps"], stream)
+            torch.cuda.synchronize()
+        res[name] = s.state_read(key_field(mpdc, w), stream=stream)
+        d = s.diagnostics(key_field(mpdc, w), stream=stream, check=False)
+        res[name + "_nonfinite"] = d["nonfinite"]
+    return res
+
+
+def oracle_baseline(mesh, w, st, nsteps):
+    from oracle import OracleMesh, oracle_lib
+    om = OracleMesh(mesh)
+    t0 = time.perf_counter()
+    if w["model"] == "SW":
+        h, _ = om.sw_run(st["h"], st["u"], st["b"], w["dt"], nsteps)
+        key = h
+    elif w["model"] == "HDC":
+        ps0, Th0, u0 = st["ps"], st["Theta"], st["u"]
+        if w["M"] > 1:
+            ps0, Th0, u0 = ps0[:, 0], Th0[:, :, 0], u0[:, :, 0]
+        key, _, _ = om.hdc_run(ps0, Th0, u0, w["dt"], nsteps)
+    elif w["model"] == "NDC":
+        key = om.ndc_run(st["ps"], st["Theta"], st["u"], st["w"], st["phi"], w["dt"], nsteps)[0]
+    else:
+        _, key = om.tracer_run(st["F"], st["dpi"], st["q"], w["dt"], nsteps)
+    el = time.perf_counter() - t0
+    return key, el, oracle_lib().or_num_threads()
+
+
+def rel_l2(x, r):
+    x, r = np.asarray(x, np.float64).ravel(), np.asarray(r, np.float64).ravel()
+    return float(np.sqrt(((x - r) ** 2).sum() / (r ** 2).sum()))
+
+
+def copy_calibration(torch, mib):
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 3}), flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the design for sharding members and subdomains is in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2404_08849_amd.mpdc as mpdc
+    if args.copy_calib:
+        copy_calibration(torch, args.copy_calib)
+        return
+    w = WORKLOADS[args.workload]
+    mesh, st = build_inputs(w)
+    g = mpdc.Mesh(mesh)
+    stream = torch.cuda.Stream()
+    N, K, M, T = mesh["nCells"], w["K"], w["M"], w["T"]
+    units = N * K * M
+
+    s_mix, sec_mix = timed_run(torch, mpdc, g, w, st, mpdc.POLICY_MIX, args.steps, args.warmup, stream)
+    kt = kernel_times(torch, s_mix, w, args.profile_steps, stream)
+    step_bytes_mix = s_mix.step_bytes()
+    sec_dbl, kt_dbl, step_bytes_dbl = None, None, None
+    if not args.no_dbl:
+        s_dbl, sec_dbl = timed_run(torch, mpdc, g, w, st, mpdc.POLICY_DBL, args.steps, args.warmup, stream)
+        kt_dbl = kernel_times(torch, s_dbl, w, args.profile_steps, stream)
+        step_bytes_dbl = s_dbl.step_bytes()
+        del s_dbl
+    # dominant kernel of the mixed step: the largest share of the step time
+    dom = max(kt, key=lambda k: kt[k]["ms"] * kt[k]["launches"])
+    ach = kt[dom]["bytes"] / (kt[dom]["ms"] * 1e-3) / 1e9
+    acc = accuracy_run(torch, mpdc, g, w, st, stream)
+    gate = {"mix_vs_dbl_l2": rel_l2(acc["MIX"], acc["DBL"]), "nonfinite": acc["MIX_nonfinite"] + acc["DBL_nonfinite"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        nst = w["steps"] if w["level"] <= 6 else 1
+        key, el, cores = oracle_baseline(mesh, w, st, nst)
+        ref = np.asarray(key)
+        gpu_dbl = acc["DBL"] if nst == w["steps"] else None
+        if gpu_dbl is not None:
+            if w["model"] == "HDC" and M > 1:
+                gpu_dbl, gpu_mix = acc["DBL"][:, 0], acc["MIX"][:, 0]
+            else:
+                gpu_dbl, gpu_mix = acc["DBL"].reshape(ref.shape), acc["MIX"].reshape(ref.shape)
+            gate["dbl_vs_oracle_l2"] = rel_l2(gpu_dbl, ref)
+            gate["mix_vs_oracle_l2"] = rel_l2(gpu_mix, ref)
+        per_member = N * K * (T if w["model"] == "TRACER" else 1)
+        cpu = {"value": per_member * nst / el, "unit": "cell-level-steps/s" if w["model"] != "TRACER"
+               else "cell-level-tracer-steps/s", "cores": cores, "kind": "oracle",
+               "sample": "%d step(s) of one member of %s on the host (%.1f s)" % (nst, args.workload, el)}
+    gate["passes"] = bool(gate.get("mix_vs_oracle_l2", gate["mix_vs_dbl_l2"]) <= 1e-5 and gate["nonfinite"] == 0)
+
+    value = units / sec_mix
+    unit = "cell-level-steps/s"
+    out = {
+        "metric": "cell-level-steps/s (mixed vs all-FP64) at fixed L2 error; HBM GB/s",
+        "value": value,
+        "unit": unit,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec_mix * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "mixed f32/f64",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "mesh": "G%d" % w["level"], "cells": N, "levels": K,
+                   "members": M, "tracers": T, "policy": "MIX", "global_batch": M, "seq_len": K,
+                   "parallelism": "single GPU"},
+        "dbl_value": (units / sec_dbl) if sec_dbl else None,
+        "dbl_ms_per_step": sec_dbl * 1e3 if sec_dbl else None,
+        "mix_over_dbl_speedup": (sec_dbl / sec_mix) if sec_dbl else None,
+        "hbm_gbs_step": {"mix": step_bytes_mix / sec_mix / 1e9,
+                         "dbl": step_bytes_dbl / sec_dbl / 1e9 if sec_dbl else None},
+        "accuracy_gate": gate,
+        "kernels_mix": {k: {"ms": v["ms"], "MB": v["bytes"] / 1e6, "GB/s": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
+                        for k, v in kt.items()},
+        "kernels_dbl": ({k: {"ms": v["ms"], "MB": v["bytes"] / 1e6, "GB/s": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
+                         for k, v in kt_dbl.items()} if kt_dbl else None),
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": kt[dom]["bytes"], "ms_per_launch": kt[dom]["ms"]},
+        "cpu_baseline": cpu,
+    }
+    if w["model"] == "TRACER":
+        out["tracer_cell_level_steps_per_s"] = value * T
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

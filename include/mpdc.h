@@ -204,8 +204,21 @@ int mpdc_set_launch(mpdc_state *st, int cells_per_block, int flat_block);
  * duration.  The state is advanced by nothing (inputs are not modified).  */
 int mpdc_time_kernel(mpdc_state *st, int kernel_id, int nreps, void *stream, double *ms_avg);
 
-/* Algorithmic HBM bytes of one launch of a kernel class (same ids) and of one
- * whole step, from the arrays each kernel must read and write once. */
+/* Run nsteps steps with direct launches and a HIP event between consecutive
+ * launches on stream, and return per kernel class (ids as above) the summed
+ * duration in ms (ms_total[4]) and the launch count (launches[4]).  The state
+ * advances by nsteps exactly as with mpdc_dycore_step / mpdc_tracer_step. */
+int mpdc_profile_steps(mpdc_state *st, int nsteps, void *stream, double *ms_total, int *launches);
+
+/* Pick the launch shape (cells per work-group of the column kernels, threads
+ * per work-group of the flat kernels) with the shortest first-stage kernel
+ * times among the legal candidates, set it, and return it.  Uses
+ * mpdc_time_kernel, so the state is not advanced. */
+int mpdc_autotune(mpdc_state *st, void *stream, int *cells_per_block, int *flat_block);
+
+/* Algorithmic HBM bytes of one launch of a kernel class (same ids; mean over
+ * the three RK stages) and of one whole step, from the arrays each kernel
+ * must read and write once. */
 double mpdc_kernel_bytes(const mpdc_state *st, int kernel_id);
 double mpdc_step_bytes(const mpdc_state *st);
 

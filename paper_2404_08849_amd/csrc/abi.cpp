@@ -811,7 +811,90 @@ static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
 
 double mpdc_kernel_bytes(const mpdc_state *st, int id) {
     if (!st) return 0;
-    return kernel_bytes_stage(st, id, 0);
+    return (kernel_bytes_stage(st, id, 0) + kernel_bytes_stage(st, id, 1) + kernel_bytes_stage(st, id, 2)) / 3.0;
+}
+
+int mpdc_profile_steps(mpdc_state *st, int nsteps, void *stream, double *ms_total, int *launches) {
+    if (!st || !ms_total || !launches || nsteps < 0) return fail(MPDC_E_INVAL, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    const bool tr = st->model == MPDC_MODEL_TRACER;
+    const int nk = tr ? 3 : 4;
+    for (int k = 0; k < 4; k++) {
+        ms_total[k] = 0.0;
+        launches[k] = 0;
+    }
+    std::vector<hipEvent_t> ev(3 * nk + 1, nullptr);
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    int rc = MPDC_OK;
+    for (int n = 0; n < nsteps && rc == MPDC_OK; n++) {
+        const int parity = tr ? st->parity : 0;
+        std::vector<int> kid;
+        HIP_TRY(hipEventRecord(ev[0], s));
+        for (int stage = 0; stage < 3; stage++) {
+            for (int k = 0; k < nk; k++) {
+                hipError_t e;
+                if (tr) e = launch_tracer_kernel(st->policy, tracer_args(st, stage, parity), k, s);
+                else e = launch_stage_kernel(st->model, st->policy, stage_args(st, stage), k, s);
+                if (e != hipSuccess) { rc = hip_fail(e, "kernel launch"); break; }
+                HIP_TRY(hipEventRecord(ev[kid.size() + 1], s));
+                kid.push_back(k);
+            }
+            if (rc) break;
+        }
+        HIP_TRY(hipEventSynchronize(ev[kid.size()]));
+        for (size_t j = 0; j < kid.size(); j++) {
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, ev[j], ev[j + 1]));
+            if (!tr && st->model == MPDC_MODEL_SW && kid[j] == KERNEL_CELL_B) continue;   // no-op for SW
+            ms_total[kid[j]] += ms;
+            launches[kid[j]] += 1;
+        }
+        if (tr) st->parity = 1 - st->parity;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    return rc;
+}
+
+int mpdc_autotune(mpdc_state *st, void *stream, int *cells_per_block, int *flat_block) {
+    if (!st || !cells_per_block || !flat_block) return fail(MPDC_E_INVAL, "bad arguments");
+    const Launch keep = st->launch;
+    const bool tr = st->model == MPDC_MODEL_TRACER;
+    const int flats[] = {64, 128, 256, 512, 1024};
+    const int cpbs[] = {1, 2, 3, 4, 6, 8, 12, 16, 32, 64, 128, 256};
+    double best_flat_ms = 1e30, best_col_ms = 1e30;
+    int best_flat = keep.flat_block, best_cpb = keep.cells_per_block;
+    for (int fb : flats) {
+        st->launch.flat_block = fb;
+        double t = 0, ms = 0;
+        int rc = MPDC_OK;
+        if (tr) {
+            for (int k = 0; k < 3 && rc == MPDC_OK; k++) { rc = mpdc_time_kernel(st, k, 5, stream, &ms); t += ms; }
+        } else {
+            rc = mpdc_time_kernel(st, KERNEL_VERTEX, 5, stream, &ms); t += ms;
+            if (rc == MPDC_OK) { rc = mpdc_time_kernel(st, KERNEL_EDGE, 5, stream, &ms); t += ms; }
+        }
+        if (rc != MPDC_OK) { st->launch = keep; return rc; }
+        if (t < best_flat_ms) { best_flat_ms = t; best_flat = fb; }
+    }
+    st->launch.flat_block = best_flat;
+    if (!tr) {
+        for (int c : cpbs) {
+            if ((long)c * st->K * st->M > 1024) continue;
+            if (stage_lds_bytes(st->model, KERNEL_CELL_B, c, st->K, st->M) > 65536) continue;
+            st->launch.cells_per_block = c;
+            double t = 0, ms = 0;
+            int rc = mpdc_time_kernel(st, KERNEL_CELL_A, 5, stream, &ms);
+            t += ms;
+            if (rc == MPDC_OK && st->model != MPDC_MODEL_SW) { rc = mpdc_time_kernel(st, KERNEL_CELL_B, 5, stream, &ms); t += ms; }
+            if (rc != MPDC_OK) { st->launch = keep; return rc; }
+            if (t < best_col_ms) { best_col_ms = t; best_cpb = c; }
+        }
+        st->launch.cells_per_block = best_cpb;
+    }
+    drop_graphs(st);
+    *cells_per_block = st->launch.cells_per_block > 0 ? st->launch.cells_per_block : auto_cpb(st);
+    *flat_block = st->launch.flat_block;
+    return MPDC_OK;
 }
 
 double mpdc_step_bytes(const mpdc_state *st) {

@@ -461,91 +461,214 @@ __global__ void __launch_bounds__(1024) k_cell_b(StageArgs a) {
 // ---------------------------------------------------------------------------
 // edge: momentum
 // ---------------------------------------------------------------------------
-template <int MODEL, typename R>
+// Each lane owns L consecutive (k, m) values of one edge, so every gather is
+// one L-wide vector load and the per-edge table lookups are shared by L
+// values.  With M == 1 the L values are consecutive levels; with M > 1 they
+// are consecutive members of one level (L divides M).
+template <typename T, int L> struct alignas(sizeof(T) * L) Pack {
+    T v[L];
+};
+template <typename T, int L> __device__ __forceinline__ Pack<T, L> ldp(const T *p) {
+    return *reinterpret_cast<const Pack<T, L> *>(p);
+}
+template <typename T, int L> __device__ __forceinline__ void stp(T *p, const Pack<T, L> &x) {
+    *reinterpret_cast<Pack<T, L> *>(p) = x;
+}
+
+template <int MODEL, typename R, int L, bool M1>
 __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
     const DevMesh &m = a.mesh;
-    const int K = a.K, M = a.M, KM = K * M;
+    const int K = a.K, M = M1 ? 1 : a.M, KM = K * M;
+    const int lanes = KM / L;                       // lanes per edge
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long)m.E * KM) return;
-    const int e = (int)(idx / KM);
-    const int km = (int)(idx - (long)e * KM);
-    const int k = km / M, mm = km - k * M;
+    if (idx >= (long)m.E * lanes) return;
+    const int e = (int)(idx / lanes);
+    const int km0 = (int)(idx - (long)e * lanes) * L;
+    const long base = (long)e * KM + km0;
+    constexpr bool m1 = M1;
+    const int k0 = M1 ? km0 : km0 / M, mm0 = km0 - k0 * M;   // M > 1: all L values share level k0
+    int kk[L];
+    double dsg[L];                                   // layer sigma thickness of each value
+#pragma unroll
+    for (int j = 0; j < L; j++) {
+        kk[j] = m1 ? k0 + j : k0;
+        dsg[j] = (MODEL == MODEL_SW) ? 1.0 : a.dsig[kk[j]];
+    }
+
+    // layer mass of the L values at cell c of the previous stage
+    auto dpi_at = [&](int c, double out[L]) {
+        if (m1) {
+            const double s = a.ps_s[c];
+#pragma unroll
+            for (int j = 0; j < L; j++) out[j] = (MODEL == MODEL_SW) ? s : dsg[j] * (s - a.ptop);
+        } else {
+            const Pack<double, L> s = ldp<double, L>(a.ps_s + (long)c * M + mm0);
+#pragma unroll
+            for (int j = 0; j < L; j++) out[j] = (MODEL == MODEL_SW) ? s.v[j] : dsg[j] * (s.v[j] - a.ptop);
+        }
+    };
+
     const int c1 = m.e_cell[2 * (long)e], c2 = m.e_cell[2 * (long)e + 1];
     const int v1 = m.e_vert[2 * (long)e], v2 = m.e_vert[2 * (long)e + 1];
     const R *qv = a.qv_in<R>();
     const R *ke = a.ke_in<R>();
 
     // TRiSK Coriolis term: sum_e' w l_e'/d_e F_e' (q_e + q_e')/2
-    const R qe = (R)0.5 * (qv[(long)v1 * KM + km] + qv[(long)v2 * KM + km]);
+    R qe[L], Q[L];
+    {
+        const Pack<R, L> qa = ldp<R, L>(qv + (long)v1 * KM + km0), qb = ldp<R, L>(qv + (long)v2 * KM + km0);
+#pragma unroll
+        for (int j = 0; j < L; j++) {
+            qe[j] = (R)0.5 * (qa.v[j] + qb.v[j]);
+            Q[j] = 0;
+        }
+    }
     const R *tkw = pick<R>(m.e_tkw, m.e_tkw32) + (long)e * kTriskSlots;
-    R Q = 0;
 #pragma unroll
     for (int t = 0; t < kTriskSlots; t++) {
         const int ep = m.e_tk[(long)e * kTriskSlots + t];
         if (ep < 0) continue;
         const int a1 = m.e_cell[2 * (long)ep], a2 = m.e_cell[2 * (long)ep + 1];
-        const double dpe = 0.5 * (layer_mass<MODEL>(a, k, a.ps_s[(long)a1 * M + mm]) +
-                                  layer_mass<MODEL>(a, k, a.ps_s[(long)a2 * M + mm]));
-        const R up = u_prev<R>(a, (long)ep * KM + km);
-        R F;
-        if constexpr (sizeof(R) == 8) F = dpe * up;
-        else F = (float)dpe * up;
         const int w1 = m.e_vert[2 * (long)ep], w2 = m.e_vert[2 * (long)ep + 1];
-        const R qep = (R)0.5 * (qv[(long)w1 * KM + km] + qv[(long)w2 * KM + km]);
-        Q += tkw[t] * F * ((R)0.5 * (qe + qep));
+        double d1[L], d2[L];
+        dpi_at(a1, d1);
+        dpi_at(a2, d2);
+        const Pack<R, L> up = ldp<R, L>((sizeof(R) == 8 ? (const R *)a.u_s : (const R *)a.u32_s) + (long)ep * KM + km0);
+        const Pack<R, L> qa = ldp<R, L>(qv + (long)w1 * KM + km0), qb = ldp<R, L>(qv + (long)w2 * KM + km0);
+        const R wt = tkw[t];
+#pragma unroll
+        for (int j = 0; j < L; j++) {
+            const double dpe = 0.5 * (d1[j] + d2[j]);
+            R F;
+            if constexpr (sizeof(R) == 8) F = dpe * up.v[j];
+            else F = (float)dpe * up.v[j];
+            const R qep = (R)0.5 * (qa.v[j] + qb.v[j]);
+            Q[j] += wt * F * ((R)0.5 * (qe[j] + qep));
+        }
     }
     const R dinv = pick<R>(m.e_dinv, m.e_dinv32)[e];
-    const R gk = (ke[(long)c2 * KM + km] - ke[(long)c1 * KM + km]) * dinv;
-    R adv = Q - gk;
+    R adv[L];
+    {
+        const Pack<R, L> k1 = ldp<R, L>(ke + (long)c1 * KM + km0), k2 = ldp<R, L>(ke + (long)c2 * KM + km0);
+#pragma unroll
+        for (int j = 0; j < L; j++) adv[j] = Q[j] - (k2.v[j] - k1.v[j]) * dinv;
+    }
 
     if constexpr (MODEL != MODEL_SW) {
         // centred vertical advection of u by the interface mass flux
+        const R *us = (sizeof(R) == 8) ? (const R *)a.u_s : (const R *)a.u32_s;
         const long K1M = (long)(K + 1) * M;
-        const double dpe = 0.5 * (layer_mass<MODEL>(a, k, a.ps_s[(long)c1 * M + mm]) +
-                                   layer_mass<MODEL>(a, k, a.ps_s[(long)c2 * M + mm]));
-        const R uk = u_prev<R>(a, idx);
-        R va = 0;
-        if (k < K - 1) {
-            const R mb = (R)(0.5 * (a.mdot[(long)c1 * K1M + (long)(k + 1) * M + mm] +
-                                    a.mdot[(long)c2 * K1M + (long)(k + 1) * M + mm]));
-            va += mb * (u_prev<R>(a, idx + M) - uk);
+        double e1[L], e2[L];
+        dpi_at(c1, e1);
+        dpi_at(c2, e2);
+        const Pack<R, L> uk = ldp<R, L>(us + base);
+        // u one level above / below each value, and the interface mass fluxes
+        // at the top (k) and bottom (k+1) of each value's layer
+        R uup[L], udn[L];
+        double mt[L], mb[L];
+        if (m1) {
+#pragma unroll
+            for (int j = 0; j < L; j++) {
+                uup[j] = (j > 0) ? uk.v[j - 1] : ((k0 > 0) ? us[base - 1] : (R)0);
+                udn[j] = (j < L - 1) ? uk.v[j + 1] : ((kk[j] < K - 1) ? us[base + L] : (R)0);
+            }
+            const double *m1p = a.mdot + (long)c1 * K1M + k0, *m2p = a.mdot + (long)c2 * K1M + k0;
+            double i1[L + 1], i2[L + 1];
+#pragma unroll
+            for (int j = 0; j <= L; j++) {
+                i1[j] = m1p[j];
+                i2[j] = m2p[j];
+            }
+#pragma unroll
+            for (int j = 0; j < L; j++) {
+                mt[j] = 0.5 * (i1[j] + i2[j]);
+                mb[j] = 0.5 * (i1[j + 1] + i2[j + 1]);
+            }
+        } else {
+            Pack<R, L> pu, pd;
+            if (k0 > 0) pu = ldp<R, L>(us + base - M);
+            if (k0 < K - 1) pd = ldp<R, L>(us + base + M);
+            const Pack<double, L> t1 = ldp<double, L>(a.mdot + (long)c1 * K1M + (long)k0 * M + mm0);
+            const Pack<double, L> t2 = ldp<double, L>(a.mdot + (long)c2 * K1M + (long)k0 * M + mm0);
+            const Pack<double, L> b1 = ldp<double, L>(a.mdot + (long)c1 * K1M + (long)(k0 + 1) * M + mm0);
+            const Pack<double, L> b2 = ldp<double, L>(a.mdot + (long)c2 * K1M + (long)(k0 + 1) * M + mm0);
+#pragma unroll
+            for (int j = 0; j < L; j++) {
+                uup[j] = (k0 > 0) ? pu.v[j] : (R)0;
+                udn[j] = (k0 < K - 1) ? pd.v[j] : (R)0;
+                mt[j] = 0.5 * (t1.v[j] + t2.v[j]);
+                mb[j] = 0.5 * (b1.v[j] + b2.v[j]);
+            }
         }
-        if (k > 0) {
-            const R mt = (R)(0.5 * (a.mdot[(long)c1 * K1M + (long)k * M + mm] +
-                                    a.mdot[(long)c2 * K1M + (long)k * M + mm]));
-            va += mt * (uk - u_prev<R>(a, idx - M));
+#pragma unroll
+        for (int j = 0; j < L; j++) {
+            const double dpe = 0.5 * (e1[j] + e2[j]);
+            R va = 0;
+            if (kk[j] < K - 1) va += (R)mb[j] * (udn[j] - uk.v[j]);
+            if (kk[j] > 0) va += (R)mt[j] * (uk.v[j] - uup[j]);
+            va = va / (R)(2.0 * dpe);
+            adv[j] = adv[j] - va;
         }
-        va = va / (R)(2.0 * dpe);
-        adv = adv - va;
     }
 
     // pressure-gradient force and gravity in FP64 from the updated mass/Theta
     const double dinv64 = m.e_dinv[e];
-    double pgf;
+    double pgf[L];
     if constexpr (MODEL == MODEL_SW) {
-        const double h1 = a.ps_o[(long)c1 * M + mm] + a.b[c1];
-        const double h2 = a.ps_o[(long)c2 * M + mm] + a.b[c2];
-        pgf = -a.grav * (h2 - h1) * dinv64;
+        const Pack<double, L> h1 = ldp<double, L>(a.ps_o + (long)c1 * M + mm0);
+        const Pack<double, L> h2 = ldp<double, L>(a.ps_o + (long)c2 * M + mm0);
+#pragma unroll
+        for (int j = 0; j < L; j++) pgf[j] = -a.grav * ((h2.v[j] + a.b[c2]) - (h1.v[j] + a.b[c1])) * dinv64;
     } else {
-        const long x1 = (long)c1 * KM + km, x2 = (long)c2 * KM + km;
-        const double ae = 0.5 * (a.alpha[x1] + a.alpha[x2]);
-        double p1, p2;
+        const long x1 = (long)c1 * KM + km0, x2 = (long)c2 * KM + km0;
+        const Pack<double, L> al1 = ldp<double, L>(a.alpha + x1), al2 = ldp<double, L>(a.alpha + x2);
+        const Pack<double, L> ph1 = ldp<double, L>(a.phim + x1), ph2 = ldp<double, L>(a.phim + x2);
         if constexpr (MODEL == MODEL_HDC) {
-            const double s1 = a.ps_o[(long)c1 * M + mm], s2 = a.ps_o[(long)c2 * M + mm];
-            p1 = 0.5 * ((a.ptop + a.sig[k] * (s1 - a.ptop)) + (a.ptop + a.sig[k + 1] * (s1 - a.ptop)));
-            p2 = 0.5 * ((a.ptop + a.sig[k] * (s2 - a.ptop)) + (a.ptop + a.sig[k + 1] * (s2 - a.ptop)));
-            pgf = -(ae * (p2 - p1) + (a.phim[x2] - a.phim[x1])) * dinv64;
+            double s1[L], s2[L];
+            if (m1) {
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    s1[j] = a.ps_o[c1];
+                    s2[j] = a.ps_o[c2];
+                }
+            } else {
+                const Pack<double, L> q1 = ldp<double, L>(a.ps_o + (long)c1 * M + mm0);
+                const Pack<double, L> q2 = ldp<double, L>(a.ps_o + (long)c2 * M + mm0);
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    s1[j] = q1.v[j];
+                    s2[j] = q2.v[j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < L; j++) {
+                const int k = kk[j];
+                const double p1 = 0.5 * ((a.ptop + a.sig[k] * (s1[j] - a.ptop)) + (a.ptop + a.sig[k + 1] * (s1[j] - a.ptop)));
+                const double p2 = 0.5 * ((a.ptop + a.sig[k] * (s2[j] - a.ptop)) + (a.ptop + a.sig[k + 1] * (s2[j] - a.ptop)));
+                const double ae = 0.5 * (al1.v[j] + al2.v[j]);
+                pgf[j] = -(ae * (p2 - p1) + (ph2.v[j] - ph1.v[j])) * dinv64;
+            }
         } else {
-            p1 = a.pm[x1];
-            p2 = a.pm[x2];
-            const double me = 0.5 * (a.mum[x1] + a.mum[x2]);
-            pgf = -(ae * (p2 - p1) + me * (a.phim[x2] - a.phim[x1])) * dinv64;
+            const Pack<double, L> p1 = ldp<double, L>(a.pm + x1), p2 = ldp<double, L>(a.pm + x2);
+            const Pack<double, L> u1 = ldp<double, L>(a.mum + x1), u2 = ldp<double, L>(a.mum + x2);
+#pragma unroll
+            for (int j = 0; j < L; j++) {
+                const double ae = 0.5 * (al1.v[j] + al2.v[j]);
+                const double me = 0.5 * (u1.v[j] + u2.v[j]);
+                pgf[j] = -(ae * (p2.v[j] - p1.v[j]) + me * (ph2.v[j] - ph1.v[j])) * dinv64;
+            }
         }
     }
-    const double un = a.u_n[idx];
-    const double unew = un + a.dts * ((double)adv + pgf);
-    a.u_o[idx] = unew;
-    if (a.u32_o) a.u32_o[idx] = (float)unew;
+    const Pack<double, L> un = ldp<double, L>(a.u_n + base);
+    Pack<double, L> uo;
+    Pack<float, L> u32;
+#pragma unroll
+    for (int j = 0; j < L; j++) {
+        uo.v[j] = un.v[j] + a.dts * ((double)adv[j] + pgf[j]);
+        u32.v[j] = (float)uo.v[j];
+    }
+    stp<double, L>(a.u_o + base, uo);
+    if (a.u32_o) stp<float, L>(a.u32_o + base, u32);
 }
 
 // ---------------------------------------------------------------------------
@@ -570,6 +693,8 @@ __global__ void k_shadows(StageArgs a) {
 // ---------------------------------------------------------------------------
 namespace {
 inline unsigned nblocks(long n, int b) { return (unsigned)((n + b - 1) / b); }
+// values per lane of the edge kernel: 2 when the (k, m) pairs split evenly
+inline int edge_values_per_lane(int K, int M) { return (M == 1 ? (K % 2 == 0) : (M % 2 == 0)) ? 2 : 1; }
 
 template <int MODEL, typename R>
 hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
@@ -592,9 +717,20 @@ hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
         if (MODEL == MODEL_SW) return hipSuccess;
         hipLaunchKernelGGL((k_cell_b<MODEL, R>), dim3(colblocks), dim3(colthreads), lds_b, s, a);
         break;
-    case KERNEL_EDGE:
-        hipLaunchKernelGGL((k_edge<MODEL, R>), dim3(nblocks((long)a.mesh.E * KM, fb)), dim3(fb), 0, s, a);
+    case KERNEL_EDGE: {
+        const int L = edge_values_per_lane(a.K, a.M);
+        const long n = (long)a.mesh.E * (KM / L);
+        const bool one = (a.M == 1);
+        if (L == 2 && one)
+            hipLaunchKernelGGL((k_edge<MODEL, R, 2, true>), dim3(nblocks(n, fb)), dim3(fb), 0, s, a);
+        else if (L == 2)
+            hipLaunchKernelGGL((k_edge<MODEL, R, 2, false>), dim3(nblocks(n, fb)), dim3(fb), 0, s, a);
+        else if (one)
+            hipLaunchKernelGGL((k_edge<MODEL, R, 1, true>), dim3(nblocks(n, fb)), dim3(fb), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_edge<MODEL, R, 1, false>), dim3(nblocks(n, fb)), dim3(fb), 0, s, a);
         break;
+    }
     default:
         return hipErrorInvalidValue;
     }

@@ -81,6 +81,9 @@ def _load():
         "mpdc_set_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
         "mpdc_time_kernel": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double)]),
         "mpdc_kernel_bytes": (ctypes.c_double, [_vp, ctypes.c_int]),
+        "mpdc_profile_steps": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_int)]),
+        "mpdc_autotune": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
         "mpdc_step_bytes": (ctypes.c_double, [_vp]),
         "mpdc_state_destroy": (None, [_vp]),
         "mpdc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -233,6 +236,18 @@ class State:
         ms = ctypes.c_double()
         _check(lib.mpdc_time_kernel(self.h, kernel_id, nreps, _stream(stream), ctypes.byref(ms)))
         return ms.value
+
+    def profile_steps(self, nsteps, stream=None):
+        """Advance nsteps with HIP events between launches; returns {kernel id: (total ms, launches)}."""
+        ms = (ctypes.c_double * 4)()
+        n = (ctypes.c_int * 4)()
+        _check(lib.mpdc_profile_steps(self.h, nsteps, _stream(stream), ms, n))
+        return {k: (ms[k], n[k]) for k in range(4) if n[k] > 0}
+
+    def autotune(self, stream=None):
+        c, f = ctypes.c_int(), ctypes.c_int()
+        _check(lib.mpdc_autotune(self.h, _stream(stream), ctypes.byref(c), ctypes.byref(f)))
+        return c.value, f.value
 
     def kernel_bytes(self, kernel_id):
         return lib.mpdc_kernel_bytes(self.h, kernel_id)

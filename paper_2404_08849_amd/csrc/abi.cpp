@@ -52,12 +52,12 @@ int hip_fail(hipError_t e, const char *where) {
 
 // ---------------- mesh workspace layout ----------------
 struct MeshLayout {
-    int *c_edge, *c_nbr;
-    double *c_div, *c_ke, *c_hess, *c_area;
-    float *c_div32, *c_ke32, *c_hess32;
-    int *e_cell, *e_vert, *e_tk;
-    double *e_dinv, *e_d2, *e_hdir, *e_tkw;
-    float *e_dinv32, *e_d2_32, *e_hdir32, *e_tkw32;
+    int *c_edge, *c_nbr, *c_vert;
+    double *c_div, *c_ke, *c_gk, *c_hess, *c_tk, *c_area;
+    float *c_div32, *c_ke32, *c_gk32, *c_hess32, *c_tk32;
+    int *e_cell, *e_vert;
+    double *e_dinv, *e_d2, *e_hdir;
+    float *e_dinv32, *e_d2_32, *e_hdir32;
     int *v_edge, *v_cell;
     double *v_curl, *v_kite, *v_f;
     float *v_curl32;
@@ -70,30 +70,32 @@ MeshLayout mesh_layout(void *base, long N, long E, long V) {
     const int S = kCellSlots;
     L.c_edge = c.take<int>(N * S);
     L.c_nbr = c.take<int>(N * S);
+    L.c_vert = c.take<int>(N * S);
     L.c_div = c.take<double>(N * S);
     L.c_ke = c.take<double>(N * S);
+    L.c_gk = c.take<double>(N * S);
     L.c_hess = c.take<double>(N * 3 * S);
+    L.c_tk = c.take<double>(N * S * S);
     L.c_area = c.take<double>(N);
     L.c_div32 = c.take<float>(N * S);
     L.c_ke32 = c.take<float>(N * S);
+    L.c_gk32 = c.take<float>(N * S);
     L.c_hess32 = c.take<float>(N * 3 * S);
+    L.c_tk32 = c.take<float>(N * S * S);
     L.e_cell = c.take<int>(2 * E);
     L.e_vert = c.take<int>(2 * E);
-    L.e_tk = c.take<int>(E * kTriskSlots);
     L.e_dinv = c.take<double>(E);
     L.e_d2 = c.take<double>(E);
     L.e_hdir = c.take<double>(6 * E);
-    L.e_tkw = c.take<double>(E * kTriskSlots);
     L.e_dinv32 = c.take<float>(E);
     L.e_d2_32 = c.take<float>(E);
     L.e_hdir32 = c.take<float>(6 * E);
-    L.e_tkw32 = c.take<float>(E * kTriskSlots);
-    L.v_edge = c.take<int>(3 * V);
-    L.v_cell = c.take<int>(3 * V);
-    L.v_curl = c.take<double>(3 * V);
-    L.v_kite = c.take<double>(3 * V);
+    L.v_edge = c.take<int>(4 * V);
+    L.v_cell = c.take<int>(4 * V);
+    L.v_curl = c.take<double>(4 * V);
+    L.v_kite = c.take<double>(4 * V);
     L.v_f = c.take<double>(V);
-    L.v_curl32 = c.take<float>(3 * V);
+    L.v_curl32 = c.take<float>(4 * V);
     L.bytes = c.off;
     return L;
 }
@@ -130,7 +132,7 @@ struct mpdc_state {
     // dycore
     StateSet set[3];
     double *b = nullptr, *dsig = nullptr, *sig = nullptr, *dps = nullptr, *mdot = nullptr;
-    void *ke = nullptr, *hth = nullptr, *qv = nullptr;
+    void *ke = nullptr, *hth = nullptr, *qv = nullptr, *qh = nullptr;
     double *alpha = nullptr, *phim = nullptr, *pm = nullptr, *mum = nullptr, *wstar = nullptr, *phistar = nullptr;
     // tracer
     double *F = nullptr, *dpi[2] = {nullptr, nullptr};
@@ -197,6 +199,7 @@ size_t state_layout(mpdc_state *st, void *base) {
     st->ke = c.take<char>(N * KM * r);
     if (!sw) st->hth = c.take<char>(3 * N * KM * r);
     st->qv = c.take<char>(V * KM * r);
+    st->qh = c.take<char>(2 * E * KM * r);
     if (!sw) {
         st->alpha = c.take<double>(N * KM);
         st->phim = c.take<double>(N * KM);
@@ -210,10 +213,13 @@ size_t state_layout(mpdc_state *st, void *base) {
     return c.off;
 }
 
+// lanes of one cell column in the column kernels
+int col_lanes(const mpdc_state *st) { return st->K * st->M / values_per_lane(st->K, st->M); }
+
 int auto_cpb(const mpdc_state *st) {
-    const int KM = st->K * st->M;
-    int c = std::max(1, 256 / KM);
-    while (c > 1 && c * KM > 1024) c--;
+    const int lanes = col_lanes(st);
+    int c = std::max(1, 256 / lanes);
+    while (c > 1 && c * lanes > 1024) c--;
     return c;
 }
 
@@ -255,6 +261,7 @@ StageArgs stage_args(const mpdc_state *st, int s) {
     a.ke = st->ke;
     a.hth = st->hth;
     a.qv = st->qv;
+    a.qh = st->qh;
     a.alpha = st->alpha; a.phim = st->phim; a.pm = st->pm; a.mum = st->mum;
     a.wstar = st->wstar; a.phistar = st->phistar;
     return a;
@@ -422,24 +429,26 @@ int mpdc_mesh_create(const mpdc_mesh_desc *d, void *dev_ws, size_t ws_bytes, voi
         std::vector<char> host(L.bytes, 0);
         put(host, dev_ws, L.c_edge, t.c_edge);
         put(host, dev_ws, L.c_nbr, t.c_nbr);
+        put(host, dev_ws, L.c_vert, t.c_vert);
         put(host, dev_ws, L.c_div, t.c_div);
         put(host, dev_ws, L.c_ke, t.c_ke);
+        put(host, dev_ws, L.c_gk, t.c_gk);
         put(host, dev_ws, L.c_hess, t.c_hess);
+        put(host, dev_ws, L.c_tk, t.c_tk);
         put(host, dev_ws, L.c_area, t.c_area);
         put32(host, dev_ws, L.c_div32, t.c_div);
         put32(host, dev_ws, L.c_ke32, t.c_ke);
+        put32(host, dev_ws, L.c_gk32, t.c_gk);
         put32(host, dev_ws, L.c_hess32, t.c_hess);
+        put32(host, dev_ws, L.c_tk32, t.c_tk);
         put(host, dev_ws, L.e_cell, t.e_cell);
         put(host, dev_ws, L.e_vert, t.e_vert);
-        put(host, dev_ws, L.e_tk, t.e_tk);
         put(host, dev_ws, L.e_dinv, t.e_dinv);
         put(host, dev_ws, L.e_d2, t.e_d2);
         put(host, dev_ws, L.e_hdir, t.e_hdir);
-        put(host, dev_ws, L.e_tkw, t.e_tkw);
         put32(host, dev_ws, L.e_dinv32, t.e_dinv);
         put32(host, dev_ws, L.e_d2_32, t.e_d2);
         put32(host, dev_ws, L.e_hdir32, t.e_hdir);
-        put32(host, dev_ws, L.e_tkw32, t.e_tkw);
         put(host, dev_ws, L.v_edge, t.v_edge);
         put(host, dev_ws, L.v_cell, t.v_cell);
         put(host, dev_ws, L.v_curl, t.v_curl);
@@ -456,11 +465,12 @@ int mpdc_mesh_create(const mpdc_mesh_desc *d, void *dev_ws, size_t ws_bytes, voi
         m->stream = s;
         DevMesh &D = m->dev;
         D.N = (int)N; D.E = (int)E; D.V = (int)V;
-        D.c_edge = L.c_edge; D.c_nbr = L.c_nbr; D.c_div = L.c_div; D.c_div32 = L.c_div32;
-        D.c_ke = L.c_ke; D.c_ke32 = L.c_ke32; D.c_hess = L.c_hess; D.c_hess32 = L.c_hess32; D.c_area = L.c_area;
+        D.c_edge = L.c_edge; D.c_nbr = L.c_nbr; D.c_vert = L.c_vert;
+        D.c_div = L.c_div; D.c_div32 = L.c_div32; D.c_ke = L.c_ke; D.c_ke32 = L.c_ke32;
+        D.c_gk = L.c_gk; D.c_gk32 = L.c_gk32; D.c_hess = L.c_hess; D.c_hess32 = L.c_hess32;
+        D.c_tk = L.c_tk; D.c_tk32 = L.c_tk32; D.c_area = L.c_area;
         D.e_cell = L.e_cell; D.e_vert = L.e_vert; D.e_dinv = L.e_dinv; D.e_dinv32 = L.e_dinv32;
         D.e_d2 = L.e_d2; D.e_d2_32 = L.e_d2_32; D.e_hdir = L.e_hdir; D.e_hdir32 = L.e_hdir32;
-        D.e_tk = L.e_tk; D.e_tkw = L.e_tkw; D.e_tkw32 = L.e_tkw32;
         D.v_edge = L.v_edge; D.v_cell = L.v_cell; D.v_curl = L.v_curl; D.v_curl32 = L.v_curl32;
         D.v_kite = L.v_kite; D.v_f = L.v_f;
         m->cells_on_cell = std::move(t.cells_on_cell);
@@ -665,8 +675,9 @@ int mpdc_set_launch(mpdc_state *st, int cells_per_block, int flat_block) {
     if (!st) return fail(MPDC_E_INVAL, "null state");
     if (flat_block == 0) flat_block = 256;
     if (flat_block < 64 || flat_block > 1024 || flat_block % 64) return fail(MPDC_E_INVAL, "flat block must be 64..1024, a multiple of 64");
-    if (cells_per_block < 0 || (long)cells_per_block * st->K * st->M > 1024)
-        return fail(MPDC_E_INVAL, "cells per block times K*M must be at most 1024");
+    if (cells_per_block < 0 ||
+        (st->model != MPDC_MODEL_TRACER && (long)cells_per_block * col_lanes(st) > 1024))
+        return fail(MPDC_E_INVAL, "cells per block times the column's lanes must be at most 1024");
     if (st->model == MPDC_MODEL_NDC && cells_per_block > 0 &&
         stage_lds_bytes(st->model, KERNEL_CELL_B, cells_per_block, st->K, st->M) > 65536)
         return fail(MPDC_E_INVAL, "column kernel would need more than 64 KiB of LDS");
@@ -777,32 +788,36 @@ static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
     const double th_s = sw ? 0 : N * KM * (mix ? 4 : 8);
     switch (id) {
     case KERNEL_CELL_A: {
+        // tables, u, ps, theta -> K (+ second derivatives, mdot, dps; NDC: w*, phi*)
         double b = cellI + N * kCellSlots * (8 + r) + u_s + ps + th_s + N * KM * r /*ke*/;
         if (sw) return b + ps /*h_n*/ + ps /*h_o*/;
         b += N * 3 * kCellSlots * r + 3 * N * KM * r /*hth*/ + N * K1M * 8 /*mdot*/ + ps /*dps*/;
-        if (nh) b += 4 * N * K1M * 8 /*w_s, phi_s (+ w_n, phi_n)*/ + 2 * N * K1M * 8 /*w*, phi* */ -
+        if (nh) b += 4 * N * K1M * 8 /*w_s, phi_s, w_n, phi_n*/ + 2 * N * K1M * 8 /*w*, phi* */ -
                      (first ? 2 * N * K1M * 8 : 0);
         return b;
     }
     case KERNEL_VERTEX:
-        return V * 3 * 8 + V * 3 * (r + 8) + V * 8 + u_s + ps + V * KM * r;
+        return V * 4 * 8 + V * 4 * (r + 8) + V * 8 + u_s + ps + V * KM * r;
     case KERNEL_CELL_B: {
-        if (sw) return 0;
-        double b = cellI + N * kCellSlots * r + E * 8 + E * 6 * r + E * r + ps + th_s + 3 * N * KM * r + u_s +
-                   N * K1M * 8 + ps /*dps*/;
+        // Coriolis/KE shares: c_vert, c_div, c_gk, c_tk, q_v, K, u, ps -> qh
+        double b = cellI + N * kCellSlots * 4 + N * kCellSlots * 2 * r + N * 36 * r + V * KM * r + N * KM * r +
+                   u_s + ps + 2 * E * KM * r;
+        if (sw) return b;
+        // theta transport and update: e_cell, hdir, d2, theta, hth, mdot, dps, Th_n, ps_n
+        b += E * 8 + E * 6 * r + E * r + th_s + 3 * N * KM * r + N * K1M * 8 + ps;
         b += (first && !mix) ? 0 : N * KM * 8 + ps;       // Th_n, ps_n (stage 1 FP64: same arrays as _s)
         b += N * KM * 8 + ps + 2 * N * KM * 8 + (mix ? N * KM * 4 : 0);   // Th_o, ps_o, alpha, phim, th32_o
         if (nh) b += 2 * N * K1M * 8 /*w*, phi* */ + 2 * N * K1M * 8 /*w_o, phi_o*/ + 2 * N * KM * 8 /*pm, mum*/;
         return b;
     }
     case KERNEL_EDGE: {
-        double b = E * (2 * 4 + 2 * 4 + kTriskSlots * (4 + r) + 8 + (mix ? 4 : 0)) + V * KM * r + ps + u_s +
-                   N * KM * r /*ke*/;
+        // e_cell, e_dinv, qh, u_n -> u_o (+u32_o)
+        double b = E * (2 * 4 + 8) + 2 * E * KM * r;
         b += (first && !mix) ? 0 : E * KM * 8;             // u_n
         b += E * KM * 8 + (mix ? E * KM * 4 : 0);           // u_o, u32_o
         if (sw) return b + ps /*h_o*/ + N * 8 /*b*/;
-        b += N * K1M * 8 + 2 * N * KM * 8 + ps;             // mdot, alpha, phim, ps_o
-        if (nh) b += 2 * N * KM * 8;                         // pm, mum
+        b += u_s + ps + N * K1M * 8 + 2 * N * KM * 8 + ps; // u_s, ps_s, mdot, alpha, phim, ps_o
+        if (nh) b += 2 * N * KM * 8;                        // pm, mum
         return b;
     }
     }
@@ -845,7 +860,6 @@ int mpdc_profile_steps(mpdc_state *st, int nsteps, void *stream, double *ms_tota
         for (size_t j = 0; j < kid.size(); j++) {
             float ms = 0;
             HIP_TRY(hipEventElapsedTime(&ms, ev[j], ev[j + 1]));
-            if (!tr && st->model == MPDC_MODEL_SW && kid[j] == KERNEL_CELL_B) continue;   // no-op for SW
             ms_total[kid[j]] += ms;
             launches[kid[j]] += 1;
         }
@@ -879,13 +893,13 @@ int mpdc_autotune(mpdc_state *st, void *stream, int *cells_per_block, int *flat_
     st->launch.flat_block = best_flat;
     if (!tr) {
         for (int c : cpbs) {
-            if ((long)c * st->K * st->M > 1024) continue;
+            if ((long)c * col_lanes(st) > 1024) continue;
             if (stage_lds_bytes(st->model, KERNEL_CELL_B, c, st->K, st->M) > 65536) continue;
             st->launch.cells_per_block = c;
             double t = 0, ms = 0;
             int rc = mpdc_time_kernel(st, KERNEL_CELL_A, 5, stream, &ms);
             t += ms;
-            if (rc == MPDC_OK && st->model != MPDC_MODEL_SW) { rc = mpdc_time_kernel(st, KERNEL_CELL_B, 5, stream, &ms); t += ms; }
+            if (rc == MPDC_OK) { rc = mpdc_time_kernel(st, KERNEL_CELL_B, 5, stream, &ms); t += ms; }
             if (rc != MPDC_OK) { st->launch = keep; return rc; }
             if (t < best_col_ms) { best_col_ms = t; best_cpb = c; }
         }

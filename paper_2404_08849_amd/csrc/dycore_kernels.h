@@ -34,6 +34,7 @@ struct StageArgs {
     void *ke;            // [N][K][M]      (R)
     void *hth;           // [N][3][K][M]   (R)
     void *qv;            // [V][K][M]      (R)
+    void *qh;            // [E][2][K][M]   (R) each cell's share of Coriolis - grad K per edge
     double *alpha, *phim, *pm, *mum;   // [N][K][M]
     double *wstar, *phistar;           // [N][K+1][M]
 
@@ -43,11 +44,15 @@ struct StageArgs {
     template <typename R> __device__ const R *hth_in() const { return (const R *)hth; }
     template <typename R> __device__ R *qv_out() const { return (R *)qv; }
     template <typename R> __device__ const R *qv_in() const { return (const R *)qv; }
+    template <typename R> __device__ R *qh_out() const { return (R *)qh; }
+    template <typename R> __device__ const R *qh_in() const { return (const R *)qh; }
 };
 
 hipError_t launch_stage_kernel(int model, int policy, const StageArgs &a, int which, hipStream_t s);
 hipError_t launch_shadows(int model, const StageArgs &a, hipStream_t s);
 size_t stage_lds_bytes(int model, int which, int cpb, int K, int M);
+// (k, m) values per lane of the dycore kernels: 2 when K*M splits evenly
+int values_per_lane(int K, int M);
 
 // ---- tracer transport ----
 enum { TKERNEL_LOW = 0, TKERNEL_LIMIT = 1, TKERNEL_UPDATE = 2 };

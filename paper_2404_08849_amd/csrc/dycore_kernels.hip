@@ -2,28 +2,37 @@
 //
 // One RK3 stage of the shallow-water (SW), hydrostatic (HDC) and
 // non-hydrostatic (NDC) C-grid dycore, written for a level- and
-// member-innermost layout ([entity][k][m]): consecutive lanes of a wavefront
-// handle consecutive (k, m) of one entity, so every stencil gather reads a
-// contiguous run of K*M values and every store is coalesced.
+// member-innermost layout ([entity][k][m]).  Each lane owns L consecutive
+// (k, m) values of one entity (L = 2 whenever K*M allows it), so every
+// stencil gather is an L-wide vector load of a contiguous run and the
+// per-entity table lookups are shared by L values.  With M == 1 the L values
+// are consecutive levels; with M > 1 they are consecutive members of one
+// level.
 //
 // Per stage (tendencies from the previous stage y^(s-1), base state y^n):
 //   cell_a  (cell columns)  divergence of the mass flux, column mass tendency
 //                           and vertical mass flux (Eq. 3, LDS prefix sum),
 //                           kinetic energy, second derivatives of theta;
-//                           NDC: explicit advective step of w and phi (Eqs. 6-7)
+//                           NDC: explicit advective step of w and phi (Eqs. 6-7);
+//                           SW: the depth update
 //   vertex  (vertex x km)   vorticity, FP64 vertex mass, potential vorticity
-//   cell_b  (cell columns)  theta_m flux-form transport (Eq. 4, third-order
-//                           upwind) and the mass/Theta update; then the FP64
-//                           column diagnostics of the updated state: pressure,
-//                           alpha and the hydrostatic geopotential (Eq. 8, LDS
-//                           scan), or for NDC the equation of state (Eq. 9) and
-//                           the implicit vertical acoustic solve (HEVI)
-//   edge    (edge x km)     TRiSK Coriolis term, kinetic-energy gradient,
-//                           vertical advection of u, FP64 pressure-gradient and
-//                           gravity term (Eq. 5), RK update of u
-// The mass flux F = dpi_e u is recomputed by each consumer from u and the
-// 2-D surface pressure instead of being stored: that reads as many bytes as
-// a stored F would and saves writing it.
+//   cell_b  (cell columns)  each cell's share of the Coriolis and KE-gradient
+//                           terms of its six edges (TRiSK, Eq. 5), theta_m
+//                           flux-form transport (Eq. 4, third-order upwind) and
+//                           the mass/Theta update; then the FP64 column
+//                           diagnostics of the updated state: pressure, alpha
+//                           and the hydrostatic geopotential (Eq. 8, LDS scan),
+//                           or for NDC the equation of state (Eq. 9) and the
+//                           implicit vertical acoustic solve (HEVI)
+//   edge    (edge x km)     adds the two cells' shares, vertical advection of
+//                           u, FP64 pressure-gradient and gravity term (Eq. 5),
+//                           RK update of u
+// The TRiSK sum of an edge runs over the other edges of its two cells, so it
+// splits exactly into one partial sum per cell; a cell forms both partial
+// sums of all its edges from its own six fluxes and six vertex PVs, which
+// replaces a ten-edge indirect gather per edge-level.  The mass flux
+// F = dpi_e u is recomputed from u and the 2-D surface pressure wherever it is
+// needed instead of being stored.
 //
 // Template parameter R is the arithmetic type of the advective terms:
 // double for the all-FP64 policy, float for the mixed policy.  Everything
@@ -40,431 +49,6 @@ template <typename R> __device__ __forceinline__ const R *pick(const double *d, 
 template <> __device__ __forceinline__ const double *pick<double>(const double *d, const float *) { return d; }
 template <> __device__ __forceinline__ const float *pick<float>(const double *, const float *f) { return f; }
 
-// layer mass of layer k for surface pressure ps (HDC/NDC) or depth h (SW)
-template <int MODEL>
-__device__ __forceinline__ double layer_mass(const StageArgs &a, int k, double ps) {
-    if (MODEL == MODEL_SW) return ps;
-    return a.dsig[k] * (ps - a.ptop);
-}
-
-// u of the previous stage in the advective precision
-template <typename R>
-__device__ __forceinline__ R u_prev(const StageArgs &a, long idx) {
-    if constexpr (sizeof(R) == 8) return a.u_s[idx];
-    else return a.u32_s[idx];
-}
-
-// theta of the previous stage in the advective precision
-template <int MODEL, typename R>
-__device__ __forceinline__ R theta_prev(const StageArgs &a, int i, int k, int mm) {
-    const long KM = (long)a.K * a.M;
-    const long idx = (long)i * KM + (long)k * a.M + mm;
-    if constexpr (sizeof(R) == 8) {
-        double dpi = layer_mass<MODEL>(a, k, a.ps_s[(long)i * a.M + mm]);
-        return a.Th_s[idx] / dpi;
-    } else {
-        return a.th32_s[idx];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// cell_a
-// ---------------------------------------------------------------------------
-template <int MODEL, typename R>
-__global__ void __launch_bounds__(1024) k_cell_a(StageArgs a) {
-    extern __shared__ double lds[];
-    const DevMesh &m = a.mesh;
-    const int K = a.K, M = a.M, KM = K * M;
-    const int tid = threadIdx.x;
-    const int lc = tid / KM;
-    const int km = tid - lc * KM;
-    const int i = blockIdx.x * a.cpb + lc;
-    const bool valid = (lc < a.cpb) && (i < m.N);
-    const int k = km / M, mm = km - k * M;
-    double *sD = lds;                           // [cpb][KM]
-    double *sMd = lds + a.cpb * KM;             // [cpb][(K+1) M]  (NDC)
-
-    double D = 0.0;
-    double ps_i = 0.0;
-    R ke = 0;
-    if (valid) {
-        ps_i = a.ps_s[(long)i * M + mm];
-        const double dpi_i = layer_mass<MODEL>(a, k, ps_i);
-        const double *cdiv = m.c_div + (long)i * kCellSlots;
-        const R *cke = pick<R>(m.c_ke, m.c_ke32) + (long)i * kCellSlots;
-#pragma unroll
-        for (int j = 0; j < kCellSlots; j++) {
-            const int e = m.c_edge[(long)i * kCellSlots + j];
-            if (e < 0) continue;
-            const int nb = m.c_nbr[(long)i * kCellSlots + j];
-            const double dpi_nb = layer_mass<MODEL>(a, k, a.ps_s[(long)nb * M + mm]);
-            const double dpe = 0.5 * (dpi_i + dpi_nb);
-            const R ue = u_prev<R>(a, (long)e * KM + km);
-            if constexpr (sizeof(R) == 8) {
-                D += cdiv[j] * (dpe * ue);
-            } else {
-                const float F32 = (float)dpe * ue;
-                D += cdiv[j] * (double)F32;
-            }
-            ke += cke[j] * ue * ue;
-        }
-        a.ke_out<R>()[(long)i * KM + km] = ke;
-    }
-
-    if constexpr (MODEL == MODEL_SW) {
-        if (valid) {
-            // h^(s) = h^n - dt_s D  (forward part of the stage)
-            const long x = (long)i * M + mm;
-            const double hn = a.ps_n[x];
-            a.ps_o[x] = hn + a.dts * (-D);
-        }
-        return;
-    } else {
-        // ---- column mass tendency and vertical mass flux (LDS scan) ----
-        if (valid) sD[lc * KM + km] = D;
-        __syncthreads();
-        double dps = 0.0, mdot_b = 0.0;
-        if (valid) {
-            double s = 0.0;
-            for (int j = 0; j < K; j++) s += sD[lc * KM + j * M + mm];
-            dps = -s;
-            double acc = 0.0;
-            for (int j = 0; j <= k; j++) acc += sD[lc * KM + j * M + mm];
-            mdot_b = (k == K - 1) ? 0.0 : -acc - a.sig[k + 1] * dps;
-            const long K1M = (long)(K + 1) * M;
-            a.mdot[(long)i * K1M + (long)(k + 1) * M + mm] = mdot_b;
-            if (k == 0) {
-                a.mdot[(long)i * K1M + mm] = 0.0;
-                a.dps[(long)i * M + mm] = dps;
-            }
-        }
-
-        // ---- second derivatives of theta (quadratic fit) ----
-        if (valid) {
-            const R th_i = theta_prev<MODEL, R>(a, i, k, mm);
-            const R *ch = pick<R>(m.c_hess, m.c_hess32) + (long)i * 3 * kCellSlots;
-            R h0 = 0, h1 = 0, h2 = 0;
-#pragma unroll
-            for (int j = 0; j < kCellSlots; j++) {
-                const int nb = m.c_nbr[(long)i * kCellSlots + j];
-                const R dth = theta_prev<MODEL, R>(a, nb, k, mm) - th_i;
-                h0 += ch[j] * dth;
-                h1 += ch[kCellSlots + j] * dth;
-                h2 += ch[2 * kCellSlots + j] * dth;
-            }
-            R *H = a.hth_out<R>() + (long)i * 3 * KM;
-            H[km] = h0;
-            H[KM + km] = h1;
-            H[2 * KM + km] = h2;
-        }
-
-        if constexpr (MODEL == MODEL_NDC) {
-            // ---- explicit advective step of w and phi at interface k ----
-            const int K1 = K + 1;
-            if (valid) {
-                sMd[lc * K1 * M + (k + 1) * M + mm] = mdot_b;
-                if (k == 0) sMd[lc * K1 * M + mm] = 0.0;
-            }
-            __syncthreads();
-            if (valid) {
-                const long K1M = (long)K1 * M;
-                const double *md = sMd + lc * K1 * M;
-                const double *wn = a.w_n + (long)i * K1M;
-                const double *pn = a.phi_n + (long)i * K1M;
-                const double *ws = a.w_s + (long)i * K1M;
-                const double *phs = a.phi_s + (long)i * K1M;
-                // interface masses from the previous stage's layer masses
-                const double dk = layer_mass<MODEL>(a, k, ps_i);
-                const double dkm = (k > 0) ? layer_mass<MODEL>(a, k - 1, ps_i) : 0.0;
-                const double dh = (k == 0) ? 0.5 * dk : 0.5 * (dkm + dk);
-                const double *cdiv = m.c_div + (long)i * kCellSlots;
-                R aw = 0, ap = 0;
-                const double wi = ws[(long)k * M + mm], pi_ = phs[(long)k * M + mm];
-#pragma unroll
-                for (int j = 0; j < kCellSlots; j++) {
-                    const int e = m.c_edge[(long)i * kCellSlots + j];
-                    if (e < 0) continue;
-                    const int nb = m.c_nbr[(long)i * kCellSlots + j];
-                    const double psnb = a.ps_s[(long)nb * M + mm];
-                    // mass flux averaged to interface k (half of layer 0 at the top)
-                    const double dpe_k = 0.5 * (dk + layer_mass<MODEL>(a, k, psnb));
-                    const double Fk = dpe_k * (double)u_prev<R>(a, (long)e * KM + km);
-                    double Fh;
-                    if (k == 0) {
-                        Fh = 0.5 * Fk;
-                    } else {
-                        const double dpe_m = 0.5 * (dkm + layer_mass<MODEL>(a, k - 1, psnb));
-                        const double Fm = dpe_m * (double)u_prev<R>(a, (long)e * KM + km - M);
-                        Fh = 0.5 * (Fm + Fk);
-                    }
-                    const long nbo = (long)nb * K1M + (long)k * M + mm;
-                    if constexpr (sizeof(R) == 8) {
-                        aw += cdiv[j] * Fh * 0.5 * (a.w_s[nbo] - wi);
-                        ap += cdiv[j] * Fh * 0.5 * (a.phi_s[nbo] - pi_);
-                    } else {
-                        const float c = (float)cdiv[j] * (float)Fh * 0.5f;
-                        aw += c * (float)(a.w_s[nbo] - wi);
-                        ap += c * (float)(a.phi_s[nbo] - pi_);
-                    }
-                }
-                const R inv_dh = (R)(1.0 / dh);
-                R vw = 0, vp = 0;
-                if (k >= 1) {
-                    const R ml = (R)(0.5 * (md[(k - 1) * M + mm] + md[k * M + mm]));
-                    vw += ml * (R)(wi - ws[(long)(k - 1) * M + mm]);
-                    vp += ml * (R)(pi_ - phs[(long)(k - 1) * M + mm]);
-                }
-                {
-                    const R ml = (R)(0.5 * (md[k * M + mm] + md[(k + 1) * M + mm]));
-                    vw += ml * (R)(ws[(long)(k + 1) * M + mm] - wi);
-                    vp += ml * (R)(phs[(long)(k + 1) * M + mm] - pi_);
-                }
-                const R advw = aw * inv_dh + vw * (inv_dh * (R)0.5);
-                const R advp = ap * inv_dh + vp * (inv_dh * (R)0.5);
-                const long o = (long)i * K1M + (long)k * M + mm;
-                a.wstar[o] = (k == 0) ? 0.0 : wn[(long)k * M + mm] - a.dts * (double)advw;
-                a.phistar[o] = pn[(long)k * M + mm] - a.dts * (double)advp;
-                if (k == K - 1) {
-                    a.wstar[o + M] = 0.0;
-                    a.phistar[o + M] = pn[(long)K * M + mm];
-                }
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// vertex: vorticity, FP64 vertex mass, potential vorticity
-// ---------------------------------------------------------------------------
-template <int MODEL, typename R>
-__global__ void __launch_bounds__(1024) k_vertex(StageArgs a) {
-    const DevMesh &m = a.mesh;
-    const int KM = a.K * a.M;
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long)m.V * KM) return;
-    const int v = (int)(idx / KM);
-    const int km = (int)(idx - (long)v * KM);
-    const int k = km / a.M, mm = km - k * a.M;
-    const R *cw = pick<R>(m.v_curl, m.v_curl32) + (long)v * 3;
-    R zeta = 0;
-    double hv = 0.0;
-#pragma unroll
-    for (int j = 0; j < 3; j++) {
-        const int e = m.v_edge[(long)v * 3 + j];
-        zeta += cw[j] * u_prev<R>(a, (long)e * KM + km);
-        const int c = m.v_cell[(long)v * 3 + j];
-        hv += m.v_kite[(long)v * 3 + j] * layer_mass<MODEL>(a, k, a.ps_s[(long)c * a.M + mm]);
-    }
-    a.qv_out<R>()[idx] = (R)(((double)zeta + m.v_f[v]) / hv);
-}
-
-// ---------------------------------------------------------------------------
-// cell_b: theta transport, mass/Theta update, column diagnostics / NH solve
-// ---------------------------------------------------------------------------
-template <int MODEL, typename R>
-__global__ void __launch_bounds__(1024) k_cell_b(StageArgs a) {
-    extern __shared__ double lds[];
-    const DevMesh &m = a.mesh;
-    const int K = a.K, M = a.M, KM = K * M;
-    const int tid = threadIdx.x;
-    const int lc = tid / KM;
-    const int km = tid - lc * KM;
-    const int i = blockIdx.x * a.cpb + lc;
-    const bool valid = (lc < a.cpb) && (i < m.N);
-    const int k = km / M, mm = km - k * M;
-
-    double Th_new = 0.0, ps_new = 0.0;
-    if (valid) {
-        const double ps_i = a.ps_s[(long)i * M + mm];
-        const double dpi_i = layer_mass<MODEL>(a, k, ps_i);
-        const R th_i = theta_prev<MODEL, R>(a, i, k, mm);
-        const R *Hs = a.hth_in<R>();
-        const R Hi0 = Hs[(long)i * 3 * KM + km], Hi1 = Hs[(long)i * 3 * KM + KM + km],
-                Hi2 = Hs[(long)i * 3 * KM + 2 * KM + km];
-        const R *cdiv = pick<R>(m.c_div, m.c_div32) + (long)i * kCellSlots;
-        const R *hdir = pick<R>(m.e_hdir, m.e_hdir32);
-        const R *d2 = pick<R>(m.e_d2, m.e_d2_32);
-        R hdiv = 0;
-#pragma unroll
-        for (int j = 0; j < kCellSlots; j++) {
-            const int e = m.c_edge[(long)i * kCellSlots + j];
-            if (e < 0) continue;
-            const int nb = m.c_nbr[(long)i * kCellSlots + j];
-            const int side = (m.e_cell[2 * (long)e] == i) ? 0 : 1;
-            const double dpe = 0.5 * (dpi_i + layer_mass<MODEL>(a, k, a.ps_s[(long)nb * M + mm]));
-            const R ue = u_prev<R>(a, (long)e * KM + km);
-            R F;
-            if constexpr (sizeof(R) == 8) F = dpe * ue;
-            else F = (float)dpe * ue;
-            const R th_nb = theta_prev<MODEL, R>(a, nb, k, mm);
-            const long hb = (long)nb * 3 * KM + km;
-            const R *ds = hdir + (long)e * 6 + side * 3;        // direction in i's frame
-            const R *dn = hdir + (long)e * 6 + (1 - side) * 3;  // direction in nb's frame
-            const R qi = Hi0 * ds[0] + Hi1 * ds[1] + Hi2 * ds[2];
-            const R qn = Hs[hb] * dn[0] + Hs[hb + KM] * dn[1] + Hs[hb + 2 * KM] * dn[2];
-            // edge value with c1/c2 ordering of the edge
-            const R q1 = side ? th_nb : th_i, q2 = side ? th_i : th_nb;
-            const R h1 = side ? qn : qi, h2 = side ? qi : qn;
-            const R c = d2[e];
-            const R sg = (F >= (R)0) ? (R)1 : (R)-1;
-            const R tv = (R)0.5 * (q1 + q2) - c * (h1 + h2) + sg * c * (h2 - h1);
-            hdiv += cdiv[j] * (F * tv);
-        }
-        // vertical theta flux through the layer's interfaces (centred theta)
-        const long K1M = (long)(K + 1) * M;
-        const double *md = a.mdot + (long)i * K1M;
-        R top = 0, bot = 0;
-        if (k > 0) top = (R)md[(long)k * M + mm] * ((R)0.5 * (theta_prev<MODEL, R>(a, i, k - 1, mm) + th_i));
-        if (k < K - 1) bot = (R)md[(long)(k + 1) * M + mm] * ((R)0.5 * (th_i + theta_prev<MODEL, R>(a, i, k + 1, mm)));
-        const R dTh = -hdiv - (bot - top);
-        const long x = (long)i * KM + km;
-        Th_new = a.Th_n[x] + a.dts * (double)dTh;
-        ps_new = a.ps_n[(long)i * M + mm] + a.dts * a.dps[(long)i * M + mm];
-        (void)dpi_i;
-    }
-    // all reads of ps_n / Th_n happen before this barrier (stage 3 writes in place)
-    double *sA = lds;                       // [cpb][KM]
-    __syncthreads();
-
-    if constexpr (MODEL == MODEL_HDC) {
-        double pk = 0.0, al = 0.0, dpn = 0.0;
-        if (valid) {
-            const long x = (long)i * KM + km;
-            a.Th_o[x] = Th_new;
-            if (k == 0) a.ps_o[(long)i * M + mm] = ps_new;
-            const double pit = a.ptop + a.sig[k] * (ps_new - a.ptop);
-            const double pib = a.ptop + a.sig[k + 1] * (ps_new - a.ptop);
-            dpn = a.dsig[k] * (ps_new - a.ptop);
-            pk = 0.5 * (pit + pib);
-            const double th = Th_new / dpn;
-            const double T = th * pow(pk / a.p0, a.kappa);
-            al = a.rd * T / pk;
-            sA[lc * KM + km] = al * dpn;
-            if (a.th32_o) a.th32_o[x] = (float)th;
-        }
-        __syncthreads();
-        if (valid) {
-            // hydrostatic geopotential from the flat surface upwards (Eq. 8)
-            double acc = 0.0;
-            for (int j = K - 1; j > k; j--) acc += sA[lc * KM + j * M + mm];
-            const double phit = acc + sA[lc * KM + k * M + mm];
-            const long x = (long)i * KM + km;
-            a.alpha[x] = al;
-            a.phim[x] = 0.5 * (phit + acc);
-        }
-    } else if constexpr (MODEL == MODEL_NDC) {
-        // ---- implicit vertical acoustic solve of the column (FP64) ----
-        const int K1 = K + 1;
-        const long K1M = (long)K1 * M;
-        double *sP = lds;                         // p*   [cpb][KM]
-        double *sC = sP + a.cpb * KM;             // C    [cpb][KM]
-        double *sSub = sC + a.cpb * KM;           // rows [cpb][KM]
-        double *sDia = sSub + a.cpb * KM;
-        double *sSup = sDia + a.cpb * KM;
-        double *sRhs = sSup + a.cpb * KM;
-        double *sCp = sRhs + a.cpb * KM;
-        double *sDp = sCp + a.cpb * KM;
-        double *sPhi = sDp + a.cpb * KM;          // [cpb][(K+1) M]
-        double *sPn = sPhi + a.cpb * K1 * M;      // [cpb][KM] updated pressure
-        const int base = lc * KM;
-        double dpn = 0.0, phs_k = 0.0, phs_k1 = 0.0, ws_k = 0.0;
-        if (valid) {
-            const long x = (long)i * KM + km;
-            a.Th_o[x] = Th_new;
-            if (k == 0) a.ps_o[(long)i * M + mm] = ps_new;
-            dpn = a.dsig[k] * (ps_new - a.ptop);
-            phs_k = a.phistar[(long)i * K1M + (long)k * M + mm];
-            phs_k1 = a.phistar[(long)i * K1M + (long)(k + 1) * M + mm];
-            ws_k = a.wstar[(long)i * K1M + (long)k * M + mm];
-            const double dphi = phs_k - phs_k1;
-            const double p = a.p0 * pow(a.rd * Th_new / (a.p0 * dphi), a.gamma);
-            sP[base + km] = p;
-            sC[base + km] = a.gamma * a.grav * a.dts * p / dphi;
-        }
-        __syncthreads();
-        if (valid && k >= 1) {
-            // row r = k-1 for interior interface k (between layers k-1 and k)
-            const double dpm = a.dsig[k - 1] * (ps_new - a.ptop);
-            const double D = a.grav * a.dts / (0.5 * (dpm + dpn));
-            const double Cm = sC[base + (k - 1) * M + mm], Ck = sC[base + km];
-            const int r = (k - 1) * M + mm;
-            sSub[base + r] = -D * Cm;
-            sDia[base + r] = 1.0 + D * (Cm + Ck);
-            sSup[base + r] = -D * Ck;
-            sRhs[base + r] = ws_k + D * (sP[base + km] - sP[base + (k - 1) * M + mm]) - a.grav * a.dts;
-        }
-        __syncthreads();
-        if (valid && k == 0) {
-            // Thomas algorithm over the K-1 interior interfaces of member mm
-            const int n = K - 1;
-            if (n > 0) {
-                double den = sDia[base + mm];
-                sCp[base + mm] = sSup[base + mm] / den;
-                sDp[base + mm] = sRhs[base + mm] / den;
-                for (int r = 1; r < n; r++) {
-                    const int o = base + r * M + mm, op = base + (r - 1) * M + mm;
-                    den = sDia[o] - sSub[o] * sCp[op];
-                    sCp[o] = (r < n - 1) ? sSup[o] / den : 0.0;
-                    sDp[o] = (sRhs[o] - sSub[o] * sDp[op]) / den;
-                }
-                // back substitution: the solution overwrites sDp
-                for (int r = n - 2; r >= 0; r--) {
-                    const int o = base + r * M + mm;
-                    sDp[o] = sDp[o] - sCp[o] * sDp[o + M];
-                }
-            }
-        }
-        __syncthreads();
-        double wk = 0.0, phk = 0.0;
-        if (valid) {
-            wk = (k == 0) ? 0.0 : sDp[base + (k - 1) * M + mm];
-            phk = phs_k + a.grav * a.dts * wk;
-            sPhi[lc * K1 * M + k * M + mm] = phk;
-            if (k == K - 1) sPhi[lc * K1 * M + K * M + mm] = phs_k1;   // surface: w = 0
-            const long o = (long)i * K1M + (long)k * M + mm;
-            a.w_o[o] = wk;
-            a.phi_o[o] = phk;
-            if (k == K - 1) {
-                a.w_o[o + M] = 0.0;
-                a.phi_o[o + M] = phs_k1;
-            }
-        }
-        __syncthreads();
-        double pk = 0.0, dphi = 0.0;
-        if (valid) {
-            const double phb = sPhi[lc * K1 * M + (k + 1) * M + mm];
-            dphi = phk - phb;
-            pk = a.p0 * pow(a.rd * Th_new / (a.p0 * dphi), a.gamma);
-            sPn[base + km] = pk;
-            const long x = (long)i * KM + km;
-            a.alpha[x] = dphi / dpn;
-            a.pm[x] = pk;
-            a.phim[x] = 0.5 * (phk + phb);
-            if (a.th32_o) a.th32_o[x] = (float)(Th_new / dpn);
-        }
-        __syncthreads();
-        if (valid) {
-            // mu = dp/dpi at interfaces, copied to the ends, averaged to the layer
-            auto mu_at = [&](int kk) -> double {
-                if (K == 1) return 1.0;
-                if (kk < 1) kk = 1;
-                if (kk > K - 1) kk = K - 1;
-                const double dp_a = a.dsig[kk - 1] * (ps_new - a.ptop);
-                const double dp_b = a.dsig[kk] * (ps_new - a.ptop);
-                return (sPn[base + kk * M + mm] - sPn[base + (kk - 1) * M + mm]) / (0.5 * (dp_a + dp_b));
-            };
-            a.mum[(long)i * KM + km] = 0.5 * (mu_at(k) + mu_at(k + 1));
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// edge: momentum
-// ---------------------------------------------------------------------------
-// Each lane owns L consecutive (k, m) values of one edge, so every gather is
-// one L-wide vector load and the per-edge table lookups are shared by L
-// values.  With M == 1 the L values are consecutive levels; with M > 1 they
-// are consecutive members of one level (L divides M).
 template <typename T, int L> struct alignas(sizeof(T) * L) Pack {
     T v[L];
 };
@@ -474,105 +58,850 @@ template <typename T, int L> __device__ __forceinline__ Pack<T, L> ldp(const T *
 template <typename T, int L> __device__ __forceinline__ void stp(T *p, const Pack<T, L> &x) {
     *reinterpret_cast<Pack<T, L> *>(p) = x;
 }
+// six consecutive table entries (rows of [..][6] tables are 8-byte aligned
+// for 4-byte types and 16-byte aligned for 8-byte types)
+template <typename T> __device__ __forceinline__ void ld6(const T *p, T out[6]) {
+    const Pack<T, 2> a = ldp<T, 2>(p), b = ldp<T, 2>(p + 2), c = ldp<T, 2>(p + 4);
+    out[0] = a.v[0]; out[1] = a.v[1]; out[2] = b.v[0]; out[3] = b.v[1]; out[4] = c.v[0]; out[5] = c.v[1];
+}
 
+template <typename R> __device__ __forceinline__ const R *u_prev_ptr(const StageArgs &a) {
+    if constexpr (sizeof(R) == 8) return a.u_s;
+    else return a.u32_s;
+}
+
+// Lane decomposition: L values of (k, m) starting at km0.
+template <int L, bool M1> struct Vals {
+    int k0, mm0;
+    int k[L];
+    __device__ __forceinline__ Vals(int km0, int M) {
+        k0 = M1 ? km0 : km0 / M;
+        mm0 = km0 - k0 * M;
+#pragma unroll
+        for (int j = 0; j < L; j++) k[j] = M1 ? k0 + j : k0;
+    }
+};
+
+// 2-D field (surface pressure, depth) of the L values at cell c
+template <int L, bool M1> __device__ __forceinline__ void ld2d(const double *f, int c, int M, int mm0, double out[L]) {
+    if constexpr (M1) {
+        const double s = f[c];
+#pragma unroll
+        for (int j = 0; j < L; j++) out[j] = s;
+    } else {
+        const Pack<double, L> s = ldp<double, L>(f + (long)c * M + mm0);
+#pragma unroll
+        for (int j = 0; j < L; j++) out[j] = s.v[j];
+    }
+}
+
+// layer mass from surface pressure (HDC/NDC) or depth (SW)
+template <int MODEL> __device__ __forceinline__ double lmass(double dsg, double ps, double ptop) {
+    if constexpr (MODEL == MODEL_SW) return ps;
+    else return dsg * (ps - ptop);
+}
+
+// interface field X[N][K+1][M] at interface k + kk_off of the L values
+template <int L, bool M1>
+__device__ __forceinline__ void ld_iface(const double *X, long cbase, const Vals<L, M1> &v, int M, int kk_off,
+                                         double out[L]) {
+    if constexpr (M1) {
+#pragma unroll
+        for (int j = 0; j < L; j++) out[j] = X[cbase + v.k[j] + kk_off];
+    } else {
+        const Pack<double, L> p = ldp<double, L>(X + cbase + (long)(v.k0 + kk_off) * M + v.mm0);
+#pragma unroll
+        for (int j = 0; j < L; j++) out[j] = p.v[j];
+    }
+}
+template <int L, bool M1>
+__device__ __forceinline__ void st_iface(double *X, long cbase, const Vals<L, M1> &v, int M, int kk_off,
+                                         const double in[L]) {
+    if constexpr (M1) {
+#pragma unroll
+        for (int j = 0; j < L; j++) X[cbase + v.k[j] + kk_off] = in[j];
+    } else {
+        Pack<double, L> p;
+#pragma unroll
+        for (int j = 0; j < L; j++) p.v[j] = in[j];
+        stp<double, L>(X + cbase + (long)(v.k0 + kk_off) * M + v.mm0, p);
+    }
+}
+
+// theta of the previous stage at cell c, values starting at km0 (R precision)
+template <int MODEL, typename R, int L>
+__device__ __forceinline__ void theta_prev(const StageArgs &a, int c, long KM, long km0, const double dsg[L],
+                                           const double psc[L], R out[L]) {
+    if constexpr (sizeof(R) == 8) {
+        const Pack<double, L> T = ldp<double, L>(a.Th_s + (long)c * KM + km0);
+#pragma unroll
+        for (int j = 0; j < L; j++) out[j] = T.v[j] / lmass<MODEL>(dsg[j], psc[j], a.ptop);
+    } else {
+        const Pack<float, L> T = ldp<float, L>(a.th32_s + (long)c * KM + km0);
+#pragma unroll
+        for (int j = 0; j < L; j++) out[j] = T.v[j];
+    }
+}
+
+// column-kernel lane setup: work-group = cpb cells x (K*M/L) lanes
+struct ColLane {
+    int lc, km0, i;
+    bool valid;
+};
+template <int L> __device__ __forceinline__ ColLane col_lane(const StageArgs &a, int KM) {
+    ColLane c;
+    const int lanes = KM / L;
+    const int tid = threadIdx.x;
+    c.lc = tid / lanes;
+    c.km0 = (tid - c.lc * lanes) * L;
+    c.i = blockIdx.x * a.cpb + c.lc;
+    c.valid = (c.lc < a.cpb) && (c.i < a.mesh.N);
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// cell_a
+// ---------------------------------------------------------------------------
+template <int MODEL, typename R, int L, bool M1>
+__global__ void __launch_bounds__(1024) k_cell_a(StageArgs a) {
+    extern __shared__ double lds[];
+    const DevMesh &m = a.mesh;
+    const int K = a.K, M = M1 ? 1 : a.M, KM = K * M;
+    const ColLane cl = col_lane<L>(a, KM);
+    const int i = cl.i, km0 = cl.km0, lc = cl.lc;
+    const Vals<L, M1> v(km0, M);
+    double *sD = lds;                        // [cpb][KM]
+    double *sMd = lds + a.cpb * KM;          // [cpb][(K+1) M]  (NDC)
+
+    double dsg[L], psi[L], dpi_i[L], D[L];
+    R ke[L], Fs[kCellSlots][L];
+    R h0[L], h1[L], h2[L], th_i[L];
+    int ce[6], cn[6];
+    if (cl.valid) {
+        ld2d<L, M1>(a.ps_s, i, M, v.mm0, psi);
+#pragma unroll
+        for (int j = 0; j < L; j++) {
+            dsg[j] = (MODEL == MODEL_SW) ? 1.0 : a.dsig[v.k[j]];
+            dpi_i[j] = lmass<MODEL>(dsg[j], psi[j], a.ptop);
+            D[j] = 0.0;
+            ke[j] = 0;
+            h0[j] = h1[j] = h2[j] = 0;
+        }
+        ld6<int>(m.c_edge + (long)i * kCellSlots, ce);
+        ld6<int>(m.c_nbr + (long)i * kCellSlots, cn);
+        double cdiv[6];
+        R cke[6], ch0[6], ch1[6], ch2[6];
+        ld6<double>(m.c_div + (long)i * kCellSlots, cdiv);
+        ld6<R>(pick<R>(m.c_ke, m.c_ke32) + (long)i * kCellSlots, cke);
+        if constexpr (MODEL != MODEL_SW) {
+            const R *ch = pick<R>(m.c_hess, m.c_hess32) + (long)i * 3 * kCellSlots;
+            ld6<R>(ch, ch0);
+            ld6<R>(ch + kCellSlots, ch1);
+            ld6<R>(ch + 2 * kCellSlots, ch2);
+            theta_prev<MODEL, R, L>(a, i, KM, km0, dsg, psi, th_i);
+        }
+        const R *us = u_prev_ptr<R>(a);
+#pragma unroll
+        for (int s = 0; s < kCellSlots; s++) {
+#pragma unroll
+            for (int j = 0; j < L; j++) Fs[s][j] = 0;
+            const int e = ce[s];
+            if (e < 0) continue;
+            const int nb = cn[s];
+            double psn[L];
+            ld2d<L, M1>(a.ps_s, nb, M, v.mm0, psn);
+            const Pack<R, L> u = ldp<R, L>(us + (long)e * KM + km0);
+#pragma unroll
+            for (int j = 0; j < L; j++) {
+                const double dpe = 0.5 * (dpi_i[j] + lmass<MODEL>(dsg[j], psn[j], a.ptop));
+                if constexpr (sizeof(R) == 8) {
+                    Fs[s][j] = dpe * u.v[j];
+                    D[j] += cdiv[s] * Fs[s][j];
+                } else {
+                    Fs[s][j] = (float)dpe * u.v[j];
+                    D[j] += cdiv[s] * (double)Fs[s][j];
+                }
+                ke[j] += cke[s] * u.v[j] * u.v[j];
+            }
+            if constexpr (MODEL != MODEL_SW) {
+                R th_n[L];
+                theta_prev<MODEL, R, L>(a, nb, KM, km0, dsg, psn, th_n);
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    const R dth = th_n[j] - th_i[j];
+                    h0[j] += ch0[s] * dth;
+                    h1[j] += ch1[s] * dth;
+                    h2[j] += ch2[s] * dth;
+                }
+            }
+        }
+        Pack<R, L> kp;
+#pragma unroll
+        for (int j = 0; j < L; j++) kp.v[j] = ke[j];
+        stp<R, L>(a.ke_out<R>() + (long)i * KM + km0, kp);
+    }
+
+    if constexpr (MODEL == MODEL_SW) {
+        if (cl.valid) {
+            // h^(s) = h^n - dt_s D  (forward part of the stage)
+            double hn[L];
+            ld2d<L, M1>(a.ps_n, i, M, v.mm0, hn);
+            Pack<double, L> ho;
+#pragma unroll
+            for (int j = 0; j < L; j++) ho.v[j] = hn[j] + a.dts * (-D[j]);
+            stp<double, L>(a.ps_o + (long)i * M + v.mm0, ho);
+        }
+        return;
+    } else {
+        // ---- column mass tendency and vertical mass flux (LDS scan) ----
+        if (cl.valid) {
+#pragma unroll
+            for (int j = 0; j < L; j++) sD[lc * KM + km0 + j] = D[j];
+        }
+        __syncthreads();
+        double mdot_b[L];
+        if (cl.valid) {
+            const long K1M = (long)(K + 1) * M;
+#pragma unroll
+            for (int j = 0; j < L; j++) {
+                const int mm = v.mm0 + (M1 ? 0 : j);
+                double s = 0.0;
+                for (int q = 0; q < K; q++) s += sD[lc * KM + q * M + mm];
+                const double dps = -s;
+                double acc = 0.0;
+                for (int q = 0; q <= v.k[j]; q++) acc += sD[lc * KM + q * M + mm];
+                mdot_b[j] = (v.k[j] == K - 1) ? 0.0 : -acc - a.sig[v.k[j] + 1] * dps;
+                a.mdot[(long)i * K1M + (long)(v.k[j] + 1) * M + mm] = mdot_b[j];
+                if (v.k[j] == 0) {
+                    a.mdot[(long)i * K1M + mm] = 0.0;
+                    a.dps[(long)i * M + mm] = dps;
+                }
+            }
+            // ---- second derivatives of theta ----
+            Pack<R, L> p0, p1, p2;
+#pragma unroll
+            for (int j = 0; j < L; j++) {
+                p0.v[j] = h0[j];
+                p1.v[j] = h1[j];
+                p2.v[j] = h2[j];
+            }
+            R *H = a.hth_out<R>() + (long)i * 3 * KM + km0;
+            stp<R, L>(H, p0);
+            stp<R, L>(H + KM, p1);
+            stp<R, L>(H + 2 * KM, p2);
+        }
+
+        if constexpr (MODEL == MODEL_NDC) {
+            // ---- explicit advective step of w and phi at interface k ----
+            const int K1 = K + 1;
+            if (cl.valid) {
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    const int mm = v.mm0 + (M1 ? 0 : j);
+                    sMd[lc * K1 * M + (v.k[j] + 1) * M + mm] = mdot_b[j];
+                    if (v.k[j] == 0) sMd[lc * K1 * M + mm] = 0.0;
+                }
+            }
+            __syncthreads();
+            if (cl.valid) {
+                const long K1M = (long)K1 * M;
+                const long cb = (long)i * K1M;
+                const double *md = sMd + lc * K1 * M;
+                // interface masses (half layers either side; half of layer 0 at the top)
+                double dh[L];
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    const double dkm = (v.k[j] > 0) ? lmass<MODEL>(a.dsig[v.k[j] - 1], psi[j], a.ptop) : 0.0;
+                    dh[j] = (v.k[j] == 0) ? 0.5 * dpi_i[j] : 0.5 * (dkm + dpi_i[j]);
+                }
+                double wi[L], pi_[L];
+                ld_iface<L, M1>(a.w_s, cb, v, M, 0, wi);
+                ld_iface<L, M1>(a.phi_s, cb, v, M, 0, pi_);
+                const R *us = u_prev_ptr<R>(a);
+                R aw[L], ap[L];
+#pragma unroll
+                for (int j = 0; j < L; j++) aw[j] = ap[j] = 0;
+                double cdiv[6];
+                ld6<double>(m.c_div + (long)i * kCellSlots, cdiv);
+#pragma unroll
+                for (int s = 0; s < kCellSlots; s++) {
+                    const int e = ce[s];
+                    if (e < 0) continue;
+                    const int nb = cn[s];
+                    double psn[L];
+                    ld2d<L, M1>(a.ps_s, nb, M, v.mm0, psn);
+                    // mass flux of the layer above each value (for the interface average)
+                    R Fm[L];
+                    if constexpr (M1) {
+#pragma unroll
+                        for (int j = 1; j < L; j++) Fm[j] = Fs[s][j - 1];
+                        if (v.k0 > 0) {
+                            const double d1 = lmass<MODEL>(a.dsig[v.k0 - 1], psi[0], a.ptop);
+                            const double d2 = lmass<MODEL>(a.dsig[v.k0 - 1], psn[0], a.ptop);
+                            const R um = us[(long)e * KM + km0 - 1];
+                            if constexpr (sizeof(R) == 8) Fm[0] = 0.5 * (d1 + d2) * um;
+                            else Fm[0] = (float)(0.5 * (d1 + d2)) * um;
+                        } else {
+                            Fm[0] = 0;
+                        }
+                    } else {
+                        if (v.k0 > 0) {
+                            const Pack<R, L> um = ldp<R, L>(us + (long)e * KM + km0 - M);
+#pragma unroll
+                            for (int j = 0; j < L; j++) {
+                                const double d1 = lmass<MODEL>(a.dsig[v.k0 - 1], psi[j], a.ptop);
+                                const double d2 = lmass<MODEL>(a.dsig[v.k0 - 1], psn[j], a.ptop);
+                                if constexpr (sizeof(R) == 8) Fm[j] = 0.5 * (d1 + d2) * um.v[j];
+                                else Fm[j] = (float)(0.5 * (d1 + d2)) * um.v[j];
+                            }
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < L; j++) Fm[j] = 0;
+                        }
+                    }
+                    double wn_[L], pn_[L];
+                    ld_iface<L, M1>(a.w_s, (long)nb * K1M, v, M, 0, wn_);
+                    ld_iface<L, M1>(a.phi_s, (long)nb * K1M, v, M, 0, pn_);
+#pragma unroll
+                    for (int j = 0; j < L; j++) {
+                        const R Fh = (v.k[j] == 0) ? (R)0.5 * Fs[s][j] : (R)0.5 * (Fm[j] + Fs[s][j]);
+                        const R c = (R)cdiv[s] * Fh * (R)0.5;
+                        aw[j] += c * (R)(wn_[j] - wi[j]);
+                        ap[j] += c * (R)(pn_[j] - pi_[j]);
+                    }
+                }
+                double wu[L], wd[L], pu[L], pd[L], wn0[L], pn0[L], ws_[L], ps_[L];
+                ld_iface<L, M1>(a.w_n, cb, v, M, 0, wn0);
+                ld_iface<L, M1>(a.phi_n, cb, v, M, 0, pn0);
+                ld_iface<L, M1>(a.w_s, cb, v, M, 1, wd);
+                ld_iface<L, M1>(a.phi_s, cb, v, M, 1, pd);
+                // the interface above each value (none above the top interface)
+                if constexpr (M1) {
+#pragma unroll
+                    for (int j = 0; j < L; j++) {
+                        wu[j] = (v.k[j] >= 1) ? a.w_s[cb + v.k[j] - 1] : 0.0;
+                        pu[j] = (v.k[j] >= 1) ? a.phi_s[cb + v.k[j] - 1] : 0.0;
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < L; j++) wu[j] = pu[j] = 0.0;
+                    if (v.k0 > 0) {
+                        ld_iface<L, M1>(a.w_s, cb, v, M, -1, wu);
+                        ld_iface<L, M1>(a.phi_s, cb, v, M, -1, pu);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    const int kk = v.k[j], mm = v.mm0 + (M1 ? 0 : j);
+                    const R inv_dh = (R)(1.0 / dh[j]);
+                    R vw = 0, vp = 0;
+                    if (kk >= 1) {
+                        const R ml = (R)(0.5 * (md[(kk - 1) * M + mm] + md[kk * M + mm]));
+                        vw += ml * (R)(wi[j] - wu[j]);
+                        vp += ml * (R)(pi_[j] - pu[j]);
+                    }
+                    {
+                        const R ml = (R)(0.5 * (md[kk * M + mm] + md[(kk + 1) * M + mm]));
+                        vw += ml * (R)(wd[j] - wi[j]);
+                        vp += ml * (R)(pd[j] - pi_[j]);
+                    }
+                    const R advw = aw[j] * inv_dh + vw * (inv_dh * (R)0.5);
+                    const R advp = ap[j] * inv_dh + vp * (inv_dh * (R)0.5);
+                    ws_[j] = (kk == 0) ? 0.0 : wn0[j] - a.dts * (double)advw;
+                    ps_[j] = pn0[j] - a.dts * (double)advp;
+                }
+                st_iface<L, M1>(a.wstar, cb, v, M, 0, ws_);
+                st_iface<L, M1>(a.phistar, cb, v, M, 0, ps_);
+                // surface interface: w = 0, phi fixed
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    if (v.k[j] == K - 1) {
+                        const int mm = v.mm0 + (M1 ? 0 : j);
+                        a.wstar[cb + (long)K * M + mm] = 0.0;
+                        a.phistar[cb + (long)K * M + mm] = a.phi_n[cb + (long)K * M + mm];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// vertex: vorticity, FP64 vertex mass, potential vorticity
+// ---------------------------------------------------------------------------
+template <int MODEL, typename R, int L, bool M1>
+__global__ void __launch_bounds__(1024) k_vertex(StageArgs a) {
+    const DevMesh &m = a.mesh;
+    const int K = a.K, M = M1 ? 1 : a.M, KM = K * M;
+    const int lanes = KM / L;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)m.V * lanes) return;
+    const int vx = (int)(idx / lanes);
+    const int km0 = (int)(idx - (long)vx * lanes) * L;
+    const Vals<L, M1> v(km0, M);
+    const Pack<int, 4> ve = ldp<int, 4>(m.v_edge + 4 * (long)vx);
+    const Pack<int, 4> vc = ldp<int, 4>(m.v_cell + 4 * (long)vx);
+    R cw[4];
+    if constexpr (sizeof(R) == 4) {
+        const Pack<float, 4> c = ldp<float, 4>(m.v_curl32 + 4 * (long)vx);
+#pragma unroll
+        for (int r = 0; r < 4; r++) cw[r] = c.v[r];
+    } else {
+        const Pack<double, 2> c0 = ldp<double, 2>(m.v_curl + 4 * (long)vx), c1 = ldp<double, 2>(m.v_curl + 4 * (long)vx + 2);
+        cw[0] = c0.v[0]; cw[1] = c0.v[1]; cw[2] = c1.v[0]; cw[3] = c1.v[1];
+    }
+    const Pack<double, 2> k0 = ldp<double, 2>(m.v_kite + 4 * (long)vx), k1 = ldp<double, 2>(m.v_kite + 4 * (long)vx + 2);
+    const double kw[3] = {k0.v[0], k0.v[1], k1.v[0]};
+    double dsg[L];
+#pragma unroll
+    for (int j = 0; j < L; j++) dsg[j] = (MODEL == MODEL_SW) ? 1.0 : a.dsig[v.k[j]];
+    R zeta[L];
+    double hv[L];
+#pragma unroll
+    for (int j = 0; j < L; j++) {
+        zeta[j] = 0;
+        hv[j] = 0.0;
+    }
+    const R *us = u_prev_ptr<R>(a);
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        const Pack<R, L> u = ldp<R, L>(us + (long)ve.v[r] * KM + km0);
+        double ps[L];
+        ld2d<L, M1>(a.ps_s, vc.v[r], M, v.mm0, ps);
+#pragma unroll
+        for (int j = 0; j < L; j++) {
+            zeta[j] += cw[r] * u.v[j];
+            hv[j] += kw[r] * lmass<MODEL>(dsg[j], ps[j], a.ptop);
+        }
+    }
+    const double f = m.v_f[vx];
+    Pack<R, L> q;
+#pragma unroll
+    for (int j = 0; j < L; j++) q.v[j] = (R)(((double)zeta[j] + f) / hv[j]);
+    stp<R, L>(a.qv_out<R>() + (long)vx * KM + km0, q);
+}
+
+// ---------------------------------------------------------------------------
+// cell_b: Coriolis/KE shares, theta transport, mass/Theta update, column
+// diagnostics or the NH column solve
+// ---------------------------------------------------------------------------
+template <int MODEL, typename R, int L, bool M1>
+__global__ void __launch_bounds__(1024) k_cell_b(StageArgs a) {
+    extern __shared__ double lds[];
+    const DevMesh &m = a.mesh;
+    const int K = a.K, M = M1 ? 1 : a.M, KM = K * M;
+    const ColLane cl = col_lane<L>(a, KM);
+    const int i = cl.i, km0 = cl.km0, lc = cl.lc;
+    const Vals<L, M1> v(km0, M);
+
+    double Th_new[L], ps_new[L], dsg[L];
+    if (cl.valid) {
+        double psi[L], dpi_i[L];
+        ld2d<L, M1>(a.ps_s, i, M, v.mm0, psi);
+#pragma unroll
+        for (int j = 0; j < L; j++) {
+            dsg[j] = (MODEL == MODEL_SW) ? 1.0 : a.dsig[v.k[j]];
+            dpi_i[j] = lmass<MODEL>(dsg[j], psi[j], a.ptop);
+        }
+        int ce[6], cn[6], cv[6];
+        ld6<int>(m.c_edge + (long)i * kCellSlots, ce);
+        ld6<int>(m.c_nbr + (long)i * kCellSlots, cn);
+        ld6<int>(m.c_vert + (long)i * kCellSlots, cv);
+        R cdiv[6], cgk[6];
+        ld6<R>(pick<R>(m.c_div, m.c_div32) + (long)i * kCellSlots, cdiv);
+        ld6<R>(pick<R>(m.c_gk, m.c_gk32) + (long)i * kCellSlots, cgk);
+        const R *us = u_prev_ptr<R>(a);
+        const R *Hs = a.hth_in<R>();
+        const R *hdir = pick<R>(m.e_hdir, m.e_hdir32);
+        const R *d2 = pick<R>(m.e_d2, m.e_d2_32);
+
+        R th_i[L], Hi0[L], Hi1[L], Hi2[L];
+        if constexpr (MODEL != MODEL_SW) {
+            theta_prev<MODEL, R, L>(a, i, KM, km0, dsg, psi, th_i);
+            const Pack<R, L> a0 = ldp<R, L>(Hs + (long)i * 3 * KM + km0);
+            const Pack<R, L> a1 = ldp<R, L>(Hs + (long)i * 3 * KM + KM + km0);
+            const Pack<R, L> a2 = ldp<R, L>(Hs + (long)i * 3 * KM + 2 * KM + km0);
+#pragma unroll
+            for (int j = 0; j < L; j++) {
+                Hi0[j] = a0.v[j];
+                Hi1[j] = a1.v[j];
+                Hi2[j] = a2.v[j];
+            }
+        }
+        // fluxes of the six edges and the theta flux divergence
+        R Fs[kCellSlots][L], hdiv[L];
+#pragma unroll
+        for (int j = 0; j < L; j++) hdiv[j] = 0;
+#pragma unroll
+        for (int s = 0; s < kCellSlots; s++) {
+#pragma unroll
+            for (int j = 0; j < L; j++) Fs[s][j] = 0;
+            const int e = ce[s];
+            if (e < 0) continue;
+            const int nb = cn[s];
+            double psn[L];
+            ld2d<L, M1>(a.ps_s, nb, M, v.mm0, psn);
+            const Pack<R, L> u = ldp<R, L>(us + (long)e * KM + km0);
+#pragma unroll
+            for (int j = 0; j < L; j++) {
+                const double dpe = 0.5 * (dpi_i[j] + lmass<MODEL>(dsg[j], psn[j], a.ptop));
+                if constexpr (sizeof(R) == 8) Fs[s][j] = dpe * u.v[j];
+                else Fs[s][j] = (float)dpe * u.v[j];
+            }
+            if constexpr (MODEL != MODEL_SW) {
+                const int side = (cdiv[s] > (R)0) ? 0 : 1;   // i is c1 of e when its outward sign is +
+                R th_n[L];
+                theta_prev<MODEL, R, L>(a, nb, KM, km0, dsg, psn, th_n);
+                const long hb = (long)nb * 3 * KM + km0;
+                const Pack<R, L> b0 = ldp<R, L>(Hs + hb), b1 = ldp<R, L>(Hs + hb + KM), b2 = ldp<R, L>(Hs + hb + 2 * KM);
+                const R *ds = hdir + (long)e * 6 + side * 3;        // direction in i's frame
+                const R *dn = hdir + (long)e * 6 + (1 - side) * 3;  // direction in nb's frame
+                const R c = d2[e];
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    const R qi = Hi0[j] * ds[0] + Hi1[j] * ds[1] + Hi2[j] * ds[2];
+                    const R qn = b0.v[j] * dn[0] + b1.v[j] * dn[1] + b2.v[j] * dn[2];
+                    const R q1 = side ? th_n[j] : th_i[j], q2 = side ? th_i[j] : th_n[j];
+                    const R hh1 = side ? qn : qi, hh2 = side ? qi : qn;
+                    const R F = Fs[s][j];   // flux along n_e (c1 -> c2), the same number from either cell
+                    const R sg = (F >= (R)0) ? (R)1 : (R)-1;
+                    const R tv = (R)0.5 * (q1 + q2) - c * (hh1 + hh2) + sg * c * (hh2 - hh1);
+                    hdiv[j] += cdiv[s] * (F * tv);
+                }
+            }
+        }
+        // ---- this cell's share of Coriolis - grad K on each of its edges (TRiSK) ----
+        {
+            R QV[kCellSlots][L];
+#pragma unroll
+            for (int s = 0; s < kCellSlots; s++) {
+                const Pack<R, L> q = ldp<R, L>(a.qv_in<R>() + (long)cv[s] * KM + km0);
+#pragma unroll
+                for (int j = 0; j < L; j++) QV[s][j] = q.v[j];
+            }
+            R qe[kCellSlots][L];
+#pragma unroll
+            for (int s = 0; s < kCellSlots; s++)
+#pragma unroll
+                for (int j = 0; j < L; j++) qe[s][j] = (R)0.5 * (QV[s][j] + QV[(s + 1) % kCellSlots][j]);
+            const Pack<R, L> kp = ldp<R, L>(a.ke_in<R>() + (long)i * KM + km0);
+            const R *tk = pick<R>(m.c_tk, m.c_tk32) + (long)i * kCellSlots * kCellSlots;
+            R *qh = a.qh_out<R>();
+#pragma unroll
+            for (int s = 0; s < kCellSlots; s++) {
+                const int e = ce[s];
+                if (e < 0) continue;
+                R w[6];
+                ld6<R>(tk + s * kCellSlots, w);
+                Pack<R, L> out;
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    R acc = 0;
+#pragma unroll
+                    for (int t = 1; t < kCellSlots; t++) {
+                        const int sp = (s + t) % kCellSlots;
+                        acc += w[sp] * Fs[sp][j] * ((R)0.5 * (qe[s][j] + qe[sp][j]));
+                    }
+                    out.v[j] = acc + cgk[s] * kp.v[j];
+                }
+                const int side = (cdiv[s] > (R)0) ? 0 : 1;
+                stp<R, L>(qh + ((long)e * 2 + side) * KM + km0, out);
+            }
+        }
+        if constexpr (MODEL != MODEL_SW) {
+            // vertical theta flux through the layer's interfaces (centred theta)
+            const long K1M = (long)(K + 1) * M;
+            const double *md = a.mdot + (long)i * K1M;
+            R thu[L], thd[L];
+#pragma unroll
+            for (int j = 0; j < L; j++) thu[j] = thd[j] = 0;
+            if constexpr (M1) {
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    if (j > 0) thu[j] = th_i[j - 1];
+                    if (j < L - 1) thd[j] = th_i[j + 1];
+                }
+                if (v.k0 > 0) {
+                    if constexpr (sizeof(R) == 8)
+                        thu[0] = a.Th_s[(long)i * KM + km0 - 1] / lmass<MODEL>(a.dsig[v.k0 - 1], psi[0], a.ptop);
+                    else
+                        thu[0] = a.th32_s[(long)i * KM + km0 - 1];
+                }
+                const int kl = v.k[L - 1];
+                if (kl < K - 1) {
+                    if constexpr (sizeof(R) == 8)
+                        thd[L - 1] = a.Th_s[(long)i * KM + km0 + L] / lmass<MODEL>(a.dsig[kl + 1], psi[0], a.ptop);
+                    else
+                        thd[L - 1] = a.th32_s[(long)i * KM + km0 + L];
+                }
+            } else {
+                double dd[L];
+                if (v.k0 > 0) {
+#pragma unroll
+                    for (int j = 0; j < L; j++) dd[j] = a.dsig[v.k0 - 1];
+                    theta_prev<MODEL, R, L>(a, i, KM, km0 - M, dd, psi, thu);
+                }
+                if (v.k0 < K - 1) {
+#pragma unroll
+                    for (int j = 0; j < L; j++) dd[j] = a.dsig[v.k0 + 1];
+                    theta_prev<MODEL, R, L>(a, i, KM, km0 + M, dd, psi, thd);
+                }
+            }
+            double dps_[L], psn_[L];
+            ld2d<L, M1>(a.dps, i, M, v.mm0, dps_);
+            ld2d<L, M1>(a.ps_n, i, M, v.mm0, psn_);
+            const Pack<double, L> Thn = ldp<double, L>(a.Th_n + (long)i * KM + km0);
+#pragma unroll
+            for (int j = 0; j < L; j++) {
+                const int mm = v.mm0 + (M1 ? 0 : j);
+                R top = 0, bot = 0;
+                if (v.k[j] > 0) top = (R)md[(long)v.k[j] * M + mm] * ((R)0.5 * (thu[j] + th_i[j]));
+                if (v.k[j] < K - 1) bot = (R)md[(long)(v.k[j] + 1) * M + mm] * ((R)0.5 * (th_i[j] + thd[j]));
+                const R dTh = -hdiv[j] - (bot - top);
+                Th_new[j] = Thn.v[j] + a.dts * (double)dTh;
+                ps_new[j] = psn_[j] + a.dts * dps_[j];
+            }
+        }
+    }
+    if constexpr (MODEL == MODEL_SW) {
+        return;
+    } else {
+        // all reads of ps_n / Th_n happen before this barrier (stage 3 writes in place)
+        __syncthreads();
+        if constexpr (MODEL == MODEL_HDC) {
+            double *sA = lds;                       // [cpb][KM]
+            double al[L];
+            if (cl.valid) {
+                Pack<double, L> tho;
+                Pack<float, L> th32;
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    const int k = v.k[j];
+                    tho.v[j] = Th_new[j];
+                    const double pit = a.ptop + a.sig[k] * (ps_new[j] - a.ptop);
+                    const double pib = a.ptop + a.sig[k + 1] * (ps_new[j] - a.ptop);
+                    const double dpn = dsg[j] * (ps_new[j] - a.ptop);
+                    const double pk = 0.5 * (pit + pib);
+                    const double th = Th_new[j] / dpn;
+                    const double T = th * pow(pk / a.p0, a.kappa);
+                    al[j] = a.rd * T / pk;
+                    sA[lc * KM + km0 + j] = al[j] * dpn;
+                    th32.v[j] = (float)th;
+                }
+                stp<double, L>(a.Th_o + (long)i * KM + km0, tho);
+                if (a.th32_o) stp<float, L>(a.th32_o + (long)i * KM + km0, th32);
+#pragma unroll
+                for (int j = 0; j < L; j++)
+                    if (v.k[j] == 0) a.ps_o[(long)i * M + v.mm0 + (M1 ? 0 : j)] = ps_new[j];
+            }
+            __syncthreads();
+            if (cl.valid) {
+                // hydrostatic geopotential from the flat surface upwards (Eq. 8)
+                Pack<double, L> alp, php;
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    const int mm = v.mm0 + (M1 ? 0 : j);
+                    double acc = 0.0;
+                    for (int q = K - 1; q > v.k[j]; q--) acc += sA[lc * KM + q * M + mm];
+                    const double phit = acc + sA[lc * KM + v.k[j] * M + mm];
+                    alp.v[j] = al[j];
+                    php.v[j] = 0.5 * (phit + acc);
+                }
+                stp<double, L>(a.alpha + (long)i * KM + km0, alp);
+                stp<double, L>(a.phim + (long)i * KM + km0, php);
+            }
+        } else {
+            // ---- implicit vertical acoustic solve of the column (FP64) ----
+            const int K1 = K + 1;
+            const long K1M = (long)K1 * M;
+            const long cb = (long)i * K1M;
+            double *sP = lds;                         // p*   [cpb][KM]
+            double *sC = sP + a.cpb * KM;             // C    [cpb][KM]
+            double *sSub = sC + a.cpb * KM;           // rows [cpb][KM]
+            double *sDia = sSub + a.cpb * KM;
+            double *sSup = sDia + a.cpb * KM;
+            double *sRhs = sSup + a.cpb * KM;
+            double *sCp = sRhs + a.cpb * KM;
+            double *sDp = sCp + a.cpb * KM;
+            double *sPhi = sDp + a.cpb * KM;          // [cpb][(K+1) M]
+            double *sPn = sPhi + a.cpb * K1 * M;      // [cpb][KM] updated pressure
+            const int base = lc * KM;
+            double dpn[L], phs_k[L], phs_k1[L], ws_k[L];
+            if (cl.valid) {
+                Pack<double, L> tho;
+                Pack<float, L> th32;
+                ld_iface<L, M1>(a.phistar, cb, v, M, 0, phs_k);
+                ld_iface<L, M1>(a.phistar, cb, v, M, 1, phs_k1);
+                ld_iface<L, M1>(a.wstar, cb, v, M, 0, ws_k);
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    tho.v[j] = Th_new[j];
+                    dpn[j] = dsg[j] * (ps_new[j] - a.ptop);
+                    th32.v[j] = (float)(Th_new[j] / dpn[j]);
+                    const double dphi = phs_k[j] - phs_k1[j];
+                    const double p = a.p0 * pow(a.rd * Th_new[j] / (a.p0 * dphi), a.gamma);
+                    sP[base + km0 + j] = p;
+                    sC[base + km0 + j] = a.gamma * a.grav * a.dts * p / dphi;
+                }
+                stp<double, L>(a.Th_o + (long)i * KM + km0, tho);
+                if (a.th32_o) stp<float, L>(a.th32_o + (long)i * KM + km0, th32);
+#pragma unroll
+                for (int j = 0; j < L; j++)
+                    if (v.k[j] == 0) a.ps_o[(long)i * M + v.mm0 + (M1 ? 0 : j)] = ps_new[j];
+            }
+            __syncthreads();
+            if (cl.valid) {
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    const int k = v.k[j], mm = v.mm0 + (M1 ? 0 : j);
+                    if (k < 1) continue;
+                    // row r = k-1 for interior interface k (between layers k-1 and k)
+                    const double dpm = a.dsig[k - 1] * (ps_new[j] - a.ptop);
+                    const double D = a.grav * a.dts / (0.5 * (dpm + dpn[j]));
+                    const double Cm = sC[base + (k - 1) * M + mm], Ck = sC[base + k * M + mm];
+                    const int r = (k - 1) * M + mm;
+                    sSub[base + r] = -D * Cm;
+                    sDia[base + r] = 1.0 + D * (Cm + Ck);
+                    sSup[base + r] = -D * Ck;
+                    sRhs[base + r] = ws_k[j] + D * (sP[base + k * M + mm] - sP[base + (k - 1) * M + mm]) - a.grav * a.dts;
+                }
+            }
+            __syncthreads();
+            if (cl.valid) {
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    if (v.k[j] != 0) continue;
+                    const int mm = v.mm0 + (M1 ? 0 : j);
+                    // Thomas algorithm over the K-1 interior interfaces of member mm
+                    const int n = K - 1;
+                    if (n > 0) {
+                        double den = sDia[base + mm];
+                        sCp[base + mm] = sSup[base + mm] / den;
+                        sDp[base + mm] = sRhs[base + mm] / den;
+                        for (int r = 1; r < n; r++) {
+                            const int o = base + r * M + mm, op = base + (r - 1) * M + mm;
+                            den = sDia[o] - sSub[o] * sCp[op];
+                            sCp[o] = (r < n - 1) ? sSup[o] / den : 0.0;
+                            sDp[o] = (sRhs[o] - sSub[o] * sDp[op]) / den;
+                        }
+                        // back substitution: the solution overwrites sDp
+                        for (int r = n - 2; r >= 0; r--) {
+                            const int o = base + r * M + mm;
+                            sDp[o] = sDp[o] - sCp[o] * sDp[o + M];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            double phk[L];
+            if (cl.valid) {
+                double wk[L];
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    const int k = v.k[j], mm = v.mm0 + (M1 ? 0 : j);
+                    wk[j] = (k == 0) ? 0.0 : sDp[base + (k - 1) * M + mm];
+                    phk[j] = phs_k[j] + a.grav * a.dts * wk[j];
+                    sPhi[lc * K1 * M + k * M + mm] = phk[j];
+                    if (k == K - 1) sPhi[lc * K1 * M + K * M + mm] = phs_k1[j];   // surface: w = 0
+                }
+                st_iface<L, M1>(a.w_o, cb, v, M, 0, wk);
+                st_iface<L, M1>(a.phi_o, cb, v, M, 0, phk);
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    if (v.k[j] == K - 1) {
+                        const int mm = v.mm0 + (M1 ? 0 : j);
+                        a.w_o[cb + (long)K * M + mm] = 0.0;
+                        a.phi_o[cb + (long)K * M + mm] = phs_k1[j];
+                    }
+                }
+            }
+            __syncthreads();
+            if (cl.valid) {
+                Pack<double, L> alp, pmp, php;
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    const int k = v.k[j], mm = v.mm0 + (M1 ? 0 : j);
+                    const double phb = sPhi[lc * K1 * M + (k + 1) * M + mm];
+                    const double dphi = phk[j] - phb;
+                    const double pk = a.p0 * pow(a.rd * Th_new[j] / (a.p0 * dphi), a.gamma);
+                    sPn[base + k * M + mm] = pk;
+                    alp.v[j] = dphi / dpn[j];
+                    pmp.v[j] = pk;
+                    php.v[j] = 0.5 * (phk[j] + phb);
+                }
+                stp<double, L>(a.alpha + (long)i * KM + km0, alp);
+                stp<double, L>(a.pm + (long)i * KM + km0, pmp);
+                stp<double, L>(a.phim + (long)i * KM + km0, php);
+            }
+            __syncthreads();
+            if (cl.valid) {
+                // mu = dp/dpi at interfaces, copied to the ends, averaged to the layer
+                Pack<double, L> mup;
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    const int mm = v.mm0 + (M1 ? 0 : j);
+                    const double psj = ps_new[j];
+                    auto mu_at = [&](int kk) -> double {
+                        if (K == 1) return 1.0;
+                        if (kk < 1) kk = 1;
+                        if (kk > K - 1) kk = K - 1;
+                        const double dp_a = a.dsig[kk - 1] * (psj - a.ptop);
+                        const double dp_b = a.dsig[kk] * (psj - a.ptop);
+                        return (sPn[base + kk * M + mm] - sPn[base + (kk - 1) * M + mm]) / (0.5 * (dp_a + dp_b));
+                    };
+                    mup.v[j] = 0.5 * (mu_at(v.k[j]) + mu_at(v.k[j] + 1));
+                }
+                stp<double, L>(a.mum + (long)i * KM + km0, mup);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// edge: momentum
+// ---------------------------------------------------------------------------
 template <int MODEL, typename R, int L, bool M1>
 __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
     const DevMesh &m = a.mesh;
     const int K = a.K, M = M1 ? 1 : a.M, KM = K * M;
-    const int lanes = KM / L;                       // lanes per edge
+    const int lanes = KM / L;
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)m.E * lanes) return;
     const int e = (int)(idx / lanes);
     const int km0 = (int)(idx - (long)e * lanes) * L;
     const long base = (long)e * KM + km0;
-    constexpr bool m1 = M1;
-    const int k0 = M1 ? km0 : km0 / M, mm0 = km0 - k0 * M;   // M > 1: all L values share level k0
-    int kk[L];
-    double dsg[L];                                   // layer sigma thickness of each value
-#pragma unroll
-    for (int j = 0; j < L; j++) {
-        kk[j] = m1 ? k0 + j : k0;
-        dsg[j] = (MODEL == MODEL_SW) ? 1.0 : a.dsig[kk[j]];
-    }
+    const Vals<L, M1> v(km0, M);
+    const Pack<int, 2> cc = ldp<int, 2>(m.e_cell + 2 * (long)e);
+    const int c1 = cc.v[0], c2 = cc.v[1];
 
-    // layer mass of the L values at cell c of the previous stage
-    auto dpi_at = [&](int c, double out[L]) {
-        if (m1) {
-            const double s = a.ps_s[c];
-#pragma unroll
-            for (int j = 0; j < L; j++) out[j] = (MODEL == MODEL_SW) ? s : dsg[j] * (s - a.ptop);
-        } else {
-            const Pack<double, L> s = ldp<double, L>(a.ps_s + (long)c * M + mm0);
-#pragma unroll
-            for (int j = 0; j < L; j++) out[j] = (MODEL == MODEL_SW) ? s.v[j] : dsg[j] * (s.v[j] - a.ptop);
-        }
-    };
-
-    const int c1 = m.e_cell[2 * (long)e], c2 = m.e_cell[2 * (long)e + 1];
-    const int v1 = m.e_vert[2 * (long)e], v2 = m.e_vert[2 * (long)e + 1];
-    const R *qv = a.qv_in<R>();
-    const R *ke = a.ke_in<R>();
-
-    // TRiSK Coriolis term: sum_e' w l_e'/d_e F_e' (q_e + q_e')/2
-    R qe[L], Q[L];
-    {
-        const Pack<R, L> qa = ldp<R, L>(qv + (long)v1 * KM + km0), qb = ldp<R, L>(qv + (long)v2 * KM + km0);
-#pragma unroll
-        for (int j = 0; j < L; j++) {
-            qe[j] = (R)0.5 * (qa.v[j] + qb.v[j]);
-            Q[j] = 0;
-        }
-    }
-    const R *tkw = pick<R>(m.e_tkw, m.e_tkw32) + (long)e * kTriskSlots;
-#pragma unroll
-    for (int t = 0; t < kTriskSlots; t++) {
-        const int ep = m.e_tk[(long)e * kTriskSlots + t];
-        if (ep < 0) continue;
-        const int a1 = m.e_cell[2 * (long)ep], a2 = m.e_cell[2 * (long)ep + 1];
-        const int w1 = m.e_vert[2 * (long)ep], w2 = m.e_vert[2 * (long)ep + 1];
-        double d1[L], d2[L];
-        dpi_at(a1, d1);
-        dpi_at(a2, d2);
-        const Pack<R, L> up = ldp<R, L>((sizeof(R) == 8 ? (const R *)a.u_s : (const R *)a.u32_s) + (long)ep * KM + km0);
-        const Pack<R, L> qa = ldp<R, L>(qv + (long)w1 * KM + km0), qb = ldp<R, L>(qv + (long)w2 * KM + km0);
-        const R wt = tkw[t];
-#pragma unroll
-        for (int j = 0; j < L; j++) {
-            const double dpe = 0.5 * (d1[j] + d2[j]);
-            R F;
-            if constexpr (sizeof(R) == 8) F = dpe * up.v[j];
-            else F = (float)dpe * up.v[j];
-            const R qep = (R)0.5 * (qa.v[j] + qb.v[j]);
-            Q[j] += wt * F * ((R)0.5 * (qe[j] + qep));
-        }
-    }
-    const R dinv = pick<R>(m.e_dinv, m.e_dinv32)[e];
+    // Coriolis - grad K: the two cells' shares
     R adv[L];
     {
-        const Pack<R, L> k1 = ldp<R, L>(ke + (long)c1 * KM + km0), k2 = ldp<R, L>(ke + (long)c2 * KM + km0);
+        const R *qh = a.qh_in<R>();
+        const Pack<R, L> q1 = ldp<R, L>(qh + (long)e * 2 * KM + km0), q2 = ldp<R, L>(qh + ((long)e * 2 + 1) * KM + km0);
 #pragma unroll
-        for (int j = 0; j < L; j++) adv[j] = Q[j] - (k2.v[j] - k1.v[j]) * dinv;
+        for (int j = 0; j < L; j++) adv[j] = q1.v[j] + q2.v[j];
     }
 
     if constexpr (MODEL != MODEL_SW) {
         // centred vertical advection of u by the interface mass flux
-        const R *us = (sizeof(R) == 8) ? (const R *)a.u_s : (const R *)a.u32_s;
+        const R *us = u_prev_ptr<R>(a);
         const long K1M = (long)(K + 1) * M;
-        double e1[L], e2[L];
-        dpi_at(c1, e1);
-        dpi_at(c2, e2);
+        double p1[L], p2[L], dsg[L];
+        ld2d<L, M1>(a.ps_s, c1, M, v.mm0, p1);
+        ld2d<L, M1>(a.ps_s, c2, M, v.mm0, p2);
+#pragma unroll
+        for (int j = 0; j < L; j++) dsg[j] = a.dsig[v.k[j]];
         const Pack<R, L> uk = ldp<R, L>(us + base);
-        // u one level above / below each value, and the interface mass fluxes
-        // at the top (k) and bottom (k+1) of each value's layer
         R uup[L], udn[L];
         double mt[L], mb[L];
-        if (m1) {
+        if constexpr (M1) {
 #pragma unroll
             for (int j = 0; j < L; j++) {
-                uup[j] = (j > 0) ? uk.v[j - 1] : ((k0 > 0) ? us[base - 1] : (R)0);
-                udn[j] = (j < L - 1) ? uk.v[j + 1] : ((kk[j] < K - 1) ? us[base + L] : (R)0);
+                uup[j] = (j > 0) ? uk.v[j - 1] : ((v.k0 > 0) ? us[base - 1] : (R)0);
+                udn[j] = (j < L - 1) ? uk.v[j + 1] : ((v.k[j] < K - 1) ? us[base + L] : (R)0);
             }
-            const double *m1p = a.mdot + (long)c1 * K1M + k0, *m2p = a.mdot + (long)c2 * K1M + k0;
+            const double *m1p = a.mdot + (long)c1 * K1M + v.k0, *m2p = a.mdot + (long)c2 * K1M + v.k0;
             double i1[L + 1], i2[L + 1];
 #pragma unroll
             for (int j = 0; j <= L; j++) {
@@ -586,26 +915,26 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
             }
         } else {
             Pack<R, L> pu, pd;
-            if (k0 > 0) pu = ldp<R, L>(us + base - M);
-            if (k0 < K - 1) pd = ldp<R, L>(us + base + M);
-            const Pack<double, L> t1 = ldp<double, L>(a.mdot + (long)c1 * K1M + (long)k0 * M + mm0);
-            const Pack<double, L> t2 = ldp<double, L>(a.mdot + (long)c2 * K1M + (long)k0 * M + mm0);
-            const Pack<double, L> b1 = ldp<double, L>(a.mdot + (long)c1 * K1M + (long)(k0 + 1) * M + mm0);
-            const Pack<double, L> b2 = ldp<double, L>(a.mdot + (long)c2 * K1M + (long)(k0 + 1) * M + mm0);
+            if (v.k0 > 0) pu = ldp<R, L>(us + base - M);
+            if (v.k0 < K - 1) pd = ldp<R, L>(us + base + M);
+            const Pack<double, L> t1 = ldp<double, L>(a.mdot + (long)c1 * K1M + (long)v.k0 * M + v.mm0);
+            const Pack<double, L> t2 = ldp<double, L>(a.mdot + (long)c2 * K1M + (long)v.k0 * M + v.mm0);
+            const Pack<double, L> b1 = ldp<double, L>(a.mdot + (long)c1 * K1M + (long)(v.k0 + 1) * M + v.mm0);
+            const Pack<double, L> b2 = ldp<double, L>(a.mdot + (long)c2 * K1M + (long)(v.k0 + 1) * M + v.mm0);
 #pragma unroll
             for (int j = 0; j < L; j++) {
-                uup[j] = (k0 > 0) ? pu.v[j] : (R)0;
-                udn[j] = (k0 < K - 1) ? pd.v[j] : (R)0;
+                uup[j] = (v.k0 > 0) ? pu.v[j] : (R)0;
+                udn[j] = (v.k0 < K - 1) ? pd.v[j] : (R)0;
                 mt[j] = 0.5 * (t1.v[j] + t2.v[j]);
                 mb[j] = 0.5 * (b1.v[j] + b2.v[j]);
             }
         }
 #pragma unroll
         for (int j = 0; j < L; j++) {
-            const double dpe = 0.5 * (e1[j] + e2[j]);
+            const double dpe = 0.5 * (lmass<MODEL>(dsg[j], p1[j], a.ptop) + lmass<MODEL>(dsg[j], p2[j], a.ptop));
             R va = 0;
-            if (kk[j] < K - 1) va += (R)mb[j] * (udn[j] - uk.v[j]);
-            if (kk[j] > 0) va += (R)mt[j] * (uk.v[j] - uup[j]);
+            if (v.k[j] < K - 1) va += (R)mb[j] * (udn[j] - uk.v[j]);
+            if (v.k[j] > 0) va += (R)mt[j] * (uk.v[j] - uup[j]);
             va = va / (R)(2.0 * dpe);
             adv[j] = adv[j] - va;
         }
@@ -615,47 +944,36 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
     const double dinv64 = m.e_dinv[e];
     double pgf[L];
     if constexpr (MODEL == MODEL_SW) {
-        const Pack<double, L> h1 = ldp<double, L>(a.ps_o + (long)c1 * M + mm0);
-        const Pack<double, L> h2 = ldp<double, L>(a.ps_o + (long)c2 * M + mm0);
+        double h1[L], h2[L];
+        ld2d<L, M1>(a.ps_o, c1, M, v.mm0, h1);
+        ld2d<L, M1>(a.ps_o, c2, M, v.mm0, h2);
+        const double b1 = a.b[c1], b2 = a.b[c2];
 #pragma unroll
-        for (int j = 0; j < L; j++) pgf[j] = -a.grav * ((h2.v[j] + a.b[c2]) - (h1.v[j] + a.b[c1])) * dinv64;
+        for (int j = 0; j < L; j++) pgf[j] = -a.grav * ((h2[j] + b2) - (h1[j] + b1)) * dinv64;
     } else {
         const long x1 = (long)c1 * KM + km0, x2 = (long)c2 * KM + km0;
         const Pack<double, L> al1 = ldp<double, L>(a.alpha + x1), al2 = ldp<double, L>(a.alpha + x2);
         const Pack<double, L> ph1 = ldp<double, L>(a.phim + x1), ph2 = ldp<double, L>(a.phim + x2);
         if constexpr (MODEL == MODEL_HDC) {
             double s1[L], s2[L];
-            if (m1) {
-#pragma unroll
-                for (int j = 0; j < L; j++) {
-                    s1[j] = a.ps_o[c1];
-                    s2[j] = a.ps_o[c2];
-                }
-            } else {
-                const Pack<double, L> q1 = ldp<double, L>(a.ps_o + (long)c1 * M + mm0);
-                const Pack<double, L> q2 = ldp<double, L>(a.ps_o + (long)c2 * M + mm0);
-#pragma unroll
-                for (int j = 0; j < L; j++) {
-                    s1[j] = q1.v[j];
-                    s2[j] = q2.v[j];
-                }
-            }
+            ld2d<L, M1>(a.ps_o, c1, M, v.mm0, s1);
+            ld2d<L, M1>(a.ps_o, c2, M, v.mm0, s2);
 #pragma unroll
             for (int j = 0; j < L; j++) {
-                const int k = kk[j];
-                const double p1 = 0.5 * ((a.ptop + a.sig[k] * (s1[j] - a.ptop)) + (a.ptop + a.sig[k + 1] * (s1[j] - a.ptop)));
-                const double p2 = 0.5 * ((a.ptop + a.sig[k] * (s2[j] - a.ptop)) + (a.ptop + a.sig[k + 1] * (s2[j] - a.ptop)));
+                const int k = v.k[j];
+                const double q1 = 0.5 * ((a.ptop + a.sig[k] * (s1[j] - a.ptop)) + (a.ptop + a.sig[k + 1] * (s1[j] - a.ptop)));
+                const double q2 = 0.5 * ((a.ptop + a.sig[k] * (s2[j] - a.ptop)) + (a.ptop + a.sig[k + 1] * (s2[j] - a.ptop)));
                 const double ae = 0.5 * (al1.v[j] + al2.v[j]);
-                pgf[j] = -(ae * (p2 - p1) + (ph2.v[j] - ph1.v[j])) * dinv64;
+                pgf[j] = -(ae * (q2 - q1) + (ph2.v[j] - ph1.v[j])) * dinv64;
             }
         } else {
-            const Pack<double, L> p1 = ldp<double, L>(a.pm + x1), p2 = ldp<double, L>(a.pm + x2);
+            const Pack<double, L> q1 = ldp<double, L>(a.pm + x1), q2 = ldp<double, L>(a.pm + x2);
             const Pack<double, L> u1 = ldp<double, L>(a.mum + x1), u2 = ldp<double, L>(a.mum + x2);
 #pragma unroll
             for (int j = 0; j < L; j++) {
                 const double ae = 0.5 * (al1.v[j] + al2.v[j]);
                 const double me = 0.5 * (u1.v[j] + u2.v[j]);
-                pgf[j] = -(ae * (p2.v[j] - p1.v[j]) + me * (ph2.v[j] - ph1.v[j])) * dinv64;
+                pgf[j] = -(ae * (q2.v[j] - q1.v[j]) + me * (ph2.v[j] - ph1.v[j])) * dinv64;
             }
         }
     }
@@ -684,7 +1002,7 @@ __global__ void k_shadows(StageArgs a) {
         const int i = (int)(idx / KM);
         const int km = (int)(idx - (long)i * KM);
         const int k = km / a.M, mm = km - k * a.M;
-        a.th32_o[idx] = (float)(a.Th_o[idx] / layer_mass<MODEL>(a, k, a.ps_o[(long)i * a.M + mm]));
+        a.th32_o[idx] = (float)(a.Th_o[idx] / lmass<MODEL>(a.dsig[k], a.ps_o[(long)i * a.M + mm], a.ptop));
     }
 }
 
@@ -693,67 +1011,64 @@ __global__ void k_shadows(StageArgs a) {
 // ---------------------------------------------------------------------------
 namespace {
 inline unsigned nblocks(long n, int b) { return (unsigned)((n + b - 1) / b); }
-// values per lane of the edge kernel: 2 when the (k, m) pairs split evenly
-inline int edge_values_per_lane(int K, int M) { return (M == 1 ? (K % 2 == 0) : (M % 2 == 0)) ? 2 : 1; }
 
-template <int MODEL, typename R>
+template <int MODEL, typename R, int L, bool M1>
 hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
     const int KM = a.K * a.M;
-    const int colthreads = a.cpb * KM;
+    const int lanes = KM / L;
+    const int colthreads = a.cpb * lanes;
     const unsigned colblocks = nblocks(a.mesh.N, a.cpb);
     const int fb = a.flat_block;
-    size_t lds_a = (size_t)a.cpb * KM * sizeof(double);
-    if (MODEL == MODEL_NDC) lds_a += (size_t)a.cpb * (a.K + 1) * a.M * sizeof(double);
-    size_t lds_b = (size_t)a.cpb * KM * sizeof(double);
-    if (MODEL == MODEL_NDC) lds_b = (size_t)a.cpb * (9 * KM + (a.K + 1) * a.M + KM) * sizeof(double);
+    const size_t lds_a = stage_lds_bytes(MODEL, KERNEL_CELL_A, a.cpb, a.K, a.M);
+    const size_t lds_b = stage_lds_bytes(MODEL, KERNEL_CELL_B, a.cpb, a.K, a.M);
     switch (which) {
     case KERNEL_CELL_A:
-        hipLaunchKernelGGL((k_cell_a<MODEL, R>), dim3(colblocks), dim3(colthreads), lds_a, s, a);
+        hipLaunchKernelGGL((k_cell_a<MODEL, R, L, M1>), dim3(colblocks), dim3(colthreads), lds_a, s, a);
         break;
     case KERNEL_VERTEX:
-        hipLaunchKernelGGL((k_vertex<MODEL, R>), dim3(nblocks((long)a.mesh.V * KM, fb)), dim3(fb), 0, s, a);
+        hipLaunchKernelGGL((k_vertex<MODEL, R, L, M1>), dim3(nblocks((long)a.mesh.V * lanes, fb)), dim3(fb), 0, s, a);
         break;
     case KERNEL_CELL_B:
-        if (MODEL == MODEL_SW) return hipSuccess;
-        hipLaunchKernelGGL((k_cell_b<MODEL, R>), dim3(colblocks), dim3(colthreads), lds_b, s, a);
+        hipLaunchKernelGGL((k_cell_b<MODEL, R, L, M1>), dim3(colblocks), dim3(colthreads), lds_b, s, a);
         break;
-    case KERNEL_EDGE: {
-        const int L = edge_values_per_lane(a.K, a.M);
-        const long n = (long)a.mesh.E * (KM / L);
-        const bool one = (a.M == 1);
-        if (L == 2 && one)
-            hipLaunchKernelGGL((k_edge<MODEL, R, 2, true>), dim3(nblocks(n, fb)), dim3(fb), 0, s, a);
-        else if (L == 2)
-            hipLaunchKernelGGL((k_edge<MODEL, R, 2, false>), dim3(nblocks(n, fb)), dim3(fb), 0, s, a);
-        else if (one)
-            hipLaunchKernelGGL((k_edge<MODEL, R, 1, true>), dim3(nblocks(n, fb)), dim3(fb), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_edge<MODEL, R, 1, false>), dim3(nblocks(n, fb)), dim3(fb), 0, s, a);
+    case KERNEL_EDGE:
+        hipLaunchKernelGGL((k_edge<MODEL, R, L, M1>), dim3(nblocks((long)a.mesh.E * lanes, fb)), dim3(fb), 0, s, a);
         break;
-    }
     default:
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
+
+template <int MODEL, typename R>
+hipError_t launch_stage_r(const StageArgs &a, int which, hipStream_t s) {
+    const int L = values_per_lane(a.K, a.M);
+    if (a.M == 1) return L == 2 ? launch_stage_t<MODEL, R, 2, true>(a, which, s) : launch_stage_t<MODEL, R, 1, true>(a, which, s);
+    return L == 2 ? launch_stage_t<MODEL, R, 2, false>(a, which, s) : launch_stage_t<MODEL, R, 1, false>(a, which, s);
+}
 }  // namespace
+
+int values_per_lane(int K, int M) { return (M == 1 ? (K % 2 == 0) : (M % 2 == 0)) ? 2 : 1; }
 
 size_t stage_lds_bytes(int model, int which, int cpb, int K, int M) {
     const size_t KM = (size_t)K * M;
     if (which == KERNEL_CELL_A) return cpb * KM * 8 + (model == MODEL_NDC ? cpb * (K + 1) * (size_t)M * 8 : 0);
-    if (which == KERNEL_CELL_B) return model == MODEL_NDC ? cpb * (10 * KM + (K + 1) * (size_t)M) * 8 : cpb * KM * 8;
+    if (which == KERNEL_CELL_B) {
+        if (model == MODEL_SW) return 0;
+        return model == MODEL_NDC ? cpb * (10 * KM + (K + 1) * (size_t)M) * 8 : cpb * KM * 8;
+    }
     return 0;
 }
 
 hipError_t launch_stage_kernel(int model, int policy, const StageArgs &a, int which, hipStream_t s) {
     if (policy == POLICY_DBL) {
-        if (model == MODEL_SW) return launch_stage_t<MODEL_SW, double>(a, which, s);
-        if (model == MODEL_HDC) return launch_stage_t<MODEL_HDC, double>(a, which, s);
-        return launch_stage_t<MODEL_NDC, double>(a, which, s);
+        if (model == MODEL_SW) return launch_stage_r<MODEL_SW, double>(a, which, s);
+        if (model == MODEL_HDC) return launch_stage_r<MODEL_HDC, double>(a, which, s);
+        return launch_stage_r<MODEL_NDC, double>(a, which, s);
     }
-    if (model == MODEL_SW) return launch_stage_t<MODEL_SW, float>(a, which, s);
-    if (model == MODEL_HDC) return launch_stage_t<MODEL_HDC, float>(a, which, s);
-    return launch_stage_t<MODEL_NDC, float>(a, which, s);
+    if (model == MODEL_SW) return launch_stage_r<MODEL_SW, float>(a, which, s);
+    if (model == MODEL_HDC) return launch_stage_r<MODEL_HDC, float>(a, which, s);
+    return launch_stage_r<MODEL_NDC, float>(a, which, s);
 }
 
 hipError_t launch_shadows(int model, const StageArgs &a, hipStream_t s) {

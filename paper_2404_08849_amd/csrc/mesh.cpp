@@ -155,8 +155,11 @@ std::string derive_tables(const mpdc_mesh_desc *d, HostTables &t) {
     // ---- cells: slots, signs, divergence and kinetic-energy weights ----
     t.c_edge.assign(N * S, -1);
     t.c_nbr.assign(N * S, 0);
+    t.c_vert.assign(N * S, 0);
     t.c_div.assign(N * S, 0.0);
     t.c_ke.assign(N * S, 0.0);
+    t.c_gk.assign(N * S, 0.0);
+    t.c_tk.assign(N * S * S, 0.0);
     t.c_area.assign(d->areaCell, d->areaCell + N);
     t.cells_on_cell.assign(2 * E, 0);
     t.edge_sign.assign(2 * E, 0.0);
@@ -171,12 +174,16 @@ std::string derive_tables(const mpdc_mesh_desc *d, HostTables &t) {
             int nb = first ? ce[2 * e + 1] : ce[2 * e];
             t.c_edge[i * S + j] = e;
             t.c_nbr[i * S + j] = nb;
+            t.c_vert[i * S + j] = vc[off[i] + j];
             t.c_div[i * S + j] = s * d->lEdge[e] / d->areaCell[i];
             t.c_ke[i * S + j] = 0.25 * d->lEdge[e] * d->dEdge[e] / d->areaCell[i];
+            t.c_gk[i * S + j] = s / d->dEdge[e];
             t.cells_on_cell[off[i] + j] = nb;
             t.edge_sign[off[i] + j] = s;
             slot_of[2 * e + (first ? 0 : 1)] = j;
         }
+        // a pentagon's sixth vertex slot repeats vertex 0, so edge 4 joins slots 4 and 5
+        for (int j = n; j < S; j++) t.c_vert[i * S + j] = vc[off[i]];
     }
 
     // ---- kite fractions R_{i,v}/A_i around each cell, in CSR order ----
@@ -193,8 +200,6 @@ std::string derive_tables(const mpdc_mesh_desc *d, HostTables &t) {
 
     // ---- TRiSK: for edge e and each of its cells, the cell's other edges
     //      counter-clockwise from e with w = s_{e,i} s_{e',i} (1/2 - S_j) ----
-    t.e_tk.assign(E * kTriskSlots, -1);
-    t.e_tkw.assign(E * kTriskSlots, 0.0);
     t.trisk_off.assign(E + 1, 0);
     t.trisk_edge.clear();
     t.trisk_w.clear();
@@ -219,8 +224,8 @@ std::string derive_tables(const mpdc_mesh_desc *d, HostTables &t) {
                 double s_epi = (ce[2 * ep] == i) ? 1.0 : -1.0;
                 double w = s_ei * s_epi * (0.5 - acc);
                 if (pos >= kTriskSlots) return msg("TRiSK stencil wider than 10 edges", e);
-                t.e_tk[e * kTriskSlots + pos] = ep;
-                t.e_tkw[e * kTriskSlots + pos] = w * d->lEdge[ep] / d->dEdge[e];
+                // cell i's half-stencil row of edge e (slot j0), column slot j
+                t.c_tk[(i * S + j0) * S + j] = w * d->lEdge[ep] / d->dEdge[e];
                 t.trisk_edge.push_back(ep);
                 t.trisk_w.push_back(w);
                 pos++;
@@ -292,20 +297,25 @@ std::string derive_tables(const mpdc_mesh_desc *d, HostTables &t) {
         }
 
     // ---- vertices ----
-    t.v_edge.assign(ev, ev + 3 * V);
-    t.v_cell.assign(cv, cv + 3 * V);
-    t.v_curl.resize(3 * V);
-    t.v_kite.resize(3 * V);
+    t.v_edge.assign(4 * V, 0);
+    t.v_cell.assign(4 * V, 0);
+    t.v_curl.assign(4 * V, 0.0);
+    t.v_kite.assign(4 * V, 0.0);
     t.v_f.assign(d->fVertex, d->fVertex + V);
     t.vertex_sign.resize(3 * V);
-    for (long v = 0; v < V; v++)
+    for (long v = 0; v < V; v++) {
         for (int j = 0; j < 3; j++) {
             int e = ev[3 * v + j];
             double s = (ve[2 * e + 1] == v) ? 1.0 : -1.0;
             t.vertex_sign[3 * v + j] = s;
-            t.v_curl[3 * v + j] = s * d->dEdge[e] / d->areaVertex[v];
-            t.v_kite[3 * v + j] = d->kiteArea[3 * v + j] / d->areaVertex[v];
+            t.v_edge[4 * v + j] = e;
+            t.v_cell[4 * v + j] = cv[3 * v + j];
+            t.v_curl[4 * v + j] = s * d->dEdge[e] / d->areaVertex[v];
+            t.v_kite[4 * v + j] = d->kiteArea[3 * v + j] / d->areaVertex[v];
         }
+        t.v_edge[4 * v + 3] = ev[3 * v];   // pad: valid index, zero weight
+        t.v_cell[4 * v + 3] = cv[3 * v];
+    }
     return "";
 }
 

@@ -25,15 +25,20 @@ constexpr int kTriskSlots = 10;
 // Device view of the mesh tables (pointers into the caller's workspace).
 struct DevMesh {
     int N, E, V;
-    // cells
+    // cells: 6 slots, counter-clockwise, pentagons padded
     const int *c_edge;      // [N][6] edge of slot j (-1 pad)
     const int *c_nbr;       // [N][6] neighbour across slot j (self for pads)
+    const int *c_vert;      // [N][6] vertex j, between edges j-1 and j (pentagon pad = vertex 0)
     const double *c_div;    // [N][6] s_{e,i} l_e / A_i
     const float *c_div32;
     const double *c_ke;     // [N][6] l_e d_e / (4 A_i)
     const float *c_ke32;
+    const double *c_gk;     // [N][6] s_{e,i} / d_e   (cell i's share of -grad K on edge j)
+    const float *c_gk32;
     const double *c_hess;   // [N][3][6] slot differences -> (Hxx, Hxy, Hyy)
     const float *c_hess32;
+    const double *c_tk;     // [N][6][6] TRiSK half-stencil: w_{e_j,e_j'} l_{e_j'} / d_{e_j} from cell i
+    const float *c_tk32;
     const double *c_area;   // [N]
     // edges
     const int *e_cell;      // [E][2]
@@ -44,15 +49,12 @@ struct DevMesh {
     const float *e_d2_32;
     const double *e_hdir;   // [E][2][3] (c^2, 2cs, s^2) of the neighbour direction in c1's / c2's frame
     const float *e_hdir32;
-    const int *e_tk;        // [E][10] TRiSK edges (-1 pad)
-    const double *e_tkw;    // [E][10] w_{e,e'} l_{e'} / d_e
-    const float *e_tkw32;
-    // vertices
-    const int *v_edge;      // [V][3]
-    const int *v_cell;      // [V][3]
-    const double *v_curl;   // [V][3] s'_{e,v} d_e / A_v
+    // vertices (padded to 4)
+    const int *v_edge;      // [V][4]
+    const int *v_cell;      // [V][4]
+    const double *v_curl;   // [V][4] s'_{e,v} d_e / A_v
     const float *v_curl32;
-    const double *v_kite;   // [V][3] R_{i,v} / A_v
+    const double *v_kite;   // [V][4] R_{i,v} / A_v
     const double *v_f;      // [V]
 };
 
@@ -92,13 +94,12 @@ int fail(int code, const std::string &msg);
 
 // Table derivation (host, FP64); returns "" or an error message.
 struct HostTables {
-    std::vector<int> c_edge, c_nbr;
-    std::vector<double> c_div, c_ke, c_hess, c_area;
+    std::vector<int> c_edge, c_nbr, c_vert;
+    std::vector<double> c_div, c_ke, c_gk, c_hess, c_tk, c_area;
     std::vector<int> e_cell, e_vert;
-    std::vector<double> e_dinv, e_d2, e_hdir, e_tkw;
-    std::vector<int> e_tk;
-    std::vector<int> v_edge, v_cell;
-    std::vector<double> v_curl, v_kite, v_f;
+    std::vector<double> e_dinv, e_d2, e_hdir;
+    std::vector<int> v_edge, v_cell;              // [V][4]
+    std::vector<double> v_curl, v_kite, v_f;      // [V][4], [V][4], [V]
     // exported (reference-form) tables
     std::vector<int> cells_on_cell, trisk_off, trisk_edge;
     std::vector<double> edge_sign, vertex_sign, trisk_w, hessian;

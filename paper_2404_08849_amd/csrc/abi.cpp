@@ -218,9 +218,7 @@ int col_lanes(const mpdc_state *st) { return st->K * st->M / values_per_lane(st-
 
 int auto_cpb(const mpdc_state *st) {
     const int lanes = col_lanes(st);
-    int c = std::max(1, 256 / lanes);
-    while (c > 1 && c * lanes > 1024) c--;
-    return c;
+    return std::max(1, 256 / lanes);
 }
 
 int cpb_of(const mpdc_state *st) {
@@ -534,8 +532,8 @@ static int check_config(const mpdc_mesh *m, const mpdc_config *c) {
     if (c->model == MPDC_MODEL_NDC && c->K < 2) return fail(MPDC_E_UNSUPPORTED, "the NH column solve needs K >= 2");
     if (c->model == MPDC_MODEL_TRACER && (c->T < 1 || c->M != 1))
         return fail(MPDC_E_UNSUPPORTED, "tracer transport needs T >= 1 and M = 1");
-    if ((long)c->K * c->M > 1024 && c->model != MPDC_MODEL_TRACER)
-        return fail(MPDC_E_UNSUPPORTED, "a column (K*M) must fit one work-group of 1024 lanes");
+    if ((long)c->K * c->M / values_per_lane(c->K, c->M) > kColumnThreads && c->model != MPDC_MODEL_TRACER)
+        return fail(MPDC_E_UNSUPPORTED, "a column (K*M values, two per lane) must fit one work-group of 512 lanes");
     if (!(c->dt > 0)) return fail(MPDC_E_INVAL, "dt must be positive");
     if (c->model != MPDC_MODEL_SW) {
         if (!c->sigma) return fail(MPDC_E_INVAL, "sigma interfaces required");
@@ -675,9 +673,11 @@ int mpdc_set_launch(mpdc_state *st, int cells_per_block, int flat_block) {
     if (!st) return fail(MPDC_E_INVAL, "null state");
     if (flat_block == 0) flat_block = 256;
     if (flat_block < 64 || flat_block > 1024 || flat_block % 64) return fail(MPDC_E_INVAL, "flat block must be 64..1024, a multiple of 64");
+    if (st->model == MPDC_MODEL_TRACER && flat_block > kTracerThreads)
+        return fail(MPDC_E_INVAL, "tracer work-groups hold at most 512 lanes");
     if (cells_per_block < 0 ||
-        (st->model != MPDC_MODEL_TRACER && (long)cells_per_block * col_lanes(st) > 1024))
-        return fail(MPDC_E_INVAL, "cells per block times the column's lanes must be at most 1024");
+        (st->model != MPDC_MODEL_TRACER && (long)cells_per_block * col_lanes(st) > kColumnThreads))
+        return fail(MPDC_E_INVAL, "cells per block times the column's lanes must be at most 512");
     if (st->model == MPDC_MODEL_NDC && cells_per_block > 0 &&
         stage_lds_bytes(st->model, KERNEL_CELL_B, cells_per_block, st->K, st->M) > 65536)
         return fail(MPDC_E_INVAL, "column kernel would need more than 64 KiB of LDS");
@@ -878,6 +878,7 @@ int mpdc_autotune(mpdc_state *st, void *stream, int *cells_per_block, int *flat_
     double best_flat_ms = 1e30, best_col_ms = 1e30;
     int best_flat = keep.flat_block, best_cpb = keep.cells_per_block;
     for (int fb : flats) {
+        if (tr && fb > kTracerThreads) continue;
         st->launch.flat_block = fb;
         double t = 0, ms = 0;
         int rc = MPDC_OK;
@@ -893,7 +894,7 @@ int mpdc_autotune(mpdc_state *st, void *stream, int *cells_per_block, int *flat_
     st->launch.flat_block = best_flat;
     if (!tr) {
         for (int c : cpbs) {
-            if ((long)c * col_lanes(st) > 1024) continue;
+            if ((long)c * col_lanes(st) > kColumnThreads) continue;
             if (stage_lds_bytes(st->model, KERNEL_CELL_B, c, st->K, st->M) > 65536) continue;
             st->launch.cells_per_block = c;
             double t = 0, ms = 0;

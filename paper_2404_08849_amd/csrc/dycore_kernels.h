@@ -10,6 +10,8 @@ namespace mpdc {
 enum { MODEL_SW = MPDC_MODEL_SW, MODEL_HDC = MPDC_MODEL_HDC, MODEL_NDC = MPDC_MODEL_NDC };
 enum { POLICY_DBL = MPDC_POLICY_DBL, POLICY_MIX = MPDC_POLICY_MIX };
 enum { KERNEL_CELL_A = 0, KERNEL_VERTEX = 1, KERNEL_CELL_B = 2, KERNEL_EDGE = 3 };
+// largest work-group of the column kernels (keeps 256 VGPRs available per lane)
+constexpr int kColumnThreads = 512;
 
 // Everything one dycore stage reads and writes.  Pointers of another model
 // or policy are null.  "_n": state at the start of the step; "_s": state of
@@ -56,6 +58,8 @@ int values_per_lane(int K, int M);
 
 // ---- tracer transport ----
 enum { TKERNEL_LOW = 0, TKERNEL_LIMIT = 1, TKERNEL_UPDATE = 2 };
+// largest work-group of the tracer kernels
+constexpr int kTracerThreads = 512;
 
 struct TracerArgs {
     DevMesh mesh;

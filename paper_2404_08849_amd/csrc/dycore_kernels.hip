@@ -163,7 +163,7 @@ template <int L> __device__ __forceinline__ ColLane col_lane(const StageArgs &a,
 // cell_a
 // ---------------------------------------------------------------------------
 template <int MODEL, typename R, int L, bool M1>
-__global__ void __launch_bounds__(1024) k_cell_a(StageArgs a) {
+__global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
     extern __shared__ double lds[];
     const DevMesh &m = a.mesh;
     const int K = a.K, M = M1 ? 1 : a.M, KM = K * M;
@@ -486,7 +486,7 @@ __global__ void __launch_bounds__(1024) k_vertex(StageArgs a) {
 // diagnostics or the NH column solve
 // ---------------------------------------------------------------------------
 template <int MODEL, typename R, int L, bool M1>
-__global__ void __launch_bounds__(1024) k_cell_b(StageArgs a) {
+__global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
     extern __shared__ double lds[];
     const DevMesh &m = a.mesh;
     const int K = a.K, M = M1 ? 1 : a.M, KM = K * M;

@@ -30,182 +30,282 @@ template <typename R> __device__ __forceinline__ R rinf();
 template <> __device__ __forceinline__ double rinf<double>() { return __builtin_huge_val(); }
 template <> __device__ __forceinline__ float rinf<float>() { return __builtin_huge_valf(); }
 
-struct TIdx {
-    int i, k, t;
-    long x;       // (i, k, t) linear index
+template <typename T, int L> struct alignas(sizeof(T) * L) TPack {
+    T v[L];
+};
+template <typename T, int L> __device__ __forceinline__ TPack<T, L> tld(const T *p) {
+    return *reinterpret_cast<const TPack<T, L> *>(p);
+}
+template <typename T, int L> __device__ __forceinline__ void tst(T *p, const TPack<T, L> &x) {
+    *reinterpret_cast<TPack<T, L> *>(p) = x;
+}
+template <typename T> __device__ __forceinline__ void tld6(const T *p, T out[6]) {
+    const TPack<T, 2> a = tld<T, 2>(p), b = tld<T, 2>(p + 2), c = tld<T, 2>(p + 4);
+    out[0] = a.v[0]; out[1] = a.v[1]; out[2] = b.v[0]; out[3] = b.v[1]; out[4] = c.v[0]; out[5] = c.v[1];
+}
+
+// One lane = L consecutive tracers of one (cell, level).
+struct TLane {
+    int i, k, t0;
+    long x;       // linear index of (i, k, t0)
     bool ok;
 };
-
-__device__ __forceinline__ TIdx tracer_index(const TracerArgs &a) {
-    TIdx r;
-    const int KT = a.K * a.T;
+template <int L> __device__ __forceinline__ TLane tracer_lane(const TracerArgs &a) {
+    TLane r;
+    const int lanes_k = a.T / L;
+    const int lanes = a.K * lanes_k;
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    r.ok = idx < (long)a.mesh.N * KT;
-    r.i = (int)(idx / KT);
-    const int kt = (int)(idx - (long)r.i * KT);
-    r.k = kt / a.T;
-    r.t = kt - r.k * a.T;
-    r.x = idx;
+    r.ok = idx < (long)a.mesh.N * lanes;
+    r.i = (int)(idx / lanes);
+    const int rem = (int)(idx - (long)r.i * lanes);
+    r.k = rem / lanes_k;
+    r.t0 = (rem - r.k * lanes_k) * L;
+    r.x = ((long)r.i * a.K + r.k) * a.T + r.t0;
     return r;
 }
 
-// divergence of the FP64 mass flux at (i, k): sum_j s l F / A
-__device__ __forceinline__ double div_F(const TracerArgs &a, int i, int k) {
+// Per-cell stencil shared by the three passes: edges, neighbours, outward
+// signs via the divergence weights, the FP64 mass flux of each edge and the
+// layer mass after this stage's FP64 continuity step.
+template <typename R> struct Stencil {
+    int ce[6], cn[6];
+    R cdiv[6];
+    double F[6];
+    double dpi_n, dpin;
+};
+template <typename R>
+__device__ __forceinline__ void load_stencil(const TracerArgs &a, int i, int k, Stencil<R> &st) {
     const DevMesh &m = a.mesh;
+    tld6<int>(m.c_edge + (long)i * kCellSlots, st.ce);
+    tld6<int>(m.c_nbr + (long)i * kCellSlots, st.cn);
+    tld6<R>(tpick<R>(m.c_div, m.c_div32) + (long)i * kCellSlots, st.cdiv);
+    double c64[6];
+    tld6<double>(m.c_div + (long)i * kCellSlots, c64);
     double d = 0.0;
 #pragma unroll
-    for (int j = 0; j < kCellSlots; j++) {
-        const int e = m.c_edge[(long)i * kCellSlots + j];
-        if (e < 0) continue;
-        d += m.c_div[(long)i * kCellSlots + j] * a.F[(long)e * a.K + k];
+    for (int s = 0; s < kCellSlots; s++) {
+        st.F[s] = (st.ce[s] >= 0) ? a.F[(long)st.ce[s] * a.K + k] : 0.0;
+        d += c64[s] * st.F[s];
     }
-    return d;
+    st.dpi_n = a.dpi_n[(long)i * a.K + k];
+    st.dpin = st.dpi_n - a.dts * d;
 }
 
-// low-order (upwind) flux and antidiffusive flux A = F q~ - F^L of edge e,
-// seen from cell i (slot j).  q~ is the third-order upwind edge value of q_s.
-template <typename R>
-__device__ __forceinline__ void edge_fluxes(const TracerArgs &a, int i, int e, int nb, int k, int t, R &FL, R &Aa) {
+// Low-order (upwind) flux and antidiffusive flux A = F q~ - F^L of the edge in
+// slot s of cell i, for L tracers.  q~ is the third-order upwind edge value of
+// q_s built from both cells' second derivatives along the edge direction.
+template <typename R, int L>
+__device__ __forceinline__ void edge_fluxes(const TracerArgs &a, const Stencil<R> &st, int s, int i, int k, int t0,
+                                            const R qn_i[L], const R qs_i[L], const R Hi[3][L], R FL[L], R Aa[L]) {
     const DevMesh &m = a.mesh;
     const int KT = a.K * a.T;
-    const R *qn = (const R *)a.q_n;
-    const R *qs = (const R *)a.q_s;
-    const R *H = (const R *)a.hq;
-    const int side = (m.e_cell[2 * (long)e] == i) ? 0 : 1;
-    const int c1 = side ? nb : i, c2 = side ? i : nb;
-    const double Fd = a.F[(long)e * a.K + k];
-    const R F = (R)Fd;
-    const long o1 = (long)c1 * KT + (long)k * a.T + t, o2 = (long)c2 * KT + (long)k * a.T + t;
-    FL = F * ((Fd >= 0.0) ? qn[o1] : qn[o2]);
-    const R *hdir = tpick<R>(m.e_hdir, m.e_hdir32) + (long)e * 6;
-    const long h1 = (long)c1 * 3 * KT + (long)k * a.T + t, h2 = (long)c2 * 3 * KT + (long)k * a.T + t;
-    const R q1d = H[h1] * hdir[0] + H[h1 + KT] * hdir[1] + H[h1 + 2 * KT] * hdir[2];
-    const R q2d = H[h2] * hdir[3] + H[h2 + KT] * hdir[4] + H[h2 + 2 * KT] * hdir[5];
+    const int e = st.ce[s], nb = st.cn[s];
+    const bool self_c1 = st.cdiv[s] > (R)0;
+    const long on = (long)nb * KT + (long)k * a.T + t0;
+    const TPack<R, L> qn_n = tld<R, L>((const R *)a.q_n + on);
+    const TPack<R, L> qs_n = tld<R, L>((const R *)a.q_s + on);
+    const R *Hb = (const R *)a.hq + (long)nb * 3 * KT + (long)k * a.T + t0;
+    const TPack<R, L> h0 = tld<R, L>(Hb), h1 = tld<R, L>(Hb + KT), h2 = tld<R, L>(Hb + 2 * KT);
+    R hd[6];
+    tld6<R>(tpick<R>(m.e_hdir, m.e_hdir32) + (long)e * 6, hd);
     const R c = tpick<R>(m.e_d2, m.e_d2_32)[e];
+    const double Fd = st.F[s];
+    const R F = (R)Fd;
     const R sg = (Fd >= 0.0) ? (R)1 : (R)-1;
-    const R qe = (R)0.5 * (qs[o1] + qs[o2]) - c * (q1d + q2d) + sg * c * (q2d - q1d);
-    Aa = F * qe - FL;
+    // frame directions: c1 uses hd[0..2], c2 uses hd[3..5]
+    const R *di = self_c1 ? hd : hd + 3;
+    const R *dn = self_c1 ? hd + 3 : hd;
+#pragma unroll
+    for (int j = 0; j < L; j++) {
+        const R qid = Hi[0][j] * di[0] + Hi[1][j] * di[1] + Hi[2][j] * di[2];
+        const R qnd = h0.v[j] * dn[0] + h1.v[j] * dn[1] + h2.v[j] * dn[2];
+        const R q1 = self_c1 ? qs_i[j] : qs_n.v[j], q2 = self_c1 ? qs_n.v[j] : qs_i[j];
+        const R d1 = self_c1 ? qid : qnd, d2 = self_c1 ? qnd : qid;
+        const R up1 = self_c1 ? qn_i[j] : qn_n.v[j], up2 = self_c1 ? qn_n.v[j] : qn_i[j];
+        FL[j] = F * ((Fd >= 0.0) ? up1 : up2);
+        const R qe = (R)0.5 * (q1 + q2) - c * (d1 + d2) + sg * c * (d2 - d1);
+        Aa[j] = F * qe - FL[j];
+    }
 }
 
-template <typename R>
-__global__ void __launch_bounds__(1024) k_tr_low(TracerArgs a) {
-    const TIdx ix = tracer_index(a);
-    if (!ix.ok) return;
+template <typename R, int L>
+__global__ void __launch_bounds__(kTracerThreads) k_tr_low(TracerArgs a) {
+    const TLane ln = tracer_lane<L>(a);
+    if (!ln.ok) return;
     const DevMesh &m = a.mesh;
     const int KT = a.K * a.T;
-    const int i = ix.i, k = ix.k, t = ix.t;
+    const int i = ln.i, k = ln.k, t0 = ln.t0;
+    Stencil<R> st;
+    load_stencil<R>(a, i, k, st);
     const R *qn = (const R *)a.q_n;
     const R *qs = (const R *)a.q_s;
-    const R *cdiv = tpick<R>(m.c_div, m.c_div32) + (long)i * kCellSlots;
-    const R *ch = tpick<R>(m.c_hess, m.c_hess32) + (long)i * 3 * kCellSlots;
-    const double dpi_n = a.dpi_n[(long)i * a.K + k];
-    const double dpin = dpi_n - a.dts * div_F(a, i, k);
-    const R qni = qn[ix.x], qsi = qs[ix.x];
-    R dL = 0, h0 = 0, h1 = 0, h2 = 0;
+    R ch[3][6];
+    const R *chp = tpick<R>(m.c_hess, m.c_hess32) + (long)i * 3 * kCellSlots;
+    tld6<R>(chp, ch[0]);
+    tld6<R>(chp + kCellSlots, ch[1]);
+    tld6<R>(chp + 2 * kCellSlots, ch[2]);
+    const TPack<R, L> qni = tld<R, L>(qn + ln.x), qsi = tld<R, L>(qs + ln.x);
+    R dL[L], h[3][L];
 #pragma unroll
-    for (int j = 0; j < kCellSlots; j++) {
-        const int nb = m.c_nbr[(long)i * kCellSlots + j];
-        const long on = (long)nb * KT + (long)k * a.T + t;
-        const R dq = qs[on] - qsi;
-        h0 += ch[j] * dq;
-        h1 += ch[kCellSlots + j] * dq;
-        h2 += ch[2 * kCellSlots + j] * dq;
-        const int e = m.c_edge[(long)i * kCellSlots + j];
-        if (e < 0) continue;
-        const double Fd = a.F[(long)e * a.K + k];
-        const bool up_self = (Fd >= 0.0) == (m.e_cell[2 * (long)e] == i);
-        dL += cdiv[j] * ((R)Fd * (up_self ? qni : qn[on]));
+    for (int j = 0; j < L; j++) dL[j] = h[0][j] = h[1][j] = h[2][j] = 0;
+#pragma unroll
+    for (int s = 0; s < kCellSlots; s++) {
+        if (st.ce[s] < 0) continue;
+        const long on = (long)st.cn[s] * KT + (long)k * a.T + t0;
+        const TPack<R, L> qsn = tld<R, L>(qs + on), qnn = tld<R, L>(qn + on);
+        const double Fd = st.F[s];
+        const bool up_self = (Fd >= 0.0) == (st.cdiv[s] > (R)0);
+#pragma unroll
+        for (int j = 0; j < L; j++) {
+            const R dq = qsn.v[j] - qsi.v[j];
+            h[0][j] += ch[0][s] * dq;
+            h[1][j] += ch[1][s] * dq;
+            h[2][j] += ch[2][s] * dq;
+            dL[j] += st.cdiv[s] * ((R)Fd * (up_self ? qni.v[j] : qnn.v[j]));
+        }
     }
-    R *H = (R *)a.hq + (long)i * 3 * KT + (long)k * a.T + t;
-    H[0] = h0;
-    H[KT] = h1;
-    H[2 * KT] = h2;
-    ((R *)a.qtd)[ix.x] = ((R)dpi_n * qni - (R)a.dts * dL) / (R)dpin;
+    R *H = (R *)a.hq + (long)i * 3 * KT + (long)k * a.T + t0;
+    TPack<R, L> p0, p1, p2, qt;
+#pragma unroll
+    for (int j = 0; j < L; j++) {
+        p0.v[j] = h[0][j];
+        p1.v[j] = h[1][j];
+        p2.v[j] = h[2][j];
+        qt.v[j] = ((R)st.dpi_n * qni.v[j] - (R)a.dts * dL[j]) / (R)st.dpin;
+    }
+    tst<R, L>(H, p0);
+    tst<R, L>(H + KT, p1);
+    tst<R, L>(H + 2 * KT, p2);
+    tst<R, L>((R *)a.qtd + ln.x, qt);
 }
 
-template <typename R>
-__global__ void __launch_bounds__(1024) k_tr_limit(TracerArgs a) {
-    const TIdx ix = tracer_index(a);
-    if (!ix.ok) return;
-    const DevMesh &m = a.mesh;
+template <typename R, int L>
+__device__ __forceinline__ void load_own(const TracerArgs &a, const TLane &ln, R qn_i[L], R qs_i[L], R Hi[3][L]) {
     const int KT = a.K * a.T;
-    const int i = ix.i, k = ix.k, t = ix.t;
+    const TPack<R, L> qn = tld<R, L>((const R *)a.q_n + ln.x), qs = tld<R, L>((const R *)a.q_s + ln.x);
+    const R *Hb = (const R *)a.hq + (long)ln.i * 3 * KT + (long)ln.k * a.T + ln.t0;
+    const TPack<R, L> h0 = tld<R, L>(Hb), h1 = tld<R, L>(Hb + KT), h2 = tld<R, L>(Hb + 2 * KT);
+#pragma unroll
+    for (int j = 0; j < L; j++) {
+        qn_i[j] = qn.v[j];
+        qs_i[j] = qs.v[j];
+        Hi[0][j] = h0.v[j];
+        Hi[1][j] = h1.v[j];
+        Hi[2][j] = h2.v[j];
+    }
+}
+
+template <typename R, int L>
+__global__ void __launch_bounds__(kTracerThreads) k_tr_limit(TracerArgs a) {
+    const TLane ln = tracer_lane<L>(a);
+    if (!ln.ok) return;
+    const int KT = a.K * a.T;
+    const int i = ln.i, k = ln.k, t0 = ln.t0;
+    Stencil<R> st;
+    load_stencil<R>(a, i, k, st);
+    R qn_i[L], qs_i[L], Hi[3][L];
+    load_own<R, L>(a, ln, qn_i, qs_i, Hi);
     const R *qn = (const R *)a.q_n;
     const R *qtd = (const R *)a.qtd;
-    const R *cdiv = tpick<R>(m.c_div, m.c_div32) + (long)i * kCellSlots;
-    const double dpin = a.dpi_n[(long)i * a.K + k] - a.dts * div_F(a, i, k);
-    const R qtdi = qtd[ix.x];
-    R qmax = qn[ix.x] > qtdi ? qn[ix.x] : qtdi;
-    R qmin = qn[ix.x] < qtdi ? qn[ix.x] : qtdi;
-    R Pp = 0, Pm = 0;
+    const TPack<R, L> qti = tld<R, L>(qtd + ln.x);
+    R qmax[L], qmin[L], Pp[L], Pm[L];
 #pragma unroll
-    for (int j = 0; j < kCellSlots; j++) {
-        const int e = m.c_edge[(long)i * kCellSlots + j];
-        if (e < 0) continue;
-        const int nb = m.c_nbr[(long)i * kCellSlots + j];
-        const long on = (long)nb * KT + (long)k * a.T + t;
-        qmax = fmax(qmax, fmax(qn[on], qtd[on]));
-        qmin = fmin(qmin, fmin(qn[on], qtd[on]));
-        R FL, Aa;
-        edge_fluxes<R>(a, i, e, nb, k, t, FL, Aa);
-        const R fo = cdiv[j] * Aa;
-        if (fo < (R)0) Pp -= fo;
-        if (fo > (R)0) Pm += fo;
+    for (int j = 0; j < L; j++) {
+        qmax[j] = qn_i[j] > qti.v[j] ? qn_i[j] : qti.v[j];
+        qmin[j] = qn_i[j] < qti.v[j] ? qn_i[j] : qti.v[j];
+        Pp[j] = Pm[j] = 0;
     }
-    if (!a.fct) {
-        qmax = rinf<R>();
-        qmin = -rinf<R>();
+#pragma unroll
+    for (int s = 0; s < kCellSlots; s++) {
+        if (st.ce[s] < 0) continue;
+        const long on = (long)st.cn[s] * KT + (long)k * a.T + t0;
+        const TPack<R, L> qnn = tld<R, L>(qn + on), qtn = tld<R, L>(qtd + on);
+        R FL[L], Aa[L];
+        edge_fluxes<R, L>(a, st, s, i, k, t0, qn_i, qs_i, Hi, FL, Aa);
+#pragma unroll
+        for (int j = 0; j < L; j++) {
+            qmax[j] = fmax(qmax[j], fmax(qnn.v[j], qtn.v[j]));
+            qmin[j] = fmin(qmin[j], fmin(qnn.v[j], qtn.v[j]));
+            const R fo = st.cdiv[s] * Aa[j];
+            if (fo < (R)0) Pp[j] -= fo;
+            if (fo > (R)0) Pm[j] += fo;
+        }
     }
-    const R rdt = (R)(dpin / a.dts);
-    const R Qp = (qmax - qtdi) * rdt, Qm = (qtdi - qmin) * rdt;
-    ((R *)a.rp)[ix.x] = (Pp > (R)0) ? fmin((R)1, Qp / Pp) : (R)0;
-    ((R *)a.rm)[ix.x] = (Pm > (R)0) ? fmin((R)1, Qm / Pm) : (R)0;
+    const R rdt = (R)(st.dpin / a.dts);
+    TPack<R, L> rp, rm;
+#pragma unroll
+    for (int j = 0; j < L; j++) {
+        if (!a.fct) {
+            qmax[j] = rinf<R>();
+            qmin[j] = -rinf<R>();
+        }
+        const R Qp = (qmax[j] - qti.v[j]) * rdt, Qm = (qti.v[j] - qmin[j]) * rdt;
+        rp.v[j] = (Pp[j] > (R)0) ? fmin((R)1, Qp / Pp[j]) : (R)0;
+        rm.v[j] = (Pm[j] > (R)0) ? fmin((R)1, Qm / Pm[j]) : (R)0;
+    }
+    tst<R, L>((R *)a.rp + ln.x, rp);
+    tst<R, L>((R *)a.rm + ln.x, rm);
 }
 
-template <typename R>
-__global__ void __launch_bounds__(1024) k_tr_update(TracerArgs a) {
-    const TIdx ix = tracer_index(a);
-    if (!ix.ok) return;
-    const DevMesh &m = a.mesh;
+template <typename R, int L>
+__global__ void __launch_bounds__(kTracerThreads) k_tr_update(TracerArgs a) {
+    const TLane ln = tracer_lane<L>(a);
+    if (!ln.ok) return;
     const int KT = a.K * a.T;
-    const int i = ix.i, k = ix.k, t = ix.t;
-    const R *qn = (const R *)a.q_n;
+    const int i = ln.i, k = ln.k, t0 = ln.t0;
+    Stencil<R> st;
+    load_stencil<R>(a, i, k, st);
+    R qn_i[L], qs_i[L], Hi[3][L];
+    load_own<R, L>(a, ln, qn_i, qs_i, Hi);
     const R *rp = (const R *)a.rp;
     const R *rm = (const R *)a.rm;
-    const R *cdiv = tpick<R>(m.c_div, m.c_div32) + (long)i * kCellSlots;
-    const double dpi_n = a.dpi_n[(long)i * a.K + k];
-    const double dpin = dpi_n - a.dts * div_F(a, i, k);
-    R dT = 0;
+    const TPack<R, L> rpi = tld<R, L>(rp + ln.x), rmi = tld<R, L>(rm + ln.x);
+    R dT[L];
 #pragma unroll
-    for (int j = 0; j < kCellSlots; j++) {
-        const int e = m.c_edge[(long)i * kCellSlots + j];
-        if (e < 0) continue;
-        const int nb = m.c_nbr[(long)i * kCellSlots + j];
-        R FL, Aa;
-        edge_fluxes<R>(a, i, e, nb, k, t, FL, Aa);
-        const bool self_c1 = (m.e_cell[2 * (long)e] == i);
-        const long oi = ix.x, on = (long)nb * KT + (long)k * a.T + t;
-        const long o1 = self_c1 ? oi : on, o2 = self_c1 ? on : oi;
-        const R C = (Aa >= (R)0) ? fmin(rp[o2], rm[o1]) : fmin(rp[o1], rm[o2]);
-        dT += cdiv[j] * (FL + C * Aa);
+    for (int j = 0; j < L; j++) dT[j] = 0;
+#pragma unroll
+    for (int s = 0; s < kCellSlots; s++) {
+        if (st.ce[s] < 0) continue;
+        const long on = (long)st.cn[s] * KT + (long)k * a.T + t0;
+        const TPack<R, L> rpn = tld<R, L>(rp + on), rmn = tld<R, L>(rm + on);
+        R FL[L], Aa[L];
+        edge_fluxes<R, L>(a, st, s, i, k, t0, qn_i, qs_i, Hi, FL, Aa);
+        const bool self_c1 = st.cdiv[s] > (R)0;
+#pragma unroll
+        for (int j = 0; j < L; j++) {
+            const R rp1 = self_c1 ? rpi.v[j] : rpn.v[j], rp2 = self_c1 ? rpn.v[j] : rpi.v[j];
+            const R rm1 = self_c1 ? rmi.v[j] : rmn.v[j], rm2 = self_c1 ? rmn.v[j] : rmi.v[j];
+            const R C = (Aa[j] >= (R)0) ? fmin(rp2, rm1) : fmin(rp1, rm2);
+            dT[j] += st.cdiv[s] * (FL[j] + C * Aa[j]);
+        }
     }
-    ((R *)a.q_o)[ix.x] = ((R)dpi_n * qn[ix.x] - (R)a.dts * dT) / (R)dpin;
-    if (a.last_stage && t == 0) a.dpi_o[(long)i * a.K + k] = dpin;
+    TPack<R, L> qo;
+#pragma unroll
+    for (int j = 0; j < L; j++) qo.v[j] = ((R)st.dpi_n * qn_i[j] - (R)a.dts * dT[j]) / (R)st.dpin;
+    tst<R, L>((R *)a.q_o + ln.x, qo);
+    if (a.last_stage && t0 == 0) a.dpi_o[(long)i * a.K + k] = st.dpin;
 }
 
 namespace {
 inline unsigned tblocks(long n, int b) { return (unsigned)((n + b - 1) / b); }
-template <typename R>
-hipError_t launch_tr(const TracerArgs &a, int which, hipStream_t s) {
-    const long n = (long)a.mesh.N * a.K * a.T;
+template <typename R, int L>
+hipError_t launch_tr_l(const TracerArgs &a, int which, hipStream_t s) {
+    const long n = (long)a.mesh.N * a.K * (a.T / L);
     const int b = a.cpb > 0 ? a.cpb : 256;
     switch (which) {
-    case TKERNEL_LOW: hipLaunchKernelGGL(k_tr_low<R>, dim3(tblocks(n, b)), dim3(b), 0, s, a); break;
-    case TKERNEL_LIMIT: hipLaunchKernelGGL(k_tr_limit<R>, dim3(tblocks(n, b)), dim3(b), 0, s, a); break;
-    case TKERNEL_UPDATE: hipLaunchKernelGGL(k_tr_update<R>, dim3(tblocks(n, b)), dim3(b), 0, s, a); break;
+    case TKERNEL_LOW: hipLaunchKernelGGL((k_tr_low<R, L>), dim3(tblocks(n, b)), dim3(b), 0, s, a); break;
+    case TKERNEL_LIMIT: hipLaunchKernelGGL((k_tr_limit<R, L>), dim3(tblocks(n, b)), dim3(b), 0, s, a); break;
+    case TKERNEL_UPDATE: hipLaunchKernelGGL((k_tr_update<R, L>), dim3(tblocks(n, b)), dim3(b), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+template <typename R>
+hipError_t launch_tr(const TracerArgs &a, int which, hipStream_t s) {
+    // four FP32 or two FP64 tracers per lane (16-byte loads)
+    if (sizeof(R) == 4 && a.T % 4 == 0) return launch_tr_l<R, 4>(a, which, s);
+    if (a.T % 2 == 0) return launch_tr_l<R, 2>(a, which, s);
+    return launch_tr_l<R, 1>(a, which, s);
 }
 }  // namespace
 

@@ -57,6 +57,7 @@ def parse():
     p.add_argument("--workload", default="hdc-g6", choices=sorted(WORKLOADS))
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-dbl", action="store_true", help="skip the all-FP64 timing")
+    p.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     p.add_argument("--profile-steps", type=int, default=20,
                    help="steps run with HIP events between launches for per-kernel durations")
     p.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -117,8 +118,14 @@ def key_field(mpdc, w):
     return {"SW": mpdc.FIELD_H, "TRACER": mpdc.FIELD_TR_Q}.get(w["model"], mpdc.FIELD_PS)
 
 
-def timed_run(torch, mpdc, g, w, st, policy, steps, warmup, stream):
+def timed_run(torch, mpdc, g, w, st, policy, steps, warmup, stream, autotune=True):
     s = make_state(mpdc, g, w, st, policy)
+    shapes = None
+    if autotune:
+        with torch.cuda.stream(stream):
+            s.autotune(stream=stream)
+        nk = 3 if w["model"] == "TRACER" else 4
+        shapes = [s.get_kernel_launch(k) for k in range(nk)]
     s.set_graph(True)
     with torch.cuda.stream(stream):
         step(s, w, warmup, stream)
@@ -127,6 +134,7 @@ def timed_run(torch, mpdc, g, w, st, policy, steps, warmup, stream):
         step(s, w, steps, stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+    s.launch_shapes = shapes
     return s, (t1 - t0) / max(steps, 1)
 
 
@@ -210,12 +218,15 @@ def main():
     N, K, M, T = mesh["nCells"], w["K"], w["M"], w["T"]
     units = N * K * M
 
-    s_mix, sec_mix = timed_run(torch, mpdc, g, w, st, mpdc.POLICY_MIX, args.steps, args.warmup, stream)
+    s_mix, sec_mix = timed_run(torch, mpdc, g, w, st, mpdc.POLICY_MIX, args.steps, args.warmup, stream,
+                               not args.no_autotune)
     kt = kernel_times(torch, s_mix, w, args.profile_steps, stream)
     step_bytes_mix = s_mix.step_bytes()
-    sec_dbl, kt_dbl, step_bytes_dbl = None, None, None
+    sec_dbl, kt_dbl, step_bytes_dbl, shapes_dbl = None, None, None, None
     if not args.no_dbl:
-        s_dbl, sec_dbl = timed_run(torch, mpdc, g, w, st, mpdc.POLICY_DBL, args.steps, args.warmup, stream)
+        s_dbl, sec_dbl = timed_run(torch, mpdc, g, w, st, mpdc.POLICY_DBL, args.steps, args.warmup, stream,
+                                   not args.no_autotune)
+        shapes_dbl = s_dbl.launch_shapes
         kt_dbl = kernel_times(torch, s_dbl, w, args.profile_steps, stream)
         step_bytes_dbl = s_dbl.step_bytes()
         del s_dbl
@@ -272,6 +283,8 @@ def main():
                         for k, v in kt.items()},
         "kernels_dbl": ({k: {"ms": v["ms"], "MB": v["bytes"] / 1e6, "GB/s": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
                          for k, v in kt_dbl.items()} if kt_dbl else None),
+        "launch_shapes": {"mix": s_mix.launch_shapes, "dbl": shapes_dbl,
+                          "note": "(values per lane, cells or threads per work-group) per kernel, autotuned"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": kt[dom]["bytes"], "ms_per_launch": kt[dom]["ms"]},

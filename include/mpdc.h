@@ -193,10 +193,22 @@ int mpdc_diagnostics(mpdc_state *st, int field_id, const void *ref_dev, mpdc_dia
  * not be the legacy default stream while graphs are enabled. */
 int mpdc_set_graph(mpdc_state *st, int enable);
 
-/* Launch shape of the state's kernels: cells per work-group for the column
- * kernels and threads per work-group for the flat kernels (0 = default).
- * Any legal shape gives bitwise identical results. */
+/* Launch shape of all the state's kernels: cells per work-group for the
+ * column kernels (0 = default) and threads per work-group for the flat
+ * kernels (0 = 256).  Any legal shape gives bitwise identical results.
+ * Errors: INVAL (a work-group over 512 column lanes or 64 KiB of LDS, or a
+ * thread count that is not a multiple of 64 up to 1024, 512 for tracers). */
 int mpdc_set_launch(mpdc_state *st, int cells_per_block, int flat_block);
+
+/* Launch shape of one kernel class (ids as for mpdc_time_kernel):
+ * values_per_lane = (level, member) values a lane computes -- 1 or 2 for the
+ * column kernels, 1, 2 or 4 for the flat kernels, 1, 2 or 4 tracers for the
+ * tracer kernels; it must divide K (M == 1), M (M > 1) or T; 0 = default --
+ * and group = cells per work-group (column kernels) or threads per
+ * work-group (others), 0 = keep.  Results are bitwise identical for every
+ * legal shape.  Errors: INVAL. */
+int mpdc_set_kernel_launch(mpdc_state *st, int kernel_id, int values_per_lane, int group);
+int mpdc_get_kernel_launch(const mpdc_state *st, int kernel_id, int *values_per_lane, int *group);
 
 /* Time nreps launches of one kernel class (0 = first cell kernel, 1 = vertex,
  * 2 = second cell kernel, 3 = edge/momentum kernel; tracer: 0..2 its three
@@ -210,10 +222,11 @@ int mpdc_time_kernel(mpdc_state *st, int kernel_id, int nreps, void *stream, dou
  * advances by nsteps exactly as with mpdc_dycore_step / mpdc_tracer_step. */
 int mpdc_profile_steps(mpdc_state *st, int nsteps, void *stream, double *ms_total, int *launches);
 
-/* Pick the launch shape (cells per work-group of the column kernels, threads
- * per work-group of the flat kernels) with the shortest first-stage kernel
- * times among the legal candidates, set it, and return it.  Uses
- * mpdc_time_kernel, so the state is not advanced. */
+/* Autotuner: for each kernel class in launch order, time every legal
+ * (values per lane, work-group) pair with mpdc_time_kernel (so the state is
+ * not advanced), keep the fastest, and return the column kernels' cells per
+ * work-group and the last flat kernel's threads per work-group.  Results stay
+ * bitwise identical; mpdc_get_kernel_launch reads the choice back. */
 int mpdc_autotune(mpdc_state *st, void *stream, int *cells_per_block, int *flat_block);
 
 /* Algorithmic HBM bytes of one launch of a kernel class (same ids; mean over

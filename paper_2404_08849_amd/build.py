@@ -26,6 +26,9 @@ def build(verbose=False):
     cmd = [hipcc(), "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=" + ARCH,
            # no packed-FP32 instructions (v_pk_*_f32) anywhere in the device code
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           # no FMA contraction: every value is computed by the same operations whatever
+           # the launch shape (bitwise-reproducible across shapes and the autotuner)
+           "-ffp-contract=off",
            "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
            "-x", "hip"] + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
     if verbose:

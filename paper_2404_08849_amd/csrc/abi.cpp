@@ -213,17 +213,34 @@ size_t state_layout(mpdc_state *st, void *base) {
     return c.off;
 }
 
-// lanes of one cell column in the column kernels
-int col_lanes(const mpdc_state *st) { return st->K * st->M / values_per_lane(st->K, st->M); }
+bool is_column(int k) { return k == KERNEL_CELL_A || k == KERNEL_CELL_B; }
 
-int auto_cpb(const mpdc_state *st) {
-    const int lanes = col_lanes(st);
-    return std::max(1, 256 / lanes);
+// values per lane of kernel class k (0 in the launch table = automatic)
+int vpl_of(const mpdc_state *st, int k) {
+    if (st->launch.vpl[k] > 0) return st->launch.vpl[k];
+    if (st->model == MPDC_MODEL_TRACER) {
+        if (st->policy == MPDC_POLICY_MIX && st->T % 4 == 0) return 4;   // 16-byte FP32 loads
+        return (st->T % 2 == 0) ? 2 : 1;
+    }
+    return values_per_lane(st->K, st->M);
 }
 
-int cpb_of(const mpdc_state *st) {
-    if (st->model == MPDC_MODEL_TRACER) return st->launch.flat_block;
-    return st->launch.cells_per_block > 0 ? st->launch.cells_per_block : auto_cpb(st);
+// legal values per lane for kernel class k
+bool vpl_ok(const mpdc_state *st, int k, int L) {
+    if (L != 1 && L != 2 && L != 4) return false;
+    if (st->model == MPDC_MODEL_TRACER) return st->T % L == 0;
+    if (L == 4 && is_column(k)) return false;
+    if (st->M == 1) return st->K % L == 0;
+    return st->M % L == 0;
+}
+
+// lanes of one cell column in a column kernel of class k
+int col_lanes(const mpdc_state *st, int k) { return st->K * st->M / vpl_of(st, k); }
+
+int cpb_of(const mpdc_state *st, int k) {
+    if (st->model == MPDC_MODEL_TRACER) return st->launch.flat[k];
+    if (st->launch.cpb[k] > 0) return st->launch.cpb[k];
+    return std::max(1, 256 / col_lanes(st, k));
 }
 
 StageArgs stage_args(const mpdc_state *st, int s) {
@@ -232,8 +249,9 @@ StageArgs stage_args(const mpdc_state *st, int s) {
     a.mesh = st->mesh->dev;
     a.K = st->K;
     a.M = st->M;
-    a.cpb = cpb_of(st);
-    a.flat_block = st->launch.flat_block;
+    a.cpb = 1;
+    a.flat_block = 256;
+    a.vpl = 1;
     static const double frac[3] = {1.0 / 3.0, 0.5, 1.0};
     a.dts = frac[s] * st->cfg.dt;
     a.grav = st->cfg.grav;
@@ -271,7 +289,8 @@ TracerArgs tracer_args(const mpdc_state *st, int s, int parity) {
     a.mesh = st->mesh->dev;
     a.K = st->K;
     a.T = st->T;
-    a.cpb = st->launch.flat_block;
+    a.cpb = 256;
+    a.vpl = 1;
     a.fct = st->cfg.fct;
     static const double frac[3] = {1.0 / 3.0, 0.5, 1.0};
     a.dts = frac[s] * st->cfg.dt;
@@ -290,11 +309,24 @@ TracerArgs tracer_args(const mpdc_state *st, int s, int parity) {
     return a;
 }
 
+// launch one kernel class with this state's shape for it
+hipError_t launch_dycore(const mpdc_state *st, StageArgs a, int k, hipStream_t s) {
+    a.vpl = vpl_of(st, k);
+    a.cpb = cpb_of(st, k);
+    a.flat_block = st->launch.flat[k];
+    return launch_stage_kernel(st->model, st->policy, a, k, s);
+}
+hipError_t launch_tracer(const mpdc_state *st, TracerArgs a, int k, hipStream_t s) {
+    a.vpl = vpl_of(st, k);
+    a.cpb = st->launch.flat[k];
+    return launch_tracer_kernel(st->policy, a, k, s);
+}
+
 int run_dycore_step(mpdc_state *st, hipStream_t s) {
     for (int stage = 0; stage < 3; stage++) {
         StageArgs a = stage_args(st, stage);
         for (int k = KERNEL_CELL_A; k <= KERNEL_EDGE; k++) {
-            hipError_t e = launch_stage_kernel(st->model, st->policy, a, k, s);
+            hipError_t e = launch_dycore(st, a, k, s);
             if (e != hipSuccess) return hip_fail(e, "dycore kernel launch");
         }
     }
@@ -305,7 +337,7 @@ int run_tracer_step(mpdc_state *st, int parity, hipStream_t s) {
     for (int stage = 0; stage < 3; stage++) {
         TracerArgs a = tracer_args(st, stage, parity);
         for (int k = TKERNEL_LOW; k <= TKERNEL_UPDATE; k++) {
-            hipError_t e = launch_tracer_kernel(st->policy, a, k, s);
+            hipError_t e = launch_tracer(st, a, k, s);
             if (e != hipSuccess) return hip_fail(e, "tracer kernel launch");
         }
     }
@@ -669,21 +701,79 @@ int mpdc_set_graph(mpdc_state *st, int enable) {
     return MPDC_OK;
 }
 
+static int check_group(const mpdc_state *st, int k, int L, int group) {
+    if (st->model != MPDC_MODEL_TRACER && is_column(k)) {
+        const long lanes = (long)st->K * st->M / L;
+        if (group < 1 || group * lanes > kColumnThreads)
+            return fail(MPDC_E_INVAL, "cells per work-group times the column's lanes must be 1..512");
+        if (stage_lds_bytes(st->model, k, group, st->K, st->M) > 65536)
+            return fail(MPDC_E_INVAL, "column work-group would need more than 64 KiB of LDS");
+        return MPDC_OK;
+    }
+    const int cap = (st->model == MPDC_MODEL_TRACER) ? kTracerThreads : 1024;
+    if (group < 64 || group > cap || group % 64) return fail(MPDC_E_INVAL, "threads per work-group must be a multiple of 64 up to 512 (tracer) or 1024");
+    return MPDC_OK;
+}
+
 int mpdc_set_launch(mpdc_state *st, int cells_per_block, int flat_block) {
     if (!st) return fail(MPDC_E_INVAL, "null state");
     if (flat_block == 0) flat_block = 256;
-    if (flat_block < 64 || flat_block > 1024 || flat_block % 64) return fail(MPDC_E_INVAL, "flat block must be 64..1024, a multiple of 64");
-    if (st->model == MPDC_MODEL_TRACER && flat_block > kTracerThreads)
-        return fail(MPDC_E_INVAL, "tracer work-groups hold at most 512 lanes");
-    if (cells_per_block < 0 ||
-        (st->model != MPDC_MODEL_TRACER && (long)cells_per_block * col_lanes(st) > kColumnThreads))
-        return fail(MPDC_E_INVAL, "cells per block times the column's lanes must be at most 512");
-    if (st->model == MPDC_MODEL_NDC && cells_per_block > 0 &&
-        stage_lds_bytes(st->model, KERNEL_CELL_B, cells_per_block, st->K, st->M) > 65536)
-        return fail(MPDC_E_INVAL, "column kernel would need more than 64 KiB of LDS");
+    const int nk = st->model == MPDC_MODEL_TRACER ? 3 : 4;
+    Launch L = st->launch;
+    for (int k = 0; k < nk; k++) {
+        const bool col = st->model != MPDC_MODEL_TRACER && is_column(k);
+        if (col) {
+            if (cells_per_block < 0) return fail(MPDC_E_INVAL, "negative cells per block");
+            if (cells_per_block > 0) {
+                int rc = check_group(st, k, vpl_of(st, k), cells_per_block);
+                if (rc) return rc;
+            }
+            L.cpb[k] = cells_per_block;
+        } else {
+            int rc = check_group(st, k, vpl_of(st, k), flat_block);
+            if (rc) return rc;
+            L.flat[k] = flat_block;
+        }
+    }
     drop_graphs(st);
-    st->launch.cells_per_block = cells_per_block;
-    st->launch.flat_block = flat_block;
+    st->launch = L;
+    return MPDC_OK;
+}
+
+int mpdc_set_kernel_launch(mpdc_state *st, int kernel_id, int values_per_lane_, int group) {
+    if (!st) return fail(MPDC_E_INVAL, "null state");
+    const int nk = st->model == MPDC_MODEL_TRACER ? 3 : 4;
+    if (kernel_id < 0 || kernel_id >= nk) return fail(MPDC_E_INVAL, "kernel id out of range");
+    Launch L = st->launch;
+    L.vpl[kernel_id] = values_per_lane_;
+    mpdc_state probe = *st;
+    probe.launch = L;
+    const int v = vpl_of(&probe, kernel_id);
+    if (!vpl_ok(st, kernel_id, v)) return fail(MPDC_E_INVAL, "values per lane must be 1, 2 or 4 and divide the column");
+    const bool col = st->model != MPDC_MODEL_TRACER && is_column(kernel_id);
+    if (group != 0) {
+        int rc = check_group(st, kernel_id, v, group);
+        if (rc) return rc;
+        if (col) L.cpb[kernel_id] = group;
+        else L.flat[kernel_id] = group;
+    } else if (col) {
+        L.cpb[kernel_id] = 0;
+    }
+    if (col && L.cpb[kernel_id] > 0) {
+        int rc = check_group(st, kernel_id, v, L.cpb[kernel_id]);
+        if (rc) return rc;
+    }
+    drop_graphs(st);
+    st->launch = L;
+    return MPDC_OK;
+}
+
+int mpdc_get_kernel_launch(const mpdc_state *st, int kernel_id, int *values_per_lane_, int *group) {
+    if (!st || !values_per_lane_ || !group) return fail(MPDC_E_INVAL, "null argument");
+    const int nk = st->model == MPDC_MODEL_TRACER ? 3 : 4;
+    if (kernel_id < 0 || kernel_id >= nk) return fail(MPDC_E_INVAL, "kernel id out of range");
+    *values_per_lane_ = vpl_of(st, kernel_id);
+    *group = (st->model != MPDC_MODEL_TRACER && is_column(kernel_id)) ? cpb_of(st, kernel_id) : st->launch.flat[kernel_id];
     return MPDC_OK;
 }
 
@@ -694,7 +784,7 @@ static int step_common(mpdc_state *st, int nsteps, void *stream, bool tracer) {
         return fail(MPDC_E_STATE, tracer ? "tracer_step on a dycore state" : "dycore_step on a tracer state");
     hipStream_t s = (hipStream_t)stream;
     if (st->model == MPDC_MODEL_NDC &&
-        stage_lds_bytes(st->model, KERNEL_CELL_B, cpb_of(st), st->K, st->M) > 65536)
+        stage_lds_bytes(st->model, KERNEL_CELL_B, cpb_of(st, KERNEL_CELL_B), st->K, st->M) > 65536)
         return fail(MPDC_E_UNSUPPORTED, "column too tall for the LDS of one work-group");
     for (int n = 0; n < nsteps; n++) {
         int parity = tracer ? st->parity : 0;
@@ -728,12 +818,12 @@ int mpdc_time_kernel(mpdc_state *st, int kernel_id, int nreps, void *stream, dou
     if (tr) {
         TracerArgs a = tracer_args(st, 0, st->parity);
         a.last_stage = 0;
-        for (int k = 0; k < kernel_id; k++) HIP_TRY(launch_tracer_kernel(st->policy, a, k, s));
+        for (int k = 0; k < kernel_id; k++) HIP_TRY(launch_tracer(st, a, k, s));
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
         HIP_TRY(hipEventRecord(e0, s));
-        for (int r = 0; r < nreps; r++) HIP_TRY(launch_tracer_kernel(st->policy, a, kernel_id, s));
+        for (int r = 0; r < nreps; r++) HIP_TRY(launch_tracer(st, a, kernel_id, s));
         HIP_TRY(hipEventRecord(e1, s));
         HIP_TRY(hipEventSynchronize(e1));
         float ms = 0;
@@ -744,12 +834,12 @@ int mpdc_time_kernel(mpdc_state *st, int kernel_id, int nreps, void *stream, dou
         return MPDC_OK;
     }
     StageArgs a = stage_args(st, 0);
-    for (int k = 0; k < kernel_id; k++) HIP_TRY(launch_stage_kernel(st->model, st->policy, a, k, s));
+    for (int k = 0; k < kernel_id; k++) HIP_TRY(launch_dycore(st, a, k, s));
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, s));
-    for (int r = 0; r < nreps; r++) HIP_TRY(launch_stage_kernel(st->model, st->policy, a, kernel_id, s));
+    for (int r = 0; r < nreps; r++) HIP_TRY(launch_dycore(st, a, kernel_id, s));
     HIP_TRY(hipEventRecord(e1, s));
     HIP_TRY(hipEventSynchronize(e1));
     float ms = 0;
@@ -848,8 +938,8 @@ int mpdc_profile_steps(mpdc_state *st, int nsteps, void *stream, double *ms_tota
         for (int stage = 0; stage < 3; stage++) {
             for (int k = 0; k < nk; k++) {
                 hipError_t e;
-                if (tr) e = launch_tracer_kernel(st->policy, tracer_args(st, stage, parity), k, s);
-                else e = launch_stage_kernel(st->model, st->policy, stage_args(st, stage), k, s);
+                if (tr) e = launch_tracer(st, tracer_args(st, stage, parity), k, s);
+                else e = launch_dycore(st, stage_args(st, stage), k, s);
                 if (e != hipSuccess) { rc = hip_fail(e, "kernel launch"); break; }
                 HIP_TRY(hipEventRecord(ev[kid.size() + 1], s));
                 kid.push_back(k);
@@ -871,44 +961,47 @@ int mpdc_profile_steps(mpdc_state *st, int nsteps, void *stream, double *ms_tota
 
 int mpdc_autotune(mpdc_state *st, void *stream, int *cells_per_block, int *flat_block) {
     if (!st || !cells_per_block || !flat_block) return fail(MPDC_E_INVAL, "bad arguments");
-    const Launch keep = st->launch;
     const bool tr = st->model == MPDC_MODEL_TRACER;
+    const int nk = tr ? 3 : 4;
     const int flats[] = {64, 128, 256, 512, 1024};
-    const int cpbs[] = {1, 2, 3, 4, 6, 8, 12, 16, 32, 64, 128, 256};
-    double best_flat_ms = 1e30, best_col_ms = 1e30;
-    int best_flat = keep.flat_block, best_cpb = keep.cells_per_block;
-    for (int fb : flats) {
-        if (tr && fb > kTracerThreads) continue;
-        st->launch.flat_block = fb;
-        double t = 0, ms = 0;
-        int rc = MPDC_OK;
-        if (tr) {
-            for (int k = 0; k < 3 && rc == MPDC_OK; k++) { rc = mpdc_time_kernel(st, k, 5, stream, &ms); t += ms; }
-        } else {
-            rc = mpdc_time_kernel(st, KERNEL_VERTEX, 5, stream, &ms); t += ms;
-            if (rc == MPDC_OK) { rc = mpdc_time_kernel(st, KERNEL_EDGE, 5, stream, &ms); t += ms; }
+    const int cpbs[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 64, 128, 256, 512};
+    const int vpls[] = {1, 2, 4};
+    // kernels are tuned in launch order, each with the already tuned shapes of
+    // the kernels before it (their outputs are its inputs)
+    for (int k = 0; k < nk; k++) {
+        double best = 1e30;
+        int best_v = vpl_of(st, k), best_g = 0;
+        const bool col = !tr && is_column(k);
+        for (int v : vpls) {
+            if (!vpl_ok(st, k, v)) continue;
+            const int *gs = col ? cpbs : flats;
+            const int ng = col ? (int)(sizeof(cpbs) / sizeof(int)) : (int)(sizeof(flats) / sizeof(int));
+            for (int gi = 0; gi < ng; gi++) {
+                const int g = gs[gi];
+                if (check_group(st, k, v, g) != MPDC_OK) continue;
+                Launch keep = st->launch;
+                st->launch.vpl[k] = v;
+                if (col) st->launch.cpb[k] = g;
+                else st->launch.flat[k] = g;
+                double ms = 0;
+                int rc = mpdc_time_kernel(st, k, 5, stream, &ms);
+                st->launch = keep;
+                if (rc != MPDC_OK) return rc;
+                if (ms < best) {
+                    best = ms;
+                    best_v = v;
+                    best_g = g;
+                }
+            }
         }
-        if (rc != MPDC_OK) { st->launch = keep; return rc; }
-        if (t < best_flat_ms) { best_flat_ms = t; best_flat = fb; }
+        st->launch.vpl[k] = best_v;
+        if (col) st->launch.cpb[k] = best_g;
+        else st->launch.flat[k] = best_g;
     }
-    st->launch.flat_block = best_flat;
-    if (!tr) {
-        for (int c : cpbs) {
-            if ((long)c * col_lanes(st) > kColumnThreads) continue;
-            if (stage_lds_bytes(st->model, KERNEL_CELL_B, c, st->K, st->M) > 65536) continue;
-            st->launch.cells_per_block = c;
-            double t = 0, ms = 0;
-            int rc = mpdc_time_kernel(st, KERNEL_CELL_A, 5, stream, &ms);
-            t += ms;
-            if (rc == MPDC_OK) { rc = mpdc_time_kernel(st, KERNEL_CELL_B, 5, stream, &ms); t += ms; }
-            if (rc != MPDC_OK) { st->launch = keep; return rc; }
-            if (t < best_col_ms) { best_col_ms = t; best_cpb = c; }
-        }
-        st->launch.cells_per_block = best_cpb;
-    }
+    set_error("");
     drop_graphs(st);
-    *cells_per_block = st->launch.cells_per_block > 0 ? st->launch.cells_per_block : auto_cpb(st);
-    *flat_block = st->launch.flat_block;
+    *cells_per_block = tr ? 0 : cpb_of(st, KERNEL_CELL_A);
+    *flat_block = st->launch.flat[tr ? 0 : KERNEL_EDGE];
     return MPDC_OK;
 }
 

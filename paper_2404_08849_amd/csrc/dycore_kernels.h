@@ -21,6 +21,7 @@ struct StageArgs {
     int K, M;
     int cpb;          // cells per work-group of the column kernels
     int flat_block;   // threads per work-group of the flat kernels
+    int vpl;          // (k, m) values per lane of this launch (1, 2; flat kernels also 4)
     double dts, grav, rd, cp, p0, ptop, kappa, gamma;
     const double *dsig;  // [K]
     const double *sig;   // [K+1]
@@ -64,7 +65,8 @@ constexpr int kTracerThreads = 512;
 struct TracerArgs {
     DevMesh mesh;
     int K, T;
-    int cpb;           // cells per work-group
+    int cpb;           // threads per work-group
+    int vpl;           // tracers per lane (1, 2 or 4, dividing T)
     int fct;
     double dts;
     const double *F;       // [E][K]   prescribed FP64 mass flux

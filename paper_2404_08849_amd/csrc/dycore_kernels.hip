@@ -159,6 +159,36 @@ template <int L> __device__ __forceinline__ ColLane col_lane(const StageArgs &a,
     return c;
 }
 
+// Sequential sums over LDS with the loads issued four at a time (the adds
+// keep their order): sum_{q=q0}^{q1-1} p[q*stride], and the same downwards.
+__device__ __forceinline__ double lds_sum_up(const double *p, int stride, int q0, int q1) {
+    double s = 0.0;
+    int q = q0;
+    for (; q + 4 <= q1; q += 4) {
+        const double a0 = p[q * stride], a1 = p[(q + 1) * stride], a2 = p[(q + 2) * stride], a3 = p[(q + 3) * stride];
+        s += a0;
+        s += a1;
+        s += a2;
+        s += a3;
+    }
+    for (; q < q1; q++) s += p[q * stride];
+    return s;
+}
+__device__ __forceinline__ double lds_sum_down(const double *p, int stride, int q_hi, int q_lo) {
+    // sum over q = q_hi, q_hi-1, ..., q_lo+1 (in that order)
+    double s = 0.0;
+    int q = q_hi;
+    for (; q - 4 >= q_lo; q -= 4) {
+        const double a0 = p[q * stride], a1 = p[(q - 1) * stride], a2 = p[(q - 2) * stride], a3 = p[(q - 3) * stride];
+        s += a0;
+        s += a1;
+        s += a2;
+        s += a3;
+    }
+    for (; q > q_lo; q--) s += p[q * stride];
+    return s;
+}
+
 // ---------------------------------------------------------------------------
 // cell_a
 // ---------------------------------------------------------------------------
@@ -262,14 +292,25 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
         double mdot_b[L];
         if (cl.valid) {
             const long K1M = (long)(K + 1) * M;
+            // M == 1: the L values are consecutive levels of one column, so the
+            // column sum is shared and each prefix extends the previous one
+            double tot = 0.0, pre = 0.0;
+            if constexpr (M1) {
+                tot = lds_sum_up(sD + lc * KM, 1, 0, K);
+                pre = lds_sum_up(sD + lc * KM, 1, 0, v.k0);
+            }
 #pragma unroll
             for (int j = 0; j < L; j++) {
                 const int mm = v.mm0 + (M1 ? 0 : j);
-                double s = 0.0;
-                for (int q = 0; q < K; q++) s += sD[lc * KM + q * M + mm];
-                const double dps = -s;
-                double acc = 0.0;
-                for (int q = 0; q <= v.k[j]; q++) acc += sD[lc * KM + q * M + mm];
+                double dps, acc;
+                if constexpr (M1) {
+                    pre += sD[lc * KM + v.k[j]];
+                    dps = -tot;
+                    acc = pre;
+                } else {
+                    dps = -lds_sum_up(sD + lc * KM + mm, M, 0, K);
+                    acc = lds_sum_up(sD + lc * KM + mm, M, 0, v.k[j] + 1);
+                }
                 mdot_b[j] = (v.k[j] == K - 1) ? 0.0 : -acc - a.sig[v.k[j] + 1] * dps;
                 a.mdot[(long)i * K1M + (long)(v.k[j] + 1) * M + mm] = mdot_b[j];
                 if (v.k[j] == 0) {
@@ -698,14 +739,25 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
             if (cl.valid) {
                 // hydrostatic geopotential from the flat surface upwards (Eq. 8)
                 Pack<double, L> alp, php;
+                if constexpr (M1) {
+                    // consecutive levels: the deepest value's partial sum is extended upwards
+                    double acc = lds_sum_down(sA + lc * KM, 1, K - 1, v.k[L - 1]);
 #pragma unroll
-                for (int j = 0; j < L; j++) {
-                    const int mm = v.mm0 + (M1 ? 0 : j);
-                    double acc = 0.0;
-                    for (int q = K - 1; q > v.k[j]; q--) acc += sA[lc * KM + q * M + mm];
-                    const double phit = acc + sA[lc * KM + v.k[j] * M + mm];
-                    alp.v[j] = al[j];
-                    php.v[j] = 0.5 * (phit + acc);
+                    for (int j = L - 1; j >= 0; j--) {
+                        const double phit = acc + sA[lc * KM + v.k[j]];
+                        alp.v[j] = al[j];
+                        php.v[j] = 0.5 * (phit + acc);
+                        acc = phit;
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < L; j++) {
+                        const int mm = v.mm0 + j;
+                        const double acc = lds_sum_down(sA + lc * KM + mm, M, K - 1, v.k[j]);
+                        const double phit = acc + sA[lc * KM + v.k[j] * M + mm];
+                        alp.v[j] = al[j];
+                        php.v[j] = 0.5 * (phit + acc);
+                    }
                 }
                 stp<double, L>(a.alpha + (long)i * KM + km0, alp);
                 stp<double, L>(a.phim + (long)i * KM + km0, php);
@@ -1040,10 +1092,29 @@ hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
     return hipGetLastError();
 }
 
+// flat kernels (vertex, edge) also take four values per lane
+template <int MODEL, typename R, bool M1>
+hipError_t launch_flat4(const StageArgs &a, int which, hipStream_t s) {
+    const int KM = a.K * a.M;
+    const int lanes = KM / 4;
+    const int fb = a.flat_block;
+    if (which == KERNEL_VERTEX)
+        hipLaunchKernelGGL((k_vertex<MODEL, R, 4, M1>), dim3(nblocks((long)a.mesh.V * lanes, fb)), dim3(fb), 0, s, a);
+    else if (which == KERNEL_EDGE)
+        hipLaunchKernelGGL((k_edge<MODEL, R, 4, M1>), dim3(nblocks((long)a.mesh.E * lanes, fb)), dim3(fb), 0, s, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 template <int MODEL, typename R>
 hipError_t launch_stage_r(const StageArgs &a, int which, hipStream_t s) {
-    const int L = values_per_lane(a.K, a.M);
-    if (a.M == 1) return L == 2 ? launch_stage_t<MODEL, R, 2, true>(a, which, s) : launch_stage_t<MODEL, R, 1, true>(a, which, s);
+    const int L = a.vpl;
+    if (a.M == 1) {
+        if (L == 4) return launch_flat4<MODEL, R, true>(a, which, s);
+        return L == 2 ? launch_stage_t<MODEL, R, 2, true>(a, which, s) : launch_stage_t<MODEL, R, 1, true>(a, which, s);
+    }
+    if (L == 4) return launch_flat4<MODEL, R, false>(a, which, s);
     return L == 2 ? launch_stage_t<MODEL, R, 2, false>(a, which, s) : launch_stage_t<MODEL, R, 1, false>(a, which, s);
 }
 }  // namespace

@@ -83,9 +83,12 @@ struct Dims {
 };
 
 // Kernel launch shape
+// Launch shape per kernel class (dycore: cell_a, vertex, cell_b, edge;
+// tracer: low, limit, update).  Any legal shape gives bitwise identical results.
 struct Launch {
-    int cells_per_block = 0;   // column kernels: cells per work-group (0 = auto)
-    int flat_block = 256;      // flat kernels: threads per work-group
+    int cpb[4] = {0, 0, 0, 0};            // column kernels: cells per work-group (0 = auto)
+    int flat[4] = {256, 256, 256, 256};   // flat kernels: threads per work-group
+    int vpl[4] = {0, 0, 0, 0};            // (k, m) or tracer values per lane (0 = auto)
 };
 
 // Thread-local error message

@@ -302,9 +302,8 @@ hipError_t launch_tr_l(const TracerArgs &a, int which, hipStream_t s) {
 }
 template <typename R>
 hipError_t launch_tr(const TracerArgs &a, int which, hipStream_t s) {
-    // four FP32 or two FP64 tracers per lane (16-byte loads)
-    if (sizeof(R) == 4 && a.T % 4 == 0) return launch_tr_l<R, 4>(a, which, s);
-    if (a.T % 2 == 0) return launch_tr_l<R, 2>(a, which, s);
+    if (a.vpl == 4) return launch_tr_l<R, 4>(a, which, s);
+    if (a.vpl == 2) return launch_tr_l<R, 2>(a, which, s);
     return launch_tr_l<R, 1>(a, which, s);
 }
 }  // namespace

@@ -79,6 +79,9 @@ def _load():
         "mpdc_diagnostics": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.POINTER(Diag), _vp]),
         "mpdc_set_graph": (ctypes.c_int, [_vp, ctypes.c_int]),
         "mpdc_set_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+        "mpdc_set_kernel_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+        "mpdc_get_kernel_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                                  ctypes.POINTER(ctypes.c_int)]),
         "mpdc_time_kernel": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double)]),
         "mpdc_kernel_bytes": (ctypes.c_double, [_vp, ctypes.c_int]),
         "mpdc_profile_steps": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double),
@@ -231,6 +234,14 @@ class State:
 
     def set_launch(self, cells_per_block=0, flat_block=0):
         _check(lib.mpdc_set_launch(self.h, cells_per_block, flat_block))
+
+    def set_kernel_launch(self, kernel_id, values_per_lane=0, group=0):
+        _check(lib.mpdc_set_kernel_launch(self.h, kernel_id, values_per_lane, group))
+
+    def get_kernel_launch(self, kernel_id):
+        v, g = ctypes.c_int(), ctypes.c_int()
+        _check(lib.mpdc_get_kernel_launch(self.h, kernel_id, ctypes.byref(v), ctypes.byref(g)))
+        return v.value, g.value
 
     def time_kernel(self, kernel_id, nreps=10, stream=None):
         ms = ctypes.c_double()

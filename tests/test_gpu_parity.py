@@ -177,6 +177,31 @@ def test_graph_replay_and_launch_shapes_are_bitwise_identical(mpdc, mesh_cache):
             ref = out
         for a, b in zip(out, ref):
             assert np.array_equal(a, b)
+    # per-kernel values per lane and work-group sizes, and the autotuner's choice
+    for shapes in ([(1, 8), (1, 64), (1, 4), (1, 128)], [(2, 3), (4, 256), (2, 1), (4, 512)]):
+        _say("hdc G4x10 per-kernel shapes %s" % (shapes,))
+        st = mpdc.State(g, mpdc.MODEL_HDC, mpdc.POLICY_MIX, K=K, dt=600.0, sigma=ic.sigma_interfaces(K))
+        for kid, (vpl, grp) in enumerate(shapes):
+            if vpl == 4 and K % 4:
+                vpl = 2
+            st.set_kernel_launch(kid, vpl, grp)
+        st.state_write(mpdc.FIELD_PS, s["ps"][:, None])
+        st.state_write(mpdc.FIELD_THETA, s["Theta"][:, :, None])
+        st.state_write(mpdc.FIELD_U, s["u"][:, :, None])
+        st.dycore_step(4)
+        out = [st.state_read(f)[..., 0] for f in (mpdc.FIELD_PS, mpdc.FIELD_THETA, mpdc.FIELD_U)]
+        for a, b in zip(out, ref):
+            assert np.array_equal(a, b)
+    st = mpdc.State(g, mpdc.MODEL_HDC, mpdc.POLICY_MIX, K=K, dt=600.0, sigma=ic.sigma_interfaces(K))
+    st.state_write(mpdc.FIELD_PS, s["ps"][:, None])
+    st.state_write(mpdc.FIELD_THETA, s["Theta"][:, :, None])
+    st.state_write(mpdc.FIELD_U, s["u"][:, :, None])
+    st.autotune()
+    _say("  autotuned " + str([st.get_kernel_launch(k) for k in range(4)]))
+    st.dycore_step(4)
+    out = [st.state_read(f)[..., 0] for f in (mpdc.FIELD_PS, mpdc.FIELD_THETA, mpdc.FIELD_U)]
+    for a, b in zip(out, ref):
+        assert np.array_equal(a, b)
     tr = ic.tracer_solid_body(m, 3, 2, seed=3000)
     tref = None
     for graph, launch in [(False, None), (True, None), (True, (0, 128))]:
@@ -185,6 +210,21 @@ def test_graph_replay_and_launch_shapes_are_bitwise_identical(mpdc, mesh_cache):
         if tref is None:
             tref = (dpi, q)
         assert np.array_equal(dpi, tref[0]) and np.array_equal(q, tref[1])
+    tr4 = ic.tracer_solid_body(m, 3, 4, seed=3000)
+    t4 = None
+    for vpl in (1, 2, 4):
+        _say("tracer G4 T=4 values per lane %d" % vpl)
+        st = mpdc.State(g, mpdc.MODEL_TRACER, mpdc.POLICY_MIX, K=3, T=4, dt=3000.0)
+        for kid in range(3):
+            st.set_kernel_launch(kid, vpl, 128)
+        st.state_write(mpdc.FIELD_TR_FLUX, tr4["F"])
+        st.state_write(mpdc.FIELD_TR_DPI, tr4["dpi"])
+        st.state_write(mpdc.FIELD_TR_Q, tr4["q"])
+        st.tracer_step(3)
+        q = st.state_read(mpdc.FIELD_TR_Q)
+        if t4 is None:
+            t4 = q
+        assert np.array_equal(q, t4)
 
 
 def test_diagnostics_match_oracle(mpdc, oracle_mod, mesh_cache):

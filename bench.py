@@ -62,6 +62,9 @@ def parse():
                    help="steps run with HIP events between launches for per-kernel durations")
     p.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                    help="only run a plain device copy of this many MiB (HBM counter calibration)")
+    p.add_argument("--shapes", default=None, metavar="JSON",
+                   help='fixed launch shapes instead of autotuning, e.g. {"mix": [[2,16],[2,256],[2,16],[2,512]], '
+                        '"dbl": [...]}: (values per lane, cells or threads per work-group) per kernel')
     return p.parse_args()
 
 
@@ -82,12 +85,14 @@ def build_inputs(w):
     return mesh, st
 
 
-def make_state(mpdc, g, w, st, policy):
+def make_state(mpdc, g, w, st, policy, shapes=None):
     from paper_2404_08849_amd.inputs import initial as ic
     K, M, T = w["K"], w["M"], w["T"]
     model = getattr(mpdc, "MODEL_" + w["model"])
     s = mpdc.State(g, model, policy, K=K, M=M, T=T, dt=w["dt"],
                    sigma=ic.sigma_interfaces(K) if w["model"] != "SW" else None)
+    for k, (v, grp) in enumerate(shapes or []):
+        s.set_kernel_launch(k, v, grp)
     if w["model"] == "SW":
         s.state_write(mpdc.FIELD_H, st["h"])
         s.state_write(mpdc.FIELD_U, st["u"])
@@ -118,14 +123,13 @@ def key_field(mpdc, w):
     return {"SW": mpdc.FIELD_H, "TRACER": mpdc.FIELD_TR_Q}.get(w["model"], mpdc.FIELD_PS)
 
 
-def timed_run(torch, mpdc, g, w, st, policy, steps, warmup, stream, autotune=True):
-    s = make_state(mpdc, g, w, st, policy)
-    shapes = None
-    if autotune:
+def timed_run(torch, mpdc, g, w, st, policy, steps, warmup, stream, autotune=True, fixed=None):
+    s = make_state(mpdc, g, w, st, policy, fixed)
+    if autotune and not fixed:
         with torch.cuda.stream(stream):
             s.autotune(stream=stream)
-        nk = 3 if w["model"] == "TRACER" else 4
-        shapes = [s.get_kernel_launch(k) for k in range(nk)]
+    nk = 3 if w["model"] == "TRACER" else 4
+    shapes = [list(s.get_kernel_launch(k)) for k in range(nk)]
     s.set_graph(True)
     with torch.cuda.stream(stream):
         step(s, w, warmup, stream)
@@ -151,11 +155,12 @@ def kernel_times(torch, s, w, nsteps, stream):
     return out
 
 
-def accuracy_run(torch, mpdc, g, w, st, stream):
-    """Both policies for the workload's own step count from the same input."""
+def accuracy_run(torch, mpdc, g, w, st, stream, shapes):
+    """Both policies for the workload's own step count from the same input, in
+    the launch shapes of the timed runs."""
     res = {}
     for name, pol in (("DBL", mpdc.POLICY_DBL), ("MIX", mpdc.POLICY_MIX)):
-        s = make_state(mpdc, g, w, st, pol)
+        s = make_state(mpdc, g, w, st, pol, shapes.get(name.lower()))
         with torch.cuda.stream(stream):
             step(s, w, w["steps"], stream)
             torch.cuda.synchronize()
@@ -190,6 +195,21 @@ def rel_l2(x, r):
     return float(np.sqrt(((x - r) ** 2).sum() / (r ** 2).sum()))
 
 
+def recorded_traffic(workload, kernel, shape, digest):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary of
+    this workload, if it was taken from these sources in this launch shape."""
+    from paper_2404_08849_amd.profsum import read_record
+    path = os.path.join(ROOT, "profiles", "%s_%s.md" % (kernel, workload.replace("-", "_")))
+    rec = read_record(path)
+    if not rec:
+        return None, "no counter summary for this kernel and workload"
+    if rec.get("source_sha256") != digest:
+        return None, "counters were taken from other library sources"
+    if rec.get("kernel") != kernel or [int(rec["values_per_lane"]), int(rec["group"])] != list(shape):
+        return None, "counters were taken in another launch shape %s" % [rec.get("values_per_lane"), rec.get("group")]
+    return float(rec["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+
+
 def copy_calibration(torch, mib):
     n = mib * (1 << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -218,14 +238,15 @@ def main():
     N, K, M, T = mesh["nCells"], w["K"], w["M"], w["T"]
     units = N * K * M
 
+    fixed = json.loads(args.shapes) if args.shapes else {}
     s_mix, sec_mix = timed_run(torch, mpdc, g, w, st, mpdc.POLICY_MIX, args.steps, args.warmup, stream,
-                               not args.no_autotune)
+                               not args.no_autotune, fixed.get("mix"))
     kt = kernel_times(torch, s_mix, w, args.profile_steps, stream)
     step_bytes_mix = s_mix.step_bytes()
     sec_dbl, kt_dbl, step_bytes_dbl, shapes_dbl = None, None, None, None
     if not args.no_dbl:
         s_dbl, sec_dbl = timed_run(torch, mpdc, g, w, st, mpdc.POLICY_DBL, args.steps, args.warmup, stream,
-                                   not args.no_autotune)
+                                   not args.no_autotune, fixed.get("dbl"))
         shapes_dbl = s_dbl.launch_shapes
         kt_dbl = kernel_times(torch, s_dbl, w, args.profile_steps, stream)
         step_bytes_dbl = s_dbl.step_bytes()
@@ -233,7 +254,11 @@ def main():
     # dominant kernel of the mixed step: the largest share of the step time
     dom = max(kt, key=lambda k: kt[k]["ms"] * kt[k]["launches"])
     ach = kt[dom]["bytes"] / (kt[dom]["ms"] * 1e-3) / 1e9
-    acc = accuracy_run(torch, mpdc, g, w, st, stream)
+    acc = accuracy_run(torch, mpdc, g, w, st, stream, {"mix": s_mix.launch_shapes, "dbl": shapes_dbl})
+    from paper_2404_08849_amd.profsum import source_digest
+    digest = source_digest()
+    names = KERNEL_NAMES["tracer" if w["model"] == "TRACER" else "dycore"]
+    traffic, traffic_src = recorded_traffic(args.workload, dom, s_mix.launch_shapes[names.index(dom)], digest)
     gate = {"mix_vs_dbl_l2": rel_l2(acc["MIX"], acc["DBL"]), "nonfinite": acc["MIX_nonfinite"] + acc["DBL_nonfinite"]}
 
     cpu = None
@@ -286,9 +311,10 @@ def main():
         "launch_shapes": {"mix": s_mix.launch_shapes, "dbl": shapes_dbl,
                           "note": "(values per lane, cells or threads per work-group) per kernel, autotuned"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": traffic_src,
                      "bytes_per_launch": kt[dom]["bytes"], "ms_per_launch": kt[dom]["ms"]},
         "cpu_baseline": cpu,
+        "source_sha256": digest,
     }
     if w["model"] == "TRACER":
         out["tracer_cell_level_steps_per_s"] = value * T

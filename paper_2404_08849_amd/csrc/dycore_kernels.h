@@ -13,6 +13,26 @@ enum { KERNEL_CELL_A = 0, KERNEL_VERTEX = 1, KERNEL_CELL_B = 2, KERNEL_EDGE = 3 
 // largest work-group of the column kernels (keeps 256 VGPRs available per lane)
 constexpr int kColumnThreads = 512;
 
+#ifndef MPDC_XCD_REMAP
+#define MPDC_XCD_REMAP 1
+#endif
+// The dispatcher hands work-groups to the eight XCDs in turn (group b to XCD
+// b mod 8), and each XCD has its own L2.  Renumbering the groups so that every
+// XCD walks one contiguous run of the curve-ordered cells, edges or vertices
+// keeps a stencil's neighbours in the L2 of the XCD that reads them.  The map
+// is a bijection of [0, gridDim.x): it moves work between XCDs, never changes
+// what a lane computes.
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ unsigned xcd_block() {
+#if MPDC_XCD_REMAP
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned q = nb / kXcds, r = nb % kXcds, x = b % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
+#else
+    return blockIdx.x;
+#endif
+}
+
 // Everything one dycore stage reads and writes.  Pointers of another model
 // or policy are null.  "_n": state at the start of the step; "_s": state of
 // the previous stage; "_o": output state of this stage.

@@ -154,7 +154,7 @@ template <int L> __device__ __forceinline__ ColLane col_lane(const StageArgs &a,
     const int tid = threadIdx.x;
     c.lc = tid / lanes;
     c.km0 = (tid - c.lc * lanes) * L;
-    c.i = blockIdx.x * a.cpb + c.lc;
+    c.i = (int)xcd_block() * a.cpb + c.lc;
     c.valid = (c.lc < a.cpb) && (c.i < a.mesh.N);
     return c;
 }
@@ -475,7 +475,7 @@ __global__ void __launch_bounds__(1024) k_vertex(StageArgs a) {
     const DevMesh &m = a.mesh;
     const int K = a.K, M = M1 ? 1 : a.M, KM = K * M;
     const int lanes = KM / L;
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long idx = (long)xcd_block() * blockDim.x + threadIdx.x;
     if (idx >= (long)m.V * lanes) return;
     const int vx = (int)(idx / lanes);
     const int km0 = (int)(idx - (long)vx * lanes) * L;
@@ -917,7 +917,7 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
     const DevMesh &m = a.mesh;
     const int K = a.K, M = M1 ? 1 : a.M, KM = K * M;
     const int lanes = KM / L;
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long idx = (long)xcd_block() * blockDim.x + threadIdx.x;
     if (idx >= (long)m.E * lanes) return;
     const int e = (int)(idx / lanes);
     const int km0 = (int)(idx - (long)e * lanes) * L;
@@ -1047,7 +1047,7 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
 template <int MODEL>
 __global__ void k_shadows(StageArgs a) {
     const int KM = a.K * a.M;
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long idx = (long)xcd_block() * blockDim.x + threadIdx.x;
     const long nE = (long)a.mesh.E * KM, nC = (long)a.mesh.N * KM;
     if (idx < nE) a.u32_o[idx] = (float)a.u_o[idx];
     if (MODEL != MODEL_SW && a.th32_o && idx < nC) {

@@ -54,7 +54,7 @@ template <int L> __device__ __forceinline__ TLane tracer_lane(const TracerArgs &
     TLane r;
     const int lanes_k = a.T / L;
     const int lanes = a.K * lanes_k;
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long idx = (long)xcd_block() * blockDim.x + threadIdx.x;
     r.ok = idx < (long)a.mesh.N * lanes;
     r.i = (int)(idx / lanes);
     const int rem = (int)(idx - (long)r.i * lanes);

@@ -260,6 +260,7 @@ StageArgs stage_args(const mpdc_state *st, int s) {
     a.p0 = st->cfg.p0;
     a.ptop = st->cfg.ptop;
     a.kappa = st->cfg.rd / st->cfg.cp;
+    a.inv_p0 = 1.0 / st->cfg.p0;
     a.gamma = st->cfg.cp / (st->cfg.cp - st->cfg.rd);
     a.dsig = st->dsig;
     a.sig = st->sig;

@@ -42,7 +42,7 @@ struct StageArgs {
     int cpb;          // cells per work-group of the column kernels
     int flat_block;   // threads per work-group of the flat kernels
     int vpl;          // (k, m) values per lane of this launch (1, 2; flat kernels also 4)
-    double dts, grav, rd, cp, p0, ptop, kappa, gamma;
+    double dts, grav, rd, cp, p0, ptop, kappa, gamma, inv_p0;
     const double *dsig;  // [K]
     const double *sig;   // [K+1]
     const double *ps_n, *Th_n, *u_n, *w_n, *phi_n;

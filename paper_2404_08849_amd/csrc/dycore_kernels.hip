@@ -65,6 +65,16 @@ template <typename T> __device__ __forceinline__ void ld6(const T *p, T out[6]) 
     out[0] = a.v[0]; out[1] = a.v[1]; out[2] = b.v[0]; out[3] = b.v[1]; out[4] = c.v[0]; out[5] = c.v[1];
 }
 
+// a * b + c with one rounding.  The library is built without FMA contraction,
+// so every fused operation is written out and is the same in every template
+// instance (the results do not depend on the launch shape).
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// x^y for x > 0 as exp(y log x) (the exponents here are fixed gas constants
+// and x a pressure ratio near 1, so this stays within a few ulps of pow)
+__device__ __forceinline__ double powpos(double x, double y) { return exp(y * log(x)); }
+
 template <typename R> __device__ __forceinline__ const R *u_prev_ptr(const StageArgs &a) {
     if constexpr (sizeof(R) == 8) return a.u_s;
     else return a.u32_s;
@@ -590,41 +600,62 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                 else Fs[s][j] = (float)dpe * u.v[j];
             }
             if constexpr (MODEL != MODEL_SW) {
-                const int side = (cdiv[s] > (R)0) ? 0 : 1;   // i is c1 of e when its outward sign is +
-                R th_n[L];
-                theta_prev<MODEL, R, L>(a, nb, KM, km0, dsg, psn, th_n);
-                const long hb = (long)nb * 3 * KM + km0;
-                const Pack<R, L> b0 = ldp<R, L>(Hs + hb), b1 = ldp<R, L>(Hs + hb + KM), b2 = ldp<R, L>(Hs + hb + 2 * KM);
-                const R *ds = hdir + (long)e * 6 + side * 3;        // direction in i's frame
-                const R *dn = hdir + (long)e * 6 + (1 - side) * 3;  // direction in nb's frame
-                const R c = d2[e];
+                // Third-order upwind edge value: with the upwind weight 1 the two
+                // second-derivative terms reduce to -d^2/6 times the second
+                // derivative (along the edge) of the upwind cell alone.  Fs is the
+                // flux along n_e (c1 -> c2), the same number from either cell.
+                const bool c1 = cdiv[s] > (R)0;                 // i is c1 of e
+                bool up_i[L], need_n = false;
 #pragma unroll
                 for (int j = 0; j < L; j++) {
-                    const R qi = Hi0[j] * ds[0] + Hi1[j] * ds[1] + Hi2[j] * ds[2];
-                    const R qn = b0.v[j] * dn[0] + b1.v[j] * dn[1] + b2.v[j] * dn[2];
-                    const R q1 = side ? th_n[j] : th_i[j], q2 = side ? th_i[j] : th_n[j];
-                    const R hh1 = side ? qn : qi, hh2 = side ? qi : qn;
-                    const R F = Fs[s][j];   // flux along n_e (c1 -> c2), the same number from either cell
-                    const R sg = (F >= (R)0) ? (R)1 : (R)-1;
-                    const R tv = (R)0.5 * (q1 + q2) - c * (hh1 + hh2) + sg * c * (hh2 - hh1);
-                    hdiv[j] += cdiv[s] * (F * tv);
+                    up_i[j] = (Fs[s][j] >= (R)0) == c1;
+                    need_n = need_n || !up_i[j];
+                }
+                R th_n[L];
+                theta_prev<MODEL, R, L>(a, nb, KM, km0, dsg, psn, th_n);
+                const R *ds = hdir + (long)e * 6 + (c1 ? 0 : 3);   // direction in i's frame
+                const R *dn = hdir + (long)e * 6 + (c1 ? 3 : 0);   // direction in nb's frame
+                Pack<R, L> b0, b1, b2;
+#pragma unroll
+                for (int j = 0; j < L; j++) b0.v[j] = b1.v[j] = b2.v[j] = (R)0;
+                if (need_n) {
+                    const long hb = (long)nb * 3 * KM + km0;
+                    b0 = ldp<R, L>(Hs + hb);
+                    b1 = ldp<R, L>(Hs + hb + KM);
+                    b2 = ldp<R, L>(Hs + hb + 2 * KM);
+                }
+                const R m2c = (R)-2 * d2[e];
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    const R hi = fmar(Hi0[j], ds[0], fmar(Hi1[j], ds[1], Hi2[j] * ds[2]));
+                    const R hn = fmar(b0.v[j], dn[0], fmar(b1.v[j], dn[1], b2.v[j] * dn[2]));
+                    const R tv = fmar(m2c, up_i[j] ? hi : hn, (R)0.5 * (th_i[j] + th_n[j]));
+                    hdiv[j] = fmar(cdiv[s], Fs[s][j] * tv, hdiv[j]);
                 }
             }
         }
         // ---- this cell's share of Coriolis - grad K on each of its edges (TRiSK) ----
+        // With Q_s = q_v(s) + q_v(s+1) (twice the PV of edge s) the half sum
+        //   sum_t w F_t (q_e(s) + q_e(t)) / 2 = Q_s sum_t w' F_t + sum_t w' F_t Q_t
+        // with w' = w / 4 (the table holds w l_t / d_s already divided by 4).
         {
-            R QV[kCellSlots][L];
+            R Q[kCellSlots][L], G[kCellSlots][L];
+            {
+                R QV[kCellSlots][L];
 #pragma unroll
-            for (int s = 0; s < kCellSlots; s++) {
-                const Pack<R, L> q = ldp<R, L>(a.qv_in<R>() + (long)cv[s] * KM + km0);
+                for (int s = 0; s < kCellSlots; s++) {
+                    const Pack<R, L> q = ldp<R, L>(a.qv_in<R>() + (long)cv[s] * KM + km0);
 #pragma unroll
-                for (int j = 0; j < L; j++) QV[s][j] = q.v[j];
+                    for (int j = 0; j < L; j++) QV[s][j] = q.v[j];
+                }
+#pragma unroll
+                for (int s = 0; s < kCellSlots; s++)
+#pragma unroll
+                    for (int j = 0; j < L; j++) {
+                        Q[s][j] = QV[s][j] + QV[(s + 1) % kCellSlots][j];
+                        G[s][j] = Fs[s][j] * Q[s][j];
+                    }
             }
-            R qe[kCellSlots][L];
-#pragma unroll
-            for (int s = 0; s < kCellSlots; s++)
-#pragma unroll
-                for (int j = 0; j < L; j++) qe[s][j] = (R)0.5 * (QV[s][j] + QV[(s + 1) % kCellSlots][j]);
             const Pack<R, L> kp = ldp<R, L>(a.ke_in<R>() + (long)i * KM + km0);
             const R *tk = pick<R>(m.c_tk, m.c_tk32) + (long)i * kCellSlots * kCellSlots;
             R *qh = a.qh_out<R>();
@@ -637,13 +668,15 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                 Pack<R, L> out;
 #pragma unroll
                 for (int j = 0; j < L; j++) {
-                    R acc = 0;
+                    const int s1 = (s + 1) % kCellSlots;
+                    R A = w[s1] * Fs[s1][j], B = w[s1] * G[s1][j];
 #pragma unroll
-                    for (int t = 1; t < kCellSlots; t++) {
+                    for (int t = 2; t < kCellSlots; t++) {
                         const int sp = (s + t) % kCellSlots;
-                        acc += w[sp] * Fs[sp][j] * ((R)0.5 * (qe[s][j] + qe[sp][j]));
+                        A = fmar(w[sp], Fs[sp][j], A);
+                        B = fmar(w[sp], G[sp][j], B);
                     }
-                    out.v[j] = acc + cgk[s] * kp.v[j];
+                    out.v[j] = fmar(cgk[s], kp.v[j], fmar(Q[s][j], A, B));
                 }
                 const int side = (cdiv[s] > (R)0) ? 0 : 1;
                 stp<R, L>(qh + ((long)e * 2 + side) * KM + km0, out);
@@ -724,7 +757,7 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                     const double dpn = dsg[j] * (ps_new[j] - a.ptop);
                     const double pk = 0.5 * (pit + pib);
                     const double th = Th_new[j] / dpn;
-                    const double T = th * pow(pk / a.p0, a.kappa);
+                    const double T = th * powpos(pk * a.inv_p0, a.kappa);
                     al[j] = a.rd * T / pk;
                     sA[lc * KM + km0 + j] = al[j] * dpn;
                     th32.v[j] = (float)th;
@@ -791,7 +824,7 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                     dpn[j] = dsg[j] * (ps_new[j] - a.ptop);
                     th32.v[j] = (float)(Th_new[j] / dpn[j]);
                     const double dphi = phs_k[j] - phs_k1[j];
-                    const double p = a.p0 * pow(a.rd * Th_new[j] / (a.p0 * dphi), a.gamma);
+                    const double p = a.p0 * powpos(a.rd * Th_new[j] / (a.p0 * dphi), a.gamma);
                     sP[base + km0 + j] = p;
                     sC[base + km0 + j] = a.gamma * a.grav * a.dts * p / dphi;
                 }
@@ -875,7 +908,7 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                     const int k = v.k[j], mm = v.mm0 + (M1 ? 0 : j);
                     const double phb = sPhi[lc * K1 * M + (k + 1) * M + mm];
                     const double dphi = phk[j] - phb;
-                    const double pk = a.p0 * pow(a.rd * Th_new[j] / (a.p0 * dphi), a.gamma);
+                    const double pk = a.p0 * powpos(a.rd * Th_new[j] / (a.p0 * dphi), a.gamma);
                     sPn[base + k * M + mm] = pk;
                     alp.v[j] = dphi / dpn[j];
                     pmp.v[j] = pk;

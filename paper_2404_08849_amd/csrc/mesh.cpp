@@ -224,8 +224,9 @@ std::string derive_tables(const mpdc_mesh_desc *d, HostTables &t) {
                 double s_epi = (ce[2 * ep] == i) ? 1.0 : -1.0;
                 double w = s_ei * s_epi * (0.5 - acc);
                 if (pos >= kTriskSlots) return msg("TRiSK stencil wider than 10 edges", e);
-                // cell i's half-stencil row of edge e (slot j0), column slot j
-                t.c_tk[(i * S + j0) * S + j] = w * d->lEdge[ep] / d->dEdge[e];
+                // cell i's half-stencil row of edge e (slot j0), column slot j,
+                // divided by 4 (the two PV means of the kernels' factored sum)
+                t.c_tk[(i * S + j0) * S + j] = 0.25 * (w * d->lEdge[ep] / d->dEdge[e]);
                 t.trisk_edge.push_back(ep);
                 t.trisk_w.push_back(w);
                 pos++;

@@ -37,7 +37,7 @@ struct DevMesh {
     const float *c_gk32;
     const double *c_hess;   // [N][3][6] slot differences -> (Hxx, Hxy, Hyy)
     const float *c_hess32;
-    const double *c_tk;     // [N][6][6] TRiSK half-stencil: w_{e_j,e_j'} l_{e_j'} / d_{e_j} from cell i
+    const double *c_tk;     // [N][6][6] TRiSK half-stencil: w_{e_j,e_j'} l_{e_j'} / (4 d_{e_j}) from cell i
     const float *c_tk32;
     const double *c_area;   // [N]
     // edges

@@ -30,6 +30,10 @@ template <typename R> __device__ __forceinline__ R rinf();
 template <> __device__ __forceinline__ double rinf<double>() { return __builtin_huge_val(); }
 template <> __device__ __forceinline__ float rinf<float>() { return __builtin_huge_valf(); }
 
+// a * b + c with one rounding (the library is built without FMA contraction)
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T, int L> struct alignas(sizeof(T) * L) TPack {
     T v[L];
 };
@@ -93,38 +97,56 @@ __device__ __forceinline__ void load_stencil(const TracerArgs &a, int i, int k, 
 
 // Low-order (upwind) flux and antidiffusive flux A = F q~ - F^L of the edge in
 // slot s of cell i, for L tracers.  q~ is the third-order upwind edge value of
-// q_s built from both cells' second derivatives along the edge direction.
+// q_s: with the upwind weight 1 the two second-derivative terms reduce to
+// -d^2/6 times the second derivative along the edge of the upwind cell alone,
+// so only the upwind cell's q^n and second derivatives are read.  The flux
+// F_e is one FP64 number per edge-level, so the upwind cell is the same for
+// the L tracers of a lane.  qn_nb, if given, is q^n of the neighbour already
+// loaded by the caller.
 template <typename R, int L>
-__device__ __forceinline__ void edge_fluxes(const TracerArgs &a, const Stencil<R> &st, int s, int i, int k, int t0,
-                                            const R qn_i[L], const R qs_i[L], const R Hi[3][L], R FL[L], R Aa[L]) {
+__device__ __forceinline__ void edge_fluxes(const TracerArgs &a, const Stencil<R> &st, int s, int k, int t0,
+                                            const R qn_i[L], const R qs_i[L], const R Hi[3][L],
+                                            const TPack<R, L> *qn_nb, R FL[L], R Aa[L]) {
     const DevMesh &m = a.mesh;
     const int KT = a.K * a.T;
     const int e = st.ce[s], nb = st.cn[s];
-    const bool self_c1 = st.cdiv[s] > (R)0;
-    const long on = (long)nb * KT + (long)k * a.T + t0;
-    const TPack<R, L> qn_n = tld<R, L>((const R *)a.q_n + on);
-    const TPack<R, L> qs_n = tld<R, L>((const R *)a.q_s + on);
-    const R *Hb = (const R *)a.hq + (long)nb * 3 * KT + (long)k * a.T + t0;
-    const TPack<R, L> h0 = tld<R, L>(Hb), h1 = tld<R, L>(Hb + KT), h2 = tld<R, L>(Hb + 2 * KT);
-    R hd[6];
-    tld6<R>(tpick<R>(m.e_hdir, m.e_hdir32) + (long)e * 6, hd);
-    const R c = tpick<R>(m.e_d2, m.e_d2_32)[e];
     const double Fd = st.F[s];
+    const bool fwd = Fd >= 0.0;                              // c1 is upwind
+    const bool up_self = fwd == (st.cdiv[s] > (R)0);
+    const long on = (long)nb * KT + (long)k * a.T + t0;
+    const TPack<R, L> qs_n = tld<R, L>((const R *)a.q_s + on);
+    R qup[L], H0[L], H1[L], H2[L];
+    if (up_self) {
+#pragma unroll
+        for (int j = 0; j < L; j++) {
+            qup[j] = qn_i[j];
+            H0[j] = Hi[0][j];
+            H1[j] = Hi[1][j];
+            H2[j] = Hi[2][j];
+        }
+    } else {
+        const TPack<R, L> qn_n = qn_nb ? *qn_nb : tld<R, L>((const R *)a.q_n + on);
+        const R *Hb = (const R *)a.hq + (long)nb * 3 * KT + (long)k * a.T + t0;
+        const TPack<R, L> h0 = tld<R, L>(Hb), h1 = tld<R, L>(Hb + KT), h2 = tld<R, L>(Hb + 2 * KT);
+#pragma unroll
+        for (int j = 0; j < L; j++) {
+            qup[j] = qn_n.v[j];
+            H0[j] = h0.v[j];
+            H1[j] = h1.v[j];
+            H2[j] = h2.v[j];
+        }
+    }
+    // the neighbour direction in the upwind cell's frame (c1: first triple)
+    const R *dir = tpick<R>(m.e_hdir, m.e_hdir32) + (long)e * 6 + (fwd ? 0 : 3);
+    const R d0 = dir[0], d1 = dir[1], d2 = dir[2];
+    const R m2c = (R)-2 * tpick<R>(m.e_d2, m.e_d2_32)[e];
     const R F = (R)Fd;
-    const R sg = (Fd >= 0.0) ? (R)1 : (R)-1;
-    // frame directions: c1 uses hd[0..2], c2 uses hd[3..5]
-    const R *di = self_c1 ? hd : hd + 3;
-    const R *dn = self_c1 ? hd + 3 : hd;
 #pragma unroll
     for (int j = 0; j < L; j++) {
-        const R qid = Hi[0][j] * di[0] + Hi[1][j] * di[1] + Hi[2][j] * di[2];
-        const R qnd = h0.v[j] * dn[0] + h1.v[j] * dn[1] + h2.v[j] * dn[2];
-        const R q1 = self_c1 ? qs_i[j] : qs_n.v[j], q2 = self_c1 ? qs_n.v[j] : qs_i[j];
-        const R d1 = self_c1 ? qid : qnd, d2 = self_c1 ? qnd : qid;
-        const R up1 = self_c1 ? qn_i[j] : qn_n.v[j], up2 = self_c1 ? qn_n.v[j] : qn_i[j];
-        FL[j] = F * ((Fd >= 0.0) ? up1 : up2);
-        const R qe = (R)0.5 * (q1 + q2) - c * (d1 + d2) + sg * c * (d2 - d1);
-        Aa[j] = F * qe - FL[j];
+        const R h = fmar(H0[j], d0, fmar(H1[j], d1, H2[j] * d2));
+        const R qe = fmar(m2c, h, (R)0.5 * (qs_i[j] + qs_n.v[j]));
+        FL[j] = F * qup[j];
+        Aa[j] = fmar(F, qe, -FL[j]);
     }
 }
 
@@ -158,10 +180,10 @@ __global__ void __launch_bounds__(kTracerThreads) k_tr_low(TracerArgs a) {
 #pragma unroll
         for (int j = 0; j < L; j++) {
             const R dq = qsn.v[j] - qsi.v[j];
-            h[0][j] += ch[0][s] * dq;
-            h[1][j] += ch[1][s] * dq;
-            h[2][j] += ch[2][s] * dq;
-            dL[j] += st.cdiv[s] * ((R)Fd * (up_self ? qni.v[j] : qnn.v[j]));
+            h[0][j] = fmar(ch[0][s], dq, h[0][j]);
+            h[1][j] = fmar(ch[1][s], dq, h[1][j]);
+            h[2][j] = fmar(ch[2][s], dq, h[2][j]);
+            dL[j] = fmar(st.cdiv[s], (R)Fd * (up_self ? qni.v[j] : qnn.v[j]), dL[j]);
         }
     }
     R *H = (R *)a.hq + (long)i * 3 * KT + (long)k * a.T + t0;
@@ -221,7 +243,7 @@ __global__ void __launch_bounds__(kTracerThreads) k_tr_limit(TracerArgs a) {
         const long on = (long)st.cn[s] * KT + (long)k * a.T + t0;
         const TPack<R, L> qnn = tld<R, L>(qn + on), qtn = tld<R, L>(qtd + on);
         R FL[L], Aa[L];
-        edge_fluxes<R, L>(a, st, s, i, k, t0, qn_i, qs_i, Hi, FL, Aa);
+        edge_fluxes<R, L>(a, st, s, k, t0, qn_i, qs_i, Hi, &qnn, FL, Aa);
 #pragma unroll
         for (int j = 0; j < L; j++) {
             qmax[j] = fmax(qmax[j], fmax(qnn.v[j], qtn.v[j]));
@@ -269,14 +291,14 @@ __global__ void __launch_bounds__(kTracerThreads) k_tr_update(TracerArgs a) {
         const long on = (long)st.cn[s] * KT + (long)k * a.T + t0;
         const TPack<R, L> rpn = tld<R, L>(rp + on), rmn = tld<R, L>(rm + on);
         R FL[L], Aa[L];
-        edge_fluxes<R, L>(a, st, s, i, k, t0, qn_i, qs_i, Hi, FL, Aa);
+        edge_fluxes<R, L>(a, st, s, k, t0, qn_i, qs_i, Hi, nullptr, FL, Aa);
         const bool self_c1 = st.cdiv[s] > (R)0;
 #pragma unroll
         for (int j = 0; j < L; j++) {
             const R rp1 = self_c1 ? rpi.v[j] : rpn.v[j], rp2 = self_c1 ? rpn.v[j] : rpi.v[j];
             const R rm1 = self_c1 ? rmi.v[j] : rmn.v[j], rm2 = self_c1 ? rmn.v[j] : rmi.v[j];
             const R C = (Aa[j] >= (R)0) ? fmin(rp2, rm1) : fmin(rp1, rm2);
-            dT[j] += st.cdiv[s] * (FL[j] + C * Aa[j]);
+            dT[j] = fmar(st.cdiv[s], fmar(C, Aa[j], FL[j]), dT[j]);
         }
     }
     TPack<R, L> qo;

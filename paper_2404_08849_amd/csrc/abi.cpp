@@ -53,8 +53,8 @@ int hip_fail(hipError_t e, const char *where) {
 // ---------------- mesh workspace layout ----------------
 struct MeshLayout {
     int *c_edge, *c_nbr, *c_vert;
-    double *c_div, *c_ke, *c_gk, *c_hess, *c_tk, *c_area;
-    float *c_div32, *c_ke32, *c_gk32, *c_hess32, *c_tk32;
+    double *c_div, *c_ke, *c_gk, *c_hess, *c_hd, *c_tk, *c_area;
+    float *c_div32, *c_ke32, *c_gk32, *c_hess32, *c_hd32, *c_tk32;
     int *e_cell, *e_vert;
     double *e_dinv, *e_d2, *e_hdir;
     float *e_dinv32, *e_d2_32, *e_hdir32;
@@ -75,12 +75,14 @@ MeshLayout mesh_layout(void *base, long N, long E, long V) {
     L.c_ke = c.take<double>(N * S);
     L.c_gk = c.take<double>(N * S);
     L.c_hess = c.take<double>(N * 3 * S);
+    L.c_hd = c.take<double>(N * S * 8);
     L.c_tk = c.take<double>(N * S * S);
     L.c_area = c.take<double>(N);
     L.c_div32 = c.take<float>(N * S);
     L.c_ke32 = c.take<float>(N * S);
     L.c_gk32 = c.take<float>(N * S);
     L.c_hess32 = c.take<float>(N * 3 * S);
+    L.c_hd32 = c.take<float>(N * S * 8);
     L.c_tk32 = c.take<float>(N * S * S);
     L.e_cell = c.take<int>(2 * E);
     L.e_vert = c.take<int>(2 * E);
@@ -240,7 +242,10 @@ int col_lanes(const mpdc_state *st, int k) { return st->K * st->M / vpl_of(st, k
 int cpb_of(const mpdc_state *st, int k) {
     if (st->model == MPDC_MODEL_TRACER) return st->launch.flat[k];
     if (st->launch.cpb[k] > 0) return st->launch.cpb[k];
-    return std::max(1, 256 / col_lanes(st, k));
+    // about 256 lanes, halved while the staged tables would take over 32 KiB of LDS
+    int cpb = std::max(1, 256 / col_lanes(st, k));
+    while (cpb > 1 && stage_lds_bytes(st->model, st->policy, k, cpb, st->K, st->M) > 32768) cpb /= 2;
+    return cpb;
 }
 
 StageArgs stage_args(const mpdc_state *st, int s) {
@@ -465,12 +470,14 @@ int mpdc_mesh_create(const mpdc_mesh_desc *d, void *dev_ws, size_t ws_bytes, voi
         put(host, dev_ws, L.c_ke, t.c_ke);
         put(host, dev_ws, L.c_gk, t.c_gk);
         put(host, dev_ws, L.c_hess, t.c_hess);
+        put(host, dev_ws, L.c_hd, t.c_hd);
         put(host, dev_ws, L.c_tk, t.c_tk);
         put(host, dev_ws, L.c_area, t.c_area);
         put32(host, dev_ws, L.c_div32, t.c_div);
         put32(host, dev_ws, L.c_ke32, t.c_ke);
         put32(host, dev_ws, L.c_gk32, t.c_gk);
         put32(host, dev_ws, L.c_hess32, t.c_hess);
+        put32(host, dev_ws, L.c_hd32, t.c_hd);
         put32(host, dev_ws, L.c_tk32, t.c_tk);
         put(host, dev_ws, L.e_cell, t.e_cell);
         put(host, dev_ws, L.e_vert, t.e_vert);
@@ -499,6 +506,7 @@ int mpdc_mesh_create(const mpdc_mesh_desc *d, void *dev_ws, size_t ws_bytes, voi
         D.c_edge = L.c_edge; D.c_nbr = L.c_nbr; D.c_vert = L.c_vert;
         D.c_div = L.c_div; D.c_div32 = L.c_div32; D.c_ke = L.c_ke; D.c_ke32 = L.c_ke32;
         D.c_gk = L.c_gk; D.c_gk32 = L.c_gk32; D.c_hess = L.c_hess; D.c_hess32 = L.c_hess32;
+        D.c_hd = L.c_hd; D.c_hd32 = L.c_hd32;
         D.c_tk = L.c_tk; D.c_tk32 = L.c_tk32; D.c_area = L.c_area;
         D.e_cell = L.e_cell; D.e_vert = L.e_vert; D.e_dinv = L.e_dinv; D.e_dinv32 = L.e_dinv32;
         D.e_d2 = L.e_d2; D.e_d2_32 = L.e_d2_32; D.e_hdir = L.e_hdir; D.e_hdir32 = L.e_hdir32;
@@ -707,7 +715,7 @@ static int check_group(const mpdc_state *st, int k, int L, int group) {
         const long lanes = (long)st->K * st->M / L;
         if (group < 1 || group * lanes > kColumnThreads)
             return fail(MPDC_E_INVAL, "cells per work-group times the column's lanes must be 1..512");
-        if (stage_lds_bytes(st->model, k, group, st->K, st->M) > 65536)
+        if (stage_lds_bytes(st->model, st->policy, k, group, st->K, st->M) > 65536)
             return fail(MPDC_E_INVAL, "column work-group would need more than 64 KiB of LDS");
         return MPDC_OK;
     }
@@ -785,7 +793,7 @@ static int step_common(mpdc_state *st, int nsteps, void *stream, bool tracer) {
         return fail(MPDC_E_STATE, tracer ? "tracer_step on a dycore state" : "dycore_step on a tracer state");
     hipStream_t s = (hipStream_t)stream;
     if (st->model == MPDC_MODEL_NDC &&
-        stage_lds_bytes(st->model, KERNEL_CELL_B, cpb_of(st, KERNEL_CELL_B), st->K, st->M) > 65536)
+        stage_lds_bytes(st->model, st->policy, KERNEL_CELL_B, cpb_of(st, KERNEL_CELL_B), st->K, st->M) > 65536)
         return fail(MPDC_E_UNSUPPORTED, "column too tall for the LDS of one work-group");
     for (int n = 0; n < nsteps; n++) {
         int parity = tracer ? st->parity : 0;

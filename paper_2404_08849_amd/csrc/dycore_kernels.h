@@ -71,9 +71,42 @@ struct StageArgs {
     template <typename R> __device__ const R *qh_in() const { return (const R *)qh; }
 };
 
+// Stencil tables of the cpb columns of a column work-group, staged once in LDS
+// (all K*M/L lanes of a column need the same ones).  Byte offsets from the
+// start of the area; every region starts on 16 bytes.  rsize is the size of
+// the advective precision R; model-specific tables are left out where unused.
+struct ColTabLayout {
+    size_t ce, cn, cv;    // int [cpb][6]: edges, neighbours, vertices
+    size_t ps;            // double [cpb][7][M]: ps_s of the cell (slot 0), then of its neighbours
+    size_t psn, dps;      // double [cpb][M]: ps_n and the column mass tendency (cell_b)
+    size_t r;             // cell_a: c_div (FP64), c_ke, c_hess; cell_b: c_div, c_gk, c_tk
+    size_t hd;            // cell_b: c_hd [cpb][6][8]
+    size_t bytes;
+};
+__host__ __device__ inline size_t coltab_round(size_t b) { return (b + 15) & ~(size_t)15; }
+__host__ __device__ inline ColTabLayout coltab_layout(int model, int which, int cpb, int M, int rsize) {
+    ColTabLayout t;
+    size_t o = 0;
+    t.ce = o; o += coltab_round((size_t)cpb * 24);
+    t.cn = o; o += coltab_round((size_t)cpb * 24);
+    t.cv = o; o += coltab_round((size_t)cpb * 24);
+    t.ps = o; o += coltab_round((size_t)cpb * 7 * M * 8);
+    t.psn = o; o += coltab_round((size_t)cpb * M * 8);
+    t.dps = o; o += coltab_round((size_t)cpb * M * 8);
+    t.r = o;
+    // cell_a: c_div in FP64, c_ke and c_hess in R; cell_b: c_div, c_gk, c_tk in R
+    if (which == KERNEL_CELL_A) o += (size_t)cpb * (6 * 8 + (6 + (model == MODEL_SW ? 0 : 18)) * rsize);
+    else o += (size_t)cpb * (6 + 6 + 36) * rsize;
+    o = coltab_round(o);
+    t.hd = o;
+    if (which == KERNEL_CELL_B && model != MODEL_SW) o += (size_t)cpb * 6 * 8 * rsize;
+    t.bytes = coltab_round(o);
+    return t;
+}
+
 hipError_t launch_stage_kernel(int model, int policy, const StageArgs &a, int which, hipStream_t s);
 hipError_t launch_shadows(int model, const StageArgs &a, hipStream_t s);
-size_t stage_lds_bytes(int model, int which, int cpb, int K, int M);
+size_t stage_lds_bytes(int model, int policy, int which, int cpb, int K, int M);
 // (k, m) values per lane of the dycore kernels: 2 when K*M splits evenly
 int values_per_lane(int K, int M);
 

@@ -153,6 +153,113 @@ __device__ __forceinline__ void theta_prev(const StageArgs &a, int c, long KM, l
     }
 }
 
+// LDS of a column kernel's own column work (scans, column solve), in bytes;
+// the staged tables follow it
+__host__ __device__ inline size_t col_lds_bytes(int model, int which, int cpb, int K, int M) {
+    const size_t KM = (size_t)K * M;
+    size_t b = 0;
+    if (which == KERNEL_CELL_A) b = cpb * KM * 8 + (model == MODEL_NDC ? cpb * (K + 1) * (size_t)M * 8 : 0);
+    if (which == KERNEL_CELL_B && model != MODEL_SW)
+        b = model == MODEL_NDC ? cpb * (10 * KM + (K + 1) * (size_t)M) * 8 : cpb * KM * 8;
+    return coltab_round(b);
+}
+
+// Pointers to the staged tables of a column work-group
+template <typename R> struct ColTab {
+    int *ce, *cn, *cv;
+    double *ps, *psn, *dps;
+    double *div64;           // cell_a: [cpb][6]
+    R *div, *gk, *ke, *hs, *tk, *hd;
+    __device__ ColTab(char *base, int model, int which, int cpb, int M) {
+        const ColTabLayout l = coltab_layout(model, which, cpb, M, (int)sizeof(R));
+        ce = (int *)(base + l.ce);
+        cn = (int *)(base + l.cn);
+        cv = (int *)(base + l.cv);
+        ps = (double *)(base + l.ps);
+        psn = (double *)(base + l.psn);
+        dps = (double *)(base + l.dps);
+        char *r = base + l.r;
+        div64 = (double *)r;
+        div = (R *)r;
+        hd = (R *)(base + l.hd);
+        if (which == KERNEL_CELL_A) {
+            ke = (R *)(r + (size_t)cpb * 48);
+            hs = ke + (size_t)cpb * 6;
+            gk = tk = nullptr;
+        } else {
+            gk = div + (size_t)cpb * 6;
+            tk = gk + (size_t)cpb * 6;
+            ke = hs = nullptr;
+        }
+    }
+};
+
+// Load the tables of the work-group's columns [i0, i0 + ncol) into LDS with
+// all its threads (contiguous rows; the neighbours' surface pressures through
+// c_nbr), then synchronise.
+template <int WHICH, int MODEL, typename R, bool M1>
+__device__ __forceinline__ void stage_columns(const StageArgs &a, const ColTab<R> &t) {
+    const DevMesh &m = a.mesh;
+    const int M = M1 ? 1 : a.M;
+    const int nthr = blockDim.x, tid = threadIdx.x;
+    const long i0 = (long)xcd_block() * a.cpb;
+    const int ncol = (int)((long)m.N - i0 < (long)a.cpb ? (long)m.N - i0 : (long)a.cpb);
+    const int n6 = ncol * kCellSlots;
+    for (int x = tid; x < n6; x += nthr) {
+        const long g = i0 * kCellSlots + x;
+        t.ce[x] = m.c_edge[g];
+        t.cn[x] = m.c_nbr[g];
+        if constexpr (WHICH == KERNEL_CELL_A) {
+            t.div64[x] = m.c_div[g];
+            t.ke[x] = pick<R>(m.c_ke, m.c_ke32)[g];
+        } else {
+            t.cv[x] = m.c_vert[g];
+            t.div[x] = pick<R>(m.c_div, m.c_div32)[g];
+            t.gk[x] = pick<R>(m.c_gk, m.c_gk32)[g];
+        }
+    }
+    if constexpr (WHICH == KERNEL_CELL_A) {
+        if constexpr (MODEL != MODEL_SW) {
+            const R *h = pick<R>(m.c_hess, m.c_hess32) + i0 * 3 * kCellSlots;
+            for (int x = tid; x < 3 * n6; x += nthr) t.hs[x] = h[x];
+        }
+    } else {
+        const R *tk = pick<R>(m.c_tk, m.c_tk32) + i0 * kCellSlots * kCellSlots;
+        for (int x = tid; x < kCellSlots * n6; x += nthr) t.tk[x] = tk[x];
+        if constexpr (MODEL != MODEL_SW) {
+            const R *hd = pick<R>(m.c_hd, m.c_hd32) + i0 * kCellSlots * 8;
+            for (int x = tid; x < 8 * n6; x += nthr) t.hd[x] = hd[x];
+        }
+        if constexpr (MODEL != MODEL_SW) {
+            for (int x = tid; x < ncol * M; x += nthr) {
+                t.psn[x] = a.ps_n[i0 * M + x];
+                t.dps[x] = a.dps[i0 * M + x];
+            }
+        }
+    }
+    const int per = 7 * M;
+    for (int x = tid; x < ncol * per; x += nthr) {
+        const int c = x / per, r = x - c * per;
+        const int sl = r / M, mm = r - sl * M;
+        const long cell = sl == 0 ? i0 + c : (long)m.c_nbr[(i0 + c) * kCellSlots + sl - 1];
+        t.ps[x] = a.ps_s[cell * M + mm];
+    }
+    __syncthreads();
+}
+
+// 2-D field of the L values from a staged row [M]
+template <int L, bool M1> __device__ __forceinline__ void ld2d_s(const double *row, int mm0, double out[L]) {
+    if constexpr (M1) {
+        const double s = row[0];
+#pragma unroll
+        for (int j = 0; j < L; j++) out[j] = s;
+    } else {
+        const Pack<double, L> s = ldp<double, L>(row + mm0);
+#pragma unroll
+        for (int j = 0; j < L; j++) out[j] = s.v[j];
+    }
+}
+
 // column-kernel lane setup: work-group = cpb cells x (K*M/L) lanes
 struct ColLane {
     int lc, km0, i;
@@ -212,13 +319,16 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
     const Vals<L, M1> v(km0, M);
     double *sD = lds;                        // [cpb][KM]
     double *sMd = lds + a.cpb * KM;          // [cpb][(K+1) M]  (NDC)
+    const ColTab<R> tb((char *)lds + col_lds_bytes(MODEL, KERNEL_CELL_A, a.cpb, K, a.M), MODEL, KERNEL_CELL_A, a.cpb, M);
+    stage_columns<KERNEL_CELL_A, MODEL, R, M1>(a, tb);
+    const double *cps = tb.ps + (long)lc * 7 * M;   // ps_s of this cell, then of its neighbours
 
     double dsg[L], psi[L], dpi_i[L], D[L];
     R ke[L], Fs[kCellSlots][L];
     R h0[L], h1[L], h2[L], th_i[L];
     int ce[6], cn[6];
     if (cl.valid) {
-        ld2d<L, M1>(a.ps_s, i, M, v.mm0, psi);
+        ld2d_s<L, M1>(cps, v.mm0, psi);
 #pragma unroll
         for (int j = 0; j < L; j++) {
             dsg[j] = (MODEL == MODEL_SW) ? 1.0 : a.dsig[v.k[j]];
@@ -227,14 +337,14 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
             ke[j] = 0;
             h0[j] = h1[j] = h2[j] = 0;
         }
-        ld6<int>(m.c_edge + (long)i * kCellSlots, ce);
-        ld6<int>(m.c_nbr + (long)i * kCellSlots, cn);
+        ld6<int>(tb.ce + lc * kCellSlots, ce);
+        ld6<int>(tb.cn + lc * kCellSlots, cn);
         double cdiv[6];
         R cke[6], ch0[6], ch1[6], ch2[6];
-        ld6<double>(m.c_div + (long)i * kCellSlots, cdiv);
-        ld6<R>(pick<R>(m.c_ke, m.c_ke32) + (long)i * kCellSlots, cke);
+        ld6<double>(tb.div64 + lc * kCellSlots, cdiv);
+        ld6<R>(tb.ke + lc * kCellSlots, cke);
         if constexpr (MODEL != MODEL_SW) {
-            const R *ch = pick<R>(m.c_hess, m.c_hess32) + (long)i * 3 * kCellSlots;
+            const R *ch = tb.hs + lc * 3 * kCellSlots;
             ld6<R>(ch, ch0);
             ld6<R>(ch + kCellSlots, ch1);
             ld6<R>(ch + 2 * kCellSlots, ch2);
@@ -249,7 +359,7 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
             if (e < 0) continue;
             const int nb = cn[s];
             double psn[L];
-            ld2d<L, M1>(a.ps_s, nb, M, v.mm0, psn);
+            ld2d_s<L, M1>(cps + (1 + s) * M, v.mm0, psn);
             const Pack<R, L> u = ldp<R, L>(us + (long)e * KM + km0);
 #pragma unroll
             for (int j = 0; j < L; j++) {
@@ -373,14 +483,14 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
 #pragma unroll
                 for (int j = 0; j < L; j++) aw[j] = ap[j] = 0;
                 double cdiv[6];
-                ld6<double>(m.c_div + (long)i * kCellSlots, cdiv);
+                ld6<double>(tb.div64 + lc * kCellSlots, cdiv);
 #pragma unroll
                 for (int s = 0; s < kCellSlots; s++) {
                     const int e = ce[s];
                     if (e < 0) continue;
                     const int nb = cn[s];
                     double psn[L];
-                    ld2d<L, M1>(a.ps_s, nb, M, v.mm0, psn);
+                    ld2d_s<L, M1>(cps + (1 + s) * M, v.mm0, psn);
                     // mass flux of the layer above each value (for the interface average)
                     R Fm[L];
                     if constexpr (M1) {
@@ -544,27 +654,28 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
     const ColLane cl = col_lane<L>(a, KM);
     const int i = cl.i, km0 = cl.km0, lc = cl.lc;
     const Vals<L, M1> v(km0, M);
+    const ColTab<R> tb((char *)lds + col_lds_bytes(MODEL, KERNEL_CELL_B, a.cpb, K, a.M), MODEL, KERNEL_CELL_B, a.cpb, M);
+    stage_columns<KERNEL_CELL_B, MODEL, R, M1>(a, tb);
+    const double *cps = tb.ps + (long)lc * 7 * M;   // ps_s of this cell, then of its neighbours
 
     double Th_new[L], ps_new[L], dsg[L];
     if (cl.valid) {
         double psi[L], dpi_i[L];
-        ld2d<L, M1>(a.ps_s, i, M, v.mm0, psi);
+        ld2d_s<L, M1>(cps, v.mm0, psi);
 #pragma unroll
         for (int j = 0; j < L; j++) {
             dsg[j] = (MODEL == MODEL_SW) ? 1.0 : a.dsig[v.k[j]];
             dpi_i[j] = lmass<MODEL>(dsg[j], psi[j], a.ptop);
         }
         int ce[6], cn[6], cv[6];
-        ld6<int>(m.c_edge + (long)i * kCellSlots, ce);
-        ld6<int>(m.c_nbr + (long)i * kCellSlots, cn);
-        ld6<int>(m.c_vert + (long)i * kCellSlots, cv);
+        ld6<int>(tb.ce + lc * kCellSlots, ce);
+        ld6<int>(tb.cn + lc * kCellSlots, cn);
+        ld6<int>(tb.cv + lc * kCellSlots, cv);
         R cdiv[6], cgk[6];
-        ld6<R>(pick<R>(m.c_div, m.c_div32) + (long)i * kCellSlots, cdiv);
-        ld6<R>(pick<R>(m.c_gk, m.c_gk32) + (long)i * kCellSlots, cgk);
+        ld6<R>(tb.div + lc * kCellSlots, cdiv);
+        ld6<R>(tb.gk + lc * kCellSlots, cgk);
         const R *us = u_prev_ptr<R>(a);
         const R *Hs = a.hth_in<R>();
-        const R *hdir = pick<R>(m.e_hdir, m.e_hdir32);
-        const R *d2 = pick<R>(m.e_d2, m.e_d2_32);
 
         R th_i[L], Hi0[L], Hi1[L], Hi2[L];
         if constexpr (MODEL != MODEL_SW) {
@@ -591,7 +702,7 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
             if (e < 0) continue;
             const int nb = cn[s];
             double psn[L];
-            ld2d<L, M1>(a.ps_s, nb, M, v.mm0, psn);
+            ld2d_s<L, M1>(cps + (1 + s) * M, v.mm0, psn);
             const Pack<R, L> u = ldp<R, L>(us + (long)e * KM + km0);
 #pragma unroll
             for (int j = 0; j < L; j++) {
@@ -613,8 +724,18 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                 }
                 R th_n[L];
                 theta_prev<MODEL, R, L>(a, nb, KM, km0, dsg, psn, th_n);
-                const R *ds = hdir + (long)e * 6 + (c1 ? 0 : 3);   // direction in i's frame
-                const R *dn = hdir + (long)e * 6 + (c1 ? 3 : 0);   // direction in nb's frame
+                // neighbour direction in i's frame, i's direction in the neighbour's, -d^2/6
+                R hd[8];
+                {
+                    const R *p = tb.hd + (lc * kCellSlots + s) * 8;
+#pragma unroll
+                    for (int q = 0; q < 8; q += 2) {
+                        const Pack<R, 2> x = ldp<R, 2>(p + q);
+                        hd[q] = x.v[0];
+                        hd[q + 1] = x.v[1];
+                    }
+                }
+                const R *ds = hd, *dn = hd + 3;
                 Pack<R, L> b0, b1, b2;
 #pragma unroll
                 for (int j = 0; j < L; j++) b0.v[j] = b1.v[j] = b2.v[j] = (R)0;
@@ -624,7 +745,7 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                     b1 = ldp<R, L>(Hs + hb + KM);
                     b2 = ldp<R, L>(Hs + hb + 2 * KM);
                 }
-                const R m2c = (R)-2 * d2[e];
+                const R m2c = hd[6];
 #pragma unroll
                 for (int j = 0; j < L; j++) {
                     const R hi = fmar(Hi0[j], ds[0], fmar(Hi1[j], ds[1], Hi2[j] * ds[2]));
@@ -657,7 +778,7 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                     }
             }
             const Pack<R, L> kp = ldp<R, L>(a.ke_in<R>() + (long)i * KM + km0);
-            const R *tk = pick<R>(m.c_tk, m.c_tk32) + (long)i * kCellSlots * kCellSlots;
+            const R *tk = tb.tk + lc * kCellSlots * kCellSlots;
             R *qh = a.qh_out<R>();
 #pragma unroll
             for (int s = 0; s < kCellSlots; s++) {
@@ -722,8 +843,8 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                 }
             }
             double dps_[L], psn_[L];
-            ld2d<L, M1>(a.dps, i, M, v.mm0, dps_);
-            ld2d<L, M1>(a.ps_n, i, M, v.mm0, psn_);
+            ld2d_s<L, M1>(tb.dps + lc * M, v.mm0, dps_);
+            ld2d_s<L, M1>(tb.psn + lc * M, v.mm0, psn_);
             const Pack<double, L> Thn = ldp<double, L>(a.Th_n + (long)i * KM + km0);
 #pragma unroll
             for (int j = 0; j < L; j++) {
@@ -1104,8 +1225,9 @@ hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
     const int colthreads = a.cpb * lanes;
     const unsigned colblocks = nblocks(a.mesh.N, a.cpb);
     const int fb = a.flat_block;
-    const size_t lds_a = stage_lds_bytes(MODEL, KERNEL_CELL_A, a.cpb, a.K, a.M);
-    const size_t lds_b = stage_lds_bytes(MODEL, KERNEL_CELL_B, a.cpb, a.K, a.M);
+    const int pol = sizeof(R) == 8 ? POLICY_DBL : POLICY_MIX;
+    const size_t lds_a = stage_lds_bytes(MODEL, pol, KERNEL_CELL_A, a.cpb, a.K, a.M);
+    const size_t lds_b = stage_lds_bytes(MODEL, pol, KERNEL_CELL_B, a.cpb, a.K, a.M);
     switch (which) {
     case KERNEL_CELL_A:
         hipLaunchKernelGGL((k_cell_a<MODEL, R, L, M1>), dim3(colblocks), dim3(colthreads), lds_a, s, a);
@@ -1154,14 +1276,10 @@ hipError_t launch_stage_r(const StageArgs &a, int which, hipStream_t s) {
 
 int values_per_lane(int K, int M) { return (M == 1 ? (K % 2 == 0) : (M % 2 == 0)) ? 2 : 1; }
 
-size_t stage_lds_bytes(int model, int which, int cpb, int K, int M) {
-    const size_t KM = (size_t)K * M;
-    if (which == KERNEL_CELL_A) return cpb * KM * 8 + (model == MODEL_NDC ? cpb * (K + 1) * (size_t)M * 8 : 0);
-    if (which == KERNEL_CELL_B) {
-        if (model == MODEL_SW) return 0;
-        return model == MODEL_NDC ? cpb * (10 * KM + (K + 1) * (size_t)M) * 8 : cpb * KM * 8;
-    }
-    return 0;
+size_t stage_lds_bytes(int model, int policy, int which, int cpb, int K, int M) {
+    if (which != KERNEL_CELL_A && which != KERNEL_CELL_B) return 0;
+    return col_lds_bytes(model, which, cpb, K, M) +
+           coltab_layout(model, which, cpb, M, policy == POLICY_DBL ? 8 : 4).bytes;
 }
 
 hipError_t launch_stage_kernel(int model, int policy, const StageArgs &a, int which, hipStream_t s) {

@@ -297,6 +297,20 @@ std::string derive_tables(const mpdc_mesh_desc *d, HostTables &t) {
             t.e_hdir[e * 6 + side * 3 + 2] = v * v;
         }
 
+    // per cell slot: the same directions from the cell's side, and -d^2/6
+    t.c_hd.assign(N * S * 8, 0.0);
+    for (long i = 0; i < N; i++)
+        for (int j = 0; j < off[i + 1] - off[i]; j++) {
+            const long e = ec[off[i] + j];
+            const int side = (ce[2 * e] == i) ? 0 : 1;
+            double *h = &t.c_hd[(i * S + j) * 8];
+            for (int q = 0; q < 3; q++) {
+                h[q] = t.e_hdir[e * 6 + side * 3 + q];
+                h[3 + q] = t.e_hdir[e * 6 + (1 - side) * 3 + q];
+            }
+            h[6] = -2.0 * t.e_d2[e];
+        }
+
     // ---- vertices ----
     t.v_edge.assign(4 * V, 0);
     t.v_cell.assign(4 * V, 0);

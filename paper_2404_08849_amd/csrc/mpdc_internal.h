@@ -37,6 +37,9 @@ struct DevMesh {
     const float *c_gk32;
     const double *c_hess;   // [N][3][6] slot differences -> (Hxx, Hxy, Hyy)
     const float *c_hess32;
+    const double *c_hd;     // [N][6][8] third-order flux of slot j: neighbour direction in i's frame
+                            // (u^2, 2uv, v^2), direction of i in the neighbour's frame, -d_e^2/6, 0
+    const float *c_hd32;
     const double *c_tk;     // [N][6][6] TRiSK half-stencil: w_{e_j,e_j'} l_{e_j'} / (4 d_{e_j}) from cell i
     const float *c_tk32;
     const double *c_area;   // [N]
@@ -98,7 +101,7 @@ int fail(int code, const std::string &msg);
 // Table derivation (host, FP64); returns "" or an error message.
 struct HostTables {
     std::vector<int> c_edge, c_nbr, c_vert;
-    std::vector<double> c_div, c_ke, c_gk, c_hess, c_tk, c_area;
+    std::vector<double> c_div, c_ke, c_gk, c_hess, c_hd, c_tk, c_area;
     std::vector<int> e_cell, e_vert;
     std::vector<double> e_dinv, e_d2, e_hdir;
     std::vector<int> v_edge, v_cell;              // [V][4]

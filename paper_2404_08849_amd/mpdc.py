@@ -158,7 +158,7 @@ class Mesh:
         return out
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:
             lib.mpdc_mesh_destroy(self.h)
             self.h = None
 
@@ -267,7 +267,7 @@ class State:
         return lib.mpdc_step_bytes(self.h)
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:
             lib.mpdc_state_destroy(self.h)
             self.h = None
 

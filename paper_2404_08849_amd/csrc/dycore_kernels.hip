@@ -973,39 +973,59 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                 }
             }
             __syncthreads();
-            if (cl.valid) {
+            // Parallel cyclic reduction over the n = K-1 interior interfaces of
+            // each member: the step with stride st eliminates, in every row at
+            // once, the couplings to the rows st above and below (rows beyond
+            // the ends count as absent); after the strides 1, 2, 4, ... < n the
+            // rows are decoupled and x_r = rhs_r / dia_r.  The rows of a lane are
+            // its own interfaces, so the arithmetic of a row does not depend on
+            // the launch shape.  p* and C are dead here and hold the second
+            // buffer with sCp and sDp.
+            const int n = K - 1;
+            double *cur[4] = {sSub, sDia, sSup, sRhs}, *nxt[4] = {sP, sC, sCp, sDp};
+            for (int st = 1; st < n; st *= 2) {
+                if (cl.valid) {
 #pragma unroll
-                for (int j = 0; j < L; j++) {
-                    if (v.k[j] != 0) continue;
-                    const int mm = v.mm0 + (M1 ? 0 : j);
-                    // Thomas algorithm over the K-1 interior interfaces of member mm
-                    const int n = K - 1;
-                    if (n > 0) {
-                        double den = sDia[base + mm];
-                        sCp[base + mm] = sSup[base + mm] / den;
-                        sDp[base + mm] = sRhs[base + mm] / den;
-                        for (int r = 1; r < n; r++) {
-                            const int o = base + r * M + mm, op = base + (r - 1) * M + mm;
-                            den = sDia[o] - sSub[o] * sCp[op];
-                            sCp[o] = (r < n - 1) ? sSup[o] / den : 0.0;
-                            sDp[o] = (sRhs[o] - sSub[o] * sDp[op]) / den;
+                    for (int j = 0; j < L; j++) {
+                        const int k = v.k[j], mm = v.mm0 + (M1 ? 0 : j);
+                        if (k < 1) continue;
+                        const int r = k - 1, o = base + r * M + mm;
+                        double bb = cur[1][o], dd = cur[3][o], na = 0.0, nc = 0.0;
+                        if (r - st >= 0) {
+                            const int q = o - st * M;
+                            const double f = cur[0][o] / cur[1][q];
+                            bb = fmar(-cur[2][q], f, bb);
+                            dd = fmar(-cur[3][q], f, dd);
+                            na = -cur[0][q] * f;
                         }
-                        // back substitution: the solution overwrites sDp
-                        for (int r = n - 2; r >= 0; r--) {
-                            const int o = base + r * M + mm;
-                            sDp[o] = sDp[o] - sCp[o] * sDp[o + M];
+                        if (r + st < n) {
+                            const int q = o + st * M;
+                            const double f = cur[2][o] / cur[1][q];
+                            bb = fmar(-cur[0][q], f, bb);
+                            dd = fmar(-cur[3][q], f, dd);
+                            nc = -cur[2][q] * f;
                         }
+                        nxt[0][o] = na;
+                        nxt[1][o] = bb;
+                        nxt[2][o] = nc;
+                        nxt[3][o] = dd;
                     }
                 }
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    double *t = cur[q];
+                    cur[q] = nxt[q];
+                    nxt[q] = t;
+                }
             }
-            __syncthreads();
             double phk[L];
             if (cl.valid) {
                 double wk[L];
 #pragma unroll
                 for (int j = 0; j < L; j++) {
                     const int k = v.k[j], mm = v.mm0 + (M1 ? 0 : j);
-                    wk[j] = (k == 0) ? 0.0 : sDp[base + (k - 1) * M + mm];
+                    wk[j] = (k == 0) ? 0.0 : cur[3][base + (k - 1) * M + mm] / cur[1][base + (k - 1) * M + mm];
                     phk[j] = phs_k[j] + a.grav * a.dts * wk[j];
                     sPhi[lc * K1 * M + k * M + mm] = phk[j];
                     if (k == K - 1) sPhi[lc * K1 * M + K * M + mm] = phs_k1[j];   // surface: w = 0

@@ -136,6 +136,11 @@ typedef struct mpdc_state mpdc_state;
  * descriptor is unusable). */
 size_t mpdc_mesh_workspace_bytes(const mpdc_mesh_desc *d);
 
+/* Host-only check of a mesh description: the validation and table
+ * derivation of mpdc_mesh_create with no device access.  Returns MPDC_OK or
+ * MPDC_E_MESH / MPDC_E_INVAL with the reason in mpdc_last_error(). */
+int mpdc_mesh_check(const mpdc_mesh_desc *d);
+
 /* Validate the mesh (index ranges, N - E + V = 2, cell degree 5/6, degree-3
  * vertices, counter-clockwise orientation, positive lengths and areas),
  * derive its operator tables in FP64 on the host (signs, cells-on-cell, TRiSK
@@ -218,7 +223,8 @@ int mpdc_time_kernel(mpdc_state *st, int kernel_id, int nreps, void *stream, dou
 
 /* Run nsteps steps with direct launches and a HIP event between consecutive
  * launches on stream, and return per kernel class (ids as above) the summed
- * duration in ms (ms_total[4]) and the launch count (launches[4]).  The state
+ * duration in ms (ms_total[4]) and the launch count (launches[4]); the
+ * tracer uses the first three entries and leaves the fourth zero.  The state
  * advances by nsteps exactly as with mpdc_dycore_step / mpdc_tracer_step. */
 int mpdc_profile_steps(mpdc_state *st, int nsteps, void *stream, double *ms_total, int *launches);
 

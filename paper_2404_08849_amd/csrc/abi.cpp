@@ -450,6 +450,21 @@ size_t mpdc_mesh_workspace_bytes(const mpdc_mesh_desc *d) {
     return mesh_layout(nullptr, d->nCells, d->nEdges, d->nVertices).bytes;
 }
 
+int mpdc_mesh_check(const mpdc_mesh_desc *d) {
+    if (!d) return fail(MPDC_E_INVAL, "null descriptor");
+    try {
+        std::string err = validate_mesh(d);
+        if (!err.empty()) return fail(MPDC_E_MESH, err);
+        HostTables t;
+        err = derive_tables(d, t);
+        if (!err.empty()) return fail(MPDC_E_MESH, err);
+    } catch (const std::exception &e) {
+        return fail(MPDC_E_INVAL, e.what());
+    }
+    set_error("");
+    return MPDC_OK;
+}
+
 int mpdc_mesh_create(const mpdc_mesh_desc *d, void *dev_ws, size_t ws_bytes, void *stream, mpdc_mesh **out) {
     if (!d || !out) return fail(MPDC_E_INVAL, "null descriptor or output handle");
     if (!dev_ws) return fail(MPDC_E_INVAL, "null device workspace");

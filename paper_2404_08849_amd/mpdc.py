@@ -66,6 +66,7 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     sig = {
         "mpdc_mesh_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(MeshDesc)]),
+        "mpdc_mesh_check": (ctypes.c_int, [ctypes.POINTER(MeshDesc)]),
         "mpdc_mesh_create": (ctypes.c_int, [ctypes.POINTER(MeshDesc), _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
         "mpdc_mesh_get_table": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_size_t]),
         "mpdc_mesh_table_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int]),

@@ -37,7 +37,7 @@ def _gpu_sw_impl(mpdc, gmesh, state, dt, nsteps, policy, graph=False, launch=Non
     return st, st.state_read(mpdc.FIELD_H)[:, 0], st.state_read(mpdc.FIELD_U)[:, 0, 0]
 
 
-def _gpu_hdc_impl(mpdc, gmesh, state, K, dt, nsteps, policy, M=1, graph=False, launch=None):
+def _gpu_hdc_impl(mpdc, gmesh, state, K, dt, nsteps, policy, M=1, graph=False, launch=None, autotune=False):
     st = mpdc.State(gmesh, mpdc.MODEL_HDC, policy, K=K, M=M, dt=dt, sigma=ic.sigma_interfaces(K))
     if launch:
         st.set_launch(*launch)
@@ -48,6 +48,8 @@ def _gpu_hdc_impl(mpdc, gmesh, state, K, dt, nsteps, policy, M=1, graph=False, l
     st.state_write(mpdc.FIELD_PS, ps)
     st.state_write(mpdc.FIELD_THETA, Th)
     st.state_write(mpdc.FIELD_U, u)
+    if autotune:
+        st.autotune()
     st.dycore_step(nsteps)
     out = [st.state_read(f) for f in (mpdc.FIELD_PS, mpdc.FIELD_THETA, mpdc.FIELD_U)]
     if M == 1:
@@ -55,7 +57,7 @@ def _gpu_hdc_impl(mpdc, gmesh, state, K, dt, nsteps, policy, M=1, graph=False, l
     return st, out
 
 
-def _gpu_ndc_impl(mpdc, gmesh, state, K, dt, nsteps, policy, graph=False, launch=None):
+def _gpu_ndc_impl(mpdc, gmesh, state, K, dt, nsteps, policy, graph=False, launch=None, autotune=False):
     st = mpdc.State(gmesh, mpdc.MODEL_NDC, policy, K=K, M=1, dt=dt, sigma=ic.sigma_interfaces(K))
     if launch:
         st.set_launch(*launch)
@@ -65,13 +67,15 @@ def _gpu_ndc_impl(mpdc, gmesh, state, K, dt, nsteps, policy, graph=False, launch
     st.state_write(mpdc.FIELD_U, state["u"][:, :, None])
     st.state_write(mpdc.FIELD_W, state["w"][:, :, None])
     st.state_write(mpdc.FIELD_PHI, state["phi"][:, :, None])
+    if autotune:
+        st.autotune()
     st.dycore_step(nsteps)
     fs = (mpdc.FIELD_PS, mpdc.FIELD_THETA, mpdc.FIELD_U, mpdc.FIELD_W, mpdc.FIELD_PHI)
     out = [st.state_read(f)[..., 0] for f in fs]
     return st, out
 
 
-def _gpu_tracer_impl(mpdc, gmesh, tr, dt, nsteps, policy, fct=True, graph=False, launch=None):
+def _gpu_tracer_impl(mpdc, gmesh, tr, dt, nsteps, policy, fct=True, graph=False, launch=None, autotune=False):
     K, T = tr["q"].shape[1], tr["q"].shape[2]
     st = mpdc.State(gmesh, mpdc.MODEL_TRACER, policy, K=K, T=T, dt=dt, fct=fct)
     if launch:
@@ -80,6 +84,8 @@ def _gpu_tracer_impl(mpdc, gmesh, tr, dt, nsteps, policy, fct=True, graph=False,
     st.state_write(mpdc.FIELD_TR_FLUX, tr["F"])
     st.state_write(mpdc.FIELD_TR_DPI, tr["dpi"])
     st.state_write(mpdc.FIELD_TR_Q, tr["q"])
+    if autotune:
+        st.autotune()
     st.tracer_step(nsteps)
     return st, st.state_read(mpdc.FIELD_TR_DPI), st.state_read(mpdc.FIELD_TR_Q)
 
@@ -89,16 +95,16 @@ def gpu_sw(mpdc, gmesh, state, dt, nsteps, policy, graph=False, launch=None):
         return _gpu_sw_impl(mpdc, gmesh, state, dt, nsteps, policy, graph, launch)
 
 
-def gpu_hdc(mpdc, gmesh, state, K, dt, nsteps, policy, M=1, graph=False, launch=None):
+def gpu_hdc(mpdc, gmesh, state, K, dt, nsteps, policy, M=1, graph=False, launch=None, autotune=False):
     with _stream_ctx(graph):
-        return _gpu_hdc_impl(mpdc, gmesh, state, K, dt, nsteps, policy, M, graph, launch)
+        return _gpu_hdc_impl(mpdc, gmesh, state, K, dt, nsteps, policy, M, graph, launch, autotune)
 
 
-def gpu_ndc(mpdc, gmesh, state, K, dt, nsteps, policy, graph=False, launch=None):
+def gpu_ndc(mpdc, gmesh, state, K, dt, nsteps, policy, graph=False, launch=None, autotune=False):
     with _stream_ctx(graph):
-        return _gpu_ndc_impl(mpdc, gmesh, state, K, dt, nsteps, policy, graph, launch)
+        return _gpu_ndc_impl(mpdc, gmesh, state, K, dt, nsteps, policy, graph, launch, autotune)
 
 
-def gpu_tracer(mpdc, gmesh, tr, dt, nsteps, policy, fct=True, graph=False, launch=None):
+def gpu_tracer(mpdc, gmesh, tr, dt, nsteps, policy, fct=True, graph=False, launch=None, autotune=False):
     with _stream_ctx(graph):
-        return _gpu_tracer_impl(mpdc, gmesh, tr, dt, nsteps, policy, fct, graph, launch)
+        return _gpu_tracer_impl(mpdc, gmesh, tr, dt, nsteps, policy, fct, graph, launch, autotune)

@@ -1,6 +1,6 @@
 """Host-side checks of the C ABI (CPU): the library loads, exports every
-symbol that include/mpdc.h declares, and rejects invalid meshes before any
-device access (mesh validation runs on the host first)."""
+symbol that include/mpdc.h declares, rejects invalid meshes and derives the
+tables of valid ones with the host-only mpdc_mesh_check (no device access)."""
 import ctypes
 import os
 import re
@@ -46,11 +46,10 @@ def _create(mpdc, mesh):
                                               "vertices_on_cell", "cells_on_vertex", "edges_on_vertex"]],
                       *[dp(keep[k]) for k in ["xCell", "xVertex", "xEdge", "dEdge", "lEdge", "areaCell",
                                               "areaVertex", "kiteArea", "fVertex"]], float(mesh["radius"]))
-    out = ctypes.c_void_p()
-    # an invalid mesh is rejected by host validation before the workspace is touched,
-    # so a dummy (never dereferenced) workspace pointer is enough here
-    rc = mpdc.lib.mpdc_mesh_create(ctypes.byref(d), ctypes.c_void_p(0x1000), 1 << 40, None, ctypes.byref(out))
-    return rc, mpdc.lib.mpdc_last_error().decode(), out
+    # the host-only check runs the same validation and table derivation as
+    # mpdc_mesh_create, without touching any device
+    rc = mpdc.lib.mpdc_mesh_check(ctypes.byref(d))
+    return rc, mpdc.lib.mpdc_last_error().decode(), None
 
 
 def _broken(mesh_cache, what):
@@ -76,9 +75,8 @@ def _broken(mesh_cache, what):
 
 @pytest.mark.parametrize("what", ["index", "orientation", "duplicate", "area", "euler", "tangent"])
 def test_invalid_mesh_rejected_on_host(mpdc, mesh_cache, what):
-    rc, msg, out = _create(mpdc, _broken(mesh_cache, what))
+    rc, msg, _ = _create(mpdc, _broken(mesh_cache, what))
     assert rc == -2, (what, rc, msg)
-    assert out.value is None
     assert msg
 
 
@@ -86,5 +84,13 @@ def test_null_arguments(mpdc):
     out = ctypes.c_void_p()
     assert mpdc.lib.mpdc_mesh_create(None, None, 0, None, ctypes.byref(out)) == -1
     assert mpdc.lib.mpdc_mesh_workspace_bytes(None) == 0
+    assert mpdc.lib.mpdc_mesh_check(None) == -1
     assert mpdc.lib.mpdc_dycore_step(None, 1, None) == -1
     assert mpdc.lib.mpdc_state_read(None, 0, None, 0, 0, None) == -1
+
+
+@pytest.mark.parametrize("level", [0, 1, 2, 3, 4, 5, 6])
+def test_valid_meshes_derive_on_host(mpdc, mesh_cache, level):
+    """Every icosahedral mesh validates and derives its tables on the host."""
+    rc, msg, _ = _create(mpdc, mesh_cache(level))
+    assert rc == 0, (level, msg)

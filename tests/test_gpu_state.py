@@ -1,0 +1,127 @@
+"""GPU state handling through the C ABI: checkpoint and resume through
+state_read / state_write is bitwise exact (the prognostic state is all a step
+carries over), and the error paths return their documented codes."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2404_08849_amd.inputs import initial as ic
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mpdc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_08849_amd.mpdc as m
+    return m
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _dycore_state(mpdc, g, model, K, fields):
+    st = mpdc.State(g, model, mpdc.POLICY_MIX, K=K, dt=300.0 if model == mpdc.MODEL_HDC else 60.0,
+                    sigma=ic.sigma_interfaces(K))
+    for f, x in fields.items():
+        st.state_write(f, x)
+    return st
+
+
+@pytest.mark.parametrize("model", ["HDC", "NDC"])
+def test_checkpoint_resume_is_bitwise(mpdc, mesh_cache, model):
+    m = mesh_cache(4)
+    K = 12
+    g = mpdc.Mesh(m)
+    if model == "HDC":
+        s = ic.hdc_jet(m, K, seed=2000)
+        fs = {mpdc.FIELD_PS: s["ps"][:, None], mpdc.FIELD_THETA: s["Theta"][:, :, None],
+              mpdc.FIELD_U: s["u"][:, :, None]}
+        mid = mpdc.MODEL_HDC
+    else:
+        s = ic.nh_warm_bubble(m, K, rh=6.0e5, seed=4000)
+        fs = {mpdc.FIELD_PS: s["ps"][:, None], mpdc.FIELD_THETA: s["Theta"][:, :, None],
+              mpdc.FIELD_U: s["u"][:, :, None], mpdc.FIELD_W: s["w"][:, :, None],
+              mpdc.FIELD_PHI: s["phi"][:, :, None]}
+        mid = mpdc.MODEL_NDC
+    _say("%s G4x%d MIX: 10 steps straight vs 5 + checkpoint + 5" % (model, K))
+    a = _dycore_state(mpdc, g, mid, K, fs)
+    a.dycore_step(10)
+    ref = {f: a.state_read(f) for f in fs}
+    b = _dycore_state(mpdc, g, mid, K, fs)
+    b.dycore_step(5)
+    ck = {f: b.state_read(f) for f in fs}
+    del b
+    c = _dycore_state(mpdc, g, mid, K, ck)
+    c.dycore_step(5)
+    for f in fs:
+        assert np.array_equal(c.state_read(f), ref[f]), f
+
+
+def test_tracer_checkpoint_resume_is_bitwise(mpdc, mesh_cache):
+    m = mesh_cache(4)
+    tr = ic.tracer_solid_body(m, 3, 4, seed=3000)
+    g = mpdc.Mesh(m)
+
+    def make(dpi, q):
+        st = mpdc.State(g, mpdc.MODEL_TRACER, mpdc.POLICY_MIX, K=3, T=4, dt=3000.0)
+        st.state_write(mpdc.FIELD_TR_FLUX, tr["F"])
+        st.state_write(mpdc.FIELD_TR_DPI, dpi)
+        st.state_write(mpdc.FIELD_TR_Q, q)
+        return st
+
+    _say("tracer G4x3x4 MIX: 6 steps straight vs 3 + checkpoint + 3")
+    a = make(tr["dpi"], tr["q"])
+    a.tracer_step(6)
+    b = make(tr["dpi"], tr["q"])
+    b.tracer_step(3)
+    c = make(b.state_read(mpdc.FIELD_TR_DPI), b.state_read(mpdc.FIELD_TR_Q))
+    c.tracer_step(3)
+    assert np.array_equal(c.state_read(mpdc.FIELD_TR_DPI), a.state_read(mpdc.FIELD_TR_DPI))
+    assert np.array_equal(c.state_read(mpdc.FIELD_TR_Q), a.state_read(mpdc.FIELD_TR_Q))
+
+
+def test_error_paths(mpdc, mesh_cache):
+    import torch
+    m = mesh_cache(2)
+    g = mpdc.Mesh(m)
+    K = 4
+    hdc = mpdc.State(g, mpdc.MODEL_HDC, mpdc.POLICY_MIX, K=K, dt=600.0, sigma=ic.sigma_interfaces(K))
+    trs = mpdc.State(g, mpdc.MODEL_TRACER, mpdc.POLICY_MIX, K=K, T=2, dt=600.0)
+    lib = mpdc.lib
+
+    # workspace too small: the state is not created
+    cfg = hdc.cfg
+    need = lib.mpdc_state_workspace_bytes(g.h, ctypes.byref(cfg))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    out = ctypes.c_void_p()
+    assert lib.mpdc_state_create(g.h, ctypes.byref(cfg), ctypes.c_void_p(ws.data_ptr()), need - 1,
+                                 ctypes.byref(out)) == -3
+    assert out.value is None
+    # steps of the wrong kind
+    assert lib.mpdc_dycore_step(trs.h, 1, None) == -7
+    assert lib.mpdc_tracer_step(hdc.h, 1, None) == -7
+    # a field the model does not have, a wrong byte count, a negative step count
+    x = np.zeros((g.N, K + 1), np.float64)
+    assert lib.mpdc_state_write(hdc.h, mpdc.FIELD_W, x.ctypes.data_as(ctypes.c_void_p), 0, x.nbytes, None) == -1
+    y = np.zeros(g.N + 1, np.float64)
+    assert lib.mpdc_state_write(hdc.h, mpdc.FIELD_PS, y.ctypes.data_as(ctypes.c_void_p), 0, y.nbytes, None) == -1
+    assert lib.mpdc_dycore_step(hdc.h, -1, None) == -1
+    # launch shapes outside the legal set
+    assert lib.mpdc_set_kernel_launch(hdc.h, 4, 0, 0) == -1          # kernel id
+    assert lib.mpdc_set_kernel_launch(hdc.h, 0, 3, 0) == -1          # values per lane
+    assert lib.mpdc_set_kernel_launch(hdc.h, 0, 4, 0) == -1          # four per lane: flat kernels only
+    assert lib.mpdc_set_kernel_launch(hdc.h, 0, 1, 1000) == -1       # column work-group over 512 lanes
+    assert lib.mpdc_set_kernel_launch(hdc.h, 3, 2, 100) == -1        # not a multiple of 64
+    assert lib.mpdc_set_kernel_launch(trs.h, 0, 4, 128) == -1        # 4 does not divide T = 2
+    assert lib.mpdc_set_kernel_launch(trs.h, 3, 0, 0) == -1          # the tracer has three kernels
+    # the states still step after the rejected calls
+    hdc.state_write(mpdc.FIELD_PS, np.full((g.N, 1), 1.0e5))
+    hdc.state_write(mpdc.FIELD_THETA, np.full((g.N, K, 1), 300.0 * 9.9e4 / K))
+    hdc.state_write(mpdc.FIELD_U, np.zeros((g.E, K, 1)))
+    hdc.dycore_step(1)
+    assert np.isfinite(hdc.state_read(mpdc.FIELD_PS)).all()

@@ -229,8 +229,9 @@ int vpl_of(const mpdc_state *st, int k) {
 
 // legal values per lane for kernel class k
 bool vpl_ok(const mpdc_state *st, int k, int L) {
+    if (st->model == MPDC_MODEL_TRACER)   // eight FP32 tracers per lane; FP64 stops at four (registers)
+        return (L == 1 || L == 2 || L == 4 || (L == 8 && st->policy == MPDC_POLICY_MIX)) && st->T % L == 0;
     if (L != 1 && L != 2 && L != 4) return false;
-    if (st->model == MPDC_MODEL_TRACER) return st->T % L == 0;
     if (L == 4 && is_column(k)) return false;
     if (st->M == 1) return st->K % L == 0;
     return st->M % L == 0;
@@ -773,7 +774,8 @@ int mpdc_set_kernel_launch(mpdc_state *st, int kernel_id, int values_per_lane_, 
     mpdc_state probe = *st;
     probe.launch = L;
     const int v = vpl_of(&probe, kernel_id);
-    if (!vpl_ok(st, kernel_id, v)) return fail(MPDC_E_INVAL, "values per lane must be 1, 2 or 4 and divide the column");
+    if (!vpl_ok(st, kernel_id, v))
+        return fail(MPDC_E_INVAL, "values per lane must be 1, 2 or 4 (tracers also 8) and divide the column");
     const bool col = st->model != MPDC_MODEL_TRACER && is_column(kernel_id);
     if (group != 0) {
         int rc = check_group(st, kernel_id, v, group);
@@ -989,7 +991,7 @@ int mpdc_autotune(mpdc_state *st, void *stream, int *cells_per_block, int *flat_
     const int nk = tr ? 3 : 4;
     const int flats[] = {64, 128, 256, 512, 1024};
     const int cpbs[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 64, 128, 256, 512};
-    const int vpls[] = {1, 2, 4};
+    const int vpls[] = {1, 2, 4, 8};
     // kernels are tuned in launch order, each with the already tuned shapes of
     // the kernels before it (their outputs are its inputs)
     for (int k = 0; k < nk; k++) {

@@ -119,7 +119,7 @@ struct TracerArgs {
     DevMesh mesh;
     int K, T;
     int cpb;           // threads per work-group
-    int vpl;           // tracers per lane (1, 2 or 4, dividing T)
+    int vpl;           // tracers per lane (1, 2, 4 or 8 (FP32 only), dividing T)
     int fct;
     double dts;
     const double *F;       // [E][K]   prescribed FP64 mass flux

@@ -324,6 +324,8 @@ hipError_t launch_tr_l(const TracerArgs &a, int which, hipStream_t s) {
 }
 template <typename R>
 hipError_t launch_tr(const TracerArgs &a, int which, hipStream_t s) {
+    if constexpr (sizeof(R) == 4)
+        if (a.vpl == 8) return launch_tr_l<R, 8>(a, which, s);
     if (a.vpl == 4) return launch_tr_l<R, 4>(a, which, s);
     if (a.vpl == 2) return launch_tr_l<R, 2>(a, which, s);
     return launch_tr_l<R, 1>(a, which, s);

@@ -210,11 +210,11 @@ def test_graph_replay_and_launch_shapes_are_bitwise_identical(mpdc, mesh_cache):
         if tref is None:
             tref = (dpi, q)
         assert np.array_equal(dpi, tref[0]) and np.array_equal(q, tref[1])
-    tr4 = ic.tracer_solid_body(m, 3, 4, seed=3000)
+    tr4 = ic.tracer_solid_body(m, 3, 8, seed=3000)
     t4 = None
-    for vpl in (1, 2, 4):
-        _say("tracer G4 T=4 values per lane %d" % vpl)
-        st = mpdc.State(g, mpdc.MODEL_TRACER, mpdc.POLICY_MIX, K=3, T=4, dt=3000.0)
+    for vpl in (1, 2, 4, 8):
+        _say("tracer G4 T=8 values per lane %d" % vpl)
+        st = mpdc.State(g, mpdc.MODEL_TRACER, mpdc.POLICY_MIX, K=3, T=8, dt=3000.0)
         for kid in range(3):
             st.set_kernel_launch(kid, vpl, 128)
         st.state_write(mpdc.FIELD_TR_FLUX, tr4["F"])

@@ -58,7 +58,7 @@ def read_record(path):
 
 def kernel_instance(kernel, policy_real, vpl):
     """Regex for the template instance of a library kernel (class, FP type, values per lane)."""
-    return re.compile(r"mpdc::%s<\d+, %s, %d[,>]" % (re.escape(kernel), policy_real, vpl))
+    return re.compile(r"mpdc::%s<(?:\d+, )?%s, %d[,>]" % (re.escape(kernel), policy_real, vpl))
 
 
 def _csv(path_glob):
@@ -148,11 +148,14 @@ def summarize(d, out):
         L.append("| %s | %s | %.2f | %.2f |" % (_short(r["Name"]), r["Calls"], float(r["AverageNs"]) * 1e-3,
                                             float(r["Percentage"])))
     L.append("")
+    in_step = rf.get("ms_per_launch_in_step")
     L.append("Dominant kernel of the mixed step: `%s` (values per lane %d, group %d).  "
              "Profiler average %.2f us over %d dispatches (trace: min %.2f, max %.2f us); the benchmark's "
-             "HIP-event average in the same run: %.2f us."
+             "HIP-event average in the same run: %.2f us over back-to-back launches (used for `achieved`)%s."
              % (_short(stat[0]["Name"]), vpl, group, avg_ms * 1e3, len(durs), min(durs) * 1e3, max(durs) * 1e3,
-                rf["ms_per_launch"] * 1e3))
+                rf["ms_per_launch"] * 1e3,
+                ", %.2f us between the launches of whole steps (event and launch overhead included)"
+                % (in_step * 1e3) if in_step else ""))
     L.append("")
     L.append("## HBM traffic (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE)")
     L.append("")

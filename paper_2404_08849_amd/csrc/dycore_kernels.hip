@@ -198,51 +198,71 @@ template <typename R> struct ColTab {
 // all its threads (contiguous rows; the neighbours' surface pressures through
 // c_nbr), then synchronise.
 template <int WHICH, int MODEL, typename R, bool M1>
-__device__ __forceinline__ void stage_columns(const StageArgs &a, const ColTab<R> &t) {
+__device__ __forceinline__ void stage_columns(const StageArgs &a, const ColTab<R> &t, int nthr) {
     const DevMesh &m = a.mesh;
     const int M = M1 ? 1 : a.M;
-    const int nthr = blockDim.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const long i0 = (long)xcd_block() * a.cpb;
     const int ncol = (int)((long)m.N - i0 < (long)a.cpb ? (long)m.N - i0 : (long)a.cpb);
-    const int n6 = ncol * kCellSlots;
-    for (int x = tid; x < n6; x += nthr) {
-        const long g = i0 * kCellSlots + x;
-        t.ce[x] = m.c_edge[g];
-        t.cn[x] = m.c_nbr[g];
-        if constexpr (WHICH == KERNEL_CELL_A) {
-            t.div64[x] = m.c_div[g];
-            t.ke[x] = pick<R>(m.c_ke, m.c_ke32)[g];
-        } else {
-            t.cv[x] = m.c_vert[g];
-            t.div[x] = pick<R>(m.c_div, m.c_div32)[g];
-            t.gk[x] = pick<R>(m.c_gk, m.c_gk32)[g];
-        }
-    }
-    if constexpr (WHICH == KERNEL_CELL_A) {
-        if constexpr (MODEL != MODEL_SW) {
-            const R *h = pick<R>(m.c_hess, m.c_hess32) + i0 * 3 * kCellSlots;
-            for (int x = tid; x < 3 * n6; x += nthr) t.hs[x] = h[x];
-        }
-    } else {
-        const R *tk = pick<R>(m.c_tk, m.c_tk32) + i0 * kCellSlots * kCellSlots;
-        for (int x = tid; x < kCellSlots * n6; x += nthr) t.tk[x] = tk[x];
-        if constexpr (MODEL != MODEL_SW) {
-            const R *hd = pick<R>(m.c_hd, m.c_hd32) + i0 * kCellSlots * 8;
-            for (int x = tid; x < 8 * n6; x += nthr) t.hd[x] = hd[x];
-        }
-        if constexpr (MODEL != MODEL_SW) {
-            for (int x = tid; x < ncol * M; x += nthr) {
-                t.psn[x] = a.ps_n[i0 * M + x];
-                t.dps[x] = a.dps[i0 * M + x];
+    constexpr bool CA = WHICH == KERNEL_CELL_A, SW = MODEL == MODEL_SW;
+    constexpr int VW = 16 / (int)sizeof(R);          // R values per 16-byte vector
+    // vectors (pairs for the [.][6] and [.][18] tables) and scalars to move
+    const int v6 = ncol * 3, v18 = ncol * 9, v36 = ncol * 36 / VW, v48 = ncol * 48 / VW;
+    const int nM = ncol * M, nps = ncol * 7 * M;
+    int nmax = v6 > nps ? v6 : nps;
+    if (CA && !SW && v18 > nmax) nmax = v18;
+    if (!CA && v36 > nmax) nmax = v36;
+    if (!CA && !SW && v48 > nmax) nmax = v48;
+    // One pass moves one vector of every table per thread, branch-free: a
+    // thread past the end of a table re-reads and re-writes its last vector
+    // (the same value), so no load sits under a condition (the compiler would
+    // sink it to its store and wait there) and the work-group waits for
+    // memory about twice per pass -- a neighbour's pressure needs its index
+    // first -- instead of once per table.  At the usual shapes there is one
+    // pass: a column has K M / L >= 12 lanes.
+    for (int x = tid; x < nmax; x += nthr) {
+        const int xp = x < nps ? x : nps - 1;
+        const int pc = xp / (7 * M), pr = xp - pc * 7 * M;
+        const int psl = pr / M, pmm = pr - psl * M;
+        const int nbr = m.c_nbr[(i0 + pc) * kCellSlots + (psl > 0 ? psl - 1 : 0)];
+        const int x6 = x < v6 ? x : v6 - 1;
+        const long o6 = i0 * kCellSlots + 2 * (long)x6;
+        const Pack<int, 2> e2 = ldp<int, 2>(m.c_edge + o6);
+        const Pack<int, 2> n2 = ldp<int, 2>(m.c_nbr + o6);
+        if constexpr (CA) {
+            const Pack<double, 2> d64 = ldp<double, 2>(m.c_div + o6);
+            const Pack<R, 2> k2 = ldp<R, 2>(pick<R>(m.c_ke, m.c_ke32) + o6);
+            if constexpr (!SW) {
+                const int x18 = x < v18 ? x : v18 - 1;
+                const Pack<R, 2> h2 = ldp<R, 2>(pick<R>(m.c_hess, m.c_hess32) + i0 * 3 * kCellSlots + 2 * (long)x18);
+                stp<R, 2>(t.hs + 2 * x18, h2);
             }
+            stp<double, 2>(t.div64 + 2 * x6, d64);
+            stp<R, 2>(t.ke + 2 * x6, k2);
+        } else {
+            const Pack<int, 2> c2 = ldp<int, 2>(m.c_vert + o6);
+            const Pack<R, 2> d2 = ldp<R, 2>(pick<R>(m.c_div, m.c_div32) + o6);
+            const Pack<R, 2> g2 = ldp<R, 2>(pick<R>(m.c_gk, m.c_gk32) + o6);
+            const int x36 = x < v36 ? x : v36 - 1;
+            const Pack<R, VW> t4 = ldp<R, VW>(pick<R>(m.c_tk, m.c_tk32) + i0 * 36 + (long)VW * x36);
+            if constexpr (!SW) {
+                const int x48 = x < v48 ? x : v48 - 1;
+                const Pack<R, VW> hd4 = ldp<R, VW>(pick<R>(m.c_hd, m.c_hd32) + i0 * 48 + (long)VW * x48);
+                const int xm = x < nM ? x : nM - 1;
+                const double pn = a.ps_n[i0 * M + xm], dp = a.dps[i0 * M + xm];
+                stp<R, VW>(t.hd + VW * x48, hd4);
+                t.psn[xm] = pn;
+                t.dps[xm] = dp;
+            }
+            stp<int, 2>(t.cv + 2 * x6, c2);
+            stp<R, 2>(t.div + 2 * x6, d2);
+            stp<R, 2>(t.gk + 2 * x6, g2);
+            stp<R, VW>(t.tk + VW * x36, t4);
         }
-    }
-    const int per = 7 * M;
-    for (int x = tid; x < ncol * per; x += nthr) {
-        const int c = x / per, r = x - c * per;
-        const int sl = r / M, mm = r - sl * M;
-        const long cell = sl == 0 ? i0 + c : (long)m.c_nbr[(i0 + c) * kCellSlots + sl - 1];
-        t.ps[x] = a.ps_s[cell * M + mm];
+        const double pv = a.ps_s[(psl == 0 ? i0 + pc : (long)nbr) * M + pmm];
+        stp<int, 2>(t.ce + 2 * x6, e2);
+        stp<int, 2>(t.cn + 2 * x6, n2);
+        t.ps[xp] = pv;
     }
     __syncthreads();
 }
@@ -258,6 +278,15 @@ template <int L, bool M1> __device__ __forceinline__ void ld2d_s(const double *r
 #pragma unroll
         for (int j = 0; j < L; j++) out[j] = s.v[j];
     }
+}
+
+// Slots of a column kernel's stencil loop per basic block: the gathers of a
+// group are issued together and waited for once.  More slots per group means
+// fewer memory round trips but more live registers; the sizes are the fastest
+// measured on MI355X (G6 x 30).
+template <int WHICH, typename R> constexpr int slot_group() {
+    if constexpr (WHICH == KERNEL_CELL_A) return sizeof(R) == 8 ? 2 : 3;
+    else return sizeof(R) == 8 ? 1 : 2;
 }
 
 // column-kernel lane setup: work-group = cpb cells x (K*M/L) lanes
@@ -320,11 +349,11 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
     double *sD = lds;                        // [cpb][KM]
     double *sMd = lds + a.cpb * KM;          // [cpb][(K+1) M]  (NDC)
     const ColTab<R> tb((char *)lds + col_lds_bytes(MODEL, KERNEL_CELL_A, a.cpb, K, a.M), MODEL, KERNEL_CELL_A, a.cpb, M);
-    stage_columns<KERNEL_CELL_A, MODEL, R, M1>(a, tb);
+    stage_columns<KERNEL_CELL_A, MODEL, R, M1>(a, tb, a.cpb * (KM / L));
     const double *cps = tb.ps + (long)lc * 7 * M;   // ps_s of this cell, then of its neighbours
 
     double dsg[L], psi[L], dpi_i[L], D[L];
-    R ke[L], Fs[kCellSlots][L];
+    R ke[L], Fs[kCellSlots][L] = {};
     R h0[L], h1[L], h2[L], th_i[L];
     int ce[6], cn[6];
     if (cl.valid) {
@@ -353,10 +382,11 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
         const R *us = u_prev_ptr<R>(a);
 #pragma unroll
         for (int s = 0; s < kCellSlots; s++) {
-#pragma unroll
-            for (int j = 0; j < L; j++) Fs[s][j] = 0;
-            const int e = ce[s];
-            if (e < 0) continue;
+            // slot_group() slots per basic block (see k_cell_b); the pad slot
+            // of a pentagon reads edge 0 and itself, with zero weights and flux
+            if (s % slot_group<KERNEL_CELL_A, R>() == 0 && ce[s] < 0) continue;   // slots 0..4 always exist
+            const bool pad = ce[s] < 0;
+            const int e = pad ? 0 : ce[s];
             const int nb = cn[s];
             double psn[L];
             ld2d_s<L, M1>(cps + (1 + s) * M, v.mm0, psn);
@@ -364,13 +394,12 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
 #pragma unroll
             for (int j = 0; j < L; j++) {
                 const double dpe = 0.5 * (dpi_i[j] + lmass<MODEL>(dsg[j], psn[j], a.ptop));
-                if constexpr (sizeof(R) == 8) {
-                    Fs[s][j] = dpe * u.v[j];
-                    D[j] += cdiv[s] * Fs[s][j];
-                } else {
-                    Fs[s][j] = (float)dpe * u.v[j];
-                    D[j] += cdiv[s] * (double)Fs[s][j];
-                }
+                R f;
+                if constexpr (sizeof(R) == 8) f = dpe * u.v[j];
+                else f = (float)dpe * u.v[j];
+                Fs[s][j] = pad ? (R)0 : f;
+                if constexpr (sizeof(R) == 8) D[j] += cdiv[s] * Fs[s][j];
+                else D[j] += cdiv[s] * (double)Fs[s][j];
                 ke[j] += cke[s] * u.v[j] * u.v[j];
             }
             if constexpr (MODEL != MODEL_SW) {
@@ -595,7 +624,7 @@ __global__ void __launch_bounds__(1024) k_vertex(StageArgs a) {
     const DevMesh &m = a.mesh;
     const int K = a.K, M = M1 ? 1 : a.M, KM = K * M;
     const int lanes = KM / L;
-    const long idx = (long)xcd_block() * blockDim.x + threadIdx.x;
+    const long idx = (long)xcd_block() * a.flat_block + threadIdx.x;   // flat_block = threads per work-group
     if (idx >= (long)m.V * lanes) return;
     const int vx = (int)(idx / lanes);
     const int km0 = (int)(idx - (long)vx * lanes) * L;
@@ -655,7 +684,7 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
     const int i = cl.i, km0 = cl.km0, lc = cl.lc;
     const Vals<L, M1> v(km0, M);
     const ColTab<R> tb((char *)lds + col_lds_bytes(MODEL, KERNEL_CELL_B, a.cpb, K, a.M), MODEL, KERNEL_CELL_B, a.cpb, M);
-    stage_columns<KERNEL_CELL_B, MODEL, R, M1>(a, tb);
+    stage_columns<KERNEL_CELL_B, MODEL, R, M1>(a, tb, a.cpb * (KM / L));
     const double *cps = tb.ps + (long)lc * 7 * M;   // ps_s of this cell, then of its neighbours
 
     double Th_new[L], ps_new[L], dsg[L];
@@ -691,15 +720,21 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
             }
         }
         // fluxes of the six edges and the theta flux divergence
-        R Fs[kCellSlots][L], hdiv[L];
+        R Fs[kCellSlots][L] = {}, hdiv[L];
 #pragma unroll
         for (int j = 0; j < L; j++) hdiv[j] = 0;
 #pragma unroll
         for (int s = 0; s < kCellSlots; s++) {
-#pragma unroll
-            for (int j = 0; j < L; j++) Fs[s][j] = 0;
-            const int e = ce[s];
-            if (e < 0) continue;
+            // slot_group() slots per basic block: the gathers of a block are
+            // issued together and waited for once; with no branch between
+            // slots at all the compiler issues all six slots' gathers at once
+            // and needs about twice the registers (measured slower).  The
+            // branch is never taken (slots 0..4 exist in every cell); the pad
+            // slot of a pentagon reads edge 0 and the cell itself, with zero
+            // weights and flux.
+            if (s % slot_group<KERNEL_CELL_B, R>() == 0 && ce[s] < 0) continue;
+            const bool pad = ce[s] < 0;
+            const int e = pad ? 0 : ce[s];
             const int nb = cn[s];
             double psn[L];
             ld2d_s<L, M1>(cps + (1 + s) * M, v.mm0, psn);
@@ -707,8 +742,10 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
 #pragma unroll
             for (int j = 0; j < L; j++) {
                 const double dpe = 0.5 * (dpi_i[j] + lmass<MODEL>(dsg[j], psn[j], a.ptop));
-                if constexpr (sizeof(R) == 8) Fs[s][j] = dpe * u.v[j];
-                else Fs[s][j] = (float)dpe * u.v[j];
+                R f;
+                if constexpr (sizeof(R) == 8) f = dpe * u.v[j];
+                else f = (float)dpe * u.v[j];
+                Fs[s][j] = pad ? (R)0 : f;
             }
             if constexpr (MODEL != MODEL_SW) {
                 // Third-order upwind edge value: with the upwind weight 1 the two
@@ -716,12 +753,6 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                 // derivative (along the edge) of the upwind cell alone.  Fs is the
                 // flux along n_e (c1 -> c2), the same number from either cell.
                 const bool c1 = cdiv[s] > (R)0;                 // i is c1 of e
-                bool up_i[L], need_n = false;
-#pragma unroll
-                for (int j = 0; j < L; j++) {
-                    up_i[j] = (Fs[s][j] >= (R)0) == c1;
-                    need_n = need_n || !up_i[j];
-                }
                 R th_n[L];
                 theta_prev<MODEL, R, L>(a, nb, KM, km0, dsg, psn, th_n);
                 // neighbour direction in i's frame, i's direction in the neighbour's, -d^2/6
@@ -736,21 +767,17 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                     }
                 }
                 const R *ds = hd, *dn = hd + 3;
-                Pack<R, L> b0, b1, b2;
-#pragma unroll
-                for (int j = 0; j < L; j++) b0.v[j] = b1.v[j] = b2.v[j] = (R)0;
-                if (need_n) {
-                    const long hb = (long)nb * 3 * KM + km0;
-                    b0 = ldp<R, L>(Hs + hb);
-                    b1 = ldp<R, L>(Hs + hb + KM);
-                    b2 = ldp<R, L>(Hs + hb + 2 * KM);
-                }
+                // (the neighbour's second derivatives are loaded whether or not it
+                // is upwind: a load under a condition costs a wait where the paths join)
+                const long hb = (long)nb * 3 * KM + km0;
+                const Pack<R, L> b0 = ldp<R, L>(Hs + hb), b1 = ldp<R, L>(Hs + hb + KM), b2 = ldp<R, L>(Hs + hb + 2 * KM);
                 const R m2c = hd[6];
 #pragma unroll
                 for (int j = 0; j < L; j++) {
+                    const bool up_i = (Fs[s][j] >= (R)0) == c1;
                     const R hi = fmar(Hi0[j], ds[0], fmar(Hi1[j], ds[1], Hi2[j] * ds[2]));
                     const R hn = fmar(b0.v[j], dn[0], fmar(b1.v[j], dn[1], b2.v[j] * dn[2]));
-                    const R tv = fmar(m2c, up_i[j] ? hi : hn, (R)0.5 * (th_i[j] + th_n[j]));
+                    const R tv = fmar(m2c, up_i ? hi : hn, (R)0.5 * (th_i[j] + th_n[j]));
                     hdiv[j] = fmar(cdiv[s], Fs[s][j] * tv, hdiv[j]);
                 }
             }
@@ -807,39 +834,44 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
             // vertical theta flux through the layer's interfaces (centred theta)
             const long K1M = (long)(K + 1) * M;
             const double *md = a.mdot + (long)i * K1M;
+            // theta of the layers above and below: read from clamped indices
+            // (the top and bottom values are not used), so no load is conditional
             R thu[L], thd[L];
-#pragma unroll
-            for (int j = 0; j < L; j++) thu[j] = thd[j] = 0;
+            const bool has_up = v.k0 > 0;
             if constexpr (M1) {
+                const int kl = v.k[L - 1];
+                const bool has_dn = kl < K - 1;
 #pragma unroll
                 for (int j = 0; j < L; j++) {
-                    if (j > 0) thu[j] = th_i[j - 1];
-                    if (j < L - 1) thd[j] = th_i[j + 1];
+                    thu[j] = j > 0 ? th_i[j - 1] : (R)0;
+                    thd[j] = j < L - 1 ? th_i[j + 1] : (R)0;
                 }
-                if (v.k0 > 0) {
-                    if constexpr (sizeof(R) == 8)
-                        thu[0] = a.Th_s[(long)i * KM + km0 - 1] / lmass<MODEL>(a.dsig[v.k0 - 1], psi[0], a.ptop);
-                    else
-                        thu[0] = a.th32_s[(long)i * KM + km0 - 1];
+                const long ou = (long)i * KM + (has_up ? km0 - 1 : km0), od = (long)i * KM + (has_dn ? km0 + L : km0);
+                R up, dn;
+                if constexpr (sizeof(R) == 8) {
+                    up = a.Th_s[ou] / lmass<MODEL>(a.dsig[has_up ? v.k0 - 1 : v.k0], psi[0], a.ptop);
+                    dn = a.Th_s[od] / lmass<MODEL>(a.dsig[has_dn ? kl + 1 : kl], psi[0], a.ptop);
+                } else {
+                    up = a.th32_s[ou];
+                    dn = a.th32_s[od];
                 }
-                const int kl = v.k[L - 1];
-                if (kl < K - 1) {
-                    if constexpr (sizeof(R) == 8)
-                        thd[L - 1] = a.Th_s[(long)i * KM + km0 + L] / lmass<MODEL>(a.dsig[kl + 1], psi[0], a.ptop);
-                    else
-                        thd[L - 1] = a.th32_s[(long)i * KM + km0 + L];
-                }
+                thu[0] = has_up ? up : (R)0;
+                thd[L - 1] = has_dn ? dn : (R)0;
             } else {
-                double dd[L];
-                if (v.k0 > 0) {
+                const bool has_dn = v.k0 < K - 1;
+                double du[L], dd[L];
 #pragma unroll
-                    for (int j = 0; j < L; j++) dd[j] = a.dsig[v.k0 - 1];
-                    theta_prev<MODEL, R, L>(a, i, KM, km0 - M, dd, psi, thu);
+                for (int j = 0; j < L; j++) {
+                    du[j] = a.dsig[has_up ? v.k0 - 1 : v.k0];
+                    dd[j] = a.dsig[has_dn ? v.k0 + 1 : v.k0];
                 }
-                if (v.k0 < K - 1) {
+                R tu[L], td[L];
+                theta_prev<MODEL, R, L>(a, i, KM, has_up ? km0 - M : km0, du, psi, tu);
+                theta_prev<MODEL, R, L>(a, i, KM, has_dn ? km0 + M : km0, dd, psi, td);
 #pragma unroll
-                    for (int j = 0; j < L; j++) dd[j] = a.dsig[v.k0 + 1];
-                    theta_prev<MODEL, R, L>(a, i, KM, km0 + M, dd, psi, thd);
+                for (int j = 0; j < L; j++) {
+                    thu[j] = has_up ? tu[j] : (R)0;
+                    thd[j] = has_dn ? td[j] : (R)0;
                 }
             }
             double dps_[L], psn_[L];
@@ -849,9 +881,11 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
 #pragma unroll
             for (int j = 0; j < L; j++) {
                 const int mm = v.mm0 + (M1 ? 0 : j);
-                R top = 0, bot = 0;
-                if (v.k[j] > 0) top = (R)md[(long)v.k[j] * M + mm] * ((R)0.5 * (thu[j] + th_i[j]));
-                if (v.k[j] < K - 1) bot = (R)md[(long)(v.k[j] + 1) * M + mm] * ((R)0.5 * (th_i[j] + thd[j]));
+                // interfaces k and k + 1 always exist in mdot [K+1]; the flux
+                // through the lid and the surface is zero
+                const R mt = (R)md[(long)v.k[j] * M + mm], mb = (R)md[(long)(v.k[j] + 1) * M + mm];
+                const R top = v.k[j] > 0 ? mt * ((R)0.5 * (thu[j] + th_i[j])) : (R)0;
+                const R bot = v.k[j] < K - 1 ? mb * ((R)0.5 * (th_i[j] + thd[j])) : (R)0;
                 const R dTh = -hdiv[j] - (bot - top);
                 Th_new[j] = Thn.v[j] + a.dts * (double)dTh;
                 ps_new[j] = psn_[j] + a.dts * dps_[j];
@@ -1091,7 +1125,7 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
     const DevMesh &m = a.mesh;
     const int K = a.K, M = M1 ? 1 : a.M, KM = K * M;
     const int lanes = KM / L;
-    const long idx = (long)xcd_block() * blockDim.x + threadIdx.x;
+    const long idx = (long)xcd_block() * a.flat_block + threadIdx.x;   // flat_block = threads per work-group
     if (idx >= (long)m.E * lanes) return;
     const int e = (int)(idx / lanes);
     const int km0 = (int)(idx - (long)e * lanes) * L;
@@ -1121,11 +1155,15 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
         const Pack<R, L> uk = ldp<R, L>(us + base);
         R uup[L], udn[L];
         double mt[L], mb[L];
+        // the levels above and below are read from clamped indices (no load
+        // under a condition); the values past the lid and the surface are unused
         if constexpr (M1) {
+            const R ua = us[base + (v.k0 > 0 ? -1 : 0)];
+            const R ub = us[base + (v.k[L - 1] < K - 1 ? L : L - 1)];
 #pragma unroll
             for (int j = 0; j < L; j++) {
-                uup[j] = (j > 0) ? uk.v[j - 1] : ((v.k0 > 0) ? us[base - 1] : (R)0);
-                udn[j] = (j < L - 1) ? uk.v[j + 1] : ((v.k[j] < K - 1) ? us[base + L] : (R)0);
+                uup[j] = (j > 0) ? uk.v[j - 1] : ((v.k0 > 0) ? ua : (R)0);
+                udn[j] = (j < L - 1) ? uk.v[j + 1] : ((v.k[j] < K - 1) ? ub : (R)0);
             }
             const double *m1p = a.mdot + (long)c1 * K1M + v.k0, *m2p = a.mdot + (long)c2 * K1M + v.k0;
             double i1[L + 1], i2[L + 1];
@@ -1140,9 +1178,8 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
                 mb[j] = 0.5 * (i1[j + 1] + i2[j + 1]);
             }
         } else {
-            Pack<R, L> pu, pd;
-            if (v.k0 > 0) pu = ldp<R, L>(us + base - M);
-            if (v.k0 < K - 1) pd = ldp<R, L>(us + base + M);
+            const Pack<R, L> pu = ldp<R, L>(us + base - (v.k0 > 0 ? M : 0));
+            const Pack<R, L> pd = ldp<R, L>(us + base + (v.k0 < K - 1 ? M : 0));
             const Pack<double, L> t1 = ldp<double, L>(a.mdot + (long)c1 * K1M + (long)v.k0 * M + v.mm0);
             const Pack<double, L> t2 = ldp<double, L>(a.mdot + (long)c2 * K1M + (long)v.k0 * M + v.mm0);
             const Pack<double, L> b1 = ldp<double, L>(a.mdot + (long)c1 * K1M + (long)(v.k0 + 1) * M + v.mm0);
@@ -1221,7 +1258,7 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
 template <int MODEL>
 __global__ void k_shadows(StageArgs a) {
     const int KM = a.K * a.M;
-    const long idx = (long)xcd_block() * blockDim.x + threadIdx.x;
+    const long idx = (long)xcd_block() * a.flat_block + threadIdx.x;   // flat_block = threads per work-group
     const long nE = (long)a.mesh.E * KM, nC = (long)a.mesh.N * KM;
     if (idx < nE) a.u32_o[idx] = (float)a.u_o[idx];
     if (MODEL != MODEL_SW && a.th32_o && idx < nC) {
@@ -1313,7 +1350,9 @@ hipError_t launch_stage_kernel(int model, int policy, const StageArgs &a, int wh
     return launch_stage_r<MODEL_NDC, float>(a, which, s);
 }
 
-hipError_t launch_shadows(int model, const StageArgs &a, hipStream_t s) {
+hipError_t launch_shadows(int model, const StageArgs &args, hipStream_t s) {
+    StageArgs a = args;
+    a.flat_block = 256;   // the kernel reads its work-group size from here
     const long n = (long)(a.mesh.E > a.mesh.N ? a.mesh.E : a.mesh.N) * a.K * a.M;
     if (model == MODEL_SW) hipLaunchKernelGGL(k_shadows<MODEL_SW>, dim3(nblocks(n, 256)), dim3(256), 0, s, a);
     else if (model == MODEL_HDC) hipLaunchKernelGGL(k_shadows<MODEL_HDC>, dim3(nblocks(n, 256)), dim3(256), 0, s, a);

@@ -48,6 +48,15 @@ template <typename T> __device__ __forceinline__ void tld6(const T *p, T out[6])
     out[0] = a.v[0]; out[1] = a.v[1]; out[2] = b.v[0]; out[3] = b.v[1]; out[4] = c.v[0]; out[5] = c.v[1];
 }
 
+// Slots per basic block of the tracer kernels' stencil loops (the gathers of
+// a block are issued together), and whether a kernel reads the neighbour's
+// q^n and second derivatives only where the neighbour is upwind (fewer bytes,
+// but a wait per slot) -- both the fastest measured on MI355X (G8 x 30 x 8).
+// A pentagon's pad slot (edge -1) is processed with edge 0, the cell itself
+// as neighbour, zero flux and zero weights, so it adds nothing.
+constexpr int kLowSlots = 3, kLimitSlots = 3, kUpdateSlots = 2;
+constexpr bool kLimitUpwindLoads = false, kUpdateUpwindLoads = true;
+
 // One lane = L consecutive tracers of one (cell, level).
 struct TLane {
     int i, k, t0;
@@ -58,7 +67,7 @@ template <int L> __device__ __forceinline__ TLane tracer_lane(const TracerArgs &
     TLane r;
     const int lanes_k = a.T / L;
     const int lanes = a.K * lanes_k;
-    const long idx = (long)xcd_block() * blockDim.x + threadIdx.x;
+    const long idx = (long)xcd_block() * a.cpb + threadIdx.x;   // a.cpb = threads per work-group
     r.ok = idx < (long)a.mesh.N * lanes;
     r.i = (int)(idx / lanes);
     const int rem = (int)(idx - (long)r.i * lanes);
@@ -88,7 +97,10 @@ __device__ __forceinline__ void load_stencil(const TracerArgs &a, int i, int k, 
     double d = 0.0;
 #pragma unroll
     for (int s = 0; s < kCellSlots; s++) {
-        st.F[s] = (st.ce[s] >= 0) ? a.F[(long)st.ce[s] * a.K + k] : 0.0;
+        // a pentagon's pad slot reads edge 0 (no load under a condition) and
+        // gets a zero flux
+        const double f = a.F[(long)(st.ce[s] < 0 ? 0 : st.ce[s]) * a.K + k];
+        st.F[s] = (st.ce[s] >= 0) ? f : 0.0;
         d += c64[s] * st.F[s];
     }
     st.dpi_n = a.dpi_n[(long)i * a.K + k];
@@ -99,41 +111,55 @@ __device__ __forceinline__ void load_stencil(const TracerArgs &a, int i, int k, 
 // slot s of cell i, for L tracers.  q~ is the third-order upwind edge value of
 // q_s: with the upwind weight 1 the two second-derivative terms reduce to
 // -d^2/6 times the second derivative along the edge of the upwind cell alone,
-// so only the upwind cell's q^n and second derivatives are read.  The flux
-// F_e is one FP64 number per edge-level, so the upwind cell is the same for
-// the L tracers of a lane.  qn_nb, if given, is q^n of the neighbour already
-// loaded by the caller.
-template <typename R, int L>
+// so only the upwind cell's q^n and second derivatives are used (the
+// neighbour's are loaded either way: a load under a condition would cost a
+// wait where the paths join).  The flux F_e is one FP64 number per
+// edge-level, so the upwind cell is the same for the L tracers of a lane.
+// qn_nb, if given, is q^n of the neighbour already loaded by the caller.
+template <typename R, int L, bool UPWIND_LOADS>
 __device__ __forceinline__ void edge_fluxes(const TracerArgs &a, const Stencil<R> &st, int s, int k, int t0,
                                             const R qn_i[L], const R qs_i[L], const R Hi[3][L],
                                             const TPack<R, L> *qn_nb, R FL[L], R Aa[L]) {
     const DevMesh &m = a.mesh;
     const int KT = a.K * a.T;
-    const int e = st.ce[s], nb = st.cn[s];
+    const int e = st.ce[s] < 0 ? 0 : st.ce[s], nb = st.cn[s];   // pad slot: edge 0, the cell itself, F = 0
     const double Fd = st.F[s];
     const bool fwd = Fd >= 0.0;                              // c1 is upwind
     const bool up_self = fwd == (st.cdiv[s] > (R)0);
     const long on = (long)nb * KT + (long)k * a.T + t0;
     const TPack<R, L> qs_n = tld<R, L>((const R *)a.q_s + on);
     R qup[L], H0[L], H1[L], H2[L];
-    if (up_self) {
+    const R *Hb = (const R *)a.hq + (long)nb * 3 * KT + (long)k * a.T + t0;
+    if constexpr (UPWIND_LOADS) {
+        // the neighbour's q^n and second derivatives only where it is upwind
+        if (up_self) {
 #pragma unroll
-        for (int j = 0; j < L; j++) {
-            qup[j] = qn_i[j];
-            H0[j] = Hi[0][j];
-            H1[j] = Hi[1][j];
-            H2[j] = Hi[2][j];
+            for (int j = 0; j < L; j++) {
+                qup[j] = qn_i[j];
+                H0[j] = Hi[0][j];
+                H1[j] = Hi[1][j];
+                H2[j] = Hi[2][j];
+            }
+        } else {
+            const TPack<R, L> qn_n = qn_nb ? *qn_nb : tld<R, L>((const R *)a.q_n + on);
+            const TPack<R, L> h0 = tld<R, L>(Hb), h1 = tld<R, L>(Hb + KT), h2 = tld<R, L>(Hb + 2 * KT);
+#pragma unroll
+            for (int j = 0; j < L; j++) {
+                qup[j] = qn_n.v[j];
+                H0[j] = h0.v[j];
+                H1[j] = h1.v[j];
+                H2[j] = h2.v[j];
+            }
         }
     } else {
         const TPack<R, L> qn_n = qn_nb ? *qn_nb : tld<R, L>((const R *)a.q_n + on);
-        const R *Hb = (const R *)a.hq + (long)nb * 3 * KT + (long)k * a.T + t0;
         const TPack<R, L> h0 = tld<R, L>(Hb), h1 = tld<R, L>(Hb + KT), h2 = tld<R, L>(Hb + 2 * KT);
 #pragma unroll
         for (int j = 0; j < L; j++) {
-            qup[j] = qn_n.v[j];
-            H0[j] = h0.v[j];
-            H1[j] = h1.v[j];
-            H2[j] = h2.v[j];
+            qup[j] = up_self ? qn_i[j] : qn_n.v[j];
+            H0[j] = up_self ? Hi[0][j] : h0.v[j];
+            H1[j] = up_self ? Hi[1][j] : h1.v[j];
+            H2[j] = up_self ? Hi[2][j] : h2.v[j];
         }
     }
     // the neighbour direction in the upwind cell's frame (c1: first triple)
@@ -172,7 +198,7 @@ __global__ void __launch_bounds__(kTracerThreads) k_tr_low(TracerArgs a) {
     for (int j = 0; j < L; j++) dL[j] = h[0][j] = h[1][j] = h[2][j] = 0;
 #pragma unroll
     for (int s = 0; s < kCellSlots; s++) {
-        if (st.ce[s] < 0) continue;
+        if (s % kLowSlots == 0 && st.ce[s] < 0) continue;   // never taken: slots 0..4 always exist
         const long on = (long)st.cn[s] * KT + (long)k * a.T + t0;
         const TPack<R, L> qsn = tld<R, L>(qs + on), qnn = tld<R, L>(qn + on);
         const double Fd = st.F[s];
@@ -239,11 +265,11 @@ __global__ void __launch_bounds__(kTracerThreads) k_tr_limit(TracerArgs a) {
     }
 #pragma unroll
     for (int s = 0; s < kCellSlots; s++) {
-        if (st.ce[s] < 0) continue;
+        if (s % kLimitSlots == 0 && st.ce[s] < 0) continue;
         const long on = (long)st.cn[s] * KT + (long)k * a.T + t0;
         const TPack<R, L> qnn = tld<R, L>(qn + on), qtn = tld<R, L>(qtd + on);
         R FL[L], Aa[L];
-        edge_fluxes<R, L>(a, st, s, k, t0, qn_i, qs_i, Hi, &qnn, FL, Aa);
+        edge_fluxes<R, L, kLimitUpwindLoads>(a, st, s, k, t0, qn_i, qs_i, Hi, &qnn, FL, Aa);
 #pragma unroll
         for (int j = 0; j < L; j++) {
             qmax[j] = fmax(qmax[j], fmax(qnn.v[j], qtn.v[j]));
@@ -287,11 +313,11 @@ __global__ void __launch_bounds__(kTracerThreads) k_tr_update(TracerArgs a) {
     for (int j = 0; j < L; j++) dT[j] = 0;
 #pragma unroll
     for (int s = 0; s < kCellSlots; s++) {
-        if (st.ce[s] < 0) continue;
+        if (s % kUpdateSlots == 0 && st.ce[s] < 0) continue;
         const long on = (long)st.cn[s] * KT + (long)k * a.T + t0;
         const TPack<R, L> rpn = tld<R, L>(rp + on), rmn = tld<R, L>(rm + on);
         R FL[L], Aa[L];
-        edge_fluxes<R, L>(a, st, s, k, t0, qn_i, qs_i, Hi, nullptr, FL, Aa);
+        edge_fluxes<R, L, kUpdateUpwindLoads>(a, st, s, k, t0, qn_i, qs_i, Hi, nullptr, FL, Aa);
         const bool self_c1 = st.cdiv[s] > (R)0;
 #pragma unroll
         for (int j = 0; j < L; j++) {
@@ -313,11 +339,13 @@ inline unsigned tblocks(long n, int b) { return (unsigned)((n + b - 1) / b); }
 template <typename R, int L>
 hipError_t launch_tr_l(const TracerArgs &a, int which, hipStream_t s) {
     const long n = (long)a.mesh.N * a.K * (a.T / L);
-    const int b = a.cpb > 0 ? a.cpb : 256;
+    TracerArgs ab = a;
+    ab.cpb = a.cpb > 0 ? a.cpb : 256;   // the kernels read the work-group size from here
+    const int b = ab.cpb;
     switch (which) {
-    case TKERNEL_LOW: hipLaunchKernelGGL((k_tr_low<R, L>), dim3(tblocks(n, b)), dim3(b), 0, s, a); break;
-    case TKERNEL_LIMIT: hipLaunchKernelGGL((k_tr_limit<R, L>), dim3(tblocks(n, b)), dim3(b), 0, s, a); break;
-    case TKERNEL_UPDATE: hipLaunchKernelGGL((k_tr_update<R, L>), dim3(tblocks(n, b)), dim3(b), 0, s, a); break;
+    case TKERNEL_LOW: hipLaunchKernelGGL((k_tr_low<R, L>), dim3(tblocks(n, b)), dim3(b), 0, s, ab); break;
+    case TKERNEL_LIMIT: hipLaunchKernelGGL((k_tr_limit<R, L>), dim3(tblocks(n, b)), dim3(b), 0, s, ab); break;
+    case TKERNEL_UPDATE: hipLaunchKernelGGL((k_tr_update<R, L>), dim3(tblocks(n, b)), dim3(b), 0, s, ab); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -352,11 +352,13 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
     stage_columns<KERNEL_CELL_A, MODEL, R, M1>(a, tb, a.cpb * (KM / L));
     const double *cps = tb.ps + (long)lc * 7 * M;   // ps_s of this cell, then of its neighbours
 
-    double dsg[L], psi[L], dpi_i[L], D[L];
+    double dsg[L], psi[L], dpi_i[L], D[L], sgb[L];
     R ke[L], Fs[kCellSlots][L] = {};
     R h0[L], h1[L], h2[L], th_i[L];
     int ce[6], cn[6];
     if (cl.valid) {
+#pragma unroll
+        for (int j = 0; j < L; j++) sgb[j] = a.sig[v.k[j] + 1];   // read before the barrier
         ld2d_s<L, M1>(cps, v.mm0, psi);
 #pragma unroll
         for (int j = 0; j < L; j++) {
@@ -460,7 +462,7 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
                     dps = -lds_sum_up(sD + lc * KM + mm, M, 0, K);
                     acc = lds_sum_up(sD + lc * KM + mm, M, 0, v.k[j] + 1);
                 }
-                mdot_b[j] = (v.k[j] == K - 1) ? 0.0 : -acc - a.sig[v.k[j] + 1] * dps;
+                mdot_b[j] = (v.k[j] == K - 1) ? 0.0 : -acc - sgb[j] * dps;
                 a.mdot[(long)i * K1M + (long)(v.k[j] + 1) * M + mm] = mdot_b[j];
                 if (v.k[j] == 0) {
                     a.mdot[(long)i * K1M + mm] = 0.0;
@@ -687,8 +689,18 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
     stage_columns<KERNEL_CELL_B, MODEL, R, M1>(a, tb, a.cpb * (KM / L));
     const double *cps = tb.ps + (long)lc * 7 * M;   // ps_s of this cell, then of its neighbours
 
-    double Th_new[L], ps_new[L], dsg[L];
+    double Th_new[L], ps_new[L], dsg[L], sgt[L], sgb[L];
     if (cl.valid) {
+        // sigma at the layer's interfaces for the column diagnostics: read
+        // here, before the barriers, in the mixed policy (in FP64 the extra
+        // live registers cost more than the late read)
+        if constexpr (sizeof(R) == 4) {
+#pragma unroll
+            for (int j = 0; j < L; j++) {
+                sgt[j] = a.sig[v.k[j]];
+                sgb[j] = a.sig[v.k[j] + 1];
+            }
+        }
         double psi[L], dpi_i[L];
         ld2d_s<L, M1>(cps, v.mm0, psi);
 #pragma unroll
@@ -907,8 +919,12 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                 for (int j = 0; j < L; j++) {
                     const int k = v.k[j];
                     tho.v[j] = Th_new[j];
-                    const double pit = a.ptop + a.sig[k] * (ps_new[j] - a.ptop);
-                    const double pib = a.ptop + a.sig[k + 1] * (ps_new[j] - a.ptop);
+                    if constexpr (sizeof(R) == 8) {
+                        sgt[j] = a.sig[k];
+                        sgb[j] = a.sig[k + 1];
+                    }
+                    const double pit = a.ptop + sgt[j] * (ps_new[j] - a.ptop);
+                    const double pib = a.ptop + sgb[j] * (ps_new[j] - a.ptop);
                     const double dpn = dsg[j] * (ps_new[j] - a.ptop);
                     const double pk = 0.5 * (pit + pib);
                     const double th = Th_new[j] / dpn;

@@ -503,8 +503,9 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
                 double dh[L];
 #pragma unroll
                 for (int j = 0; j < L; j++) {
-                    const double dkm = (v.k[j] > 0) ? lmass<MODEL>(a.dsig[v.k[j] - 1], psi[j], a.ptop) : 0.0;
-                    dh[j] = (v.k[j] == 0) ? 0.5 * dpi_i[j] : 0.5 * (dkm + dpi_i[j]);
+                    // masses as factors, not branches (the top interface has no layer above)
+                    const double dkm = (v.k[j] > 0 ? 1.0 : 0.0) * lmass<MODEL>(a.dsig[v.k[j] - (v.k[j] > 0)], psi[j], a.ptop);
+                    dh[j] = 0.5 * (dkm + dpi_i[j]);
                 }
                 double wi[L], pi_[L];
                 ld_iface<L, M1>(a.w_s, cb, v, M, 0, wi);
@@ -515,10 +516,16 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
                 for (int j = 0; j < L; j++) aw[j] = ap[j] = 0;
                 double cdiv[6];
                 ld6<double>(tb.div64 + lc * kCellSlots, cdiv);
+                // slots grouped per basic block and no load under a condition,
+                // as in the horizontal part above (pad slot: edge 0, itself,
+                // zero flux and weight; the layer above the top: clamped index)
+                const bool up = v.k0 > 0;
+                const double dsu = a.dsig[v.k0 - (int)up];
+                const R mup = up ? (R)1 : (R)0;   // the layer above: a factor, not a branch
 #pragma unroll
                 for (int s = 0; s < kCellSlots; s++) {
-                    const int e = ce[s];
-                    if (e < 0) continue;
+                    if (s % slot_group<KERNEL_CELL_A, R>() == 0 && ce[s] < 0) continue;   // never taken
+                    const int e = ce[s] < 0 ? 0 : ce[s];
                     const int nb = cn[s];
                     double psn[L];
                     ld2d_s<L, M1>(cps + (1 + s) * M, v.mm0, psn);
@@ -527,28 +534,23 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
                     if constexpr (M1) {
 #pragma unroll
                         for (int j = 1; j < L; j++) Fm[j] = Fs[s][j - 1];
-                        if (v.k0 > 0) {
-                            const double d1 = lmass<MODEL>(a.dsig[v.k0 - 1], psi[0], a.ptop);
-                            const double d2 = lmass<MODEL>(a.dsig[v.k0 - 1], psn[0], a.ptop);
-                            const R um = us[(long)e * KM + km0 - 1];
-                            if constexpr (sizeof(R) == 8) Fm[0] = 0.5 * (d1 + d2) * um;
-                            else Fm[0] = (float)(0.5 * (d1 + d2)) * um;
-                        } else {
-                            Fm[0] = 0;
-                        }
+                        const double d1 = lmass<MODEL>(dsu, psi[0], a.ptop);
+                        const double d2 = lmass<MODEL>(dsu, psn[0], a.ptop);
+                        const R um = us[(long)e * KM + km0 - (up ? 1 : 0)];
+                        R f;
+                        if constexpr (sizeof(R) == 8) f = 0.5 * (d1 + d2) * um;
+                        else f = (float)(0.5 * (d1 + d2)) * um;
+                        Fm[0] = mup * f;
                     } else {
-                        if (v.k0 > 0) {
-                            const Pack<R, L> um = ldp<R, L>(us + (long)e * KM + km0 - M);
+                        const Pack<R, L> um = ldp<R, L>(us + (long)e * KM + km0 - (up ? M : 0));
 #pragma unroll
-                            for (int j = 0; j < L; j++) {
-                                const double d1 = lmass<MODEL>(a.dsig[v.k0 - 1], psi[j], a.ptop);
-                                const double d2 = lmass<MODEL>(a.dsig[v.k0 - 1], psn[j], a.ptop);
-                                if constexpr (sizeof(R) == 8) Fm[j] = 0.5 * (d1 + d2) * um.v[j];
-                                else Fm[j] = (float)(0.5 * (d1 + d2)) * um.v[j];
-                            }
-                        } else {
-#pragma unroll
-                            for (int j = 0; j < L; j++) Fm[j] = 0;
+                        for (int j = 0; j < L; j++) {
+                            const double d1 = lmass<MODEL>(dsu, psi[j], a.ptop);
+                            const double d2 = lmass<MODEL>(dsu, psn[j], a.ptop);
+                            R f;
+                            if constexpr (sizeof(R) == 8) f = 0.5 * (d1 + d2) * um.v[j];
+                            else f = (float)(0.5 * (d1 + d2)) * um.v[j];
+                            Fm[j] = mup * f;
                         }
                     }
                     double wn_[L], pn_[L];
@@ -556,7 +558,7 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
                     ld_iface<L, M1>(a.phi_s, (long)nb * K1M, v, M, 0, pn_);
 #pragma unroll
                     for (int j = 0; j < L; j++) {
-                        const R Fh = (v.k[j] == 0) ? (R)0.5 * Fs[s][j] : (R)0.5 * (Fm[j] + Fs[s][j]);
+                        const R Fh = (R)0.5 * (Fm[j] + Fs[s][j]);   // Fm = 0 at the top interface
                         const R c = (R)cdiv[s] * Fh * (R)0.5;
                         aw[j] += c * (R)(wn_[j] - wi[j]);
                         ap[j] += c * (R)(pn_[j] - pi_[j]);
@@ -571,26 +573,24 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
                 if constexpr (M1) {
 #pragma unroll
                     for (int j = 0; j < L; j++) {
-                        wu[j] = (v.k[j] >= 1) ? a.w_s[cb + v.k[j] - 1] : 0.0;
-                        pu[j] = (v.k[j] >= 1) ? a.phi_s[cb + v.k[j] - 1] : 0.0;
+                        const int kq = v.k[j] - (v.k[j] >= 1);   // clamped; unused at the top
+                        wu[j] = a.w_s[cb + kq];
+                        pu[j] = a.phi_s[cb + kq];
                     }
                 } else {
-#pragma unroll
-                    for (int j = 0; j < L; j++) wu[j] = pu[j] = 0.0;
-                    if (v.k0 > 0) {
-                        ld_iface<L, M1>(a.w_s, cb, v, M, -1, wu);
-                        ld_iface<L, M1>(a.phi_s, cb, v, M, -1, pu);
-                    }
+                    ld_iface<L, M1>(a.w_s, cb, v, M, -(int)up, wu);   // unused at the top
+                    ld_iface<L, M1>(a.phi_s, cb, v, M, -(int)up, pu);
                 }
 #pragma unroll
                 for (int j = 0; j < L; j++) {
                     const int kk = v.k[j], mm = v.mm0 + (M1 ? 0 : j);
                     const R inv_dh = (R)(1.0 / dh[j]);
                     R vw = 0, vp = 0;
-                    if (kk >= 1) {
-                        const R ml = (R)(0.5 * (md[(kk - 1) * M + mm] + md[kk * M + mm]));
-                        vw += ml * (R)(wi[j] - wu[j]);
-                        vp += ml * (R)(pi_[j] - pu[j]);
+                    {
+                        const R fu = kk >= 1 ? (R)1 : (R)0;   // no interface above the top one
+                        const R ml = (R)(0.5 * (md[(kk - (kk >= 1)) * M + mm] + md[kk * M + mm]));
+                        vw += fu * (ml * (R)(wi[j] - wu[j]));
+                        vp += fu * (ml * (R)(pi_[j] - pu[j]));
                     }
                     {
                         const R ml = (R)(0.5 * (md[kk * M + mm] + md[(kk + 1) * M + mm]));
@@ -599,7 +599,7 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
                     }
                     const R advw = aw[j] * inv_dh + vw * (inv_dh * (R)0.5);
                     const R advp = ap[j] * inv_dh + vp * (inv_dh * (R)0.5);
-                    ws_[j] = (kk == 0) ? 0.0 : wn0[j] - a.dts * (double)advw;
+                    ws_[j] = (kk == 0 ? 0.0 : 1.0) * (wn0[j] - a.dts * (double)advw);   // w = 0 at the lid
                     ps_[j] = pn0[j] - a.dts * (double)advp;
                 }
                 st_iface<L, M1>(a.wstar, cb, v, M, 0, ws_);
@@ -867,8 +867,8 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                     up = a.th32_s[ou];
                     dn = a.th32_s[od];
                 }
-                thu[0] = has_up ? up : (R)0;
-                thd[L - 1] = has_dn ? dn : (R)0;
+                thu[0] = up;      // unused (multiplied by zero below) at the lid
+                thd[L - 1] = dn;  // and at the surface
             } else {
                 const bool has_dn = v.k0 < K - 1;
                 double du[L], dd[L];
@@ -882,8 +882,8 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                 theta_prev<MODEL, R, L>(a, i, KM, has_dn ? km0 + M : km0, dd, psi, td);
 #pragma unroll
                 for (int j = 0; j < L; j++) {
-                    thu[j] = has_up ? tu[j] : (R)0;
-                    thd[j] = has_dn ? td[j] : (R)0;
+                    thu[j] = tu[j];
+                    thd[j] = td[j];
                 }
             }
             double dps_[L], psn_[L];
@@ -896,8 +896,8 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                 // interfaces k and k + 1 always exist in mdot [K+1]; the flux
                 // through the lid and the surface is zero
                 const R mt = (R)md[(long)v.k[j] * M + mm], mb = (R)md[(long)(v.k[j] + 1) * M + mm];
-                const R top = v.k[j] > 0 ? mt * ((R)0.5 * (thu[j] + th_i[j])) : (R)0;
-                const R bot = v.k[j] < K - 1 ? mb * ((R)0.5 * (th_i[j] + thd[j])) : (R)0;
+                const R top = (v.k[j] > 0 ? (R)1 : (R)0) * (mt * ((R)0.5 * (thu[j] + th_i[j])));
+                const R bot = (v.k[j] < K - 1 ? (R)1 : (R)0) * (mb * ((R)0.5 * (th_i[j] + thd[j])));
                 const R dTh = -hdiv[j] - (bot - top);
                 Th_new[j] = Thn.v[j] + a.dts * (double)dTh;
                 ps_new[j] = psn_[j] + a.dts * dps_[j];
@@ -1178,8 +1178,8 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
             const R ub = us[base + (v.k[L - 1] < K - 1 ? L : L - 1)];
 #pragma unroll
             for (int j = 0; j < L; j++) {
-                uup[j] = (j > 0) ? uk.v[j - 1] : ((v.k0 > 0) ? ua : (R)0);
-                udn[j] = (j < L - 1) ? uk.v[j + 1] : ((v.k[j] < K - 1) ? ub : (R)0);
+                uup[j] = (j > 0) ? uk.v[j - 1] : ua;   // ua, ub: unused at the lid and the surface
+                udn[j] = (j < L - 1) ? uk.v[j + 1] : ub;
             }
             const double *m1p = a.mdot + (long)c1 * K1M + v.k0, *m2p = a.mdot + (long)c2 * K1M + v.k0;
             double i1[L + 1], i2[L + 1];
@@ -1202,8 +1202,8 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
             const Pack<double, L> b2 = ldp<double, L>(a.mdot + (long)c2 * K1M + (long)(v.k0 + 1) * M + v.mm0);
 #pragma unroll
             for (int j = 0; j < L; j++) {
-                uup[j] = (v.k0 > 0) ? pu.v[j] : (R)0;
-                udn[j] = (v.k0 < K - 1) ? pd.v[j] : (R)0;
+                uup[j] = pu.v[j];
+                udn[j] = pd.v[j];
                 mt[j] = 0.5 * (t1.v[j] + t2.v[j]);
                 mb[j] = 0.5 * (b1.v[j] + b2.v[j]);
             }
@@ -1211,9 +1211,12 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
 #pragma unroll
         for (int j = 0; j < L; j++) {
             const double dpe = 0.5 * (lmass<MODEL>(dsg[j], p1[j], a.ptop) + lmass<MODEL>(dsg[j], p2[j], a.ptop));
+            // the terms through the lid and the surface are multiplied by zero
+            // rather than skipped (a branch would hold the loads behind it)
+            const R fb = v.k[j] < K - 1 ? (R)1 : (R)0, ft = v.k[j] > 0 ? (R)1 : (R)0;
             R va = 0;
-            if (v.k[j] < K - 1) va += (R)mb[j] * (udn[j] - uk.v[j]);
-            if (v.k[j] > 0) va += (R)mt[j] * (uk.v[j] - uup[j]);
+            va += fb * ((R)mb[j] * (udn[j] - uk.v[j]));
+            va += ft * ((R)mt[j] * (uk.v[j] - uup[j]));
             va = va / (R)(2.0 * dpe);
             adv[j] = adv[j] - va;
         }

@@ -58,6 +58,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-dbl", action="store_true", help="skip the all-FP64 timing")
     p.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    p.add_argument("--no-variants", action="store_true",
+                   help="skip the mixed-policy variants (MIX_BOX, MIX_DBL_MASS, MIX_F32_DIV) of the layered dycores")
     p.add_argument("--profile-steps", type=int, default=20,
                    help="steps run with HIP events between launches for per-kernel durations")
     p.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -159,15 +161,21 @@ def kernel_times(torch, s, w, nsteps, stream, nreps=20):
     return out
 
 
-def accuracy_run(torch, mpdc, g, w, st, stream, shapes):
-    """Both policies for the workload's own step count from the same input, in
-    the launch shapes of the timed runs."""
+def accuracy_run(torch, mpdc, g, w, st, stream, shapes, names=("DBL", "MIX")):
+    """The policies for the workload's own step count from the same input, in
+    the launch shapes of the timed runs; with the relative drift of the global
+    mass sum (dycores)."""
     res = {}
-    for name, pol in (("DBL", mpdc.POLICY_DBL), ("MIX", mpdc.POLICY_MIX)):
-        s = make_state(mpdc, g, w, st, pol, shapes.get(name.lower()))
+    for name in names:
+        s = make_state(mpdc, g, w, st, getattr(mpdc, "POLICY_" + name), shapes.get(name.lower()))
+        if w["model"] != "TRACER":
+            m0 = s.diagnostics(key_field(mpdc, w), stream=stream, check=False)["mass"]
         with torch.cuda.stream(stream):
             step(s, w, w["steps"], stream)
             torch.cuda.synchronize()
+        if w["model"] != "TRACER":
+            m1 = s.diagnostics(key_field(mpdc, w), stream=stream, check=False)["mass"]
+            res[name + "_mass_drift"] = abs(m1 - m0) / abs(m0)
         res[name] = s.state_read(key_field(mpdc, w), stream=stream)
         d = s.diagnostics(key_field(mpdc, w), stream=stream, check=False)
         res[name + "_nonfinite"] = d["nonfinite"]
@@ -266,6 +274,23 @@ def main():
     names = KERNEL_NAMES["tracer" if w["model"] == "TRACER" else "dycore"]
     traffic, traffic_src = recorded_traffic(args.workload, dom, s_mix.launch_shapes[names.index(dom)], digest)
     gate = {"mix_vs_dbl_l2": rel_l2(acc["MIX"], acc["DBL"]), "nonfinite": acc["MIX_nonfinite"] + acc["DBL_nonfinite"]}
+    if "MIX_mass_drift" in acc:
+        gate["mass_drift"] = {"mix": acc["MIX_mass_drift"], "dbl": acc["DBL_mass_drift"]}
+
+    # mixed-policy variants beside MIX (layered dycores only)
+    variants, var_keys = None, {}
+    if w["model"] in ("HDC", "NDC") and not args.no_variants:
+        variants = {}
+        for name in ("MIX_BOX", "MIX_DBL_MASS", "MIX_F32_DIV"):
+            s_v, sec_v = timed_run(torch, mpdc, g, w, st, getattr(mpdc, "POLICY_" + name), args.steps, args.warmup,
+                                   stream, not args.no_autotune, fixed.get(name.lower()))
+            shp = s_v.launch_shapes
+            del s_v
+            av = accuracy_run(torch, mpdc, g, w, st, stream, {name.lower(): shp}, names=(name,))
+            var_keys[name] = av[name]
+            variants[name] = {"value": units / sec_v, "ms_per_step": sec_v * 1e3, "speed_vs_mix": sec_mix / sec_v,
+                              "vs_dbl_l2": rel_l2(av[name], acc["DBL"]), "mass_drift": av[name + "_mass_drift"],
+                              "nonfinite": av[name + "_nonfinite"], "launch_shapes": shp}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -280,6 +305,9 @@ def main():
                 gpu_dbl, gpu_mix = acc["DBL"].reshape(ref.shape), acc["MIX"].reshape(ref.shape)
             gate["dbl_vs_oracle_l2"] = rel_l2(gpu_dbl, ref)
             gate["mix_vs_oracle_l2"] = rel_l2(gpu_mix, ref)
+            for name, x in var_keys.items():
+                xv = x[:, 0] if (w["model"] == "HDC" and M > 1) else x.reshape(ref.shape)
+                variants[name]["vs_oracle_l2"] = rel_l2(xv, ref)
         per_member = N * K * (T if w["model"] == "TRACER" else 1)
         cpu = {"value": per_member * nst / el, "unit": "cell-level-steps/s" if w["model"] != "TRACER"
                else "cell-level-tracer-steps/s", "cores": cores, "kind": "oracle",
@@ -310,6 +338,7 @@ def main():
         "hbm_gbs_step": {"mix": step_bytes_mix / sec_mix / 1e9,
                          "dbl": step_bytes_dbl / sec_dbl / 1e9 if sec_dbl else None},
         "accuracy_gate": gate,
+        "variants": variants,
         "kernels_mix": {k: {"ms": v["ms"], "ms_in_step": v["ms_in_step"], "MB": v["bytes"] / 1e6,
                             "GB/s": v["bytes"] / (v["ms"] * 1e-3) / 1e9} for k, v in kt.items()},
         "kernels_dbl": ({k: {"ms": v["ms"], "ms_in_step": v["ms_in_step"], "MB": v["bytes"] / 1e6,

@@ -67,6 +67,24 @@ extern "C" {
 
 #define MPDC_POLICY_DBL 0        /* all FP64                                               */
 #define MPDC_POLICY_MIX 1        /* the paper's term split (see above)                     */
+/* Variants of MIX (hydrostatic and non-hydrostatic dycore only; otherwise
+ * MPDC_E_UNSUPPORTED):
+ *  - MIX_BOX: the terms boxed in Eq. 5 as "FP64 compute, FP32 tendency" --
+ *    the kinetic energy (from the FP64 velocity) and its gradient, the
+ *    vertical advection of u and of theta, and the pressure-gradient
+ *    operator L[...] -- are computed in FP64 and rounded to FP32 once, as a
+ *    tendency; the rest as MIX;
+ *  - MIX_DBL_MASS: the mass flux of the continuity equation (Eq. 3) is formed
+ *    in FP64 from the FP64 velocity (the FP32 users take it rounded): the
+ *    switch for local mass conservation of Section 2.3 (about 1-2% of the
+ *    run time there; its effect is examined in Section 4.4);
+ *  - MIX_F32_DIV: the literal reading of Section 2.3 for continuity: the cell
+ *    divergence of the FP32 mass flux is accumulated in FP32, so the edge
+ *    terms no longer cancel exactly in the global mass sum (compare the
+ *    global mass drift of MIX, where the FP32 fluxes are summed in FP64). */
+#define MPDC_POLICY_MIX_BOX 2
+#define MPDC_POLICY_MIX_DBL_MASS 3
+#define MPDC_POLICY_MIX_F32_DIV 4
 
 /* ---- state fields for mpdc_state_write / mpdc_state_read (FP64 in and out) ---- */
 #define MPDC_FIELD_H 0           /* SW fluid depth h          [N][M]        */

@@ -163,7 +163,7 @@ size_t state_layout(mpdc_state *st, void *base) {
     Carver c(base);
     const long N = st->N, E = st->E, V = st->V, K = st->K, M = st->M, T = st->T;
     const long KM = K * M, K1M = (K + 1) * M;
-    const bool mix = st->policy == MPDC_POLICY_MIX;
+    const bool mix = st->policy != MPDC_POLICY_DBL;
     const size_t r = rsize(st->policy);
     st->partial = c.take<double>((size_t)kDiagBlocks * 9);
     st->nfpartial = c.take<unsigned long long>(kDiagBlocks);
@@ -198,7 +198,7 @@ size_t state_layout(mpdc_state *st, void *base) {
     if (sw) st->b = c.take<double>(N);
     st->dps = c.take<double>(N * M);
     if (!sw) st->mdot = c.take<double>(N * K1M);
-    st->ke = c.take<char>(N * KM * r);
+    st->ke = c.take<char>(N * KM * (st->policy == MPDC_POLICY_MIX_BOX ? sizeof(double) : r));
     if (!sw) st->hth = c.take<char>(3 * N * KM * r);
     st->qv = c.take<char>(V * KM * r);
     st->qh = c.take<char>(2 * E * KM * r);
@@ -583,7 +583,9 @@ void mpdc_mesh_destroy(mpdc_mesh *m) { delete m; }
 static int check_config(const mpdc_mesh *m, const mpdc_config *c) {
     if (!m || !c) return fail(MPDC_E_INVAL, "null mesh or config");
     if (c->model < MPDC_MODEL_SW || c->model > MPDC_MODEL_TRACER) return fail(MPDC_E_INVAL, "unknown model");
-    if (c->policy != MPDC_POLICY_DBL && c->policy != MPDC_POLICY_MIX) return fail(MPDC_E_INVAL, "unknown policy");
+    if (c->policy < MPDC_POLICY_DBL || c->policy > MPDC_POLICY_MIX_F32_DIV) return fail(MPDC_E_INVAL, "unknown policy");
+    if (c->policy > MPDC_POLICY_MIX && c->model != MPDC_MODEL_HDC && c->model != MPDC_MODEL_NDC)
+        return fail(MPDC_E_UNSUPPORTED, "the mixed-policy variants are built for the layered dycores only");
     if (c->K < 1 || c->M < 1 || c->K > 512 || c->M > 64) return fail(MPDC_E_INVAL, "K must be 1..512 and M 1..64");
     if (c->model == MPDC_MODEL_SW && c->K != 1) return fail(MPDC_E_UNSUPPORTED, "shallow water needs K = 1");
     if (c->model == MPDC_MODEL_NDC && c->K < 2) return fail(MPDC_E_UNSUPPORTED, "the NH column solve needs K >= 2");
@@ -684,7 +686,7 @@ int mpdc_state_write(mpdc_state *st, int f, const void *src, int src_on_device, 
                            (float *)st->q[st->parity], n);
         HIP_TRY(hipGetLastError());
     }
-    if (st->policy == MPDC_POLICY_MIX && st->model != MPDC_MODEL_TRACER) {
+    if (st->policy != MPDC_POLICY_DBL && st->model != MPDC_MODEL_TRACER) {
         StageArgs a = stage_args(st, 0);
         // regenerate the FP32 shadows of the current state (set 0)
         a.u_o = st->set[0].u;
@@ -881,7 +883,9 @@ static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
     const double N = st->N, E = st->E, V = st->V, K = st->K, M = st->M;
     const double KM = K * M, K1M = (K + 1) * M;
     const double r = (double)rsize(st->policy);
-    const bool mix = st->policy == MPDC_POLICY_MIX;
+    const bool mix = st->policy != MPDC_POLICY_DBL;
+    const bool box = st->policy == MPDC_POLICY_MIX_BOX;
+    const bool u64 = box || st->policy == MPDC_POLICY_MIX_DBL_MASS;   // cell_a reads the FP64 velocity
     const bool first = (stage == 0);
     if (st->model == MPDC_MODEL_TRACER) {
         const double T = st->T, nq = N * K * T;
@@ -905,7 +909,8 @@ static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
     switch (id) {
     case KERNEL_CELL_A: {
         // tables, u, ps, theta -> K (+ second derivatives, mdot, dps; NDC: w*, phi*)
-        double b = cellI + N * kCellSlots * (8 + r) + u_s + ps + th_s + N * KM * r /*ke*/;
+        double b = cellI + N * kCellSlots * (8 + r) + (u64 ? E * KM * 8 : u_s) + ps + th_s +
+                   N * KM * (box ? 8 : r) /*ke*/ + (box ? N * kCellSlots * 8 : 0) /*FP64 c_ke*/;
         if (sw) return b + ps /*h_n*/ + ps /*h_o*/;
         b += N * 3 * kCellSlots * r + 3 * N * KM * r /*hth*/ + N * K1M * 8 /*mdot*/ + ps /*dps*/;
         if (nh) b += 4 * N * K1M * 8 /*w_s, phi_s, w_n, phi_n*/ + 2 * N * K1M * 8 /*w*, phi* */ -
@@ -916,9 +921,10 @@ static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
         return V * 4 * 8 + V * 4 * (r + 8) + V * 8 + u_s + ps + V * KM * r;
     case KERNEL_CELL_B: {
         // Coriolis/KE shares: c_vert, c_div, c_gk, c_tk, q_v, K, u, ps -> qh
-        double b = cellI + N * kCellSlots * 4 + N * kCellSlots * 2 * r + N * 36 * r + V * KM * r + N * KM * r +
-                   u_s + ps + 2 * E * KM * r;
+        double b = cellI + N * kCellSlots * 4 + N * kCellSlots * 2 * r + N * 36 * r + V * KM * r +
+                   (box ? 0 : N * KM * r) + u_s + ps + 2 * E * KM * r;
         if (sw) return b;
+        if (box && !first) b += N * KM * 8;                // FP64 Theta_s for the vertical flux
         // theta transport and update: e_cell, hdir, d2, theta, hth, mdot, dps, Th_n, ps_n
         b += E * 8 + E * 6 * r + E * r + th_s + 3 * N * KM * r + N * K1M * 8 + ps;
         b += (first && !mix) ? 0 : N * KM * 8 + ps;       // Th_n, ps_n (stage 1 FP64: same arrays as _s)
@@ -933,6 +939,7 @@ static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
         b += E * KM * 8 + (mix ? E * KM * 4 : 0);           // u_o, u32_o
         if (sw) return b + ps /*h_o*/ + N * 8 /*b*/;
         b += u_s + ps + N * K1M * 8 + 2 * N * KM * 8 + ps; // u_s, ps_s, mdot, alpha, phim, ps_o
+        if (box) b += N * KM * 8 - u_s + (first ? 0 : E * KM * 8);   // FP64 K; FP64 u_s (= u_n at stage 1)
         if (nh) b += 2 * N * KM * 8;                        // pm, mum
         return b;
     }

@@ -8,7 +8,16 @@
 namespace mpdc {
 
 enum { MODEL_SW = MPDC_MODEL_SW, MODEL_HDC = MPDC_MODEL_HDC, MODEL_NDC = MPDC_MODEL_NDC };
-enum { POLICY_DBL = MPDC_POLICY_DBL, POLICY_MIX = MPDC_POLICY_MIX };
+enum {
+    POLICY_DBL = MPDC_POLICY_DBL,
+    POLICY_MIX = MPDC_POLICY_MIX,
+    POLICY_MIX_BOX = MPDC_POLICY_MIX_BOX,
+    POLICY_MIX_DBL_MASS = MPDC_POLICY_MIX_DBL_MASS,
+    POLICY_MIX_F32_DIV = MPDC_POLICY_MIX_F32_DIV
+};
+// Variants of the mixed policy inside the FP32 kernel instances (template
+// argument VAR): which terms leave the default split.
+enum { VAR_MIX = 0, VAR_BOX = 1, VAR_DBL_MASS = 2, VAR_F32_DIV = 3 };
 enum { KERNEL_CELL_A = 0, KERNEL_VERTEX = 1, KERNEL_CELL_B = 2, KERNEL_EDGE = 3 };
 // largest work-group of the column kernels (keeps 256 VGPRs available per lane)
 constexpr int kColumnThreads = 512;
@@ -54,7 +63,7 @@ struct StageArgs {
     // stage intermediates
     double *dps;         // [N][M]
     double *mdot;        // [N][K+1][M]
-    void *ke;            // [N][K][M]      (R)
+    void *ke;            // [N][K][M]      (R; FP64 in the boxed variant)
     void *hth;           // [N][3][K][M]   (R)
     void *qv;            // [V][K][M]      (R)
     void *qh;            // [E][2][K][M]   (R) each cell's share of Coriolis - grad K per edge

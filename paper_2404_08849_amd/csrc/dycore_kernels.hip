@@ -41,6 +41,8 @@
 // state update) is double in both instantiations.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "dycore_kernels.h"
 
 namespace mpdc {
@@ -338,8 +340,11 @@ __device__ __forceinline__ double lds_sum_down(const double *p, int stride, int 
 // ---------------------------------------------------------------------------
 // cell_a
 // ---------------------------------------------------------------------------
-template <int MODEL, typename R, int L, bool M1>
+template <int MODEL, typename R, int L, bool M1, int VAR>
 __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
+    // mixed-policy variants: the boxed kinetic energy and the FP64 mass flux
+    // read the FP64 velocity instead of its FP32 shadow
+    constexpr bool U64 = VAR == VAR_BOX || VAR == VAR_DBL_MASS;
     extern __shared__ double lds[];
     const DevMesh &m = a.mesh;
     const int K = a.K, M = M1 ? 1 : a.M, KM = K * M;
@@ -352,7 +357,8 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
     stage_columns<KERNEL_CELL_A, MODEL, R, M1>(a, tb, a.cpb * (KM / L));
     const double *cps = tb.ps + (long)lc * 7 * M;   // ps_s of this cell, then of its neighbours
 
-    double dsg[L], psi[L], dpi_i[L], D[L], sgb[L];
+    double dsg[L], psi[L], dpi_i[L], D[L], sgb[L], ke64[L];
+    float Df[L];   // literal FP32 divergence
     R ke[L], Fs[kCellSlots][L] = {};
     R h0[L], h1[L], h2[L], th_i[L];
     int ce[6], cn[6];
@@ -365,7 +371,9 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
             dsg[j] = (MODEL == MODEL_SW) ? 1.0 : a.dsig[v.k[j]];
             dpi_i[j] = lmass<MODEL>(dsg[j], psi[j], a.ptop);
             D[j] = 0.0;
+            Df[j] = 0.0f;
             ke[j] = 0;
+            ke64[j] = 0.0;
             h0[j] = h1[j] = h2[j] = 0;
         }
         ld6<int>(tb.ce + lc * kCellSlots, ce);
@@ -374,6 +382,8 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
         R cke[6], ch0[6], ch1[6], ch2[6];
         ld6<double>(tb.div64 + lc * kCellSlots, cdiv);
         ld6<R>(tb.ke + lc * kCellSlots, cke);
+        double cked[6];   // FP64 kinetic-energy weights of the boxed variant
+        if constexpr (VAR == VAR_BOX) ld6<double>(m.c_ke + (long)i * kCellSlots, cked);
         if constexpr (MODEL != MODEL_SW) {
             const R *ch = tb.hs + lc * 3 * kCellSlots;
             ld6<R>(ch, ch0);
@@ -392,17 +402,39 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
             const int nb = cn[s];
             double psn[L];
             ld2d_s<L, M1>(cps + (1 + s) * M, v.mm0, psn);
-            const Pack<R, L> u = ldp<R, L>(us + (long)e * KM + km0);
+            R ur[L];
+            double ud[L];
+            if constexpr (U64) {
+                const Pack<double, L> u = ldp<double, L>(a.u_s + (long)e * KM + km0);
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    ud[j] = u.v[j];
+                    ur[j] = (R)u.v[j];   // the FP32 shadow's value
+                }
+            } else {
+                const Pack<R, L> u = ldp<R, L>(us + (long)e * KM + km0);
+#pragma unroll
+                for (int j = 0; j < L; j++) ur[j] = u.v[j];
+            }
 #pragma unroll
             for (int j = 0; j < L; j++) {
                 const double dpe = 0.5 * (dpi_i[j] + lmass<MODEL>(dsg[j], psn[j], a.ptop));
-                R f;
-                if constexpr (sizeof(R) == 8) f = dpe * u.v[j];
-                else f = (float)dpe * u.v[j];
-                Fs[s][j] = pad ? (R)0 : f;
-                if constexpr (sizeof(R) == 8) D[j] += cdiv[s] * Fs[s][j];
-                else D[j] += cdiv[s] * (double)Fs[s][j];
-                ke[j] += cke[s] * u.v[j] * u.v[j];
+                if constexpr (VAR == VAR_DBL_MASS) {
+                    // continuity in FP64; the advective users take the flux rounded
+                    const double f64 = pad ? 0.0 : dpe * ud[j];
+                    Fs[s][j] = (R)f64;
+                    D[j] += cdiv[s] * f64;
+                } else {
+                    R f;
+                    if constexpr (sizeof(R) == 8) f = dpe * ur[j];
+                    else f = (float)dpe * ur[j];
+                    Fs[s][j] = pad ? (R)0 : f;
+                    if constexpr (VAR == VAR_F32_DIV) Df[j] += (float)cdiv[s] * (float)Fs[s][j];
+                    else if constexpr (sizeof(R) == 8) D[j] += cdiv[s] * Fs[s][j];
+                    else D[j] += cdiv[s] * (double)Fs[s][j];
+                }
+                if constexpr (VAR == VAR_BOX) ke64[j] += cked[s] * ud[j] * ud[j];
+                else ke[j] += cke[s] * ur[j] * ur[j];
             }
             if constexpr (MODEL != MODEL_SW) {
                 R th_n[L];
@@ -416,10 +448,21 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_a(StageArgs a) {
                 }
             }
         }
-        Pack<R, L> kp;
+        if constexpr (VAR == VAR_F32_DIV) {
 #pragma unroll
-        for (int j = 0; j < L; j++) kp.v[j] = ke[j];
-        stp<R, L>(a.ke_out<R>() + (long)i * KM + km0, kp);
+            for (int j = 0; j < L; j++) D[j] = (double)Df[j];
+        }
+        if constexpr (VAR == VAR_BOX) {
+            Pack<double, L> kp;
+#pragma unroll
+            for (int j = 0; j < L; j++) kp.v[j] = ke64[j];
+            stp<double, L>((double *)a.ke + (long)i * KM + km0, kp);
+        } else {
+            Pack<R, L> kp;
+#pragma unroll
+            for (int j = 0; j < L; j++) kp.v[j] = ke[j];
+            stp<R, L>(a.ke_out<R>() + (long)i * KM + km0, kp);
+        }
     }
 
     if constexpr (MODEL == MODEL_SW) {
@@ -677,7 +720,7 @@ __global__ void __launch_bounds__(1024) k_vertex(StageArgs a) {
 // cell_b: Coriolis/KE shares, theta transport, mass/Theta update, column
 // diagnostics or the NH column solve
 // ---------------------------------------------------------------------------
-template <int MODEL, typename R, int L, bool M1>
+template <int MODEL, typename R, int L, bool M1, int VAR>
 __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
     extern __shared__ double lds[];
     const DevMesh &m = a.mesh;
@@ -816,7 +859,9 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                         G[s][j] = Fs[s][j] * Q[s][j];
                     }
             }
-            const Pack<R, L> kp = ldp<R, L>(a.ke_in<R>() + (long)i * KM + km0);
+            // (the boxed variant adds -grad K in FP64 on the edge instead)
+            Pack<R, L> kp;
+            if constexpr (VAR != VAR_BOX) kp = ldp<R, L>(a.ke_in<R>() + (long)i * KM + km0);
             const R *tk = tb.tk + lc * kCellSlots * kCellSlots;
             R *qh = a.qh_out<R>();
 #pragma unroll
@@ -836,7 +881,8 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                         A = fmar(w[sp], Fs[sp][j], A);
                         B = fmar(w[sp], G[sp][j], B);
                     }
-                    out.v[j] = fmar(cgk[s], kp.v[j], fmar(Q[s][j], A, B));
+                    if constexpr (VAR == VAR_BOX) out.v[j] = fmar(Q[s][j], A, B);
+                    else out.v[j] = fmar(cgk[s], kp.v[j], fmar(Q[s][j], A, B));
                 }
                 const int side = (cdiv[s] > (R)0) ? 0 : 1;
                 stp<R, L>(qh + ((long)e * 2 + side) * KM + km0, out);
@@ -850,7 +896,41 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
             // (the top and bottom values are not used), so no load is conditional
             R thu[L], thd[L];
             const bool has_up = v.k0 > 0;
-            if constexpr (M1) {
+            double vb[L];   // boxed variant: bottom minus top flux in FP64
+            if constexpr (VAR == VAR_BOX) {
+                double t64[L], tu[L], td[L];
+                theta_prev<MODEL, double, L>(a, i, KM, km0, dsg, psi, t64);
+                if constexpr (M1) {
+                    const int kl = v.k[L - 1];
+                    const bool has_dn = kl < K - 1;
+                    const long ou = (long)i * KM + (has_up ? km0 - 1 : km0), od = (long)i * KM + (has_dn ? km0 + L : km0);
+                    const double up = a.Th_s[ou] / lmass<MODEL>(a.dsig[has_up ? v.k0 - 1 : v.k0], psi[0], a.ptop);
+                    const double dn = a.Th_s[od] / lmass<MODEL>(a.dsig[has_dn ? kl + 1 : kl], psi[0], a.ptop);
+#pragma unroll
+                    for (int j = 0; j < L; j++) {
+                        tu[j] = j > 0 ? t64[j - 1] : up;
+                        td[j] = j < L - 1 ? t64[j + 1] : dn;
+                    }
+                } else {
+                    const bool has_dn = v.k0 < K - 1;
+                    double du[L], dd[L];
+#pragma unroll
+                    for (int j = 0; j < L; j++) {
+                        du[j] = a.dsig[has_up ? v.k0 - 1 : v.k0];
+                        dd[j] = a.dsig[has_dn ? v.k0 + 1 : v.k0];
+                    }
+                    theta_prev<MODEL, double, L>(a, i, KM, has_up ? km0 - M : km0, du, psi, tu);
+                    theta_prev<MODEL, double, L>(a, i, KM, has_dn ? km0 + M : km0, dd, psi, td);
+                }
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    const int mm = v.mm0 + (M1 ? 0 : j);
+                    const double mt = md[(long)v.k[j] * M + mm], mb = md[(long)(v.k[j] + 1) * M + mm];
+                    const double top = (v.k[j] > 0 ? 1.0 : 0.0) * (mt * (0.5 * (tu[j] + t64[j])));
+                    const double bot = (v.k[j] < K - 1 ? 1.0 : 0.0) * (mb * (0.5 * (t64[j] + td[j])));
+                    vb[j] = bot - top;
+                }
+            } else if constexpr (M1) {
                 const int kl = v.k[L - 1];
                 const bool has_dn = kl < K - 1;
 #pragma unroll
@@ -895,10 +975,16 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                 const int mm = v.mm0 + (M1 ? 0 : j);
                 // interfaces k and k + 1 always exist in mdot [K+1]; the flux
                 // through the lid and the surface is zero
-                const R mt = (R)md[(long)v.k[j] * M + mm], mb = (R)md[(long)(v.k[j] + 1) * M + mm];
-                const R top = (v.k[j] > 0 ? (R)1 : (R)0) * (mt * ((R)0.5 * (thu[j] + th_i[j])));
-                const R bot = (v.k[j] < K - 1 ? (R)1 : (R)0) * (mb * ((R)0.5 * (th_i[j] + thd[j])));
-                const R dTh = -hdiv[j] - (bot - top);
+                R vd;
+                if constexpr (VAR == VAR_BOX) {
+                    vd = (R)vb[j];   // FP64 compute, one rounding as a tendency
+                } else {
+                    const R mt = (R)md[(long)v.k[j] * M + mm], mb = (R)md[(long)(v.k[j] + 1) * M + mm];
+                    const R top = (v.k[j] > 0 ? (R)1 : (R)0) * (mt * ((R)0.5 * (thu[j] + th_i[j])));
+                    const R bot = (v.k[j] < K - 1 ? (R)1 : (R)0) * (mb * ((R)0.5 * (th_i[j] + thd[j])));
+                    vd = bot - top;
+                }
+                const R dTh = -hdiv[j] - vd;
                 Th_new[j] = Thn.v[j] + a.dts * (double)dTh;
                 ps_new[j] = psn_[j] + a.dts * dps_[j];
             }
@@ -1136,8 +1222,13 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
 // ---------------------------------------------------------------------------
 // edge: momentum
 // ---------------------------------------------------------------------------
-template <int MODEL, typename R, int L, bool M1>
+template <int MODEL, typename R, int L, bool M1, int VAR>
 __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
+    // boxed variant: -grad K and the vertical advection of u in FP64 (from the
+    // FP64 kinetic energy and velocity), rounded to FP32 once with the
+    // pressure-gradient term as one tendency
+    constexpr bool BOX = VAR == VAR_BOX;
+    using RU = typename std::conditional<BOX, double, R>::type;
     const DevMesh &m = a.mesh;
     const int K = a.K, M = M1 ? 1 : a.M, KM = K * M;
     const int lanes = KM / L;
@@ -1150,8 +1241,16 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
     const Pack<int, 2> cc = ldp<int, 2>(m.e_cell + 2 * (long)e);
     const int c1 = cc.v[0], c2 = cc.v[1];
 
-    // Coriolis - grad K: the two cells' shares
+    // Coriolis - grad K: the two cells' shares (Coriolis only when boxed)
     R adv[L];
+    double box[L];
+    if constexpr (BOX) {
+        const double *ke = (const double *)a.ke;
+        const Pack<double, L> k1 = ldp<double, L>(ke + (long)c1 * KM + km0), k2 = ldp<double, L>(ke + (long)c2 * KM + km0);
+        const double di = m.e_dinv[e];
+#pragma unroll
+        for (int j = 0; j < L; j++) box[j] = -(k2.v[j] - k1.v[j]) * di;
+    }
     {
         const R *qh = a.qh_in<R>();
         const Pack<R, L> q1 = ldp<R, L>(qh + (long)e * 2 * KM + km0), q2 = ldp<R, L>(qh + ((long)e * 2 + 1) * KM + km0);
@@ -1161,21 +1260,23 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
 
     if constexpr (MODEL != MODEL_SW) {
         // centred vertical advection of u by the interface mass flux
-        const R *us = u_prev_ptr<R>(a);
+        const RU *us;
+        if constexpr (BOX) us = a.u_s;
+        else us = u_prev_ptr<R>(a);
         const long K1M = (long)(K + 1) * M;
         double p1[L], p2[L], dsg[L];
         ld2d<L, M1>(a.ps_s, c1, M, v.mm0, p1);
         ld2d<L, M1>(a.ps_s, c2, M, v.mm0, p2);
 #pragma unroll
         for (int j = 0; j < L; j++) dsg[j] = a.dsig[v.k[j]];
-        const Pack<R, L> uk = ldp<R, L>(us + base);
-        R uup[L], udn[L];
+        const Pack<RU, L> uk = ldp<RU, L>(us + base);
+        RU uup[L], udn[L];
         double mt[L], mb[L];
         // the levels above and below are read from clamped indices (no load
         // under a condition); the values past the lid and the surface are unused
         if constexpr (M1) {
-            const R ua = us[base + (v.k0 > 0 ? -1 : 0)];
-            const R ub = us[base + (v.k[L - 1] < K - 1 ? L : L - 1)];
+            const RU ua = us[base + (v.k0 > 0 ? -1 : 0)];
+            const RU ub = us[base + (v.k[L - 1] < K - 1 ? L : L - 1)];
 #pragma unroll
             for (int j = 0; j < L; j++) {
                 uup[j] = (j > 0) ? uk.v[j - 1] : ua;   // ua, ub: unused at the lid and the surface
@@ -1194,8 +1295,8 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
                 mb[j] = 0.5 * (i1[j + 1] + i2[j + 1]);
             }
         } else {
-            const Pack<R, L> pu = ldp<R, L>(us + base - (v.k0 > 0 ? M : 0));
-            const Pack<R, L> pd = ldp<R, L>(us + base + (v.k0 < K - 1 ? M : 0));
+            const Pack<RU, L> pu = ldp<RU, L>(us + base - (v.k0 > 0 ? M : 0));
+            const Pack<RU, L> pd = ldp<RU, L>(us + base + (v.k0 < K - 1 ? M : 0));
             const Pack<double, L> t1 = ldp<double, L>(a.mdot + (long)c1 * K1M + (long)v.k0 * M + v.mm0);
             const Pack<double, L> t2 = ldp<double, L>(a.mdot + (long)c2 * K1M + (long)v.k0 * M + v.mm0);
             const Pack<double, L> b1 = ldp<double, L>(a.mdot + (long)c1 * K1M + (long)(v.k0 + 1) * M + v.mm0);
@@ -1213,12 +1314,13 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
             const double dpe = 0.5 * (lmass<MODEL>(dsg[j], p1[j], a.ptop) + lmass<MODEL>(dsg[j], p2[j], a.ptop));
             // the terms through the lid and the surface are multiplied by zero
             // rather than skipped (a branch would hold the loads behind it)
-            const R fb = v.k[j] < K - 1 ? (R)1 : (R)0, ft = v.k[j] > 0 ? (R)1 : (R)0;
-            R va = 0;
-            va += fb * ((R)mb[j] * (udn[j] - uk.v[j]));
-            va += ft * ((R)mt[j] * (uk.v[j] - uup[j]));
-            va = va / (R)(2.0 * dpe);
-            adv[j] = adv[j] - va;
+            const RU fb = v.k[j] < K - 1 ? (RU)1 : (RU)0, ft = v.k[j] > 0 ? (RU)1 : (RU)0;
+            RU va = 0;
+            va += fb * ((RU)mb[j] * (udn[j] - uk.v[j]));
+            va += ft * ((RU)mt[j] * (uk.v[j] - uup[j]));
+            va = va / (RU)(2.0 * dpe);
+            if constexpr (BOX) box[j] -= va;
+            else adv[j] = adv[j] - va;
         }
     }
 
@@ -1264,7 +1366,8 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
     Pack<float, L> u32;
 #pragma unroll
     for (int j = 0; j < L; j++) {
-        uo.v[j] = un.v[j] + a.dts * ((double)adv[j] + pgf[j]);
+        if constexpr (BOX) uo.v[j] = un.v[j] + a.dts * (double)(adv[j] + (float)(box[j] + pgf[j]));
+        else uo.v[j] = un.v[j] + a.dts * ((double)adv[j] + pgf[j]);
         u32.v[j] = (float)uo.v[j];
     }
     stp<double, L>(a.u_o + base, uo);
@@ -1294,8 +1397,11 @@ __global__ void k_shadows(StageArgs a) {
 namespace {
 inline unsigned nblocks(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
-template <int MODEL, typename R, int L, bool M1>
+// VAR selects the mixed-policy variant of the FP32 instances; a kernel the
+// variant does not change runs its default instance
+template <int MODEL, typename R, int L, bool M1, int VAR>
 hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
+    constexpr int VB = VAR == VAR_BOX ? VAR_BOX : VAR_MIX;
     const int KM = a.K * a.M;
     const int lanes = KM / L;
     const int colthreads = a.cpb * lanes;
@@ -1306,16 +1412,16 @@ hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
     const size_t lds_b = stage_lds_bytes(MODEL, pol, KERNEL_CELL_B, a.cpb, a.K, a.M);
     switch (which) {
     case KERNEL_CELL_A:
-        hipLaunchKernelGGL((k_cell_a<MODEL, R, L, M1>), dim3(colblocks), dim3(colthreads), lds_a, s, a);
+        hipLaunchKernelGGL((k_cell_a<MODEL, R, L, M1, VAR>), dim3(colblocks), dim3(colthreads), lds_a, s, a);
         break;
     case KERNEL_VERTEX:
         hipLaunchKernelGGL((k_vertex<MODEL, R, L, M1>), dim3(nblocks((long)a.mesh.V * lanes, fb)), dim3(fb), 0, s, a);
         break;
     case KERNEL_CELL_B:
-        hipLaunchKernelGGL((k_cell_b<MODEL, R, L, M1>), dim3(colblocks), dim3(colthreads), lds_b, s, a);
+        hipLaunchKernelGGL((k_cell_b<MODEL, R, L, M1, VB>), dim3(colblocks), dim3(colthreads), lds_b, s, a);
         break;
     case KERNEL_EDGE:
-        hipLaunchKernelGGL((k_edge<MODEL, R, L, M1>), dim3(nblocks((long)a.mesh.E * lanes, fb)), dim3(fb), 0, s, a);
+        hipLaunchKernelGGL((k_edge<MODEL, R, L, M1, VB>), dim3(nblocks((long)a.mesh.E * lanes, fb)), dim3(fb), 0, s, a);
         break;
     default:
         return hipErrorInvalidValue;
@@ -1324,29 +1430,39 @@ hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
 }
 
 // flat kernels (vertex, edge) also take four values per lane
-template <int MODEL, typename R, bool M1>
+template <int MODEL, typename R, bool M1, int VAR>
 hipError_t launch_flat4(const StageArgs &a, int which, hipStream_t s) {
+    constexpr int VB = VAR == VAR_BOX ? VAR_BOX : VAR_MIX;
     const int KM = a.K * a.M;
     const int lanes = KM / 4;
     const int fb = a.flat_block;
     if (which == KERNEL_VERTEX)
         hipLaunchKernelGGL((k_vertex<MODEL, R, 4, M1>), dim3(nblocks((long)a.mesh.V * lanes, fb)), dim3(fb), 0, s, a);
     else if (which == KERNEL_EDGE)
-        hipLaunchKernelGGL((k_edge<MODEL, R, 4, M1>), dim3(nblocks((long)a.mesh.E * lanes, fb)), dim3(fb), 0, s, a);
+        hipLaunchKernelGGL((k_edge<MODEL, R, 4, M1, VB>), dim3(nblocks((long)a.mesh.E * lanes, fb)), dim3(fb), 0, s, a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-template <int MODEL, typename R>
+template <int MODEL, typename R, int VAR>
 hipError_t launch_stage_r(const StageArgs &a, int which, hipStream_t s) {
     const int L = a.vpl;
     if (a.M == 1) {
-        if (L == 4) return launch_flat4<MODEL, R, true>(a, which, s);
-        return L == 2 ? launch_stage_t<MODEL, R, 2, true>(a, which, s) : launch_stage_t<MODEL, R, 1, true>(a, which, s);
+        if (L == 4) return launch_flat4<MODEL, R, true, VAR>(a, which, s);
+        return L == 2 ? launch_stage_t<MODEL, R, 2, true, VAR>(a, which, s)
+                      : launch_stage_t<MODEL, R, 1, true, VAR>(a, which, s);
     }
-    if (L == 4) return launch_flat4<MODEL, R, false>(a, which, s);
-    return L == 2 ? launch_stage_t<MODEL, R, 2, false>(a, which, s) : launch_stage_t<MODEL, R, 1, false>(a, which, s);
+    if (L == 4) return launch_flat4<MODEL, R, false, VAR>(a, which, s);
+    return L == 2 ? launch_stage_t<MODEL, R, 2, false, VAR>(a, which, s)
+                  : launch_stage_t<MODEL, R, 1, false, VAR>(a, which, s);
+}
+
+// the variants exist for the layered models only
+template <int VAR> hipError_t launch_variant(int model, const StageArgs &a, int which, hipStream_t s) {
+    if (model == MODEL_HDC) return launch_stage_r<MODEL_HDC, float, VAR>(a, which, s);
+    if (model == MODEL_NDC) return launch_stage_r<MODEL_NDC, float, VAR>(a, which, s);
+    return hipErrorInvalidValue;
 }
 }  // namespace
 
@@ -1359,14 +1475,19 @@ size_t stage_lds_bytes(int model, int policy, int which, int cpb, int K, int M) 
 }
 
 hipError_t launch_stage_kernel(int model, int policy, const StageArgs &a, int which, hipStream_t s) {
-    if (policy == POLICY_DBL) {
-        if (model == MODEL_SW) return launch_stage_r<MODEL_SW, double>(a, which, s);
-        if (model == MODEL_HDC) return launch_stage_r<MODEL_HDC, double>(a, which, s);
-        return launch_stage_r<MODEL_NDC, double>(a, which, s);
+    switch (policy) {
+    case POLICY_DBL:
+        if (model == MODEL_SW) return launch_stage_r<MODEL_SW, double, VAR_MIX>(a, which, s);
+        if (model == MODEL_HDC) return launch_stage_r<MODEL_HDC, double, VAR_MIX>(a, which, s);
+        return launch_stage_r<MODEL_NDC, double, VAR_MIX>(a, which, s);
+    case POLICY_MIX:
+        if (model == MODEL_SW) return launch_stage_r<MODEL_SW, float, VAR_MIX>(a, which, s);
+        return launch_variant<VAR_MIX>(model, a, which, s);
+    case POLICY_MIX_BOX: return launch_variant<VAR_BOX>(model, a, which, s);
+    case POLICY_MIX_DBL_MASS: return launch_variant<VAR_DBL_MASS>(model, a, which, s);
+    case POLICY_MIX_F32_DIV: return launch_variant<VAR_F32_DIV>(model, a, which, s);
     }
-    if (model == MODEL_SW) return launch_stage_r<MODEL_SW, float>(a, which, s);
-    if (model == MODEL_HDC) return launch_stage_r<MODEL_HDC, float>(a, which, s);
-    return launch_stage_r<MODEL_NDC, float>(a, which, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_shadows(int model, const StageArgs &args, hipStream_t s) {

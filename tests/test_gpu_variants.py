@@ -1,0 +1,186 @@
+"""GPU parity of the mixed-policy variants against the FP64 oracle.
+
+MIX_BOX computes the terms boxed in Eq. 5 (kinetic-energy gradient, vertical
+advection, pressure-gradient operator) in FP64 with one FP32 rounding as a
+tendency; MIX_DBL_MASS forms the continuity mass flux in FP64 (the local mass
+switch of Section 2.3); MIX_F32_DIV accumulates the cell divergence of the
+FP32 mass flux in FP32 (the literal reading of Section 2.3).  All three are
+held to the mixed policy's bars (1e-5 normalised L2 on the surface pressure
+and Theta, 1e-3 on u); the global mass sum tells MIX_F32_DIV apart: the
+other policies conserve it to FP64 rounding, the FP32 divergence does not.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2404_08849_amd.inputs import initial as ic
+from gpu_helpers import gpu_hdc, gpu_ndc, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+MIX_TOL = 1e-5
+VARIANTS = ["MIX_BOX", "MIX_DBL_MASS", "MIX_F32_DIV"]
+
+
+@pytest.fixture(scope="module")
+def mpdc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_08849_amd.mpdc as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def oracle_mod():
+    import oracle
+    return oracle
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def hdc_g4(mpdc, oracle_mod, mesh_cache):
+    m = mesh_cache(4)
+    K = 30
+    s = ic.hdc_jet(m, K, seed=2000)
+    _say("hdc G4x30 10 steps: oracle and MIX")
+    ref = oracle_mod.OracleMesh(m).hdc_run(s["ps"], s["Theta"], s["u"], 600.0, 10)
+    g = mpdc.Mesh(m)
+    _, mix = gpu_hdc(mpdc, g, s, K, 600.0, 10, mpdc.POLICY_MIX)
+    return m, K, s, g, ref, mix
+
+
+@pytest.mark.parametrize("policy", VARIANTS)
+def test_variant_hdc_parity_g4(mpdc, hdc_g4, policy):
+    m, K, s, g, (ps_o, Th_o, u_o), mix = hdc_g4
+    _say("hdc G4x30 10 steps", policy)
+    st, out = gpu_hdc(mpdc, g, s, K, 600.0, 10, getattr(mpdc, "POLICY_" + policy))
+    ps, Th, u = out
+    e = (rel_l2(ps, ps_o, m["areaCell"]), rel_l2(Th, Th_o, m["areaCell"]), rel_l2(u, u_o))
+    em = (rel_l2(mix[0], ps_o, m["areaCell"]), rel_l2(mix[1], Th_o, m["areaCell"]), rel_l2(mix[2], u_o))
+    du = rel_l2(u - s["u"], u_o - s["u"])
+    _say("  ps %.3e  Theta %.3e  u %.3e  du %.3e   (MIX: %.3e %.3e %.3e)" % (e + (du,) + em))
+    assert e[0] <= MIX_TOL and e[1] <= MIX_TOL and e[2] <= 1e-3
+    # the variant ran its own arithmetic: it differs from MIX somewhere
+    assert any(not np.array_equal(a, b) for a, b in zip(out, mix))
+
+
+@pytest.mark.parametrize("policy", VARIANTS)
+def test_variant_ndc_parity_g4(mpdc, oracle_mod, mesh_cache, policy):
+    m = mesh_cache(4)
+    K = 20
+    s = ic.nh_warm_bubble(m, K, rh=6.0e5, seed=4000)
+    ref = oracle_mod.OracleMesh(m).ndc_run(s["ps"], s["Theta"], s["u"], s["w"], s["phi"], 60.0, 10)
+    g = mpdc.Mesh(m)
+    _say("ndc G4x20 10 steps", policy)
+    st, out = gpu_ndc(mpdc, g, s, K, 60.0, 10, getattr(mpdc, "POLICY_" + policy))
+    names = ["ps", "Theta", "u", "w", "phi"]
+    errs = {n: rel_l2(x, r) for n, x, r in zip(names, out, ref)}
+    _say("  " + "  ".join("%s %.3e" % kv for kv in errs.items()))
+    assert all(np.isfinite(x).all() for x in out)
+    assert errs["ps"] <= MIX_TOL and errs["Theta"] <= MIX_TOL and errs["phi"] <= MIX_TOL
+    assert errs["w"] <= 1e-2
+
+
+@pytest.mark.parametrize("policy", VARIANTS)
+def test_variant_ensemble_members(mpdc, oracle_mod, mesh_cache, policy):
+    # member-innermost instances (M > 1), two values per lane
+    m = mesh_cache(3)
+    K, M = 8, 2
+    base = ic.hdc_jet(m, K, seed=5000)
+    ens = ic.ensemble(base, M, sigma=0.1, seed=5000)
+    g = mpdc.Mesh(m)
+    om = oracle_mod.OracleMesh(m)
+    _say("hdc ensemble G3x8x2 5 steps", policy)
+    st, (ps, Th, u) = gpu_hdc(mpdc, g, ens, K, 900.0, 5, getattr(mpdc, "POLICY_" + policy), M=M)
+    for j in range(M):
+        ps_o, Th_o, u_o = om.hdc_run(ens["ps"][:, j], ens["Theta"][:, :, j], ens["u"][:, :, j], 900.0, 5)
+        e = (rel_l2(ps[:, j], ps_o), rel_l2(Th[:, :, j], Th_o), rel_l2(u[:, :, j], u_o))
+        _say("  member %d: ps %.3e  Theta %.3e  u %.3e" % ((j,) + e))
+        assert e[0] <= MIX_TOL and e[1] <= MIX_TOL and e[2] <= 1e-3
+
+
+@pytest.mark.parametrize("policy", VARIANTS)
+def test_variant_launch_shapes_are_bitwise_identical(mpdc, mesh_cache, policy):
+    m = mesh_cache(4)
+    K = 10
+    s = ic.hdc_jet(m, K, seed=2000)
+    g = mpdc.Mesh(m)
+    pol = getattr(mpdc, "POLICY_" + policy)
+    ref = None
+    for shapes in (None, [(1, 8), (1, 64), (1, 4), (1, 128)], [(2, 3), (4, 256), (2, 1), (4, 512)]):
+        _say("hdc G4x10", policy, "per-kernel shapes %s" % (shapes,))
+        st = mpdc.State(g, mpdc.MODEL_HDC, pol, K=K, dt=600.0, sigma=ic.sigma_interfaces(K))
+        for kid, (vpl, grp) in enumerate(shapes or []):
+            if vpl == 4 and K % 4:
+                vpl = 2
+            st.set_kernel_launch(kid, vpl, grp)
+        st.set_graph(shapes is not None)
+        st.state_write(mpdc.FIELD_PS, s["ps"][:, None])
+        st.state_write(mpdc.FIELD_THETA, s["Theta"][:, :, None])
+        st.state_write(mpdc.FIELD_U, s["u"][:, :, None])
+        if shapes is None:
+            st.dycore_step(4)
+        else:
+            import torch
+            with torch.cuda.stream(torch.cuda.Stream()):
+                st.dycore_step(4)
+                torch.cuda.current_stream().synchronize()
+        out = [st.state_read(f)[..., 0] for f in (mpdc.FIELD_PS, mpdc.FIELD_THETA, mpdc.FIELD_U)]
+        if ref is None:
+            ref = out
+        for a, b in zip(out, ref):
+            assert np.array_equal(a, b)
+
+
+def test_global_mass_separates_fp32_divergence(mpdc, oracle_mod, mesh_cache):
+    m = mesh_cache(4)
+    K = 10
+    s = ic.hdc_jet(m, K, seed=2000)
+    g = mpdc.Mesh(m)
+    m0 = oracle_mod.area_sum(m["areaCell"], s["ps"] - 1000.0)
+    drift = {}
+    for name in ["DBL", "MIX"] + VARIANTS:
+        st, (ps, Th, u) = gpu_hdc(mpdc, g, s, K, 600.0, 10, getattr(mpdc, "POLICY_" + name))
+        drift[name] = abs(oracle_mod.area_sum(m["areaCell"], ps - 1000.0) - m0) / m0
+    _say("hdc G4x10 10 steps, relative global mass drift: " +
+         "  ".join("%s %.2e" % kv for kv in drift.items()))
+    for name in ("DBL", "MIX", "MIX_BOX", "MIX_DBL_MASS"):
+        assert drift[name] <= 1e-13, name
+    # FP32 cell divergences: the edge terms no longer cancel in the global sum
+    assert drift["MIX_F32_DIV"] > 10.0 * max(drift["MIX"], 1e-15)
+
+
+def _config(mpdc, model, policy, K, T=0):
+    sig = np.ascontiguousarray(ic.sigma_interfaces(K), dtype=np.float64)
+    cfg = mpdc.Config(model, policy, K, 1, T, 1, 600.0, 9.80616, 287.0, 1004.5, 1.0e5, 1000.0,
+                      sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return cfg, sig   # sig must outlive the calls that read cfg
+
+
+def test_variants_rejected_where_not_built(mpdc, mesh_cache):
+    m = mesh_cache(2)
+    g = mpdc.Mesh(m)
+    lib = mpdc.lib
+    for model, K, T in ((mpdc.MODEL_SW, 1, 0), (mpdc.MODEL_TRACER, 4, 2)):
+        for pol in (mpdc.POLICY_MIX_BOX, mpdc.POLICY_MIX_DBL_MASS, mpdc.POLICY_MIX_F32_DIV):
+            cfg, sig = _config(mpdc, model, pol, K, T)
+            assert lib.mpdc_state_workspace_bytes(g.h, ctypes.byref(cfg)) == 0
+            out = ctypes.c_void_p()
+            assert lib.mpdc_state_create(g.h, ctypes.byref(cfg), ctypes.c_void_p(256), 1 << 40,
+                                         ctypes.byref(out)) == -6
+            assert out.value is None
+    cfg, sig = _config(mpdc, mpdc.MODEL_HDC, 5, 4)
+    assert lib.mpdc_state_workspace_bytes(g.h, ctypes.byref(cfg)) == 0
+    # the boxed variant keeps the kinetic energy in FP64
+    b = {}
+    for pol in (mpdc.POLICY_MIX, mpdc.POLICY_MIX_BOX, mpdc.POLICY_MIX_DBL_MASS):
+        cfg, sig = _config(mpdc, mpdc.MODEL_HDC, pol, 4)
+        b[pol] = lib.mpdc_state_workspace_bytes(g.h, ctypes.byref(cfg))
+    assert b[mpdc.POLICY_MIX_DBL_MASS] == b[mpdc.POLICY_MIX]
+    # (4 more bytes per cell-level, less what the 256-byte alignment of the regions absorbs)
+    assert b[mpdc.POLICY_MIX_BOX] >= b[mpdc.POLICY_MIX] + g.N * 4 * 4 - 256

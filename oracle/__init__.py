@@ -5,4 +5,5 @@ may import this package.  It wraps ``liboracle.so`` (plain C, built from
 ``oracle.c`` by ``build_oracle``) with ctypes and shares no code with the
 GPU library.
 """
-from .pyoracle import OracleMesh, build_oracle, oracle_lib, norms, area_sum, thomas  # noqa: F401
+from .pyoracle import (OracleMesh, build_oracle, oracle_lib, norms, area_sum, thomas,  # noqa: F401
+                       tracer_vertical_column)

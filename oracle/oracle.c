@@ -651,7 +651,18 @@ static void hydro_pgf(const or_mesh *h, const or_params *p, const double *ps, co
  * Stage s: pi_s and Theta are advanced first; the PGF/gravity term then uses
  * them (forward-backward); every other term uses the previous stage's state.
  */
-void or_hdc_run(const or_mesh *h, const or_params *p, double *ps, double *Theta, double *u, int nsteps)
+/* Mass fluxes handed to a time-split tracer step (Section 2.3: the tracer's
+ * mass flux is accumulated and averaged from the dycore's, Eq. 3): the
+ * horizontal flux F [E][K] and the vertical flux mdot [N][K+1] of the last
+ * RK stage of every step (the stage that advances the state over the whole
+ * dt) are added to Facc and Macc when these are not NULL. */
+static void accumulate(size_t n, const double *x, double *acc)
+{
+    for (size_t j = 0; j < n; j++) acc[j] += x[j];
+}
+
+static void hdc_run(const or_mesh *h, const or_params *p, double *ps, double *Theta, double *u, int nsteps,
+                    double *Facc, double *Macc)
 {
     const or_mesh_in *m = &h->m;
     const int N = m->N, E = m->E, V = m->V, K = p->K;
@@ -676,6 +687,10 @@ void or_hdc_run(const or_mesh *h, const or_params *p, double *ps, double *Theta,
             for (size_t x = 0; x < NK; x++) theta[x] = Theta[x] / dpi[x];
             theta_tendency(h, p, F, theta, mdot, dTh, we, wc);
             momentum_adv(h, p, u, F, dpi, mdot, adv, ke, zeta, dpiv, qv, Q);
+            if (s == 2 && Facc) {
+                accumulate(EK, F, Facc);
+                accumulate((size_t)N * (K + 1), mdot, Macc);
+            }
             for (int i = 0; i < N; i++) psn[i] = ps0[i] + dts * dps[i];
             for (size_t x = 0; x < NK; x++) Thn[x] = Th0[x] + dts * dTh[x];
             hydro_pgf(h, p, psn, Thn, pgf, alpha, pmid, phim);
@@ -687,6 +702,17 @@ void or_hdc_run(const or_mesh *h, const or_params *p, double *ps, double *Theta,
     free(ps0); free(Th0); free(u0); free(dpi); free(F); free(D); free(dps); free(mdot); free(theta);
     free(dTh); free(we); free(wc); free(adv); free(ke); free(zeta); free(dpiv); free(qv); free(Q);
     free(pgf); free(alpha); free(pmid); free(phim); free(psn); free(Thn);
+}
+
+void or_hdc_run(const or_mesh *h, const or_params *p, double *ps, double *Theta, double *u, int nsteps)
+{
+    hdc_run(h, p, ps, Theta, u, nsteps, NULL, NULL);
+}
+
+void or_hdc_run_flux(const or_mesh *h, const or_params *p, double *ps, double *Theta, double *u, int nsteps,
+                     double *Facc, double *Macc)
+{
+    hdc_run(h, p, ps, Theta, u, nsteps, Facc, Macc);
 }
 
 /* Tendencies of one hydrostatic stage evaluated at (pi_s, Theta, u), exported
@@ -861,8 +887,8 @@ static void nh_pgf(const or_mesh *h, const or_params *p, const double *Th, const
  * and phi using the new Theta and dpi; (4) u advances with the previous
  * stage's advective terms and the PGF of the new (dpi, Theta, phi).
  */
-void or_ndc_run(const or_mesh *h, const or_params *p, double *ps, double *Theta, double *u, double *w,
-                double *phi, int nsteps)
+static void ndc_run(const or_mesh *h, const or_params *p, double *ps, double *Theta, double *u, double *w,
+                    double *phi, int nsteps, double *Facc, double *Macc)
 {
     const or_mesh_in *m = &h->m;
     const int N = m->N, E = m->E, V = m->V, K = p->K, K1 = K + 1;
@@ -892,6 +918,10 @@ void or_ndc_run(const or_mesh *h, const or_params *p, double *ps, double *Theta,
             momentum_adv(h, p, u, F, dpi, mdot, adv, ke, zeta, dpiv, qv, Q);
             iface_advection(h, K, F, dpi, mdot, w, aw);
             iface_advection(h, K, F, dpi, mdot, phi, aphi);
+            if (s == 2 && Facc) {
+                accumulate(EK, F, Facc);
+                accumulate(NK1, mdot, Macc);
+            }
             for (int i = 0; i < N; i++) psn[i] = ps0[i] + dts * dps[i];
             for (size_t x = 0; x < NK; x++) Thn[x] = Th0[x] + dts * dTh[x];
             layer_mass(p, N, psn, dpin);
@@ -920,9 +950,73 @@ void or_ndc_run(const or_mesh *h, const or_params *p, double *ps, double *Theta,
     free(aw); free(aphi); free(wn); free(phin);
 }
 
+void or_ndc_run(const or_mesh *h, const or_params *p, double *ps, double *Theta, double *u, double *w,
+                double *phi, int nsteps)
+{
+    ndc_run(h, p, ps, Theta, u, w, phi, nsteps, NULL, NULL);
+}
+
+void or_ndc_run_flux(const or_mesh *h, const or_params *p, double *ps, double *Theta, double *u, double *w,
+                     double *phi, int nsteps, double *Facc, double *Macc)
+{
+    ndc_run(h, p, ps, Theta, u, w, phi, nsteps, Facc, Macc);
+}
+
 /* ------------------------------------------------------------------ */
 /* tracer transport: third-order flux, FCT limiter, RK3                */
 /* ------------------------------------------------------------------ */
+/*
+ * Vertical transport of one column over dt (Eq. 10, the vertical flux
+ * divergence), time-split after the horizontal step.  m [K+1] is the mass
+ * flux through interface k (between layers k-1 and k), positive towards the
+ * surface; m_0 and m_K are taken as zero.  Layer masses:
+ *   dpi_new_k = dpih_k - dt (m_{k+1} - m_k).
+ * Adaptively implicit split (after Shchepetkin 2015): with the donor layer
+ * d(k) (k-1 if m_k >= 0, else k) and the Courant number c = dt |m_k| / dpih_d,
+ * the explicit part is mE_k = m_k min(1, 1/(2c)) and the implicit part
+ * mI_k = m_k - mE_k.  Both are first-order upwind, the explicit part with the
+ * incoming q^h, the implicit part with the new q (backward Euler):
+ *   dpi_new_k q_k + dt (GI_{k+1} - GI_k) = dpih_k qh_k - dt (GE_{k+1} - GE_k),
+ *   GE_k = mE_k qh_d(k),   GI_k = mI_k q_d(k),
+ * a tridiagonal system in q (the same for every tracer) solved with the Thomas
+ * algorithm.  q [K][T] holds q^h on entry and the new q on return. */
+void or_tracer_vertical_column(int K, int T, double dt, const double *dpih, const double *m, double *q,
+                               double *dpi_new)
+{
+    double *mE = dalloc(K + 1), *mI = dalloc(K + 1);
+    double *sub = dalloc(K), *dia = dalloc(K), *sup = dalloc(K), *rhs = dalloc(K), *x = dalloc(K);
+    for (int k = 0; k <= K; k++) {
+        double mk = (k == 0 || k == K) ? 0.0 : m[k];
+        mE[k] = mk;
+        if (mk != 0.0) {
+            double donor = (mk >= 0.0) ? dpih[k - 1] : dpih[k];
+            double c = dt * fabs(mk) / donor;
+            if (c > 0.5) mE[k] = mk * (0.5 / c);
+        }
+        mI[k] = mk - mE[k];
+    }
+    for (int k = 0; k < K; k++) {
+        double mt = (k == 0) ? 0.0 : m[k], mb = (k == K - 1) ? 0.0 : m[k + 1];
+        dpi_new[k] = dpih[k] - dt * (mb - mt);
+        double at = dt * mI[k], ab = dt * mI[k + 1];
+        sub[k] = -fmax(at, 0.0);                                   /* inflow from above */
+        dia[k] = dpi_new[k] + fmax(ab, 0.0) + fmax(-at, 0.0);      /* outflow through both interfaces */
+        sup[k] = -fmax(-ab, 0.0);                                  /* inflow from below */
+    }
+    for (int t = 0; t < T; t++) {
+        for (int k = 0; k < K; k++) {
+            /* explicit upwind fluxes through the top and bottom interfaces */
+            double ge_t = 0.0, ge_b = 0.0;
+            if (k > 0) ge_t = mE[k] * ((mE[k] >= 0.0) ? q[(size_t)(k - 1) * T + t] : q[(size_t)k * T + t]);
+            if (k < K - 1) ge_b = mE[k + 1] * ((mE[k + 1] >= 0.0) ? q[(size_t)k * T + t] : q[(size_t)(k + 1) * T + t]);
+            rhs[k] = dpih[k] * q[(size_t)k * T + t] - dt * (ge_b - ge_t);
+        }
+        or_thomas(K, sub, dia, sup, rhs, x);
+        for (int k = 0; k < K; k++) q[(size_t)k * T + t] = x[k];
+    }
+    free(mE); free(mI); free(sub); free(dia); free(sup); free(rhs); free(x);
+}
+
 /*
  * Per stage s with dt_s (Eq. 10, horizontal part; Zalesak 1979 FCT):
  *   dpi_new = dpi^n - dt_s D(F)                              (FP64 continuity)
@@ -938,7 +1032,8 @@ void or_ndc_run(const or_mesh *h, const or_params *p, double *ps, double *Theta,
  * With fct == 0 the bounds are +-infinity, so R = 1 where P > 0 and the step
  * is the unlimited third-order scheme.
  */
-void or_tracer_run(const or_mesh *h, const or_params *p, const double *F, double *dpi, double *q, int nsteps)
+void or_tracer_run(const or_mesh *h, const or_params *p, const double *F, const double *vflux, double *dpi,
+                   double *q, int nsteps)
 {
     const or_mesh_in *m = &h->m;
     const int N = m->N, E = m->E, K = p->K, T = p->T;
@@ -1007,6 +1102,16 @@ void or_tracer_run(const or_mesh *h, const or_params *p, const double *F, double
             for (size_t x = 0; x < NK; x++) q[x * T + t] = qs[x];
         }
         for (size_t x = 0; x < NK; x++) dpi[x] = dpi[x] - p->dt * divF[x];
+        if (vflux) {
+            /* vertical step of every column, after the horizontal one */
+#pragma omp parallel for schedule(static)
+            for (int i = 0; i < N; i++) {
+                double dpv[512];
+                or_tracer_vertical_column(K, T, p->dt, dpi + (size_t)i * K, vflux + (size_t)i * (K + 1),
+                                          q + (size_t)i * K * T, dpv);
+                memcpy(dpi + (size_t)i * K, dpv, sizeof(double) * K);
+            }
+        }
     }
     free(divF); free(dpin); free(qn); free(qs); free(qtd); free(FL); free(Aa); free(qe); free(dL);
     free(Rp); free(Rm); free(Ft); free(dT);

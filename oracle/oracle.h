@@ -85,8 +85,18 @@ void or_hdc_run(const or_mesh *m, const or_params *p, double *ps, double *Theta,
                 double *u, int nsteps);
 void or_ndc_run(const or_mesh *m, const or_params *p, double *ps, double *Theta,
                 double *u, double *w, double *phi, int nsteps);
-void or_tracer_run(const or_mesh *m, const or_params *p, const double *F,
+/* vflux [N][K+1]: vertical mass flux through the interfaces (positive towards
+ * the surface), or NULL for horizontal transport only. */
+void or_tracer_run(const or_mesh *m, const or_params *p, const double *F, const double *vflux,
                    double *dpi, double *q, int nsteps);
+void or_tracer_vertical_column(int K, int T, double dt, const double *dpih, const double *m, double *q,
+                               double *dpi_new);
+/* As or_hdc_run / or_ndc_run, adding the horizontal mass flux [E][K] and the
+ * vertical mass flux [N][K+1] of each step's last stage to Facc and Macc. */
+void or_hdc_run_flux(const or_mesh *m, const or_params *p, double *ps, double *Theta, double *u, int nsteps,
+                     double *Facc, double *Macc);
+void or_ndc_run_flux(const or_mesh *m, const or_params *p, double *ps, double *Theta, double *u, double *w,
+                     double *phi, int nsteps, double *Facc, double *Macc);
 
 void or_hdc_tendency(const or_mesh *m, const or_params *p, const double *ps, const double *Theta,
                      const double *u, double *dps, double *dTh, double *du_adv, double *mdot);

@@ -62,7 +62,12 @@ def oracle_lib():
         lib.or_sw_run.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _dp, _dp, _dp, ctypes.c_int]
         lib.or_hdc_run.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _dp, _dp, _dp, ctypes.c_int]
         lib.or_ndc_run.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
-        lib.or_tracer_run.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _dp, _dp, _dp, ctypes.c_int]
+        lib.or_tracer_run.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _dp, _dp, _dp, _dp, ctypes.c_int]
+        lib.or_tracer_vertical_column.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double] + [_dp] * 4
+        lib.or_hdc_run_flux.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _dp, _dp, _dp, ctypes.c_int,
+                                        _dp, _dp]
+        lib.or_ndc_run_flux.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _dp, _dp, _dp, _dp, _dp,
+                                        ctypes.c_int, _dp, _dp]
         lib.or_hdc_tendency.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params)] + [_dp] * 7
         lib.or_nh_column_solve.argtypes = [ctypes.POINTER(Params), ctypes.c_double, _dp, _dp, _dp, _dp]
         lib.or_norms.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp]
@@ -202,6 +207,26 @@ class OracleMesh:
         self.lib.or_hdc_run(self.h, ctypes.byref(p), _d(ps), _d(Theta), _d(u), nsteps)
         return ps, Theta, u
 
+    def hdc_run_flux(self, ps, Theta, u, dt, nsteps):
+        """hdc_run that also returns the sums of the last-stage mass fluxes
+        over the steps: (ps, Theta, u, F_sum [E][K], mdot_sum [N][K+1])."""
+        ps, Theta, u = [np.array(x, dtype=np.float64, order="C") for x in (ps, Theta, u)]
+        K = Theta.shape[1]
+        p = self.params(K, dt)
+        Fa, Ma = np.zeros((self.E, K)), np.zeros((self.N, K + 1))
+        self.lib.or_hdc_run_flux(self.h, ctypes.byref(p), _d(ps), _d(Theta), _d(u), nsteps, _d(Fa), _d(Ma))
+        return ps, Theta, u, Fa, Ma
+
+    def ndc_run_flux(self, ps, Theta, u, w, phi, dt, nsteps):
+        """ndc_run that also returns the sums of the last-stage mass fluxes."""
+        ps, Theta, u, w, phi = [np.array(x, dtype=np.float64, order="C") for x in (ps, Theta, u, w, phi)]
+        K = Theta.shape[1]
+        p = self.params(K, dt)
+        Fa, Ma = np.zeros((self.E, K)), np.zeros((self.N, K + 1))
+        self.lib.or_ndc_run_flux(self.h, ctypes.byref(p), _d(ps), _d(Theta), _d(u), _d(w), _d(phi), nsteps,
+                                 _d(Fa), _d(Ma))
+        return ps, Theta, u, w, phi, Fa, Ma
+
     def ndc_run(self, ps, Theta, u, w, phi, dt, nsteps):
         ps, Theta, u, w, phi = [np.array(x, dtype=np.float64, order="C") for x in (ps, Theta, u, w, phi)]
         K = Theta.shape[1]
@@ -232,11 +257,14 @@ class OracleMesh:
         self.lib.or_nh_column_solve(ctypes.byref(p), dts, _d(Th), _d(dp), _d(w), _d(phi))
         return w, phi
 
-    def tracer_run(self, F, dpi, q, dt, nsteps, fct=True):
+    def tracer_run(self, F, dpi, q, dt, nsteps, fct=True, vflux=None):
+        """vflux [N][K+1]: vertical mass flux through the interfaces (or None)."""
         F, dpi, q = [np.array(x, dtype=np.float64, order="C") for x in (F, dpi, q)]
         K, T = q.shape[1], q.shape[2]
         p = self.params(K, dt, T=T, fct=int(bool(fct)))
-        self.lib.or_tracer_run(self.h, ctypes.byref(p), _d(F), _d(dpi), _d(q), nsteps)
+        vf = None if vflux is None else np.ascontiguousarray(vflux, dtype=np.float64)
+        self.lib.or_tracer_run(self.h, ctypes.byref(p), _d(F), None if vf is None else _d(vf), _d(dpi), _d(q),
+                               nsteps)
         return dpi, q
 
 
@@ -259,6 +287,20 @@ def area_sum(area, x):
     area = np.ascontiguousarray(area, dtype=np.float64)
     n = area.shape[0]
     return lib.or_area_sum(n, x.size // n, _d(area), _d(x))
+
+
+def tracer_vertical_column(dpih, m, q, dt):
+    """Vertical tracer step of one column: dpih [K], m [K+1], q [K] or [K][T];
+    returns (q_new, dpi_new)."""
+    lib = oracle_lib()
+    dpih = np.ascontiguousarray(dpih, dtype=np.float64)
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    q = np.array(q, dtype=np.float64, order="C")
+    K = len(dpih)
+    T = 1 if q.ndim == 1 else q.shape[1]
+    dn = np.empty(K)
+    lib.or_tracer_vertical_column(K, T, float(dt), _d(dpih), _d(m), _d(q), _d(dn))
+    return q, dn
 
 
 def thomas(sub, diag, sup, rhs):

@@ -97,6 +97,10 @@ extern "C" {
 #define MPDC_FIELD_TR_FLUX 7     /* tracer mass flux F        [E][K]        */
 #define MPDC_FIELD_TR_DPI 8      /* tracer layer mass dpi     [N][K]        */
 #define MPDC_FIELD_TR_Q 9        /* tracer mixing ratios q    [N][K][T]     */
+#define MPDC_FIELD_TR_VFLUX 10   /* tracer vertical mass flux [N][K+1]: through interface k (between
+                                    layers k-1 and k), positive towards the surface; the lid and surface
+                                    entries are ignored.  Writing it (or mpdc_tracer_couple) turns on the
+                                    vertical step of mpdc_tracer_step */
 
 /* ---- mesh tables exported for checks (mpdc_mesh_get_table) ---- */
 #define MPDC_TABLE_CELLS_ON_CELL 0   /* int32 [2E], aligned with edges_on_cell            */
@@ -136,7 +140,9 @@ typedef struct {
     double dt;            /* time step (s)                                                  */
     double grav, rd, cp, p0, ptop;  /* g, R_d, c_p, reference and model-top pressure       */
     const double *sigma;  /* [K+1] sigma at interfaces, 0 at the top, 1 at the surface      */
-    int32_t reserved[8];  /* must be zero                                                   */
+    int32_t accumulate_flux; /* HDC/NDC with M = 1: 1 = sum each step's last-stage horizontal and
+                                vertical mass fluxes for mpdc_tracer_couple (0 otherwise)         */
+    int32_t reserved[7];  /* must be zero                                                   */
 } mpdc_config;
 
 typedef struct {
@@ -200,8 +206,31 @@ int mpdc_state_read(mpdc_state *st, int field_id, void *dst, int dst_on_device, 
 int mpdc_dycore_step(mpdc_state *st, int nsteps, void *stream);
 
 /* Advance the tracers (TRACER model) by nsteps RK3 steps with the FCT limiter
- * applied in every stage.  Asynchronous.  Errors: INVAL, STATE, DEVICE. */
+ * applied in every stage (horizontal part of Eq. 10).  Once a vertical mass
+ * flux is set, each step ends with the vertical part of Eq. 10 over the whole
+ * dt, time-split (Section 2.1: adaptively implicit in the vertical): the
+ * layer mass loses dt times the flux divergence; each interface flux splits
+ * into an explicit part capped at a Courant number of 1/2 (of its upwind
+ * layer) and an implicit remainder, both first-order upwind, the implicit one
+ * solved per column (tridiagonal, FP64).  Asynchronous.  Errors: INVAL,
+ * STATE, DEVICE. */
 int mpdc_tracer_step(mpdc_state *st, int nsteps, void *stream);
+
+/* Time-split coupling of the tracer transport to the dycore (Section 2.1;
+ * Section 2.3: the tracer's mass flux is accumulated and averaged from the
+ * dycore's and used in FP64).  The dycore state (HDC or NDC, created with
+ * accumulate_flux = 1) sums, over its steps, the horizontal mass flux of each
+ * step's last RK stage exactly as that stage's divergence used it (FP32 values
+ * under the mixed policies, FP64 under DBL and MIX_DBL_MASS) and that stage's
+ * vertical mass flux.  This call sets the tracer state's horizontal flux
+ * (MPDC_FIELD_TR_FLUX) and vertical flux (MPDC_FIELD_TR_VFLUX) to those sums
+ * divided by the number of steps n, in FP64, and clears the sums.  A tracer
+ * step of n times the dycore's dt then moves each layer mass exactly as the n
+ * dycore steps did (up to rounding).  Requirements: same mesh handle and K,
+ * tracer dt = n x dycore dt.  Asynchronous on stream.  Errors: INVAL (wrong
+ * models, mesh, K or dt), STATE (no accumulation or no step since the last
+ * coupling), UNSUPPORTED (K x T too large for the vertical step), DEVICE. */
+int mpdc_tracer_couple(mpdc_state *tracer, mpdc_state *dycore, void *stream);
 
 /* Deterministic FP64 reductions over the state: global mass, tracer masses,
  * NaN/Inf count, min/max of field_id, and (if ref_dev is not NULL) the

@@ -136,8 +136,14 @@ struct mpdc_state {
     double *b = nullptr, *dsig = nullptr, *sig = nullptr, *dps = nullptr, *mdot = nullptr;
     void *ke = nullptr, *hth = nullptr, *qv = nullptr, *qh = nullptr;
     double *alpha = nullptr, *phim = nullptr, *pm = nullptr, *mum = nullptr, *wstar = nullptr, *phistar = nullptr;
+    // dycore: last-stage mass fluxes summed over the steps since the last coupling
+    bool accumulate = false;
+    double *Facc = nullptr, *Macc = nullptr;
+    long acc_steps = 0;
     // tracer
     double *F = nullptr, *dpi[2] = {nullptr, nullptr};
+    double *vflux = nullptr;   // [N][K+1] vertical mass flux
+    bool has_vflux = false;    // run the vertical step
     void *q[3] = {nullptr, nullptr, nullptr};
     void *qtd = nullptr, *hq = nullptr, *rp = nullptr, *rm = nullptr;
     int parity = 0;
@@ -178,6 +184,7 @@ size_t state_layout(mpdc_state *st, void *base) {
         st->hq = c.take<char>(3 * N * K * T * r);
         st->rp = c.take<char>(N * K * T * r);
         st->rm = c.take<char>(N * K * T * r);
+        st->vflux = c.take<double>(N * (K + 1));
         return c.off;
     }
     const bool sw = st->model == MPDC_MODEL_SW, nh = st->model == MPDC_MODEL_NDC;
@@ -211,6 +218,10 @@ size_t state_layout(mpdc_state *st, void *base) {
         st->mum = c.take<double>(N * KM);
         st->wstar = c.take<double>(N * K1M);
         st->phistar = c.take<double>(N * K1M);
+    }
+    if (st->accumulate) {
+        st->Facc = c.take<double>(E * K);
+        st->Macc = c.take<double>(N * (K + 1));
     }
     return c.off;
 }
@@ -312,6 +323,7 @@ TracerArgs tracer_args(const mpdc_state *st, int s, int parity) {
     a.hq = st->hq;
     a.rp = st->rp;
     a.rm = st->rm;
+    a.vflux = st->vflux;
     a.last_stage = (s == 2);
     return a;
 }
@@ -337,6 +349,11 @@ int run_dycore_step(mpdc_state *st, hipStream_t s) {
             if (e != hipSuccess) return hip_fail(e, "dycore kernel launch");
         }
     }
+    if (st->accumulate) {
+        // the last stage's inputs (set 2) and vertical mass flux are still in place
+        hipError_t e = launch_flux_acc(st->model, st->policy, stage_args(st, 2), st->Facc, st->Macc, s);
+        if (e != hipSuccess) return hip_fail(e, "mass-flux accumulation launch");
+    }
     return MPDC_OK;
 }
 
@@ -347,6 +364,12 @@ int run_tracer_step(mpdc_state *st, int parity, hipStream_t s) {
             hipError_t e = launch_tracer(st, a, k, s);
             if (e != hipSuccess) return hip_fail(e, "tracer kernel launch");
         }
+    }
+    if (st->has_vflux) {
+        TracerArgs a = tracer_args(st, 2, parity);   // q_o, dpi_o: the horizontal result
+        a.dts = st->cfg.dt;
+        hipError_t e = launch_tracer_vertical(st->policy, a, s);
+        if (e != hipSuccess) return hip_fail(e, "tracer vertical step launch");
     }
     return MPDC_OK;
 }
@@ -393,6 +416,7 @@ long field_count(const mpdc_state *st, int f) {
     case MPDC_FIELD_TR_FLUX: return mdl == MPDC_MODEL_TRACER ? E * K : -1;
     case MPDC_FIELD_TR_DPI: return mdl == MPDC_MODEL_TRACER ? N * K : -1;
     case MPDC_FIELD_TR_Q: return mdl == MPDC_MODEL_TRACER ? N * K * T : -1;
+    case MPDC_FIELD_TR_VFLUX: return mdl == MPDC_MODEL_TRACER ? N * (K + 1) : -1;
     default: return -1;
     }
 }
@@ -411,6 +435,7 @@ double *field_ptr(mpdc_state *st, int f) {
     case MPDC_FIELD_TR_FLUX: return st->F;
     case MPDC_FIELD_TR_DPI: return st->dpi[st->parity];
     case MPDC_FIELD_TR_Q: return st->policy == MPDC_POLICY_DBL ? (double *)st->q[st->parity] : nullptr;
+    case MPDC_FIELD_TR_VFLUX: return st->vflux;
     default: return nullptr;
     }
 }
@@ -600,7 +625,10 @@ static int check_config(const mpdc_mesh *m, const mpdc_config *c) {
         for (int k = 0; k < c->K; k++)
             if (!(c->sigma[k + 1] > c->sigma[k])) return fail(MPDC_E_INVAL, "sigma must increase");
     }
-    for (int j = 0; j < 8; j++)
+    if (c->accumulate_flux != 0 && c->accumulate_flux != 1) return fail(MPDC_E_INVAL, "accumulate_flux must be 0 or 1");
+    if (c->accumulate_flux && (c->model == MPDC_MODEL_SW || c->model == MPDC_MODEL_TRACER || c->M != 1))
+        return fail(MPDC_E_UNSUPPORTED, "mass-flux accumulation needs a layered dycore with M = 1");
+    for (int j = 0; j < 7; j++)
         if (c->reserved[j]) return fail(MPDC_E_INVAL, "reserved config fields must be zero");
     return MPDC_OK;
 }
@@ -611,6 +639,7 @@ static mpdc_state *new_state(const mpdc_mesh *m, const mpdc_config *c) {
     st->cfg = *c;
     st->model = c->model;
     st->policy = c->policy;
+    st->accumulate = c->accumulate_flux != 0;
     st->K = c->K;
     st->M = c->M;
     st->T = c->model == MPDC_MODEL_TRACER ? c->T : 0;
@@ -672,6 +701,12 @@ int mpdc_state_write(mpdc_state *st, int f, const void *src, int src_on_device, 
     long n = field_count(st, f);
     if (n < 0) return fail(MPDC_E_INVAL, "field not part of this model");
     if (bytes != (size_t)n * sizeof(double)) return fail(MPDC_E_INVAL, "byte count does not match the field");
+    if (f == MPDC_FIELD_TR_VFLUX) {
+        if (tracer_vert_columns(st->K, st->T) < 1)
+            return fail(MPDC_E_UNSUPPORTED, "a column of K x T tracers does not fit the vertical step's LDS");
+        if (!st->has_vflux) drop_graphs(st);   // the step gains its vertical kernel
+        st->has_vflux = true;
+    }
     hipStream_t s = (hipStream_t)stream;
     hipMemcpyKind kind = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     double *dst = field_ptr(st, f);
@@ -829,12 +864,36 @@ static int step_common(mpdc_state *st, int nsteps, void *stream, bool tracer) {
             if (rc != MPDC_OK) return rc;
         }
         if (tracer) st->parity = 1 - st->parity;
+        else if (st->accumulate) st->acc_steps++;
     }
     return MPDC_OK;
 }
 
 int mpdc_dycore_step(mpdc_state *st, int nsteps, void *stream) { return step_common(st, nsteps, stream, false); }
 int mpdc_tracer_step(mpdc_state *st, int nsteps, void *stream) { return step_common(st, nsteps, stream, true); }
+
+int mpdc_tracer_couple(mpdc_state *tracer, mpdc_state *dycore, void *stream) {
+    if (!tracer || !dycore) return fail(MPDC_E_INVAL, "null state");
+    if (tracer->model != MPDC_MODEL_TRACER) return fail(MPDC_E_INVAL, "the first state must be a tracer state");
+    if (dycore->model != MPDC_MODEL_HDC && dycore->model != MPDC_MODEL_NDC)
+        return fail(MPDC_E_INVAL, "the second state must be a layered dycore state");
+    if (!dycore->accumulate) return fail(MPDC_E_STATE, "the dycore state does not accumulate its mass fluxes");
+    if (dycore->acc_steps < 1) return fail(MPDC_E_STATE, "no dycore step since the last coupling");
+    if (tracer->mesh != dycore->mesh || tracer->K != dycore->K)
+        return fail(MPDC_E_INVAL, "the states must share the mesh and the number of layers");
+    const double n = (double)dycore->acc_steps;
+    if (std::fabs(tracer->cfg.dt - n * dycore->cfg.dt) > 1e-12 * tracer->cfg.dt)
+        return fail(MPDC_E_INVAL, "the tracer step must span the accumulated dycore steps (dt_tracer = n dt)");
+    if (tracer_vert_columns(tracer->K, tracer->T) < 1)
+        return fail(MPDC_E_UNSUPPORTED, "a column of K x T tracers does not fit the vertical step's LDS");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_couple(dycore->Facc, dycore->Macc, tracer->F, tracer->vflux, tracer->E * tracer->K,
+                          tracer->N * (tracer->K + 1), dycore->acc_steps, s));
+    if (!tracer->has_vflux) drop_graphs(tracer);
+    tracer->has_vflux = true;
+    dycore->acc_steps = 0;
+    return MPDC_OK;
+}
 
 int mpdc_time_kernel(mpdc_state *st, int kernel_id, int nreps, void *stream, double *ms_avg) {
     if (!st || !ms_avg || nreps < 1) return fail(MPDC_E_INVAL, "bad arguments");

@@ -140,10 +140,21 @@ struct TracerArgs {
     void *qtd;             // [N][K][T] low-order solution (R)
     void *hq;              // [N][3][K][T] second-derivative coefficients of q_s (R)
     void *rp, *rm;         // [N][K][T] limiter ratios R+ / R- (R)
+    const double *vflux;   // [N][K+1] vertical mass flux through the interfaces (vertical step)
     int last_stage;
 };
 
 hipError_t launch_tracer_kernel(int policy, const TracerArgs &a, int which, hipStream_t s);
+// vertical step of the whole step dt (a.dts), in place on q_o and dpi_o
+hipError_t launch_tracer_vertical(int policy, const TracerArgs &a, hipStream_t s);
+// columns per work-group of the vertical step (0: a column does not fit the LDS)
+int tracer_vert_columns(int K, int T);
+// tracer fluxes from a dycore's accumulators over n steps (clears them)
+hipError_t launch_couple(double *Facc, double *Macc, double *F, double *vflux, long nF, long nM, long n,
+                         hipStream_t s);
+// add the last stage's horizontal [E][K] and vertical [N][K+1] mass fluxes
+// (a: the arguments of the last stage) to the accumulators (M = 1)
+hipError_t launch_flux_acc(int model, int policy, const StageArgs &a, double *Facc, double *Macc, hipStream_t s);
 
 // ---- diagnostics ----
 struct DiagArgs {

@@ -1490,6 +1490,43 @@ hipError_t launch_stage_kernel(int model, int policy, const StageArgs &a, int wh
     return hipErrorInvalidValue;
 }
 
+// The horizontal mass flux as the last stage's divergence used it (the same
+// operations as in k_cell_a, so the values are bitwise those of the stage:
+// FP32 from the FP32 velocity shadow, or FP64 from the FP64 velocity) and the
+// vertical mass flux of that stage, added to FP64 accumulators.  M = 1.
+template <int MODEL, bool F64>
+__global__ void k_flux_acc(StageArgs a, double *Facc, double *Macc) {
+    const long x = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int K = a.K;
+    if (x < (long)a.mesh.E * K) {
+        const int e = (int)(x / K), k = (int)(x - (long)e * K);
+        const int c1 = a.mesh.e_cell[2 * e], c2 = a.mesh.e_cell[2 * e + 1];
+        const double dsg = a.dsig[k];
+        const double dpe = 0.5 * (lmass<MODEL>(dsg, a.ps_s[c1], a.ptop) + lmass<MODEL>(dsg, a.ps_s[c2], a.ptop));
+        double f;
+        if constexpr (F64) f = dpe * a.u_s[x];
+        else f = (double)((float)dpe * a.u32_s[x]);
+        Facc[x] += f;
+    }
+    if (x < (long)a.mesh.N * (K + 1)) Macc[x] += a.mdot[x];
+}
+
+hipError_t launch_flux_acc(int model, int policy, const StageArgs &a, double *Facc, double *Macc, hipStream_t s) {
+    const long n = (long)(a.mesh.E > a.mesh.N + 1 ? a.mesh.E : a.mesh.N + 1) * (a.K + 1);
+    const bool f64 = policy == POLICY_DBL || policy == POLICY_MIX_DBL_MASS;
+    const dim3 g(nblocks(n, 256)), b(256);
+    if (model == MODEL_HDC) {
+        if (f64) hipLaunchKernelGGL((k_flux_acc<MODEL_HDC, true>), g, b, 0, s, a, Facc, Macc);
+        else hipLaunchKernelGGL((k_flux_acc<MODEL_HDC, false>), g, b, 0, s, a, Facc, Macc);
+    } else if (model == MODEL_NDC) {
+        if (f64) hipLaunchKernelGGL((k_flux_acc<MODEL_NDC, true>), g, b, 0, s, a, Facc, Macc);
+        else hipLaunchKernelGGL((k_flux_acc<MODEL_NDC, false>), g, b, 0, s, a, Facc, Macc);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_shadows(int model, const StageArgs &args, hipStream_t s) {
     StageArgs a = args;
     a.flat_block = 256;   // the kernel reads its work-group size from here

@@ -365,6 +365,132 @@ hipError_t launch_tracer_kernel(int policy, const TracerArgs &a, int which, hipS
 }
 
 // ---------------------------------------------------------------------------
+// vertical step (Eq. 10, the vertical flux divergence), time-split after the
+// horizontal stages: adaptively implicit first-order upwind
+// ---------------------------------------------------------------------------
+// Interface k (0..K) lies between layers k-1 and k; vflux[i][k] is the mass
+// flux through it, positive towards the surface (the lid and surface values
+// are taken as zero).  New layer mass: dpi_k - dt (m_{k+1} - m_k).  Each flux
+// splits into an explicit part, capped at a Courant number of 1/2 with respect
+// to its donor layer (so the explicit update alone is monotone), and the
+// implicit remainder; both are first-order upwind, the implicit part with the
+// new mixing ratio:
+//   dpi_new_k q_k + dt (GI_{k+1} - GI_k) = dpi_k qh_k - dt (GE_{k+1} - GE_k).
+// The tridiagonal matrix is an M-matrix (new q is a convex combination of the
+// old values).  One lane per (cell, tracer) runs the Thomas algorithm down the
+// column in FP64, keeping its factors in LDS; a work-group holds whole
+// columns, so the layer masses, which every lane of a column reads in the
+// forward sweep, are overwritten by the column's tracer-0 lane only after
+// the work-group's barrier.  q and dpi are updated in place.
+template <typename R>
+__global__ void __launch_bounds__(kTracerThreads) k_tr_vert(TracerArgs a, int cols) {
+    extern __shared__ double vlds[];
+    const int K = a.K, T = a.T;
+    const int tid = threadIdx.x;
+    const int lc = tid / T, t = tid - lc * T;
+    const long i = (long)blockIdx.x * cols + lc;
+    const bool valid = lc < cols && i < a.mesh.N;
+    double *cf = vlds + (long)tid * 2 * K, *df = cf + K;   // Thomas factors of this lane
+    R *q = (R *)a.q_o;
+    double *dpi = a.dpi_o;
+    const double dt = a.dts;
+    if (valid) {
+        const double *mc = a.vflux + i * (K + 1);
+        const double *dh = dpi + i * K;
+        const long qb = i * K * T + t;
+        double mEt = 0.0, aIt = 0.0;       // top interface of layer k: explicit flux, dt * implicit flux
+        double qu = 0.0;                   // q^h of the layer above
+        double qk = (double)q[qb];
+        double cprev = 0.0, dprev = 0.0;
+        for (int k = 0; k < K; k++) {
+            const bool below = k < K - 1;
+            const int kn = below ? k + 1 : k;   // clamped: the surface interface carries no flux
+            const double mb = below ? mc[k + 1] : 0.0;
+            const double mt = k > 0 ? mc[k] : 0.0;
+            const double dk = dh[k], dn = dh[kn];
+            const double qd = (double)q[qb + (long)kn * T];
+            double mEb = mb;
+            if (mb != 0.0) {
+                const double c = dt * fabs(mb) / (mb >= 0.0 ? dk : dn);
+                if (c > 0.5) mEb = mb * (0.5 / c);
+            }
+            const double aIb = dt * (mb - mEb);
+            const double dnew = dk - dt * (mb - mt);
+            const double sub = -fmax(aIt, 0.0);
+            const double dia = dnew + fmax(aIb, 0.0) + fmax(-aIt, 0.0);
+            const double sup = -fmax(-aIb, 0.0);
+            const double get = mEt * (mEt >= 0.0 ? qu : qk);   // zero at the lid (mEt = 0)
+            const double geb = mEb * (mEb >= 0.0 ? qk : qd);   // zero at the surface
+            const double rhs = dk * qk - dt * (geb - get);
+            const double den = dia - sub * cprev;
+            cprev = below ? sup / den : 0.0;
+            dprev = (rhs - sub * dprev) / den;
+            cf[k] = cprev;
+            df[k] = dprev;
+            mEt = mEb;
+            aIt = aIb;
+            qu = qk;
+            qk = qd;
+        }
+    }
+    __syncthreads();
+    if (valid) {
+        const double *mc = a.vflux + i * (K + 1);
+        const long qb = i * K * T + t;
+        double x = 0.0;
+        for (int k = K - 1; k >= 0; k--) {
+            x = df[k] - cf[k] * x;
+            q[qb + (long)k * T] = (R)x;
+            if (t == 0) {
+                const double mb = k < K - 1 ? mc[k + 1] : 0.0, mt = k > 0 ? mc[k] : 0.0;
+                dpi[i * K + k] = dpi[i * K + k] - dt * (mb - mt);
+            }
+        }
+    }
+}
+
+int tracer_vert_columns(int K, int T) {
+    if ((long)2 * K * T * 8 > 65536) return 0;   // one column's factors must fit the LDS of a work-group
+    int c = kTracerThreads / T;
+    while (c > 1 && (long)c * 2 * K * T * 8 > 32768) c--;
+    return c < 1 ? 1 : c;
+}
+
+hipError_t launch_tracer_vertical(int policy, const TracerArgs &a, hipStream_t s) {
+    const int cols = tracer_vert_columns(a.K, a.T);
+    if (cols < 1) return hipErrorInvalidValue;
+    const unsigned nb = (unsigned)((a.mesh.N + cols - 1) / cols);
+    const size_t lds = (size_t)cols * a.T * 2 * a.K * 8;
+    if (policy == POLICY_DBL)
+        hipLaunchKernelGGL(k_tr_vert<double>, dim3(nb), dim3(cols * a.T), lds, s, a, cols);
+    else
+        hipLaunchKernelGGL(k_tr_vert<float>, dim3(nb), dim3(cols * a.T), lds, s, a, cols);
+    return hipGetLastError();
+}
+
+// the dycore's accumulated mass fluxes, averaged over its n steps, become the
+// tracer's FP64 fluxes; the accumulators restart from zero
+__global__ void k_couple(double *Facc, double *Macc, double *F, double *vflux, long nF, long nM, double n) {
+    const long x = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < nF) {
+        F[x] = Facc[x] / n;
+        Facc[x] = 0.0;
+    }
+    if (x < nM) {
+        vflux[x] = Macc[x] / n;
+        Macc[x] = 0.0;
+    }
+}
+
+hipError_t launch_couple(double *Facc, double *Macc, double *F, double *vflux, long nF, long nM, long n,
+                         hipStream_t s) {
+    const long m = nF > nM ? nF : nM;
+    hipLaunchKernelGGL(k_couple, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, Facc, Macc, F, vflux, nF, nM,
+                       (double)n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // diagnostics: per-block FP64 partial sums in a fixed order (no atomics)
 // partial[b] = {sum A (x-off) w, min x, max x, sum A|x-r|, sum A|r|,
 //               sum A (x-r)^2, sum A r^2, max|x-r|, max|r|}

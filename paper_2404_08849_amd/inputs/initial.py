@@ -204,3 +204,21 @@ def tracer_solid_body(mesh, K, T, days=12.0, tilt_deg=45.0, ps=1.0e5, seed=3000)
         lo, hi = f.min(0, keepdims=True), f.max(0, keepdims=True)
         q[:, :, t] = (f - lo) / (hi - lo)
     return dict(F=F, dpi=dpi, q=q, u0=u0, period=period)
+
+
+def tracer_vertical_flux(dpi, dt, amp=0.3, seed=3100):
+    """Synthetic interface mass flux [N][K+1] (positive towards the surface,
+    zero at the lid and the surface) that changes each layer mass over dt by
+    a random fraction of at most about amp: dt (m_{k+1} - m_k) = amp xi_k dpi_k
+    with xi uniform in [-1, 1] and sum_k xi_k dpi_k = 0 per column.  The
+    Courant numbers of the interior interfaces reach about amp K / 2."""
+    r = np.random.default_rng(seed)
+    dpi = np.asarray(dpi, dtype=np.float64)
+    N, K = dpi.shape
+    xi = r.uniform(-1.0, 1.0, (N, K))
+    xi -= ((xi * dpi).sum(1) / dpi.sum(1))[:, None]          # zero column sum of xi dpi
+    xi /= np.maximum(np.abs(xi).max(1), 1e-300)[:, None]      # |xi| <= 1 again
+    m = np.zeros((N, K + 1))
+    m[:, 1:] = np.cumsum(amp * xi * dpi, axis=1) / dt
+    m[:, K] = 0.0
+    return m

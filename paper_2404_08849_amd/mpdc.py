@@ -21,7 +21,7 @@ ERRORS = {-1: "INVAL", -2: "MESH", -3: "NOMEM", -4: "DEVICE", -5: "NUMERIC", -6:
 MODEL_SW, MODEL_HDC, MODEL_NDC, MODEL_TRACER = 0, 1, 2, 3
 POLICY_DBL, POLICY_MIX, POLICY_MIX_BOX, POLICY_MIX_DBL_MASS, POLICY_MIX_F32_DIV = 0, 1, 2, 3, 4
 FIELD_H, FIELD_PS, FIELD_THETA, FIELD_U, FIELD_W, FIELD_PHI, FIELD_B = 0, 1, 2, 3, 4, 5, 6
-FIELD_TR_FLUX, FIELD_TR_DPI, FIELD_TR_Q = 7, 8, 9
+FIELD_TR_FLUX, FIELD_TR_DPI, FIELD_TR_Q, FIELD_TR_VFLUX = 7, 8, 9, 10
 TABLE_CELLS_ON_CELL, TABLE_EDGE_SIGN, TABLE_VERTEX_SIGN = 0, 1, 2
 TABLE_TRISK_OFFSET, TABLE_TRISK_EDGE, TABLE_TRISK_WEIGHT, TABLE_HESSIAN = 3, 4, 5, 6
 
@@ -50,7 +50,7 @@ class Config(ctypes.Structure):
                 ("M", ctypes.c_int32), ("T", ctypes.c_int32), ("fct", ctypes.c_int32),
                 ("dt", ctypes.c_double), ("grav", ctypes.c_double), ("rd", ctypes.c_double),
                 ("cp", ctypes.c_double), ("p0", ctypes.c_double), ("ptop", ctypes.c_double),
-                ("sigma", _dp), ("reserved", ctypes.c_int32 * 8)]
+                ("sigma", _dp), ("accumulate_flux", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
 class Diag(ctypes.Structure):
@@ -77,6 +77,7 @@ def _load():
         "mpdc_state_read": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_size_t, _vp]),
         "mpdc_dycore_step": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
         "mpdc_tracer_step": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
+        "mpdc_tracer_couple": (ctypes.c_int, [_vp, _vp, _vp]),
         "mpdc_diagnostics": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.POINTER(Diag), _vp]),
         "mpdc_set_graph": (ctypes.c_int, [_vp, ctypes.c_int]),
         "mpdc_set_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
@@ -168,12 +169,12 @@ class State:
     """mpdc_state_create and the per-state calls (dycore_step, tracer_step, diagnostics, ...)."""
 
     def __init__(self, mesh, model, policy, K=1, M=1, T=0, dt=1.0, sigma=None, fct=True,
-                 grav=9.80616, rd=287.0, cp=1004.5, p0=1.0e5, ptop=1000.0, device="cuda"):
+                 grav=9.80616, rd=287.0, cp=1004.5, p0=1.0e5, ptop=1000.0, device="cuda", accumulate_flux=False):
         self.mesh = mesh
         self.model, self.policy, self.K, self.M, self.T = model, policy, K, M, T
         self.sigma = _f64(np.arange(K + 1) / K if sigma is None else sigma)
         self.cfg = Config(model, policy, K, M, T, int(bool(fct)), dt, grav, rd, cp, p0, ptop,
-                          self.sigma.ctypes.data_as(_dp))
+                          self.sigma.ctypes.data_as(_dp), int(bool(accumulate_flux)))
         nbytes = lib.mpdc_state_workspace_bytes(mesh.h, ctypes.byref(self.cfg))
         if nbytes == 0:
             raise MpdcError(-6, lib.mpdc_last_error().decode())
@@ -187,7 +188,7 @@ class State:
         N, E, K, M, T = self.mesh.N, self.mesh.E, self.K, self.M, self.T
         shapes = {FIELD_H: (N, M), FIELD_PS: (N, M), FIELD_THETA: (N, K, M), FIELD_U: (E, K, M),
                   FIELD_W: (N, K + 1, M), FIELD_PHI: (N, K + 1, M), FIELD_B: (N,), FIELD_TR_FLUX: (E, K),
-                  FIELD_TR_DPI: (N, K), FIELD_TR_Q: (N, K, T)}
+                  FIELD_TR_DPI: (N, K), FIELD_TR_Q: (N, K, T), FIELD_TR_VFLUX: (N, K + 1)}
         return shapes[f]
 
     def state_write(self, f, data, stream=None):
@@ -216,6 +217,10 @@ class State:
 
     def tracer_step(self, nsteps=1, stream=None):
         _check(lib.mpdc_tracer_step(self.h, nsteps, _stream(stream)))
+
+    def couple(self, dycore, stream=None):
+        """mpdc_tracer_couple: this tracer state takes the dycore state's averaged mass fluxes."""
+        _check(lib.mpdc_tracer_couple(self.h, dycore.h, _stream(stream)))
 
     def diagnostics(self, f, ref=None, stream=None, check=True):
         d = Diag()

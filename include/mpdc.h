@@ -271,7 +271,8 @@ int mpdc_time_kernel(mpdc_state *st, int kernel_id, int nreps, void *stream, dou
 /* Run nsteps steps with direct launches and a HIP event between consecutive
  * launches on stream, and return per kernel class (ids as above) the summed
  * duration in ms (ms_total[4]) and the launch count (launches[4]); the
- * tracer uses the first three entries and leaves the fourth zero.  The state
+ * tracer uses the first three entries for its horizontal kernels and the
+ * fourth for the vertical step (zero without a vertical flux).  The state
  * advances by nsteps exactly as with mpdc_dycore_step / mpdc_tracer_step. */
 int mpdc_profile_steps(mpdc_state *st, int nsteps, void *stream, double *ms_total, int *launches);
 
@@ -283,8 +284,8 @@ int mpdc_profile_steps(mpdc_state *st, int nsteps, void *stream, double *ms_tota
 int mpdc_autotune(mpdc_state *st, void *stream, int *cells_per_block, int *flat_block);
 
 /* Algorithmic HBM bytes of one launch of a kernel class (same ids; mean over
- * the three RK stages) and of one whole step, from the arrays each kernel
- * must read and write once. */
+ * the three RK stages; tracer id 3: the vertical step, once per step) and of
+ * one whole step, from the arrays each kernel must read and write once. */
 double mpdc_kernel_bytes(const mpdc_state *st, int kernel_id);
 double mpdc_step_bytes(const mpdc_state *st);
 

@@ -1006,8 +1006,16 @@ static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
     return 0;
 }
 
+// the tracer's vertical step, once per step: q and dpi in and out, the interface flux in
+static double vertical_bytes(const mpdc_state *st) {
+    if (st->model != MPDC_MODEL_TRACER || !st->has_vflux) return 0;
+    const double N = st->N, K = st->K, T = st->T, r = (double)rsize(st->policy);
+    return 2 * N * K * T * r + 2 * N * K * 8 + N * (K + 1) * 8;
+}
+
 double mpdc_kernel_bytes(const mpdc_state *st, int id) {
     if (!st) return 0;
+    if (st->model == MPDC_MODEL_TRACER && id == 3) return vertical_bytes(st);
     return (kernel_bytes_stage(st, id, 0) + kernel_bytes_stage(st, id, 1) + kernel_bytes_stage(st, id, 2)) / 3.0;
 }
 
@@ -1020,7 +1028,7 @@ int mpdc_profile_steps(mpdc_state *st, int nsteps, void *stream, double *ms_tota
         ms_total[k] = 0.0;
         launches[k] = 0;
     }
-    std::vector<hipEvent_t> ev(3 * nk + 1, nullptr);
+    std::vector<hipEvent_t> ev(3 * nk + 2, nullptr);
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
     int rc = MPDC_OK;
     for (int n = 0; n < nsteps && rc == MPDC_OK; n++) {
@@ -1037,6 +1045,22 @@ int mpdc_profile_steps(mpdc_state *st, int nsteps, void *stream, double *ms_tota
                 kid.push_back(k);
             }
             if (rc) break;
+        }
+        if (rc == MPDC_OK && tr && st->has_vflux) {
+            // the tracer's vertical step is timed as kernel 3
+            TracerArgs a = tracer_args(st, 2, parity);
+            a.dts = st->cfg.dt;
+            hipError_t e = launch_tracer_vertical(st->policy, a, s);
+            if (e != hipSuccess) rc = hip_fail(e, "kernel launch");
+            else {
+                HIP_TRY(hipEventRecord(ev[kid.size() + 1], s));
+                kid.push_back(3);
+            }
+        }
+        if (rc == MPDC_OK && !tr && st->accumulate) {
+            hipError_t e = launch_flux_acc(st->model, st->policy, stage_args(st, 2), st->Facc, st->Macc, s);
+            if (e != hipSuccess) rc = hip_fail(e, "kernel launch");
+            else st->acc_steps++;
         }
         HIP_TRY(hipEventSynchronize(ev[kid.size()]));
         for (size_t j = 0; j < kid.size(); j++) {
@@ -1103,7 +1127,7 @@ double mpdc_step_bytes(const mpdc_state *st) {
     const int nk = st->model == MPDC_MODEL_TRACER ? 3 : 4;
     for (int s = 0; s < 3; s++)
         for (int k = 0; k < nk; k++) b += kernel_bytes_stage(st, k, s);
-    return b;
+    return b + vertical_bytes(st);
 }
 
 int mpdc_diagnostics(mpdc_state *st, int f, const void *ref_dev, mpdc_diag *out, void *stream) {

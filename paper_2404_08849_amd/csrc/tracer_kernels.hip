@@ -377,30 +377,63 @@ hipError_t launch_tracer_kernel(int policy, const TracerArgs &a, int which, hipS
 // new mixing ratio:
 //   dpi_new_k q_k + dt (GI_{k+1} - GI_k) = dpi_k qh_k - dt (GE_{k+1} - GE_k).
 // The tridiagonal matrix is an M-matrix (new q is a convex combination of the
-// old values).  One lane per (cell, tracer) runs the Thomas algorithm down the
-// column in FP64, keeping its factors in LDS; a work-group holds whole
-// columns, so the layer masses, which every lane of a column reads in the
-// forward sweep, are overwritten by the column's tracer-0 lane only after
-// the work-group's barrier.  q and dpi are updated in place.
+// old values) and the same for every tracer of a column.  A work-group holds
+// whole columns: it stages their q, layer masses and fluxes in LDS with
+// coalesced loads, one lane per (cell, tracer) runs the Thomas algorithm down
+// its column in FP64 on LDS (the column's tracer-0 lane keeps the shared
+// elimination factors), and the results go back with coalesced stores; q and
+// dpi are updated in place.
+constexpr int kVertThreads = 512;
+__host__ __device__ inline long vert_column_doubles(int K, int T) { return (long)K * T + 3L * K + 1; }
+
+// dst[x] = src[x] for x < n by all nthr threads of the work-group, eight loads
+// in flight per thread (clamped indices, so none sits under a condition)
+template <typename S>
+__device__ __forceinline__ void stage_in(double *dst, const S *src, long n, int tid, int nthr) {
+    constexpr int U = 8;
+    for (long b = tid; b < n; b += (long)U * nthr) {
+        S v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const long x = b + (long)u * nthr;
+            v[u] = src[x < n ? x : n - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const long x = b + (long)u * nthr;
+            if (x < n) dst[x] = (double)v[u];
+        }
+    }
+}
+
 template <typename R>
-__global__ void __launch_bounds__(kTracerThreads) k_tr_vert(TracerArgs a, int cols) {
+__global__ void __launch_bounds__(kVertThreads) k_tr_vert(TracerArgs a, int cols) {
     extern __shared__ double vlds[];
     const int K = a.K, T = a.T;
-    const int tid = threadIdx.x;
-    const int lc = tid / T, t = tid - lc * T;
-    const long i = (long)blockIdx.x * cols + lc;
-    const bool valid = lc < cols && i < a.mesh.N;
-    double *cf = vlds + (long)tid * 2 * K, *df = cf + K;   // Thomas factors of this lane
+    const int tid = threadIdx.x, nthr = cols * T;
+    const long i0 = (long)blockIdx.x * cols;
+    const int ncol = (int)(a.mesh.N - i0 < cols ? a.mesh.N - i0 : cols);
+    double *sq = vlds;                            // [cols][K][T]: q^h, then the forward factors, then q
+    double *sd = sq + (long)cols * K * T;         // [cols][K]: layer masses
+    double *sm = sd + (long)cols * K;             // [cols][K+1]: interface fluxes
+    double *sc = sm + (long)cols * (K + 1);       // [cols][K]: elimination factors (shared by the tracers)
     R *q = (R *)a.q_o;
     double *dpi = a.dpi_o;
-    const double dt = a.dts;
+    const double dt = a.dts, half_over_dt = 0.5 / a.dts;
+    const long nq = (long)ncol * K * T, nd = (long)ncol * K, nm = (long)ncol * (K + 1);
+    stage_in<R>(sq, q + i0 * K * T, nq, tid, nthr);
+    stage_in<double>(sd, dpi + i0 * K, nd, tid, nthr);
+    stage_in<double>(sm, a.vflux + i0 * (K + 1), nm, tid, nthr);
+    __syncthreads();
+    const int lc = tid / T, t = tid - lc * T;
+    const bool valid = lc < ncol;
     if (valid) {
-        const double *mc = a.vflux + i * (K + 1);
-        const double *dh = dpi + i * K;
-        const long qb = i * K * T + t;
+        double *qc = sq + (long)lc * K * T + t;
+        const double *dh = sd + (long)lc * K, *mc = sm + (long)lc * (K + 1);
+        double *cf = sc + (long)lc * K;
         double mEt = 0.0, aIt = 0.0;       // top interface of layer k: explicit flux, dt * implicit flux
         double qu = 0.0;                   // q^h of the layer above
-        double qk = (double)q[qb];
+        double qk = qc[0];
         double cprev = 0.0, dprev = 0.0;
         for (int k = 0; k < K; k++) {
             const bool below = k < K - 1;
@@ -408,12 +441,11 @@ __global__ void __launch_bounds__(kTracerThreads) k_tr_vert(TracerArgs a, int co
             const double mb = below ? mc[k + 1] : 0.0;
             const double mt = k > 0 ? mc[k] : 0.0;
             const double dk = dh[k], dn = dh[kn];
-            const double qd = (double)q[qb + (long)kn * T];
-            double mEb = mb;
-            if (mb != 0.0) {
-                const double c = dt * fabs(mb) / (mb >= 0.0 ? dk : dn);
-                if (c > 0.5) mEb = mb * (0.5 / c);
-            }
+            const double qd = qc[(long)kn * T];
+            // explicit part: the flux capped at half the donor's mass per dt
+            // (Courant number 1/2), with the flux's sign
+            const double cap = half_over_dt * (mb >= 0.0 ? dk : dn);
+            const double mEb = fabs(mb) > cap ? copysign(cap, mb) : mb;
             const double aIb = dt * (mb - mEb);
             const double dnew = dk - dt * (mb - mt);
             const double sub = -fmax(aIt, 0.0);
@@ -422,11 +454,11 @@ __global__ void __launch_bounds__(kTracerThreads) k_tr_vert(TracerArgs a, int co
             const double get = mEt * (mEt >= 0.0 ? qu : qk);   // zero at the lid (mEt = 0)
             const double geb = mEb * (mEb >= 0.0 ? qk : qd);   // zero at the surface
             const double rhs = dk * qk - dt * (geb - get);
-            const double den = dia - sub * cprev;
-            cprev = below ? sup / den : 0.0;
-            dprev = (rhs - sub * dprev) / den;
-            cf[k] = cprev;
-            df[k] = dprev;
+            const double rden = 1.0 / (dia - sub * cprev);
+            cprev = below ? sup * rden : 0.0;
+            dprev = (rhs - sub * dprev) * rden;
+            if (t == 0) cf[k] = cprev;
+            qc[(long)k * T] = dprev;           // q^h of layer k is no longer needed (qu holds it)
             mEt = mEb;
             aIt = aIb;
             qu = qk;
@@ -435,32 +467,38 @@ __global__ void __launch_bounds__(kTracerThreads) k_tr_vert(TracerArgs a, int co
     }
     __syncthreads();
     if (valid) {
-        const double *mc = a.vflux + i * (K + 1);
-        const long qb = i * K * T + t;
+        double *qc = sq + (long)lc * K * T + t;
+        const double *cf = sc + (long)lc * K;
         double x = 0.0;
         for (int k = K - 1; k >= 0; k--) {
-            x = df[k] - cf[k] * x;
-            q[qb + (long)k * T] = (R)x;
-            if (t == 0) {
-                const double mb = k < K - 1 ? mc[k + 1] : 0.0, mt = k > 0 ? mc[k] : 0.0;
-                dpi[i * K + k] = dpi[i * K + k] - dt * (mb - mt);
-            }
+            x = qc[(long)k * T] - cf[k] * x;
+            qc[(long)k * T] = x;
         }
     }
+    // new layer masses (every lane of the group has read them above)
+    for (long x = tid; x < nd; x += nthr) {
+        const int c = (int)(x / K), k = (int)(x - (long)c * K);
+        const double *mc = sm + (long)c * (K + 1);
+        const double mb = k < K - 1 ? mc[k + 1] : 0.0, mt = k > 0 ? mc[k] : 0.0;
+        dpi[i0 * K + x] = sd[x] - dt * (mb - mt);
+    }
+    __syncthreads();
+    for (long x = tid; x < nq; x += nthr) q[i0 * K * T + x] = (R)sq[x];   // (stores: no waits)
 }
 
 int tracer_vert_columns(int K, int T) {
-    if ((long)2 * K * T * 8 > 65536) return 0;   // one column's factors must fit the LDS of a work-group
-    int c = kTracerThreads / T;
-    while (c > 1 && (long)c * 2 * K * T * 8 > 32768) c--;
-    return c < 1 ? 1 : c;
+    const long per = vert_column_doubles(K, T) * 8;
+    if (per > 65536 || T > kVertThreads) return 0;   // one column must fit the LDS of a work-group
+    int c = kVertThreads / T;
+    while (c > 1 && (long)c * per > 32768) c--;
+    return c;
 }
 
 hipError_t launch_tracer_vertical(int policy, const TracerArgs &a, hipStream_t s) {
     const int cols = tracer_vert_columns(a.K, a.T);
     if (cols < 1) return hipErrorInvalidValue;
     const unsigned nb = (unsigned)((a.mesh.N + cols - 1) / cols);
-    const size_t lds = (size_t)cols * a.T * 2 * a.K * 8;
+    const size_t lds = (size_t)cols * vert_column_doubles(a.K, a.T) * 8;
     if (policy == POLICY_DBL)
         hipLaunchKernelGGL(k_tr_vert<double>, dim3(nb), dim3(cols * a.T), lds, s, a, cols);
     else

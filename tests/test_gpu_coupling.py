@@ -137,9 +137,15 @@ def test_coupled_transport(mpdc, oracle_mod, mesh_cache, model, policy):
     trs = _tracer_state(mpdc, g, tpol, K, T, n * dt, np.zeros((m["nEdges"], K)), dpi0, q0)
     for rnd in range(2):
         _say("%s G4x%d %s: %d dycore steps, couple, one tracer step (round %d)" % (model, K, policy, n, rnd))
-        dy.dycore_step(n)
-        trs.couple(dy)
-        trs.tracer_step(1)
+        if rnd == 0:
+            dy.dycore_step(n)
+            trs.couple(dy)
+            trs.tracer_step(1)
+        else:   # the profiling path advances and accumulates exactly like the plain steps
+            dy.profile_steps(n)
+            trs.couple(dy)
+            prof = trs.profile_steps(1)
+            assert prof[3][1] == 1          # the vertical step ran, timed as kernel 3
         ps = dy.state_read(mpdc.FIELD_PS)[:, 0]
         dpi_dyn = dsig[None, :] * (ps[:, None] - PTOP)
         dpi, q = trs.state_read(mpdc.FIELD_TR_DPI), trs.state_read(mpdc.FIELD_TR_Q)

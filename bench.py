@@ -47,6 +47,10 @@ WORKLOADS = {
                    desc="non-hydrostatic dycore G8 (655362 cells) x 60 levels, warm bubble, dt=60 s"),
     "ens-g7": dict(model="HDC", level=7, K=30, M=16, T=0, dt=150.0, steps=20,
                    desc="hydrostatic dycore ensemble G7 (163842 cells) x 30 levels x 16 members, dt=150 s"),
+    "coupled-g6": dict(model="COUPLED", level=6, K=30, M=1, T=8, dt=300.0, nsub=2, steps=10,
+                       desc="hydrostatic dycore G6 (40962 cells) x 30 levels coupled to 8 tracers: one tracer step "
+                            "(dt=600 s, with its vertical step) per 2 dycore steps (dt=300 s) on their accumulated "
+                            "mass fluxes"),
     "hdc-g9": dict(model="HDC", level=9, K=30, M=1, T=0, dt=37.5, steps=10,
                    desc="hydrostatic dycore G9 (2621442 cells) x 30 levels, jet, dt=37.5 s"),
 }
@@ -245,6 +249,142 @@ def copy_calibration(torch, mib):
     print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 3}), flush=True)
 
 
+def coupled_states(torch, mpdc, g, mesh, w, pol, stream, autotune):
+    """Dycore (accumulating its mass fluxes) and tracer states of the coupled
+    workload; one coupling round is run so the tracer has its fluxes."""
+    from paper_2404_08849_amd.inputs import initial as ic
+    K, T, n = w["K"], w["T"], w["nsub"]
+    s = ic.hdc_jet(mesh, K, seed=2000)
+    tr = ic.tracer_solid_body(mesh, K, T, seed=3000)
+    dsig = np.diff(ic.sigma_interfaces(K))
+    dpi0 = dsig[None, :] * (s["ps"][:, None] - 1000.0)
+    dy = mpdc.State(g, mpdc.MODEL_HDC, pol, K=K, dt=w["dt"], sigma=ic.sigma_interfaces(K), accumulate_flux=True)
+    dy.state_write(mpdc.FIELD_PS, s["ps"][:, None])
+    dy.state_write(mpdc.FIELD_THETA, s["Theta"][:, :, None])
+    dy.state_write(mpdc.FIELD_U, s["u"][:, :, None])
+    trs = mpdc.State(g, mpdc.MODEL_TRACER, pol, K=K, T=T, dt=n * w["dt"])
+    trs.state_write(mpdc.FIELD_TR_DPI, dpi0)
+    trs.state_write(mpdc.FIELD_TR_Q, tr["q"])
+    with torch.cuda.stream(stream):
+        if autotune:
+            dy.autotune(stream=stream)
+        dy.dycore_step(n, stream=stream)
+        trs.couple(dy, stream=stream)
+        if autotune:
+            trs.autotune(stream=stream)
+        trs.tracer_step(1, stream=stream)
+        torch.cuda.synchronize()
+    dy.set_graph(True)
+    trs.set_graph(True)
+    return dy, trs, s, tr, dpi0
+
+
+def coupled_step(dy, trs, n, stream):
+    dy.dycore_step(n, stream=stream)
+    trs.couple(dy, stream=stream)
+    trs.tracer_step(1, stream=stream)
+
+
+def coupled_main(args, torch, mpdc):
+    """Coupled dycore + tracer workload: one 'step' is n dycore steps, the
+    hand-over of their averaged mass fluxes and one tracer step of n dt."""
+    w = WORKLOADS[args.workload]
+    from paper_2404_08849_amd.inputs.meshgen import icosahedral_mesh
+    mesh = icosahedral_mesh(w["level"])
+    g = mpdc.Mesh(mesh)
+    stream = torch.cuda.Stream()
+    N, K, T, n = mesh["nCells"], w["K"], w["T"], w["nsub"]
+    res = {}
+    for name in ("MIX", "DBL"):
+        pol = getattr(mpdc, "POLICY_" + name)
+        dy, trs, s, tr, dpi0 = coupled_states(torch, mpdc, g, mesh, w, pol, stream, not args.no_autotune)
+        with torch.cuda.stream(stream):
+            for _ in range(args.warmup):
+                coupled_step(dy, trs, n, stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                coupled_step(dy, trs, n, stream)
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / max(args.steps, 1)
+            # one coupled step under events: n dycore steps, the hand-over, one tracer step
+            kd = kernel_times(torch, dy, dict(model="HDC"), n, stream)
+            trs.couple(dy, stream=stream)
+            kt = kernel_times(torch, trs, dict(model="TRACER"), 1, stream)
+            torch.cuda.synchronize()
+        bytes_step = n * dy.step_bytes() + trs.step_bytes()
+        shapes = {"dycore": [list(dy.get_kernel_launch(k)) for k in range(4)],
+                  "tracer": [list(trs.get_kernel_launch(k)) for k in range(3)]}
+        del dy, trs
+        # accuracy: the workload's coupled steps from the initial state
+        dy, trs, s, tr, dpi0 = coupled_states(torch, mpdc, g, mesh, w, pol, stream, False)
+        with torch.cuda.stream(stream):
+            for _ in range(w["steps"] - 1):
+                coupled_step(dy, trs, n, stream)
+            torch.cuda.synchronize()
+        ps = dy.state_read(mpdc.FIELD_PS)[:, 0]
+        dpi_dyn = np.diff(np.arange(K + 1) / K)[None, :] * (ps[:, None] - 1000.0)
+        dpi = trs.state_read(mpdc.FIELD_TR_DPI)
+        res[name] = dict(sec=sec, kernels={**kd, **kt}, bytes_step=bytes_step, shapes=shapes, ps=ps,
+                         q=trs.state_read(mpdc.FIELD_TR_Q),
+                         mass_consistency=float(np.abs(dpi - dpi_dyn).max() / np.abs(dpi_dyn).max()),
+                         nonfinite=int(dy.diagnostics(mpdc.FIELD_PS, stream=stream, check=False)["nonfinite"] +
+                                       trs.diagnostics(mpdc.FIELD_TR_Q, stream=stream, check=False)["nonfinite"]))
+        del dy, trs
+    mix, dbl = res["MIX"], res["DBL"]
+    kt = mix["kernels"]
+    dom = max(kt, key=lambda k: kt[k]["ms_in_step"] * kt[k]["launches"])
+    ach = kt[dom]["bytes"] / (kt[dom]["ms"] * 1e-3) / 1e9
+    gate = {"mix_vs_dbl_l2_ps": rel_l2(mix["ps"], dbl["ps"]), "mix_vs_dbl_l2_q": rel_l2(mix["q"], dbl["q"]),
+            "tracer_vs_dycore_layer_mass": {"mix": mix["mass_consistency"], "dbl": dbl["mass_consistency"]},
+            "nonfinite": mix["nonfinite"] + dbl["nonfinite"]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import OracleMesh, oracle_lib
+        from paper_2404_08849_amd.inputs import initial as ic
+        om = OracleMesh(mesh)
+        s = ic.hdc_jet(mesh, K, seed=2000)
+        tr = ic.tracer_solid_body(mesh, K, T, seed=3000)
+        dpi0 = np.diff(ic.sigma_interfaces(K))[None, :] * (s["ps"][:, None] - 1000.0)
+        t0 = time.perf_counter()
+        o = om.hdc_run_flux(s["ps"], s["Theta"], s["u"], w["dt"], n)
+        om.tracer_run(o[3] / n, dpi0, tr["q"], n * w["dt"], 1, vflux=o[4] / n)
+        el = time.perf_counter() - t0
+        cpu = {"value": N * K * n / el, "unit": "cell-level-steps/s", "cores": oracle_lib().or_num_threads(),
+               "kind": "oracle", "sample": "one coupled step (%d dycore steps + one tracer step of %d tracers) "
+                                           "on the host (%.1f s)" % (n, T, el)}
+    out = {
+        "metric": "cell-level-steps/s (mixed vs all-FP64) at fixed L2 error; HBM GB/s",
+        "value": N * K * n / mix["sec"],
+        "unit": "cell-level-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": mix["sec"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "mixed f32/f64", "data": "synthetic",
+        "config": {"workload": w["desc"], "mesh": "G%d" % w["level"], "cells": N, "levels": K, "members": 1,
+                   "tracers": T, "dycore_steps_per_step": n, "policy": "MIX", "global_batch": 1, "seq_len": K,
+                   "parallelism": "single GPU"},
+        "dbl_value": N * K * n / dbl["sec"], "dbl_ms_per_step": dbl["sec"] * 1e3,
+        "mix_over_dbl_speedup": dbl["sec"] / mix["sec"],
+        "tracer_cell_level_steps_per_s": N * K * T / mix["sec"],
+        "hbm_gbs_step": {"mix": mix["bytes_step"] / mix["sec"] / 1e9, "dbl": dbl["bytes_step"] / dbl["sec"] / 1e9},
+        "accuracy_gate": gate,
+        "kernels_mix": {k: {"ms": v["ms"], "ms_in_step": v["ms_in_step"], "MB": v["bytes"] / 1e6,
+                            "GB/s": v["bytes"] / (v["ms"] * 1e-3) / 1e9} for k, v in kt.items()},
+        "kernels_dbl": {k: {"ms": v["ms"], "ms_in_step": v["ms_in_step"], "MB": v["bytes"] / 1e6,
+                            "GB/s": v["bytes"] / (v["ms"] * 1e-3) / 1e9} for k, v in dbl["kernels"].items()},
+        "launch_shapes": {"mix": mix["shapes"], "dbl": dbl["shapes"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "traffic_source": "no counter summary for this workload",
+                     "bytes_per_launch": kt[dom]["bytes"], "ms_per_launch": kt[dom]["ms"],
+                     "ms_per_launch_in_step": kt[dom]["ms_in_step"],
+                     "timing": "HIP events around back-to-back launches on the launch stream"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -257,6 +397,9 @@ def main():
         copy_calibration(torch, args.copy_calib)
         return
     w = WORKLOADS[args.workload]
+    if w["model"] == "COUPLED":
+        coupled_main(args, torch, mpdc)
+        return
     mesh, st = build_inputs(w)
     g = mpdc.Mesh(mesh)
     stream = torch.cuda.Stream()

@@ -617,7 +617,7 @@ static void hydro_pgf(const or_mesh *h, const or_params *p, const double *ps, co
     const double kappa = p->rd / p->cp;
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < m->N; i++) {
-        double phib = 0.0;
+        double phib = p->phis ? p->phis[i] : 0.0;   /* geopotential of the surface (terrain) */
         for (int k = K - 1; k >= 0; k--) {
             size_t x = (size_t)i * K + k;
             double pit = p->ptop + p->sigma[k] * (ps[i] - p->ptop);
@@ -713,6 +713,17 @@ void or_hdc_run_flux(const or_mesh *h, const or_params *p, double *ps, double *T
                      double *Facc, double *Macc)
 {
     hdc_run(h, p, ps, Theta, u, nsteps, Facc, Macc);
+}
+
+/* Pressure-gradient and gravity term of the hydrostatic model at (pi_s, Theta)
+ * (Eq. 5 with Eqs. 8-9; geopotential integrated from the surface value
+ * p->phis), exported for tests: pgf [E][K]. */
+void or_hdc_pgf(const or_mesh *h, const or_params *p, const double *ps, const double *Theta, double *pgf)
+{
+    const size_t NK = (size_t)h->m.N * p->K;
+    double *alpha = dalloc(NK), *pmid = dalloc(NK), *phim = dalloc(NK);
+    hydro_pgf(h, p, ps, Theta, pgf, alpha, pmid, phim);
+    free(alpha); free(pmid); free(phim);
 }
 
 /* Tendencies of one hydrostatic stage evaluated at (pi_s, Theta, u), exported

@@ -48,6 +48,7 @@ typedef struct {
     double grav, rd, cp, p0, ptop;
     const double *sigma;   /* [K+1] interface sigma, 0 at top, 1 at bottom */
     int fct;               /* 1: FCT limiter on; 0: bounds +-inf (limiter inactive) */
+    const double *phis;    /* [N] surface geopotential of the hydrostatic model (NULL: flat) */
 } or_params;
 
 typedef struct or_mesh or_mesh;
@@ -98,6 +99,7 @@ void or_hdc_run_flux(const or_mesh *m, const or_params *p, double *ps, double *T
 void or_ndc_run_flux(const or_mesh *m, const or_params *p, double *ps, double *Theta, double *u, double *w,
                      double *phi, int nsteps, double *Facc, double *Macc);
 
+void or_hdc_pgf(const or_mesh *m, const or_params *p, const double *ps, const double *Theta, double *pgf);
 void or_hdc_tendency(const or_mesh *m, const or_params *p, const double *ps, const double *Theta,
                      const double *u, double *dps, double *dTh, double *du_adv, double *mdot);
 void or_nh_column_solve(const or_params *p, double dts, const double *Th, const double *dpi,

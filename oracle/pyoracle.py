@@ -34,7 +34,7 @@ class Params(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int), ("T", ctypes.c_int), ("dt", ctypes.c_double),
                 ("grav", ctypes.c_double), ("rd", ctypes.c_double), ("cp", ctypes.c_double),
                 ("p0", ctypes.c_double), ("ptop", ctypes.c_double), ("sigma", _dp),
-                ("fct", ctypes.c_int)]
+                ("fct", ctypes.c_int), ("phis", _dp)]
 
 
 def oracle_lib():
@@ -69,6 +69,7 @@ def oracle_lib():
         lib.or_ndc_run_flux.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _dp, _dp, _dp, _dp, _dp,
                                         ctypes.c_int, _dp, _dp]
         lib.or_hdc_tendency.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params)] + [_dp] * 7
+        lib.or_hdc_pgf.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _dp, _dp, _dp]
         lib.or_nh_column_solve.argtypes = [ctypes.POINTER(Params), ctypes.c_double, _dp, _dp, _dp, _dp]
         lib.or_norms.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp]
         lib.or_area_sum.restype = ctypes.c_double
@@ -189,11 +190,13 @@ class OracleMesh:
         return out.squeeze()
 
     # ---- models (copies; inputs untouched) ----
-    def params(self, K, dt, T=0, fct=1, sigma=None):
+    def params(self, K, dt, T=0, fct=1, sigma=None, phis=None):
         if sigma is None:
             sigma = np.arange(K + 1, dtype=np.float64) / K
         self._sigma = np.ascontiguousarray(sigma, dtype=np.float64)
-        return Params(K, T, dt, GRAV, RD, CP, P0, PTOP, _d(self._sigma), fct)
+        self._phis = None if phis is None else np.ascontiguousarray(phis, dtype=np.float64)
+        return Params(K, T, dt, GRAV, RD, CP, P0, PTOP, _d(self._sigma), fct,
+                      None if self._phis is None else _d(self._phis))
 
     def sw_run(self, h, u, b, dt, nsteps):
         h, u, b = [np.array(x, dtype=np.float64, order="C") for x in (h, u, b)]
@@ -201,9 +204,10 @@ class OracleMesh:
         self.lib.or_sw_run(self.h, ctypes.byref(p), _d(h), _d(u), _d(b), nsteps)
         return h, u
 
-    def hdc_run(self, ps, Theta, u, dt, nsteps):
+    def hdc_run(self, ps, Theta, u, dt, nsteps, phis=None):
+        """phis [N]: surface geopotential (terrain), None for a flat surface."""
         ps, Theta, u = [np.array(x, dtype=np.float64, order="C") for x in (ps, Theta, u)]
-        p = self.params(Theta.shape[1], dt)
+        p = self.params(Theta.shape[1], dt, phis=phis)
         self.lib.or_hdc_run(self.h, ctypes.byref(p), _d(ps), _d(Theta), _d(u), nsteps)
         return ps, Theta, u
 
@@ -235,6 +239,15 @@ class OracleMesh:
         p = self.params(K, dt)
         self.lib.or_ndc_run(self.h, ctypes.byref(p), _d(ps), _d(Theta), _d(u), _d(w), _d(phi), nsteps)
         return ps, Theta, u, w, phi
+
+    def hdc_pgf(self, ps, Theta, phis=None):
+        """Pressure-gradient and gravity term [E][K] of the hydrostatic model at (pi_s, Theta)."""
+        ps, Theta = [np.ascontiguousarray(x, dtype=np.float64) for x in (ps, Theta)]
+        K = Theta.shape[1]
+        p = self.params(K, 1.0, phis=phis)
+        out = np.empty((self.E, K))
+        self.lib.or_hdc_pgf(self.h, ctypes.byref(p), _d(ps), _d(Theta), _d(out))
+        return out
 
     def hdc_tendency(self, ps, Theta, u):
         """Stage tendencies at a state: (dps, dTheta, du without PGF, mdot)."""

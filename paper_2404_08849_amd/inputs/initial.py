@@ -222,3 +222,24 @@ def tracer_vertical_flux(dpi, dt, amp=0.3, seed=3100):
     m[:, 1:] = np.cumsum(amp * xi * dpi, axis=1) / dt
     m[:, K] = 0.0
     return m
+
+
+def mountain(mesh, h0=3000.0, radius=1.5e6, lon0=0.5 * np.pi, lat0=np.pi / 6.0):
+    """Surface geopotential [N] of an isolated mountain of height h0 (m):
+    g h0 cos^2(pi r / (2 radius)) within radius of (lon0, lat0), 0 outside."""
+    r = mesh["radius"] * _great_circle(mesh["xCell"], lon0, lat0)
+    h = np.where(r < radius, h0 * np.cos(0.5 * np.pi * r / radius) ** 2, 0.0)
+    return GRAV * h
+
+
+def hdc_rest_over_terrain(mesh, K, phis, T0=300.0, p_ref=1.0e5):
+    """Isothermal atmosphere at rest over terrain: pi_s = p_ref exp(-phis / (R_d T0))
+    (hydrostatic balance of the continuous equations), theta at the layer
+    midpoints such that T = T0 there, u = 0.  Returns dict(ps[N], Theta[N][K], u[E][K])."""
+    ps = p_ref * np.exp(-np.asarray(phis) / (RD * T0))
+    sig = sigma_interfaces(K)
+    smid = 0.5 * (sig[:-1] + sig[1:])
+    dpi = np.outer(ps - PTOP, np.diff(sig))
+    p = PTOP + np.outer(ps - PTOP, smid)
+    theta = T0 * (P0 / p) ** KAPPA
+    return dict(ps=ps, Theta=dpi * theta, u=np.zeros((mesh["nEdges"], K)))

@@ -85,6 +85,13 @@ extern "C" {
 #define MPDC_POLICY_MIX_BOX 2
 #define MPDC_POLICY_MIX_DBL_MASS 3
 #define MPDC_POLICY_MIX_F32_DIV 4
+/* MIX_PGF32 (hydrostatic dycore only): the precision-sensitive terms of
+ * Section 2.3 -- the column diagnostics of Eqs. 8-9 (pressure, specific
+ * volume, geopotential) and the pressure-gradient and gravity term of Eq. 5
+ * -- in FP32, as a single-precision model computes them, the rest as MIX.
+ * Over terrain these two large terms nearly cancel (Section 4), which is
+ * where FP32 fails. */
+#define MPDC_POLICY_MIX_PGF32 5
 
 /* ---- state fields for mpdc_state_write / mpdc_state_read (FP64 in and out) ---- */
 #define MPDC_FIELD_H 0           /* SW fluid depth h          [N][M]        */
@@ -101,6 +108,9 @@ extern "C" {
                                     layers k-1 and k), positive towards the surface; the lid and surface
                                     entries are ignored.  Writing it (or mpdc_tracer_couple) turns on the
                                     vertical step of mpdc_tracer_step */
+#define MPDC_FIELD_PHIS 11       /* HDC surface geopotential phi_s [N] (terrain; zero = flat surface,
+                                    the default), shared by the members; the hydrostatic geopotential
+                                    is integrated upwards from it (Eq. 8) */
 
 /* ---- mesh tables exported for checks (mpdc_mesh_get_table) ---- */
 #define MPDC_TABLE_CELLS_ON_CELL 0   /* int32 [2E], aligned with edges_on_cell            */

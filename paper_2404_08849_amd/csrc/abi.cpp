@@ -133,7 +133,7 @@ struct mpdc_state {
     long N, E, V;
     // dycore
     StateSet set[3];
-    double *b = nullptr, *dsig = nullptr, *sig = nullptr, *dps = nullptr, *mdot = nullptr;
+    double *b = nullptr, *phis = nullptr, *dsig = nullptr, *sig = nullptr, *dps = nullptr, *mdot = nullptr;
     void *ke = nullptr, *hth = nullptr, *qv = nullptr, *qh = nullptr;
     double *alpha = nullptr, *phim = nullptr, *pm = nullptr, *mum = nullptr, *wstar = nullptr, *phistar = nullptr;
     // dycore: last-stage mass fluxes summed over the steps since the last coupling
@@ -203,6 +203,7 @@ size_t state_layout(mpdc_state *st, void *base) {
         }
     }
     if (sw) st->b = c.take<double>(N);
+    if (st->model == MPDC_MODEL_HDC) st->phis = c.take<double>(N);   // zero (the workspace is cleared): flat
     st->dps = c.take<double>(N * M);
     if (!sw) st->mdot = c.take<double>(N * K1M);
     st->ke = c.take<char>(N * KM * (st->policy == MPDC_POLICY_MIX_BOX ? sizeof(double) : r));
@@ -290,6 +291,7 @@ StageArgs stage_args(const mpdc_state *st, int s) {
     a.ps_o = out.ps; a.Th_o = out.Th; a.u_o = out.u; a.w_o = out.w; a.phi_o = out.phi;
     a.u32_o = out.u32; a.th32_o = out.th32;
     a.b = st->b;
+    a.phis = st->phis;
     a.dps = st->dps;
     a.mdot = st->mdot;
     a.ke = st->ke;
@@ -417,6 +419,7 @@ long field_count(const mpdc_state *st, int f) {
     case MPDC_FIELD_TR_DPI: return mdl == MPDC_MODEL_TRACER ? N * K : -1;
     case MPDC_FIELD_TR_Q: return mdl == MPDC_MODEL_TRACER ? N * K * T : -1;
     case MPDC_FIELD_TR_VFLUX: return mdl == MPDC_MODEL_TRACER ? N * (K + 1) : -1;
+    case MPDC_FIELD_PHIS: return mdl == MPDC_MODEL_HDC ? N : -1;
     default: return -1;
     }
 }
@@ -436,6 +439,7 @@ double *field_ptr(mpdc_state *st, int f) {
     case MPDC_FIELD_TR_DPI: return st->dpi[st->parity];
     case MPDC_FIELD_TR_Q: return st->policy == MPDC_POLICY_DBL ? (double *)st->q[st->parity] : nullptr;
     case MPDC_FIELD_TR_VFLUX: return st->vflux;
+    case MPDC_FIELD_PHIS: return st->phis;
     default: return nullptr;
     }
 }
@@ -608,7 +612,9 @@ void mpdc_mesh_destroy(mpdc_mesh *m) { delete m; }
 static int check_config(const mpdc_mesh *m, const mpdc_config *c) {
     if (!m || !c) return fail(MPDC_E_INVAL, "null mesh or config");
     if (c->model < MPDC_MODEL_SW || c->model > MPDC_MODEL_TRACER) return fail(MPDC_E_INVAL, "unknown model");
-    if (c->policy < MPDC_POLICY_DBL || c->policy > MPDC_POLICY_MIX_F32_DIV) return fail(MPDC_E_INVAL, "unknown policy");
+    if (c->policy < MPDC_POLICY_DBL || c->policy > MPDC_POLICY_MIX_PGF32) return fail(MPDC_E_INVAL, "unknown policy");
+    if (c->policy == MPDC_POLICY_MIX_PGF32 && c->model != MPDC_MODEL_HDC)
+        return fail(MPDC_E_UNSUPPORTED, "the FP32 pressure-gradient variant is built for the hydrostatic dycore only");
     if (c->policy > MPDC_POLICY_MIX && c->model != MPDC_MODEL_HDC && c->model != MPDC_MODEL_NDC)
         return fail(MPDC_E_UNSUPPORTED, "the mixed-policy variants are built for the layered dycores only");
     if (c->K < 1 || c->M < 1 || c->K > 512 || c->M > 64) return fail(MPDC_E_INVAL, "K must be 1..512 and M 1..64");
@@ -988,6 +994,7 @@ static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
         b += E * 8 + E * 6 * r + E * r + th_s + 3 * N * KM * r + N * K1M * 8 + ps;
         b += (first && !mix) ? 0 : N * KM * 8 + ps;       // Th_n, ps_n (stage 1 FP64: same arrays as _s)
         b += N * KM * 8 + ps + 2 * N * KM * 8 + (mix ? N * KM * 4 : 0);   // Th_o, ps_o, alpha, phim, th32_o
+        if (!nh) b += N * 8;                               // surface geopotential
         if (nh) b += 2 * N * K1M * 8 /*w*, phi* */ + 2 * N * K1M * 8 /*w_o, phi_o*/ + 2 * N * KM * 8 /*pm, mum*/;
         return b;
     }

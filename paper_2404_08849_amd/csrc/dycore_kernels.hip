@@ -322,18 +322,19 @@ __device__ __forceinline__ double lds_sum_up(const double *p, int stride, int q0
     for (; q < q1; q++) s += p[q * stride];
     return s;
 }
-__device__ __forceinline__ double lds_sum_down(const double *p, int stride, int q_hi, int q_lo) {
-    // sum over q = q_hi, q_hi-1, ..., q_lo+1 (in that order)
-    double s = 0.0;
+template <typename T>
+__device__ __forceinline__ T lds_sum_down(const double *p, int stride, int q_hi, int q_lo, T s0) {
+    // s0 + sum over q = q_hi, q_hi-1, ..., q_lo+1 (in that order), in precision T
+    T s = s0;
     int q = q_hi;
     for (; q - 4 >= q_lo; q -= 4) {
-        const double a0 = p[q * stride], a1 = p[(q - 1) * stride], a2 = p[(q - 2) * stride], a3 = p[(q - 3) * stride];
+        const T a0 = (T)p[q * stride], a1 = (T)p[(q - 1) * stride], a2 = (T)p[(q - 2) * stride], a3 = (T)p[(q - 3) * stride];
         s += a0;
         s += a1;
         s += a2;
         s += a3;
     }
-    for (; q > q_lo; q--) s += p[q * stride];
+    for (; q > q_lo; q--) s += (T)p[q * stride];
     return s;
 }
 
@@ -996,8 +997,13 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
         // all reads of ps_n / Th_n happen before this barrier (stage 3 writes in place)
         __syncthreads();
         if constexpr (MODEL == MODEL_HDC) {
+            // FP64 column diagnostics (Eqs. 8-9); the variant VAR_PGF32 computes
+            // them in FP32, as the single-precision model would
+            constexpr bool P32 = VAR == VAR_PGF32;
+            using RP = typename std::conditional<P32, float, double>::type;
             double *sA = lds;                       // [cpb][KM]
-            double al[L];
+            RP al[L];
+            const double phs = cl.valid ? a.phis[i] : 0.0;   // surface geopotential (terrain)
             if (cl.valid) {
                 Pack<double, L> tho;
                 Pack<float, L> th32;
@@ -1009,14 +1015,24 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                         sgt[j] = a.sig[k];
                         sgb[j] = a.sig[k + 1];
                     }
-                    const double pit = a.ptop + sgt[j] * (ps_new[j] - a.ptop);
-                    const double pib = a.ptop + sgb[j] * (ps_new[j] - a.ptop);
                     const double dpn = dsg[j] * (ps_new[j] - a.ptop);
-                    const double pk = 0.5 * (pit + pib);
                     const double th = Th_new[j] / dpn;
-                    const double T = th * powpos(pk * a.inv_p0, a.kappa);
-                    al[j] = a.rd * T / pk;
-                    sA[lc * KM + km0 + j] = al[j] * dpn;
+                    if constexpr (P32) {
+                        const float pt = (float)a.ptop, psf = (float)ps_new[j];
+                        const float pit = pt + (float)sgt[j] * (psf - pt), pib = pt + (float)sgb[j] * (psf - pt);
+                        const float dpf = (float)dsg[j] * (psf - pt);
+                        const float pk = 0.5f * (pit + pib);
+                        const float T = ((float)Th_new[j] / dpf) * expf((float)a.kappa * logf(pk * (float)a.inv_p0));
+                        al[j] = (float)a.rd * T / pk;
+                        sA[lc * KM + km0 + j] = (double)(al[j] * dpf);
+                    } else {
+                        const double pit = a.ptop + sgt[j] * (ps_new[j] - a.ptop);
+                        const double pib = a.ptop + sgb[j] * (ps_new[j] - a.ptop);
+                        const double pk = 0.5 * (pit + pib);
+                        const double T = th * powpos(pk * a.inv_p0, a.kappa);
+                        al[j] = a.rd * T / pk;
+                        sA[lc * KM + km0 + j] = al[j] * dpn;
+                    }
                     th32.v[j] = (float)th;
                 }
                 stp<double, L>(a.Th_o + (long)i * KM + km0, tho);
@@ -1027,26 +1043,26 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
             }
             __syncthreads();
             if (cl.valid) {
-                // hydrostatic geopotential from the flat surface upwards (Eq. 8)
+                // hydrostatic geopotential from the surface upwards (Eq. 8)
                 Pack<double, L> alp, php;
                 if constexpr (M1) {
                     // consecutive levels: the deepest value's partial sum is extended upwards
-                    double acc = lds_sum_down(sA + lc * KM, 1, K - 1, v.k[L - 1]);
+                    RP acc = lds_sum_down<RP>(sA + lc * KM, 1, K - 1, v.k[L - 1], (RP)phs);
 #pragma unroll
                     for (int j = L - 1; j >= 0; j--) {
-                        const double phit = acc + sA[lc * KM + v.k[j]];
+                        const RP phit = acc + (RP)sA[lc * KM + v.k[j]];
                         alp.v[j] = al[j];
-                        php.v[j] = 0.5 * (phit + acc);
+                        php.v[j] = (RP)0.5 * (phit + acc);
                         acc = phit;
                     }
                 } else {
 #pragma unroll
                     for (int j = 0; j < L; j++) {
                         const int mm = v.mm0 + j;
-                        const double acc = lds_sum_down(sA + lc * KM + mm, M, K - 1, v.k[j]);
-                        const double phit = acc + sA[lc * KM + v.k[j] * M + mm];
+                        const RP acc = lds_sum_down<RP>(sA + lc * KM + mm, M, K - 1, v.k[j], (RP)phs);
+                        const RP phit = acc + (RP)sA[lc * KM + v.k[j] * M + mm];
                         alp.v[j] = al[j];
-                        php.v[j] = 0.5 * (phit + acc);
+                        php.v[j] = (RP)0.5 * (phit + acc);
                     }
                 }
                 stp<double, L>(a.alpha + (long)i * KM + km0, alp);
@@ -1345,6 +1361,16 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
 #pragma unroll
             for (int j = 0; j < L; j++) {
                 const int k = v.k[j];
+                if constexpr (VAR == VAR_PGF32) {
+                    // the single-precision pressure-gradient term of the FP32 variant
+                    const float pt = (float)a.ptop, st_ = (float)a.sig[k], sb = (float)a.sig[k + 1];
+                    const float f1 = (float)s1[j], f2 = (float)s2[j];
+                    const float q1 = 0.5f * ((pt + st_ * (f1 - pt)) + (pt + sb * (f1 - pt)));
+                    const float q2 = 0.5f * ((pt + st_ * (f2 - pt)) + (pt + sb * (f2 - pt)));
+                    const float ae = 0.5f * ((float)al1.v[j] + (float)al2.v[j]);
+                    pgf[j] = (double)(-(ae * (q2 - q1) + ((float)ph2.v[j] - (float)ph1.v[j])) * (float)dinv64);
+                    continue;
+                }
                 const double q1 = 0.5 * ((a.ptop + a.sig[k] * (s1[j] - a.ptop)) + (a.ptop + a.sig[k + 1] * (s1[j] - a.ptop)));
                 const double q2 = 0.5 * ((a.ptop + a.sig[k] * (s2[j] - a.ptop)) + (a.ptop + a.sig[k + 1] * (s2[j] - a.ptop)));
                 const double ae = 0.5 * (al1.v[j] + al2.v[j]);
@@ -1401,7 +1427,8 @@ inline unsigned nblocks(long n, int b) { return (unsigned)((n + b - 1) / b); }
 // variant does not change runs its default instance
 template <int MODEL, typename R, int L, bool M1, int VAR>
 hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
-    constexpr int VB = VAR == VAR_BOX ? VAR_BOX : VAR_MIX;
+    constexpr int VA = VAR == VAR_PGF32 ? VAR_MIX : VAR;                                   // cell_a
+    constexpr int VB = (VAR == VAR_BOX || VAR == VAR_PGF32) ? VAR : VAR_MIX;              // cell_b, edge
     const int KM = a.K * a.M;
     const int lanes = KM / L;
     const int colthreads = a.cpb * lanes;
@@ -1412,7 +1439,7 @@ hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
     const size_t lds_b = stage_lds_bytes(MODEL, pol, KERNEL_CELL_B, a.cpb, a.K, a.M);
     switch (which) {
     case KERNEL_CELL_A:
-        hipLaunchKernelGGL((k_cell_a<MODEL, R, L, M1, VAR>), dim3(colblocks), dim3(colthreads), lds_a, s, a);
+        hipLaunchKernelGGL((k_cell_a<MODEL, R, L, M1, VA>), dim3(colblocks), dim3(colthreads), lds_a, s, a);
         break;
     case KERNEL_VERTEX:
         hipLaunchKernelGGL((k_vertex<MODEL, R, L, M1>), dim3(nblocks((long)a.mesh.V * lanes, fb)), dim3(fb), 0, s, a);
@@ -1432,7 +1459,7 @@ hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
 // flat kernels (vertex, edge) also take four values per lane
 template <int MODEL, typename R, bool M1, int VAR>
 hipError_t launch_flat4(const StageArgs &a, int which, hipStream_t s) {
-    constexpr int VB = VAR == VAR_BOX ? VAR_BOX : VAR_MIX;
+    constexpr int VB = (VAR == VAR_BOX || VAR == VAR_PGF32) ? VAR : VAR_MIX;
     const int KM = a.K * a.M;
     const int lanes = KM / 4;
     const int fb = a.flat_block;
@@ -1486,6 +1513,9 @@ hipError_t launch_stage_kernel(int model, int policy, const StageArgs &a, int wh
     case POLICY_MIX_BOX: return launch_variant<VAR_BOX>(model, a, which, s);
     case POLICY_MIX_DBL_MASS: return launch_variant<VAR_DBL_MASS>(model, a, which, s);
     case POLICY_MIX_F32_DIV: return launch_variant<VAR_F32_DIV>(model, a, which, s);
+    case POLICY_MIX_PGF32:   // hydrostatic model only
+        if (model == MODEL_HDC) return launch_stage_r<MODEL_HDC, float, VAR_PGF32>(a, which, s);
+        return hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;
 }

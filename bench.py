@@ -66,7 +66,8 @@ def parse():
     p.add_argument("--no-dbl", action="store_true", help="skip the all-FP64 timing")
     p.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     p.add_argument("--no-variants", action="store_true",
-                   help="skip the mixed-policy variants (MIX_BOX, MIX_DBL_MASS, MIX_F32_DIV) of the layered dycores")
+                   help="skip the mixed-policy variants (MIX_BOX, MIX_DBL_MASS, MIX_F32_DIV; MIX_PGF32 for HDC) of "
+                             "the layered dycores")
     p.add_argument("--profile-steps", type=int, default=20,
                    help="steps run with HIP events between launches for per-kernel durations")
     p.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -239,6 +240,25 @@ def recorded_traffic(workload, kernel, shape, digest):
     return float(rec["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT) + note
 
 
+def copy_ceiling(torch, stream, mib=2048, reps=10):
+    """Streaming-copy ceiling of the device: GB/s (bytes read + written) of a
+    plain device-to-device copy of mib MiB, HIP events on the stream."""
+    n = mib * (1 << 20) // 4
+    with torch.cuda.stream(stream):
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def copy_calibration(torch, mib):
     n = mib * (1 << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -295,6 +315,7 @@ def coupled_main(args, torch, mpdc):
     stream = torch.cuda.Stream()
     N, K, T, n = mesh["nCells"], w["K"], w["T"], w["nsub"]
     res = {}
+    copy_gbs = copy_ceiling(torch, stream)
     for name in ("MIX", "DBL"):
         pol = getattr(mpdc, "POLICY_" + name)
         dy, trs, s, tr, dpi0 = coupled_states(torch, mpdc, g, mesh, w, pol, stream, not args.no_autotune)
@@ -379,7 +400,8 @@ def coupled_main(args, torch, mpdc):
                      "traffic_source": "no counter summary for this workload",
                      "bytes_per_launch": kt[dom]["bytes"], "ms_per_launch": kt[dom]["ms"],
                      "ms_per_launch_in_step": kt[dom]["ms_in_step"],
-                     "timing": "HIP events around back-to-back launches on the launch stream"},
+                     "timing": "HIP events around back-to-back launches on the launch stream",
+                     "copy_ceiling_gbs": copy_gbs, "frac_of_copy": ach / copy_gbs},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -407,6 +429,7 @@ def main():
     units = N * K * M
 
     fixed = json.loads(args.shapes) if args.shapes else {}
+    copy_gbs = copy_ceiling(torch, stream)
     s_mix, sec_mix = timed_run(torch, mpdc, g, w, st, mpdc.POLICY_MIX, args.steps, args.warmup, stream,
                                not args.no_autotune, fixed.get("mix"))
     kt = kernel_times(torch, s_mix, w, args.profile_steps, stream)
@@ -437,7 +460,7 @@ def main():
     variants, var_keys = None, {}
     if w["model"] in ("HDC", "NDC") and not args.no_variants:
         variants = {}
-        for name in ("MIX_BOX", "MIX_DBL_MASS", "MIX_F32_DIV"):
+        for name in ("MIX_BOX", "MIX_DBL_MASS", "MIX_F32_DIV") + (("MIX_PGF32",) if w["model"] == "HDC" else ()):
             s_v, sec_v = timed_run(torch, mpdc, g, w, st, getattr(mpdc, "POLICY_" + name), args.steps, args.warmup,
                                    stream, not args.no_autotune, fixed.get(name.lower()))
             shp = s_v.launch_shapes
@@ -506,7 +529,8 @@ def main():
                      "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": traffic_src,
                      "bytes_per_launch": kt[dom]["bytes"], "ms_per_launch": kt[dom]["ms"],
                      "ms_per_launch_in_step": kt[dom]["ms_in_step"],
-                     "timing": "HIP events around back-to-back launches on the launch stream"},
+                     "timing": "HIP events around back-to-back launches on the launch stream",
+                     "copy_ceiling_gbs": copy_gbs, "frac_of_copy": ach / copy_gbs},
         "cpu_baseline": cpu,
         "source_sha256": digest,
     }

@@ -108,6 +108,9 @@ extern "C" {
                                     layers k-1 and k), positive towards the surface; the lid and surface
                                     entries are ignored.  Writing it (or mpdc_tracer_couple) turns on the
                                     vertical step of mpdc_tracer_step */
+#define MPDC_FIELD_VORT 12       /* read-only (state_read, diagnostics): relative vorticity at the
+                                    vertices [V][K][M], (1/A_v) sum s' d u of the FP64 velocity; with
+                                    the surface pressure it makes the error measure E of Eqs. 1-2 */
 #define MPDC_FIELD_PHIS 11       /* HDC surface geopotential phi_s [N] (terrain; zero = flat surface,
                                     the default), shared by the members; the hydrostatic geopotential
                                     is integrated upwards from it (Eq. 8) */

@@ -59,7 +59,7 @@ struct MeshLayout {
     double *e_dinv, *e_d2, *e_hdir;
     float *e_dinv32, *e_d2_32, *e_hdir32;
     int *v_edge, *v_cell;
-    double *v_curl, *v_kite, *v_f;
+    double *v_curl, *v_kite, *v_f, *v_area;
     float *v_curl32;
     size_t bytes;
 };
@@ -97,6 +97,7 @@ MeshLayout mesh_layout(void *base, long N, long E, long V) {
     L.v_curl = c.take<double>(4 * V);
     L.v_kite = c.take<double>(4 * V);
     L.v_f = c.take<double>(V);
+    L.v_area = c.take<double>(V);
     L.v_curl32 = c.take<float>(4 * V);
     L.bytes = c.off;
     return L;
@@ -420,6 +421,7 @@ long field_count(const mpdc_state *st, int f) {
     case MPDC_FIELD_TR_Q: return mdl == MPDC_MODEL_TRACER ? N * K * T : -1;
     case MPDC_FIELD_TR_VFLUX: return mdl == MPDC_MODEL_TRACER ? N * (K + 1) : -1;
     case MPDC_FIELD_PHIS: return mdl == MPDC_MODEL_HDC ? N : -1;
+    case MPDC_FIELD_VORT: return mdl != MPDC_MODEL_TRACER ? st->V * K * M : -1;
     default: return -1;
     }
 }
@@ -537,6 +539,7 @@ int mpdc_mesh_create(const mpdc_mesh_desc *d, void *dev_ws, size_t ws_bytes, voi
         put(host, dev_ws, L.v_curl, t.v_curl);
         put(host, dev_ws, L.v_kite, t.v_kite);
         put(host, dev_ws, L.v_f, t.v_f);
+        put(host, dev_ws, L.v_area, t.v_area);
         put32(host, dev_ws, L.v_curl32, t.v_curl);
         hipStream_t s = (hipStream_t)stream;
         HIP_TRY(hipMemcpyAsync(dev_ws, host.data(), L.bytes, hipMemcpyHostToDevice, s));
@@ -556,7 +559,7 @@ int mpdc_mesh_create(const mpdc_mesh_desc *d, void *dev_ws, size_t ws_bytes, voi
         D.e_cell = L.e_cell; D.e_vert = L.e_vert; D.e_dinv = L.e_dinv; D.e_dinv32 = L.e_dinv32;
         D.e_d2 = L.e_d2; D.e_d2_32 = L.e_d2_32; D.e_hdir = L.e_hdir; D.e_hdir32 = L.e_hdir32;
         D.v_edge = L.v_edge; D.v_cell = L.v_cell; D.v_curl = L.v_curl; D.v_curl32 = L.v_curl32;
-        D.v_kite = L.v_kite; D.v_f = L.v_f;
+        D.v_kite = L.v_kite; D.v_f = L.v_f; D.v_area = L.v_area;
         m->cells_on_cell = std::move(t.cells_on_cell);
         m->edge_sign = std::move(t.edge_sign);
         m->vertex_sign = std::move(t.vertex_sign);
@@ -706,6 +709,7 @@ int mpdc_state_write(mpdc_state *st, int f, const void *src, int src_on_device, 
     if (!st || !src) return fail(MPDC_E_INVAL, "null state or source");
     long n = field_count(st, f);
     if (n < 0) return fail(MPDC_E_INVAL, "field not part of this model");
+    if (f == MPDC_FIELD_VORT) return fail(MPDC_E_INVAL, "the vorticity is derived from u and cannot be written");
     if (bytes != (size_t)n * sizeof(double)) return fail(MPDC_E_INVAL, "byte count does not match the field");
     if (f == MPDC_FIELD_TR_VFLUX) {
         if (tracer_vert_columns(st->K, st->T) < 1)
@@ -749,7 +753,12 @@ int mpdc_state_read(mpdc_state *st, int f, void *dst, int dst_on_device, size_t 
     hipStream_t s = (hipStream_t)stream;
     hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     double *srcp = field_ptr(st, f);
-    if (srcp) {
+    if (f == MPDC_FIELD_VORT) {
+        // derived from the current velocity into the stage scratch (rewritten by every stage)
+        double *tmp = (double *)st->qh;
+        HIP_TRY(launch_vorticity(st->mesh->dev, st->set[0].u, tmp, st->K * st->M, s));
+        HIP_TRY(hipMemcpyAsync(dst, tmp, bytes, kind, s));
+    } else if (srcp) {
         HIP_TRY(hipMemcpyAsync(dst, srcp, bytes, kind, s));
     } else {
         double *tmp = (double *)st->hq;
@@ -1192,18 +1201,27 @@ int mpdc_diagnostics(mpdc_state *st, int f, const void *ref_dev, mpdc_diag *out,
         if (rc) return rc;
         d.mass = r9[0];
     }
-    // field statistics and norms: cell fields area-weighted, edge fields unweighted
+    // field statistics and norms: cell fields area-weighted, vertex fields
+    // (vorticity) weighted by the dual-cell areas, edge fields unweighted
     {
         DiagArgs a{};
         const bool edge = (f == MPDC_FIELD_U || f == MPDC_FIELD_TR_FLUX);
-        a.area = edge ? nullptr : area;
-        a.n = edge ? st->E : N;
+        const bool vert = f == MPDC_FIELD_VORT;
+        a.area = edge ? nullptr : vert ? st->mesh->dev.v_area : area;
+        a.n = edge ? st->E : vert ? st->V : N;
         a.inner = nf / a.n;
         a.xs = 1;
         a.xo = 0;
         double *fp = field_ptr(st, f);
-        if (fp) a.x = fp;
-        else a.x32 = (const float *)st->q[st->parity];
+        if (vert) {
+            double *tmp = (double *)st->qh;
+            HIP_TRY(launch_vorticity(st->mesh->dev, st->set[0].u, tmp, st->K * st->M, s));
+            a.x = tmp;
+        } else if (fp) {
+            a.x = fp;
+        } else {
+            a.x32 = (const float *)st->q[st->parity];
+        }
         a.ref = (const double *)ref_dev;
         int rc = reduce(a, r9);
         if (rc) return rc;

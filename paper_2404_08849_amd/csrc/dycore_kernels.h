@@ -117,6 +117,8 @@ __host__ __device__ inline ColTabLayout coltab_layout(int model, int which, int 
 
 hipError_t launch_stage_kernel(int model, int policy, const StageArgs &a, int which, hipStream_t s);
 hipError_t launch_shadows(int model, const StageArgs &a, hipStream_t s);
+// relative vorticity at the vertices of an FP64 velocity [E][KM] into out [V][KM] (diagnostics)
+hipError_t launch_vorticity(const DevMesh &m, const double *u, double *out, int KM, hipStream_t s);
 size_t stage_lds_bytes(int model, int policy, int which, int cpb, int K, int M);
 // (k, m) values per lane of the dycore kernels: 2 when K*M splits evenly
 int values_per_lane(int K, int M);

@@ -1568,6 +1568,24 @@ hipError_t launch_flux_acc(int model, int policy, const StageArgs &a, double *Fa
     return hipGetLastError();
 }
 
+// relative vorticity (1/A_v) sum s' d u of the FP64 velocity (Eq. 5 zeta; the
+// error measure of Eqs. 1-2 uses it), one lane per vertex-level
+__global__ void k_vorticity(DevMesh m, const double *u, double *out, int KM) {
+    const long x = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= (long)m.V * KM) return;
+    const int v = (int)(x / KM), km = (int)(x - (long)v * KM);
+    double z = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; r++) z += m.v_curl[4 * (long)v + r] * u[(long)m.v_edge[4 * (long)v + r] * KM + km];
+    out[x] = z;
+}
+
+hipError_t launch_vorticity(const DevMesh &m, const double *u, double *out, int KM, hipStream_t s) {
+    const long n = (long)m.V * KM;
+    hipLaunchKernelGGL(k_vorticity, dim3(nblocks(n, 256)), dim3(256), 0, s, m, u, out, KM);
+    return hipGetLastError();
+}
+
 hipError_t launch_shadows(int model, const StageArgs &args, hipStream_t s) {
     StageArgs a = args;
     a.flat_block = 256;   // the kernel reads its work-group size from here

@@ -317,6 +317,7 @@ std::string derive_tables(const mpdc_mesh_desc *d, HostTables &t) {
     t.v_curl.assign(4 * V, 0.0);
     t.v_kite.assign(4 * V, 0.0);
     t.v_f.assign(d->fVertex, d->fVertex + V);
+    t.v_area.assign(d->areaVertex, d->areaVertex + V);
     t.vertex_sign.resize(3 * V);
     for (long v = 0; v < V; v++) {
         for (int j = 0; j < 3; j++) {

@@ -59,6 +59,7 @@ struct DevMesh {
     const float *v_curl32;
     const double *v_kite;   // [V][4] R_{i,v} / A_v
     const double *v_f;      // [V]
+    const double *v_area;   // [V] dual-cell areas (diagnostics)
 };
 
 }  // namespace mpdc
@@ -105,7 +106,7 @@ struct HostTables {
     std::vector<int> e_cell, e_vert;
     std::vector<double> e_dinv, e_d2, e_hdir;
     std::vector<int> v_edge, v_cell;              // [V][4]
-    std::vector<double> v_curl, v_kite, v_f;      // [V][4], [V][4], [V]
+    std::vector<double> v_curl, v_kite, v_f, v_area;   // [V][4], [V][4], [V], [V]
     // exported (reference-form) tables
     std::vector<int> cells_on_cell, trisk_off, trisk_edge;
     std::vector<double> edge_sign, vertex_sign, trisk_w, hessian;

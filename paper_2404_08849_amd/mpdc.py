@@ -21,7 +21,7 @@ ERRORS = {-1: "INVAL", -2: "MESH", -3: "NOMEM", -4: "DEVICE", -5: "NUMERIC", -6:
 MODEL_SW, MODEL_HDC, MODEL_NDC, MODEL_TRACER = 0, 1, 2, 3
 POLICY_DBL, POLICY_MIX, POLICY_MIX_BOX, POLICY_MIX_DBL_MASS, POLICY_MIX_F32_DIV, POLICY_MIX_PGF32 = 0, 1, 2, 3, 4, 5
 FIELD_H, FIELD_PS, FIELD_THETA, FIELD_U, FIELD_W, FIELD_PHI, FIELD_B = 0, 1, 2, 3, 4, 5, 6
-FIELD_TR_FLUX, FIELD_TR_DPI, FIELD_TR_Q, FIELD_TR_VFLUX, FIELD_PHIS = 7, 8, 9, 10, 11
+FIELD_TR_FLUX, FIELD_TR_DPI, FIELD_TR_Q, FIELD_TR_VFLUX, FIELD_PHIS, FIELD_VORT = 7, 8, 9, 10, 11, 12
 TABLE_CELLS_ON_CELL, TABLE_EDGE_SIGN, TABLE_VERTEX_SIGN = 0, 1, 2
 TABLE_TRISK_OFFSET, TABLE_TRISK_EDGE, TABLE_TRISK_WEIGHT, TABLE_HESSIAN = 3, 4, 5, 6
 
@@ -188,7 +188,8 @@ class State:
         N, E, K, M, T = self.mesh.N, self.mesh.E, self.K, self.M, self.T
         shapes = {FIELD_H: (N, M), FIELD_PS: (N, M), FIELD_THETA: (N, K, M), FIELD_U: (E, K, M),
                   FIELD_W: (N, K + 1, M), FIELD_PHI: (N, K + 1, M), FIELD_B: (N,), FIELD_TR_FLUX: (E, K),
-                  FIELD_TR_DPI: (N, K), FIELD_TR_Q: (N, K, T), FIELD_TR_VFLUX: (N, K + 1), FIELD_PHIS: (N,)}
+                  FIELD_TR_DPI: (N, K), FIELD_TR_Q: (N, K, T), FIELD_TR_VFLUX: (N, K + 1), FIELD_PHIS: (N,),
+                  FIELD_VORT: (self.mesh.V, K, M)}
         return shapes[f]
 
     def state_write(self, f, data, stream=None):

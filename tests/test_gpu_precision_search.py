@@ -1,0 +1,81 @@
+"""The precision search of Section 2.2 (Eqs. 1-2) on the GPU path.
+
+* the relative-vorticity diagnostic (MPDC_FIELD_VORT) equals the oracle's
+  curl of the same velocity, and its area-weighted norms against a reference
+  equal the oracle's norms with the dual-cell areas;
+* E of a run against itself is zero; the search accepts MIX at the paper's
+  alpha = 0.05 and goes on to the reductions built on it; with an alpha below
+  MIX's error it rejects MIX and skips what builds on it.
+"""
+import numpy as np
+import pytest
+
+from paper_2404_08849_amd.inputs import initial as ic
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mpdc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_08849_amd.mpdc as m
+    return m
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def test_vorticity_matches_oracle(mpdc, mesh_cache):
+    import torch
+    import oracle
+    m = mesh_cache(4)
+    K = 6
+    s = ic.hdc_jet(m, K, seed=2000)
+    g = mpdc.Mesh(m)
+    st = mpdc.State(g, mpdc.MODEL_HDC, mpdc.POLICY_DBL, K=K, dt=600.0, sigma=ic.sigma_interfaces(K))
+    st.state_write(mpdc.FIELD_PS, s["ps"][:, None])
+    st.state_write(mpdc.FIELD_THETA, s["Theta"][:, :, None])
+    st.state_write(mpdc.FIELD_U, s["u"][:, :, None])
+    om = oracle.OracleMesh(m)
+    vor = st.state_read(mpdc.FIELD_VORT)[:, :, 0]
+    ref = om.curl(s["u"])
+    assert np.abs(vor - ref).max() <= 1e-13 * np.abs(ref).max()
+    # norms against a perturbed reference, weighted by the dual-cell areas
+    r = np.random.default_rng(1)
+    pert = ref * (1.0 + 1e-3 * r.standard_normal(ref.shape))
+    d = st.diagnostics(mpdc.FIELD_VORT, torch.from_numpy(pert[:, :, None].copy()).cuda())
+    n = oracle.norms(m["areaVertex"], vor, pert)
+    _say("vorticity norms GPU %s oracle %s" % ((d["l1"], d["l2"], d["linf"]), tuple(n)))
+    assert np.allclose([d["l1"], d["l2"], d["linf"]], n, rtol=1e-10)
+    # the field is derived: writing it is an error
+    import ctypes
+    x = np.zeros((g.V, K, 1))
+    assert mpdc.lib.mpdc_state_write(st.h, mpdc.FIELD_VORT, x.ctypes.data_as(ctypes.c_void_p), 0, x.nbytes, None) == -1
+
+
+def test_search_accepts_and_rejects(mpdc):
+    from paper_2404_08849_amd import precision_search as ps
+    trials, accepted = ps.search(level=4, K=10, days=2.0, alpha=0.05, log=_say)
+    assert [t["policy"] for t in trials] == ["MIX", "MIX_F32_DIV", "MIX_PGF32"]
+    assert trials[0]["accepted"] and "MIX" in accepted
+    assert all(not t.get("skipped") for t in trials)
+    assert 0.0 < trials[0]["E"] < 0.05
+    # alpha below MIX's own error: MIX is rejected and the reductions built on it are skipped
+    trials2, accepted2 = ps.search(level=4, K=10, days=2.0, alpha=0.1 * trials[0]["E"], log=_say)
+    assert not trials2[0]["accepted"] and accepted2 == ["DBL"]
+    assert all(t.get("skipped") for t in trials2[1:])
+
+
+def test_error_measure_of_a_run_against_itself_is_zero(mpdc, mesh_cache):
+    from paper_2404_08849_amd import precision_search as ps
+    m = mesh_cache(3)
+    K = 6
+    s = ic.hdc_jet(m, K, seed=2000)
+    g = mpdc.Mesh(m)
+    a = ps._run(mpdc, g, s, K, 1200.0, 5, "MIX")
+    b = ps._run(mpdc, g, s, K, 1200.0, 5, "MIX")
+    E, norms = ps.error_measure(mpdc, a, b)
+    assert E == 0.0

@@ -14,6 +14,13 @@ pressure-gradient term).  A reduction is tried only on top of an accepted
 MIX.  Every run, the norms and the vorticity are computed on the GPU through
 the C ABI (``mpdc_diagnostics`` with ``MPDC_FIELD_VORT``).
 
+Beside the candidates the search reports the run's intrinsic sensitivity: E
+of an all-FP64 run whose initial Theta carries a 1e-14 relative perturbation.
+This model has no explicit dissipation, so on an unstable jet any rounding
+difference grows; a candidate whose E is near that spread differs from FP64
+no more than FP64 differs from itself (the ensemble-spread argument of
+Section 4.4).
+
 Usage: python -m paper_2404_08849_amd.precision_search [--level 6] [--days 10] [--alpha 0.05]
 """
 import argparse
@@ -28,8 +35,11 @@ from .inputs import initial as ic
 CANDIDATES = [("MIX", "DBL"), ("MIX_F32_DIV", "MIX"), ("MIX_PGF32", "MIX")]
 
 
-def _run(mpdc, g, s, K, dt, nsteps, policy, phis=None):
+def _run(mpdc, g, s, K, dt, nsteps, policy, phis=None, perturb=0.0):
     import torch
+    if perturb:
+        r = np.random.default_rng(77)
+        s = dict(s, Theta=s["Theta"] * (1.0 + perturb * r.standard_normal(s["Theta"].shape)))
     st = mpdc.State(g, mpdc.MODEL_HDC, getattr(mpdc, "POLICY_" + policy), K=K, dt=dt,
                     sigma=ic.sigma_interfaces(K))
     if phis is not None:
@@ -72,8 +82,11 @@ def search(level=6, K=30, days=10.0, dt=None, alpha=0.05, terrain=False, candida
     g = mpdc.Mesh(mesh)
     log("reference: DBL, G%d x %d, %d steps of %.1f s (%.1f days)" % (level, K, nsteps, dt, nsteps * dt / 86400.0))
     ref = _run(mpdc, g, s, K, dt, nsteps, "DBL", phis)
+    E0, n0 = error_measure(mpdc, _run(mpdc, g, s, K, dt, nsteps, "DBL", phis, perturb=1e-14), ref)
+    log("%-13s E = %.3e (L(ps) %.3e, L(vor) %.3e): intrinsic spread (FP64, Theta perturbed by 1e-14)"
+        % ("DBL+1e-14", E0, n0["ps"], n0["vor"]))
     accepted = {"DBL"}
-    trials = []
+    trials = [dict(policy="DBL+1e-14", base="DBL", E=E0, L_ps=n0["ps"], L_vor=n0["vor"], spread=True)]
     for policy, base in candidates:
         if base not in accepted:
             trials.append(dict(policy=policy, base=base, skipped=True))

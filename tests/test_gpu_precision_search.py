@@ -5,7 +5,10 @@
   equal the oracle's norms with the dual-cell areas;
 * E of a run against itself is zero; the search accepts MIX at the paper's
   alpha = 0.05 and goes on to the reductions built on it; with an alpha below
-  MIX's error it rejects MIX and skips what builds on it.
+  MIX's error it rejects MIX and skips what builds on it;
+* on the G6 jet over 4 days the search keeps the paper's split and rejects
+  the FP32 pressure-gradient term: the paper's finding that this term must
+  stay in FP64, reproduced at small scale.
 """
 import numpy as np
 import pytest
@@ -59,14 +62,16 @@ def test_vorticity_matches_oracle(mpdc, mesh_cache):
 def test_search_accepts_and_rejects(mpdc):
     from paper_2404_08849_amd import precision_search as ps
     trials, accepted = ps.search(level=4, K=10, days=2.0, alpha=0.05, log=_say)
-    assert [t["policy"] for t in trials] == ["MIX", "MIX_F32_DIV", "MIX_PGF32"]
-    assert trials[0]["accepted"] and "MIX" in accepted
-    assert all(not t.get("skipped") for t in trials)
-    assert 0.0 < trials[0]["E"] < 0.05
+    assert [t["policy"] for t in trials] == ["DBL+1e-14", "MIX", "MIX_F32_DIV", "MIX_PGF32"]
+    spread, cand = trials[0], trials[1:]
+    assert spread["spread"] and spread["E"] > 0.0
+    assert cand[0]["accepted"] and "MIX" in accepted
+    assert all(not t.get("skipped") for t in cand)
+    assert 0.0 < cand[0]["E"] < 0.05
     # alpha below MIX's own error: MIX is rejected and the reductions built on it are skipped
-    trials2, accepted2 = ps.search(level=4, K=10, days=2.0, alpha=0.1 * trials[0]["E"], log=_say)
-    assert not trials2[0]["accepted"] and accepted2 == ["DBL"]
-    assert all(t.get("skipped") for t in trials2[1:])
+    trials2, accepted2 = ps.search(level=4, K=10, days=2.0, alpha=0.1 * cand[0]["E"], log=_say)
+    assert not trials2[1]["accepted"] and accepted2 == ["DBL"]
+    assert all(t.get("skipped") for t in trials2[2:])
 
 
 def test_error_measure_of_a_run_against_itself_is_zero(mpdc, mesh_cache):
@@ -79,3 +84,16 @@ def test_error_measure_of_a_run_against_itself_is_zero(mpdc, mesh_cache):
     b = ps._run(mpdc, g, s, K, 1200.0, 5, "MIX")
     E, norms = ps.error_measure(mpdc, a, b)
     assert E == 0.0
+
+
+def test_search_keeps_fp64_pressure_gradient(mpdc):
+    # G6 x 30 jet, 4 days (1152 steps): the search accepts the paper's split and the
+    # FP32 continuity divergence, and rejects computing the pressure-gradient term
+    # and its column diagnostics in FP32 (measured E: 9.2e-3, 9.5e-3, 0.24)
+    from paper_2404_08849_amd import precision_search as ps
+    trials, accepted = ps.search(level=6, K=30, days=4.0, alpha=0.05, log=_say)
+    E = {t["policy"]: t for t in trials}
+    assert E["MIX"]["accepted"] and E["MIX_F32_DIV"]["accepted"]
+    assert not E["MIX_PGF32"]["accepted"]
+    assert E["MIX_PGF32"]["E"] > 10.0 * E["MIX"]["E"]
+    assert accepted == ["DBL", "MIX", "MIX_F32_DIV"]

@@ -460,7 +460,7 @@ def main():
     variants, var_keys = None, {}
     if w["model"] in ("HDC", "NDC") and not args.no_variants:
         variants = {}
-        for name in ("MIX_BOX", "MIX_DBL_MASS", "MIX_F32_DIV") + (("MIX_PGF32",) if w["model"] == "HDC" else ()):
+        for name in ("MIX_BOX", "MIX_DBL_MASS", "MIX_F32_DIV") + (("MIX_PGF32", "SGL") if w["model"] == "HDC" else ()):
             s_v, sec_v = timed_run(torch, mpdc, g, w, st, getattr(mpdc, "POLICY_" + name), args.steps, args.warmup,
                                    stream, not args.no_autotune, fixed.get(name.lower()))
             shp = s_v.launch_shapes

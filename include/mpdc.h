@@ -92,6 +92,13 @@ extern "C" {
  * Over terrain these two large terms nearly cancel (Section 4), which is
  * where FP32 fails. */
 #define MPDC_POLICY_MIX_PGF32 5
+/* SGL (hydrostatic dycore only): every term in FP32 -- the reductions of
+ * MIX, the FP32 cell divergence of MIX_F32_DIV, the FP32 diagnostics and
+ * pressure-gradient term of MIX_PGF32, and the vertex mass and potential
+ * vorticity in FP32 -- the single-precision configuration the paper starts
+ * from (Section 2.2) and finds unacceptable (Section 4.1).  The prognostic
+ * state is still stored in FP64 and updated with the FP32 tendencies. */
+#define MPDC_POLICY_SGL 6
 
 /* ---- state fields for mpdc_state_write / mpdc_state_read (FP64 in and out) ---- */
 #define MPDC_FIELD_H 0           /* SW fluid depth h          [N][M]        */

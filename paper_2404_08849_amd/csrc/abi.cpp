@@ -615,9 +615,9 @@ void mpdc_mesh_destroy(mpdc_mesh *m) { delete m; }
 static int check_config(const mpdc_mesh *m, const mpdc_config *c) {
     if (!m || !c) return fail(MPDC_E_INVAL, "null mesh or config");
     if (c->model < MPDC_MODEL_SW || c->model > MPDC_MODEL_TRACER) return fail(MPDC_E_INVAL, "unknown model");
-    if (c->policy < MPDC_POLICY_DBL || c->policy > MPDC_POLICY_MIX_PGF32) return fail(MPDC_E_INVAL, "unknown policy");
-    if (c->policy == MPDC_POLICY_MIX_PGF32 && c->model != MPDC_MODEL_HDC)
-        return fail(MPDC_E_UNSUPPORTED, "the FP32 pressure-gradient variant is built for the hydrostatic dycore only");
+    if (c->policy < MPDC_POLICY_DBL || c->policy > MPDC_POLICY_SGL) return fail(MPDC_E_INVAL, "unknown policy");
+    if ((c->policy == MPDC_POLICY_MIX_PGF32 || c->policy == MPDC_POLICY_SGL) && c->model != MPDC_MODEL_HDC)
+        return fail(MPDC_E_UNSUPPORTED, "the FP32 pressure-gradient variants are built for the hydrostatic dycore only");
     if (c->policy > MPDC_POLICY_MIX && c->model != MPDC_MODEL_HDC && c->model != MPDC_MODEL_NDC)
         return fail(MPDC_E_UNSUPPORTED, "the mixed-policy variants are built for the layered dycores only");
     if (c->K < 1 || c->M < 1 || c->K > 512 || c->M > 64) return fail(MPDC_E_INVAL, "K must be 1..512 and M 1..64");

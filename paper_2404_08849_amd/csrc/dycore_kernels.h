@@ -14,11 +14,12 @@ enum {
     POLICY_MIX_BOX = MPDC_POLICY_MIX_BOX,
     POLICY_MIX_DBL_MASS = MPDC_POLICY_MIX_DBL_MASS,
     POLICY_MIX_F32_DIV = MPDC_POLICY_MIX_F32_DIV,
-    POLICY_MIX_PGF32 = MPDC_POLICY_MIX_PGF32
+    POLICY_MIX_PGF32 = MPDC_POLICY_MIX_PGF32,
+    POLICY_SGL = MPDC_POLICY_SGL
 };
 // Variants of the mixed policy inside the FP32 kernel instances (template
 // argument VAR): which terms leave the default split.
-enum { VAR_MIX = 0, VAR_BOX = 1, VAR_DBL_MASS = 2, VAR_F32_DIV = 3, VAR_PGF32 = 4 };
+enum { VAR_MIX = 0, VAR_BOX = 1, VAR_DBL_MASS = 2, VAR_F32_DIV = 3, VAR_PGF32 = 4, VAR_SGL = 5 };
 enum { KERNEL_CELL_A = 0, KERNEL_VERTEX = 1, KERNEL_CELL_B = 2, KERNEL_EDGE = 3 };
 // largest work-group of the column kernels (keeps 256 VGPRs available per lane)
 constexpr int kColumnThreads = 512;

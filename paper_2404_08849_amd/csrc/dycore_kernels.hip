@@ -676,8 +676,12 @@ k_cell_a(StageArgs a) {
 // ---------------------------------------------------------------------------
 // vertex: vorticity, FP64 vertex mass, potential vorticity
 // ---------------------------------------------------------------------------
-template <int MODEL, typename R, int L, bool M1>
+template <int MODEL, typename R, int L, bool M1, int VAR>
 __global__ void __launch_bounds__(1024) k_vertex(StageArgs a) {
+    // the all-FP32 variant forms the vertex mass and the potential vorticity in
+    // FP32 (the paper keeps the vertex mass of zeta_p in FP64)
+    constexpr bool S32 = VAR == VAR_SGL;
+    using RM = typename std::conditional<S32, float, double>::type;
     const DevMesh &m = a.mesh;
     const int K = a.K, M = M1 ? 1 : a.M, KM = K * M;
     const int lanes = KM / L;
@@ -698,16 +702,16 @@ __global__ void __launch_bounds__(1024) k_vertex(StageArgs a) {
         cw[0] = c0.v[0]; cw[1] = c0.v[1]; cw[2] = c1.v[0]; cw[3] = c1.v[1];
     }
     const Pack<double, 2> k0 = ldp<double, 2>(m.v_kite + 4 * (long)vx), k1 = ldp<double, 2>(m.v_kite + 4 * (long)vx + 2);
-    const double kw[3] = {k0.v[0], k0.v[1], k1.v[0]};
+    const RM kw[3] = {(RM)k0.v[0], (RM)k0.v[1], (RM)k1.v[0]};
     double dsg[L];
 #pragma unroll
     for (int j = 0; j < L; j++) dsg[j] = (MODEL == MODEL_SW) ? 1.0 : a.dsig[v.k[j]];
     R zeta[L];
-    double hv[L];
+    RM hv[L];
 #pragma unroll
     for (int j = 0; j < L; j++) {
         zeta[j] = 0;
-        hv[j] = 0.0;
+        hv[j] = 0;
     }
     const R *us = u_prev_ptr<R>(a);
 #pragma unroll
@@ -718,13 +722,16 @@ __global__ void __launch_bounds__(1024) k_vertex(StageArgs a) {
 #pragma unroll
         for (int j = 0; j < L; j++) {
             zeta[j] += cw[r] * u.v[j];
-            hv[j] += kw[r] * lmass<MODEL>(dsg[j], ps[j], a.ptop);
+            hv[j] += kw[r] * (RM)lmass<MODEL>(dsg[j], ps[j], a.ptop);
         }
     }
     const double f = m.v_f[vx];
     Pack<R, L> q;
 #pragma unroll
-    for (int j = 0; j < L; j++) q.v[j] = (R)(((double)zeta[j] + f) / hv[j]);
+    for (int j = 0; j < L; j++) {
+        if constexpr (S32) q.v[j] = (zeta[j] + (float)f) / hv[j];
+        else q.v[j] = (R)(((double)zeta[j] + f) / hv[j]);
+    }
     stp<R, L>(a.qv_out<R>() + (long)vx * KM + km0, q);
 }
 
@@ -1438,8 +1445,11 @@ inline unsigned nblocks(long n, int b) { return (unsigned)((n + b - 1) / b); }
 // variant does not change runs its default instance
 template <int MODEL, typename R, int L, bool M1, int VAR>
 hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
-    constexpr int VA = VAR == VAR_PGF32 ? VAR_MIX : VAR;                                   // cell_a
-    constexpr int VB = (VAR == VAR_BOX || VAR == VAR_PGF32) ? VAR : VAR_MIX;              // cell_b, edge
+    // the all-FP32 variant: FP32 divergence in cell_a, its own vertex kernel, the
+    // FP32 pressure-gradient instances of cell_b and edge
+    constexpr int VA = VAR == VAR_PGF32 ? VAR_MIX : VAR == VAR_SGL ? VAR_F32_DIV : VAR;   // cell_a
+    constexpr int VB = (VAR == VAR_BOX || VAR == VAR_PGF32) ? VAR : VAR == VAR_SGL ? VAR_PGF32 : VAR_MIX;
+    constexpr int VV = VAR == VAR_SGL ? VAR_SGL : VAR_MIX;                                // vertex
     const int KM = a.K * a.M;
     const int lanes = KM / L;
     const int colthreads = a.cpb * lanes;
@@ -1453,7 +1463,7 @@ hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
         hipLaunchKernelGGL((k_cell_a<MODEL, R, L, M1, VA>), dim3(colblocks), dim3(colthreads), lds_a, s, a);
         break;
     case KERNEL_VERTEX:
-        hipLaunchKernelGGL((k_vertex<MODEL, R, L, M1>), dim3(nblocks((long)a.mesh.V * lanes, fb)), dim3(fb), 0, s, a);
+        hipLaunchKernelGGL((k_vertex<MODEL, R, L, M1, VV>), dim3(nblocks((long)a.mesh.V * lanes, fb)), dim3(fb), 0, s, a);
         break;
     case KERNEL_CELL_B:
         hipLaunchKernelGGL((k_cell_b<MODEL, R, L, M1, VB>), dim3(colblocks), dim3(colthreads), lds_b, s, a);
@@ -1470,12 +1480,13 @@ hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
 // flat kernels (vertex, edge) also take four values per lane
 template <int MODEL, typename R, bool M1, int VAR>
 hipError_t launch_flat4(const StageArgs &a, int which, hipStream_t s) {
-    constexpr int VB = (VAR == VAR_BOX || VAR == VAR_PGF32) ? VAR : VAR_MIX;
+    constexpr int VB = (VAR == VAR_BOX || VAR == VAR_PGF32) ? VAR : VAR == VAR_SGL ? VAR_PGF32 : VAR_MIX;
+    constexpr int VV = VAR == VAR_SGL ? VAR_SGL : VAR_MIX;
     const int KM = a.K * a.M;
     const int lanes = KM / 4;
     const int fb = a.flat_block;
     if (which == KERNEL_VERTEX)
-        hipLaunchKernelGGL((k_vertex<MODEL, R, 4, M1>), dim3(nblocks((long)a.mesh.V * lanes, fb)), dim3(fb), 0, s, a);
+        hipLaunchKernelGGL((k_vertex<MODEL, R, 4, M1, VV>), dim3(nblocks((long)a.mesh.V * lanes, fb)), dim3(fb), 0, s, a);
     else if (which == KERNEL_EDGE)
         hipLaunchKernelGGL((k_edge<MODEL, R, 4, M1, VB>), dim3(nblocks((long)a.mesh.E * lanes, fb)), dim3(fb), 0, s, a);
     else
@@ -1526,6 +1537,9 @@ hipError_t launch_stage_kernel(int model, int policy, const StageArgs &a, int wh
     case POLICY_MIX_F32_DIV: return launch_variant<VAR_F32_DIV>(model, a, which, s);
     case POLICY_MIX_PGF32:   // hydrostatic model only
         if (model == MODEL_HDC) return launch_stage_r<MODEL_HDC, float, VAR_PGF32>(a, which, s);
+        return hipErrorInvalidValue;
+    case POLICY_SGL:         // hydrostatic model only
+        if (model == MODEL_HDC) return launch_stage_r<MODEL_HDC, float, VAR_SGL>(a, which, s);
         return hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;

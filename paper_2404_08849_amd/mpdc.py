@@ -19,7 +19,8 @@ MPDC_OK = 0
 ERRORS = {-1: "INVAL", -2: "MESH", -3: "NOMEM", -4: "DEVICE", -5: "NUMERIC", -6: "UNSUPPORTED", -7: "STATE"}
 
 MODEL_SW, MODEL_HDC, MODEL_NDC, MODEL_TRACER = 0, 1, 2, 3
-POLICY_DBL, POLICY_MIX, POLICY_MIX_BOX, POLICY_MIX_DBL_MASS, POLICY_MIX_F32_DIV, POLICY_MIX_PGF32 = 0, 1, 2, 3, 4, 5
+POLICY_DBL, POLICY_MIX, POLICY_MIX_BOX, POLICY_MIX_DBL_MASS, POLICY_MIX_F32_DIV, POLICY_MIX_PGF32, POLICY_SGL = \
+    0, 1, 2, 3, 4, 5, 6
 FIELD_H, FIELD_PS, FIELD_THETA, FIELD_U, FIELD_W, FIELD_PHI, FIELD_B = 0, 1, 2, 3, 4, 5, 6
 FIELD_TR_FLUX, FIELD_TR_DPI, FIELD_TR_Q, FIELD_TR_VFLUX, FIELD_PHIS, FIELD_VORT = 7, 8, 9, 10, 11, 12
 TABLE_CELLS_ON_CELL, TABLE_EDGE_SIGN, TABLE_VERTEX_SIGN = 0, 1, 2

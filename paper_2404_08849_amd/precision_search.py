@@ -10,7 +10,7 @@ vorticity), stays within alpha = 0.05.  Here the changes are the library's
 precision policies, ordered by how much they take out of FP64: MIX (the
 paper's split) first, then each further reduction built on MIX (MIX_F32_DIV:
 FP32 continuity divergence; MIX_PGF32: FP32 column diagnostics and
-pressure-gradient term).  A reduction is tried only on top of an accepted
+pressure-gradient term; SGL: every term in FP32).  A reduction is tried only on top of an accepted
 MIX.  Every run, the norms and the vorticity are computed on the GPU through
 the C ABI (``mpdc_diagnostics`` with ``MPDC_FIELD_VORT``).
 
@@ -32,7 +32,7 @@ from .inputs import initial as ic
 
 # candidate reductions in the order they are tried, each with the
 # configuration it builds on
-CANDIDATES = [("MIX", "DBL"), ("MIX_F32_DIV", "MIX"), ("MIX_PGF32", "MIX")]
+CANDIDATES = [("MIX", "DBL"), ("MIX_F32_DIV", "MIX"), ("MIX_PGF32", "MIX"), ("SGL", "MIX")]
 
 
 def _run(mpdc, g, s, K, dt, nsteps, policy, phis=None, perturb=0.0):

@@ -62,7 +62,7 @@ def test_vorticity_matches_oracle(mpdc, mesh_cache):
 def test_search_accepts_and_rejects(mpdc):
     from paper_2404_08849_amd import precision_search as ps
     trials, accepted = ps.search(level=4, K=10, days=2.0, alpha=0.05, log=_say)
-    assert [t["policy"] for t in trials] == ["DBL+1e-14", "MIX", "MIX_F32_DIV", "MIX_PGF32"]
+    assert [t["policy"] for t in trials] == ["DBL+1e-14", "MIX", "MIX_F32_DIV", "MIX_PGF32", "SGL"]
     spread, cand = trials[0], trials[1:]
     assert spread["spread"] and spread["E"] > 0.0
     assert cand[0]["accepted"] and "MIX" in accepted
@@ -89,11 +89,12 @@ def test_error_measure_of_a_run_against_itself_is_zero(mpdc, mesh_cache):
 def test_search_keeps_fp64_pressure_gradient(mpdc):
     # G6 x 30 jet, 4 days (1152 steps): the search accepts the paper's split and the
     # FP32 continuity divergence, and rejects computing the pressure-gradient term
-    # and its column diagnostics in FP32 (measured E: 9.2e-3, 9.5e-3, 0.24)
+    # and its column diagnostics in FP32 (measured E: 9.2e-3, 9.5e-3, 0.24) and
+    # the all-FP32 configuration
     from paper_2404_08849_amd import precision_search as ps
     trials, accepted = ps.search(level=6, K=30, days=4.0, alpha=0.05, log=_say)
     E = {t["policy"]: t for t in trials}
     assert E["MIX"]["accepted"] and E["MIX_F32_DIV"]["accepted"]
-    assert not E["MIX_PGF32"]["accepted"]
-    assert E["MIX_PGF32"]["E"] > 10.0 * E["MIX"]["E"]
+    assert not E["MIX_PGF32"]["accepted"] and not E["SGL"]["accepted"]
+    assert E["MIX_PGF32"]["E"] > 10.0 * E["MIX"]["E"] and E["SGL"]["E"] > 10.0 * E["MIX"]["E"]
     assert accepted == ["DBL", "MIX", "MIX_F32_DIV"]

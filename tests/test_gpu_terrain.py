@@ -114,3 +114,22 @@ def test_fp32_pressure_gradient_is_less_accurate(mpdc, oracle_mod, mesh_cache):
         # the mixed policy passes its bar; the FP32 force is over 8x less accurate
         assert res["MIX"][0] <= MIX_TOL and res["MIX"][1] <= 1e-3
         assert res["MIX_PGF32"][0] > 8.0 * res["MIX"][0] and res["MIX_PGF32"][1] > 8.0 * res["MIX"][1]
+
+
+def test_sgl_parity_and_ordering(mpdc, oracle_mod, mesh_cache):
+    # the all-FP32 configuration runs (finite, close to the oracle after 10
+    # steps) and is no more accurate than MIX_PGF32, which it contains
+    m = mesh_cache(5)
+    K, dt, n = 10, 300.0, 10
+    g = mpdc.Mesh(m)
+    s = ic.hdc_jet(m, K, seed=2000)
+    zero = np.zeros(m["nCells"])
+    ref = oracle_mod.OracleMesh(m).hdc_run(s["ps"], s["Theta"], s["u"], dt, n)
+    err = {}
+    for pol in ("MIX", "MIX_PGF32", "SGL"):
+        ps, Th, u = _run(mpdc, g, s, K, dt, n, getattr(mpdc, "POLICY_" + pol), zero)
+        assert np.isfinite(ps).all() and np.isfinite(u).all()
+        err[pol] = (rel_l2(ps, ref[0], m["areaCell"]), rel_l2(u, ref[2]))
+        _say("hdc G5x%d jet, %d steps, %s: ps %.3e  u %.3e" % ((K, n, pol) + err[pol]))
+    assert err["SGL"][0] <= MIX_TOL and err["SGL"][1] <= 1e-3
+    assert err["SGL"][1] > 8.0 * err["MIX"][1]

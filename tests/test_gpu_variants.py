@@ -174,10 +174,11 @@ def test_variants_rejected_where_not_built(mpdc, mesh_cache):
             assert lib.mpdc_state_create(g.h, ctypes.byref(cfg), ctypes.c_void_p(256), 1 << 40,
                                          ctypes.byref(out)) == -6
             assert out.value is None
-    cfg, sig = _config(mpdc, mpdc.MODEL_HDC, 6, 4)                  # no such policy
+    cfg, sig = _config(mpdc, mpdc.MODEL_HDC, 7, 4)                  # no such policy
     assert lib.mpdc_state_workspace_bytes(g.h, ctypes.byref(cfg)) == 0
-    cfg, sig = _config(mpdc, mpdc.MODEL_NDC, mpdc.POLICY_MIX_PGF32, 4)   # hydrostatic only
-    assert lib.mpdc_state_workspace_bytes(g.h, ctypes.byref(cfg)) == 0
+    for pol in (mpdc.POLICY_MIX_PGF32, mpdc.POLICY_SGL):                # hydrostatic only
+        cfg, sig = _config(mpdc, mpdc.MODEL_NDC, pol, 4)
+        assert lib.mpdc_state_workspace_bytes(g.h, ctypes.byref(cfg)) == 0
     # the boxed variant keeps the kinetic energy in FP64
     b = {}
     for pol in (mpdc.POLICY_MIX, mpdc.POLICY_MIX_BOX, mpdc.POLICY_MIX_DBL_MASS):

@@ -112,14 +112,19 @@ def hdc_jet(mesh, K, u0=35.0, T0=300.0, pert=1.0, seed=2000):
     return dict(ps=ps, Theta=dpi * theta, u=np.ascontiguousarray(u))
 
 
-def ensemble(state, M, sigma=0.1, seed=5000):
+def ensemble(state, M, sigma=0.1, seed=5000, relative=None):
     """Stack M copies of a hydrostatic state member-innermost, with independent
-    N(0, sigma) perturbations on every u_{e,k} of member m (seed + m)."""
+    N(0, sigma) perturbations on every u_{e,k} of member m (seed + m), or, if
+    relative is given, u scaled by 1 + U(-relative, relative) (the paper's
+    perturbation "within 2%" of the wind is relative = 0.02)."""
     ps, Th, u = state["ps"], state["Theta"], state["u"]
     E, K = u.shape
     um = np.empty((E, K, M))
     for m in range(M):
-        um[:, :, m] = u + sigma * rng.normal(seed + m, E * K).reshape(E, K)
+        if relative is None:
+            um[:, :, m] = u + sigma * rng.normal(seed + m, E * K).reshape(E, K)
+        else:
+            um[:, :, m] = u * (1.0 + relative * (2.0 * rng.uniform(seed + m, E * K).reshape(E, K) - 1.0))
     return dict(ps=np.repeat(ps[:, None], M, 1), Theta=np.repeat(Th[:, :, None], M, 2), u=um)
 
 

@@ -211,12 +211,17 @@ int mpdc_state_create(const mpdc_mesh *m, const mpdc_config *c, void *dev_ws, si
 
 /* Write a field (MPDC_FIELD_*) from FP64 data on the host (src_on_device = 0)
  * or device; the library converts to its storage precision and regenerates
- * the FP32 shadows.  bytes must equal the field's FP64 size. */
+ * the FP32 shadows.  bytes must equal the field's FP64 size.  Errors: INVAL
+ * (field not part of the model, wrong size, or MPDC_FIELD_VORT, which is
+ * derived), UNSUPPORTED (MPDC_FIELD_TR_VFLUX with K x T too large for the
+ * vertical step), DEVICE.  Synchronous for host sources. */
 int mpdc_state_write(mpdc_state *st, int field_id, const void *src, int src_on_device, size_t bytes,
                      void *stream);
 
 /* Read a field back as FP64 into host (dst_on_device = 0; synchronous) or
- * device memory (asynchronous). */
+ * device memory (asynchronous).  MPDC_FIELD_VORT is computed from the current
+ * velocity on the fly (it uses the state's stage scratch, so it must not run
+ * concurrently with a step of the same state). */
 int mpdc_state_read(mpdc_state *st, int field_id, void *dst, int dst_on_device, size_t bytes,
                     void *stream);
 
@@ -254,9 +259,11 @@ int mpdc_tracer_couple(mpdc_state *tracer, mpdc_state *dycore, void *stream);
 
 /* Deterministic FP64 reductions over the state: global mass, tracer masses,
  * NaN/Inf count, min/max of field_id, and (if ref_dev is not NULL) the
- * area-weighted normalised L1/L2/Linf errors of field_id against the FP64
- * device array ref_dev of the same layout.  Synchronous.  Returns
- * MPDC_E_NUMERIC (with *out filled) if a NaN/Inf is present. */
+ * normalised L1/L2/Linf errors of field_id against the FP64 device array
+ * ref_dev of the same layout (Section 2.2, Eq. 2; cell fields weighted by the
+ * cell areas, MPDC_FIELD_VORT by the dual-cell areas, edge fields
+ * unweighted).  Synchronous.  Returns MPDC_E_NUMERIC (with *out filled) if a
+ * NaN/Inf is present. */
 int mpdc_diagnostics(mpdc_state *st, int field_id, const void *ref_dev, mpdc_diag *out, void *stream);
 
 /* Capture one dycore or tracer step into a HIP graph and replay it for later

@@ -198,24 +198,45 @@ def accuracy_run(torch, mpdc, g, w, st, stream, shapes, names=("DBL", "MIX")):
     return res
 
 
-def oracle_baseline(mesh, w, st, nsteps):
+def oracle_baseline(mesh, w, st, nsteps, min_seconds=10.0, max_seconds=30.0):
+    """The oracle on the host: nsteps from the workload's input (their result
+    is the accuracy reference), then further chunks of nsteps from where it
+    left off until about min_seconds of work; returns (reference, seconds,
+    steps, threads)."""
     from oracle import OracleMesh, oracle_lib
     om = OracleMesh(mesh)
-    t0 = time.perf_counter()
+    vf = st.get("vflux")
     if w["model"] == "SW":
-        h, _ = om.sw_run(st["h"], st["u"], st["b"], w["dt"], nsteps)
-        key = h
+        state = (st["h"], st["u"])
+        run = lambda s, n: om.sw_run(s[0], s[1], st["b"], w["dt"], n)
+        key_of = lambda s: s[0]
     elif w["model"] == "HDC":
         ps0, Th0, u0 = st["ps"], st["Theta"], st["u"]
         if w["M"] > 1:
             ps0, Th0, u0 = ps0[:, 0], Th0[:, :, 0], u0[:, :, 0]
-        key, _, _ = om.hdc_run(ps0, Th0, u0, w["dt"], nsteps)
+        state = (ps0, Th0, u0)
+        run = lambda s, n: om.hdc_run(s[0], s[1], s[2], w["dt"], n)
+        key_of = lambda s: s[0]
     elif w["model"] == "NDC":
-        key = om.ndc_run(st["ps"], st["Theta"], st["u"], st["w"], st["phi"], w["dt"], nsteps)[0]
+        state = (st["ps"], st["Theta"], st["u"], st["w"], st["phi"])
+        run = lambda s, n: om.ndc_run(*s, w["dt"], n)
+        key_of = lambda s: s[0]
     else:
-        _, key = om.tracer_run(st["F"], st["dpi"], st["q"], w["dt"], nsteps, vflux=st.get("vflux"))
+        state = (st["dpi"], st["q"])
+        run = lambda s, n: om.tracer_run(st["F"], s[0], s[1], w["dt"], n, vflux=vf)
+        key_of = lambda s: s[1]
+    t0 = time.perf_counter()
+    state = run(state, nsteps)
+    key = key_of(state)
+    steps = nsteps
+    while time.perf_counter() - t0 < min_seconds:
+        t1 = time.perf_counter()
+        state = run(state, nsteps)
+        steps += nsteps
+        if time.perf_counter() - t0 + (time.perf_counter() - t1) > max_seconds:
+            break
     el = time.perf_counter() - t0
-    return key, el, oracle_lib().or_num_threads()
+    return key, el, steps, oracle_lib().or_num_threads()
 
 
 def rel_l2(x, r):
@@ -368,12 +389,16 @@ def coupled_main(args, torch, mpdc):
         tr = ic.tracer_solid_body(mesh, K, T, seed=3000)
         dpi0 = np.diff(ic.sigma_interfaces(K))[None, :] * (s["ps"][:, None] - 1000.0)
         t0 = time.perf_counter()
-        o = om.hdc_run_flux(s["ps"], s["Theta"], s["u"], w["dt"], n)
-        om.tracer_run(o[3] / n, dpi0, tr["q"], n * w["dt"], 1, vflux=o[4] / n)
+        ps_, Th_, u_, q_, dpi_ = s["ps"], s["Theta"], s["u"], tr["q"], dpi0
+        ncs = 0
+        while ncs == 0 or time.perf_counter() - t0 < 10.0:
+            ps_, Th_, u_, Fs, Ms = om.hdc_run_flux(ps_, Th_, u_, w["dt"], n)
+            dpi_, q_ = om.tracer_run(Fs / n, dpi_, q_, n * w["dt"], 1, vflux=Ms / n)
+            ncs += 1
         el = time.perf_counter() - t0
-        cpu = {"value": N * K * n / el, "unit": "cell-level-steps/s", "cores": oracle_lib().or_num_threads(),
-               "kind": "oracle", "sample": "one coupled step (%d dycore steps + one tracer step of %d tracers) "
-                                           "on the host (%.1f s)" % (n, T, el)}
+        cpu = {"value": N * K * n * ncs / el, "unit": "cell-level-steps/s", "cores": oracle_lib().or_num_threads(),
+               "kind": "oracle", "sample": "%d coupled steps (each %d dycore steps + one tracer step of %d "
+                                           "tracers) on the host (%.1f s)" % (ncs, n, T, el)}
     out = {
         "metric": "cell-level-steps/s (mixed vs all-FP64) at fixed L2 error; HBM GB/s",
         "value": N * K * n / mix["sec"],
@@ -474,7 +499,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         nst = w["steps"] if w["level"] <= 6 else 1
-        key, el, cores = oracle_baseline(mesh, w, st, nst)
+        key, el, nrun, cores = oracle_baseline(mesh, w, st, nst)
         ref = np.asarray(key)
         gpu_dbl = acc["DBL"] if nst == w["steps"] else None
         if gpu_dbl is not None:
@@ -488,9 +513,10 @@ def main():
                 xv = x[:, 0] if (w["model"] == "HDC" and M > 1) else x.reshape(ref.shape)
                 variants[name]["vs_oracle_l2"] = rel_l2(xv, ref)
         per_member = N * K * (T if w["model"] == "TRACER" else 1)
-        cpu = {"value": per_member * nst / el, "unit": "cell-level-steps/s" if w["model"] != "TRACER"
+        cpu = {"value": per_member * nrun / el, "unit": "cell-level-steps/s" if w["model"] != "TRACER"
                else "cell-level-tracer-steps/s", "cores": cores, "kind": "oracle",
-               "sample": "%d step(s) of one member of %s on the host (%.1f s)" % (nst, args.workload, el)}
+               "sample": "%d step(s) of one member of %s on the host (%.1f s); the first %d are the "
+                         "accuracy reference" % (nrun, args.workload, el, nst)}
     gate["passes"] = bool(gate.get("mix_vs_oracle_l2", gate["mix_vs_dbl_l2"]) <= 1e-5 and gate["nonfinite"] == 0)
 
     value = units / sec_mix

@@ -94,3 +94,12 @@ def test_valid_meshes_derive_on_host(mpdc, mesh_cache, level):
     """Every icosahedral mesh validates and derives its tables on the host."""
     rc, msg, _ = _create(mpdc, mesh_cache(level))
     assert rc == 0, (level, msg)
+
+
+def test_relabelled_mesh_is_valid(mpdc, mesh_cache):
+    # a randomly renumbered mesh (the GPU invariance test's input) passes the
+    # library's validation and table derivation
+    from mesh_relabel import relabel
+    mp, _, _, _ = relabel(mesh_cache(3))
+    rc, msg, _ = _create(mpdc, mp)
+    assert rc == 0, msg

@@ -11,7 +11,12 @@ Construction (all geometry on the unit sphere, lengths scaled by ``radius``):
 
 * icosahedron with a vertex at each pole and two rings of five at latitude
   +-atan(1/2) (longitudes 2*pi*j/5 and 2*pi*j/5 + pi/5);
-* ``level`` recursive bisections, each new point normalised onto the sphere;
+* optionally one or more trisections first (each face into nine: two
+  points on every edge at a third and two thirds of the chord, one at the
+  face centre; the "B3" grids of Table 1, G9B3 = one trisection and nine
+  bisections), then ``level`` recursive bisections, each new point
+  normalised onto the sphere; an icosahedron edge ends up in
+  n = 3^t 2^level segments and N = 10 n^2 + 2;
 * Voronoi vertices are the spherical circumcentres of the Delaunay
   triangles; the edge point x_e is normalize(x_c1 + x_c2);
 * cells, edges and vertices are renumbered along a 3-D Hilbert curve so that
@@ -33,9 +38,10 @@ EARTH_RADIUS = 6.371e6
 OMEGA = 7.292e-5
 
 
-def mesh_counts(level):
-    """(cells, edges, vertices) of bisection level ``level``."""
-    return 10 * 4 ** level + 2, 30 * 4 ** level, 20 * 4 ** level
+def mesh_counts(level, trisections=0):
+    """(cells, edges, vertices) after ``trisections`` trisections and ``level`` bisections."""
+    n2 = 9 ** trisections * 4 ** level
+    return 10 * n2 + 2, 30 * n2, 20 * n2
 
 
 def _normalize(x):
@@ -87,6 +93,41 @@ def _bisect(pts, faces):
     return np.concatenate([pts, mid]), newf
 
 
+def _trisect(pts, faces):
+    """Split every face into nine: points at 1/3 and 2/3 of each edge's chord
+    (shared by the two faces of the edge) and at the face centre."""
+    n = pts.shape[0]
+    F = faces.shape[0]
+    e = np.concatenate([faces[:, [0, 1]], faces[:, [1, 2]], faces[:, [2, 0]]])
+    key = np.minimum(e[:, 0], e[:, 1]) * n + np.maximum(e[:, 0], e[:, 1])
+    ukey, inv = np.unique(key, return_inverse=True)
+    ea, eb = ukey // n, ukey % n                      # ea < eb
+    nE = ukey.shape[0]
+    near_a = _normalize(2.0 * pts[ea] + pts[eb])      # a third of the way from ea
+    near_b = _normalize(pts[ea] + 2.0 * pts[eb])      # a third of the way from eb
+    f0, f1, f2 = faces[:, 0], faces[:, 1], faces[:, 2]
+    cen = _normalize(pts[f0] + pts[f1] + pts[f2])
+    inv = inv.reshape(3, F)
+
+    def third(k, src):
+        """id of the point a third of the way from src along face edge k"""
+        ed = inv[k]
+        return np.where(src == ea[ed], n + ed, n + nE + ed)
+
+    a, b, c = f0, f1, f2
+    ab1, ab2 = third(0, a), third(0, b)               # edge a-b: near a, near b
+    bc1, bc2 = third(1, b), third(1, c)
+    ca1, ca2 = third(2, c), third(2, a)
+    g = n + 2 * nE + np.arange(F)
+    # lattice P(i, j) = a + i/3 (b - a) + j/3 (c - a): six upward, three downward triangles
+    newf = np.concatenate([
+        np.stack([a, ab1, ca2], 1), np.stack([ab1, ab2, g], 1), np.stack([ab2, b, bc1], 1),
+        np.stack([ca2, g, ca1], 1), np.stack([g, bc1, bc2], 1), np.stack([ca1, bc2, c], 1),
+        np.stack([ab1, g, ca2], 1), np.stack([ab2, bc1, g], 1), np.stack([g, bc2, ca1], 1),
+    ])
+    return np.concatenate([pts, near_a, near_b, cen]), newf
+
+
 def _hilbert_key(x, bits=20):
     """3-D Hilbert index (Skilling 2004, transpose form) of points in [-1,1]^3."""
     scale = (1 << bits) - 1
@@ -129,14 +170,17 @@ def _tri_area(a, b, c):
     return 2.0 * np.arctan2(num, den)
 
 
-def icosahedral_mesh(level, radius=EARTH_RADIUS, omega=OMEGA, reorder=True):
-    """Build the bisection-level ``level`` Voronoi mesh; return a dict of arrays.
+def icosahedral_mesh(level, radius=EARTH_RADIUS, omega=OMEGA, reorder=True, trisections=0):
+    """Build the Voronoi mesh of ``trisections`` trisections and ``level``
+    bisections of the icosahedron; return a dict of arrays.
 
     Index arrays are int32, geometry float64.  Positions are unit vectors;
     lengths (de, le) are in metres and areas in m^2 on a sphere of
     ``radius``.
     """
     pts, faces = _icosahedron()
+    for _ in range(trisections):
+        pts, faces = _trisect(pts, faces)
     for _ in range(level):
         pts, faces = _bisect(pts, faces)
     N = pts.shape[0]
@@ -239,7 +283,7 @@ def icosahedral_mesh(level, radius=EARTH_RADIUS, omega=OMEGA, reorder=True):
     fv = 2.0 * omega * xv[:, 2]
 
     return dict(
-        level=level, radius=radius, omega=omega,
+        level=level, trisections=trisections, radius=radius, omega=omega,
         nCells=N, nEdges=E, nVertices=nF,
         cells_on_edge=np.stack([c1, c2], 1).astype(np.int32),
         vertices_on_edge=np.stack([v1, v2], 1).astype(np.int32),

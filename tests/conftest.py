@@ -16,12 +16,13 @@ def pytest_configure(config):
 _MESHES = {}
 
 
-def get_mesh(level):
+def get_mesh(level, trisections=0):
     """Session cache of generated meshes (input generator output)."""
     from paper_2404_08849_amd.inputs.meshgen import icosahedral_mesh
-    if level not in _MESHES:
-        _MESHES[level] = icosahedral_mesh(level)
-    return _MESHES[level]
+    key = (level, trisections)
+    if key not in _MESHES:
+        _MESHES[key] = icosahedral_mesh(level, trisections=trisections)
+    return _MESHES[key]
 
 
 @pytest.fixture(scope="session")

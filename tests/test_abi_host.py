@@ -103,3 +103,10 @@ def test_relabelled_mesh_is_valid(mpdc, mesh_cache):
     mp, _, _, _ = relabel(mesh_cache(3))
     rc, msg, _ = _create(mpdc, mp)
     assert rc == 0, msg
+
+
+def test_trisected_mesh_is_valid(mpdc, mesh_cache):
+    # the B3-style grid (one trisection, then bisections) passes the library's
+    # validation and table derivation
+    rc, msg, _ = _create(mpdc, mesh_cache(1, 1))
+    assert rc == 0, msg

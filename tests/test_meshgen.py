@@ -1,9 +1,11 @@
 """Mesh input generator: counts, topology, orientation and areas (CPU).
 
 Pins: the cell counts of the paper's Table 1 (stored in
-``golden/table1_cell_counts.txt``), the closed forms N = 10*4^n + 2,
-E = 30*4^n, V = 20*4^n, Euler characteristic 2, exactly 12 pentagons,
-areas tiling the sphere, and the orientation conventions the operators rely on.
+``golden/table1_cell_counts.txt``; G9B3 through the trisection count), the
+closed forms N = 10 n^2 + 2, E = 30 n^2, V = 20 n^2 for n = 3^t 2^l segments
+per icosahedron edge (bisection and trisection grids), Euler characteristic
+2, exactly 12 pentagons, areas tiling the sphere, and the orientation
+conventions the operators rely on.
 """
 import os
 
@@ -32,12 +34,15 @@ def test_table1_counts_match_bisection_formula():
     # G9B3: one trisection and nine bisections split each icosahedron edge into
     # 3 * 2^9 segments, so N = 10 * (3 * 2^9)^2 + 2
     assert 10 * (3 * 2 ** 9) ** 2 + 2 == t["G9B3"]
+    assert mesh_counts(9, trisections=1)[0] == t["G9B3"]
 
 
-@pytest.mark.parametrize("level", [0, 1, 2, 3, 5])
-def test_counts_and_topology(mesh_cache, level):
-    m = mesh_cache(level)
-    N, E, V = mesh_counts(level)
+@pytest.mark.parametrize("level,tri", [(0, 0), (1, 0), (2, 0), (3, 0), (5, 0), (0, 1), (1, 1), (3, 1), (0, 2)])
+def test_counts_and_topology(mesh_cache, level, tri):
+    m = mesh_cache(level, tri)
+    N, E, V = mesh_counts(level, tri)
+    n = 3 ** tri * 2 ** level                      # segments per icosahedron edge
+    assert N == 10 * n * n + 2
     assert (m["nCells"], m["nEdges"], m["nVertices"]) == (N, E, V)
     assert N - E + V == 2
     deg = np.diff(m["eoc_offset"])
@@ -53,9 +58,9 @@ def test_generated_g6_matches_table1(mesh_cache):
     assert mesh_cache(6)["nCells"] == _table1()["G6"]
 
 
-@pytest.mark.parametrize("level", [2, 5])
-def test_areas_tile_sphere(mesh_cache, level):
-    m = mesh_cache(level)
+@pytest.mark.parametrize("level,tri", [(2, 0), (5, 0), (2, 1)])
+def test_areas_tile_sphere(mesh_cache, level, tri):
+    m = mesh_cache(level, tri)
     a = m["radius"]
     sphere = 4.0 * np.pi * a * a
     assert abs(m["areaCell"].sum() / sphere - 1.0) < 1e-13
@@ -67,9 +72,9 @@ def test_areas_tile_sphere(mesh_cache, level):
     assert np.allclose(ac, m["areaCell"], rtol=1e-14, atol=0)
 
 
-@pytest.mark.parametrize("level", [1, 4])
-def test_orientation_conventions(mesh_cache, level):
-    m = mesh_cache(level)
+@pytest.mark.parametrize("level,tri", [(1, 0), (4, 0), (1, 1)])
+def test_orientation_conventions(mesh_cache, level, tri):
+    m = mesh_cache(level, tri)
     xc, xv = m["xCell"], m["xVertex"]
     c1, c2 = m["cells_on_edge"].T
     v1, v2 = m["vertices_on_edge"].T

@@ -15,9 +15,10 @@ from oracle import OracleMesh, thomas, oracle_lib
 from paper_2404_08849_amd.inputs.initial import velocity_from_streamfunction
 
 
-@pytest.fixture(scope="module")
-def g3(mesh_cache):
-    m = mesh_cache(3)
+@pytest.fixture(scope="module", params=[(3, 0), (2, 1)], ids=["G3", "G2B3"])
+def g3(mesh_cache, request):
+    # a bisection grid and a trisection ("B3") grid of similar size
+    m = mesh_cache(*request.param)
     return m, OracleMesh(m)
 
 

@@ -160,7 +160,10 @@ __device__ __forceinline__ void theta_prev(const StageArgs &a, int c, long KM, l
 __host__ __device__ inline size_t col_lds_bytes(int model, int which, int cpb, int K, int M) {
     const size_t KM = (size_t)K * M;
     size_t b = 0;
-    if (which == KERNEL_CELL_A) b = cpb * KM * 8 + (model == MODEL_NDC ? cpb * (K + 1) * (size_t)M * 8 : 0);
+    // cell_a: D [cpb][KM], the NH interface mass flux [cpb][(K+1) M] and the
+    // second buffer of the column scan [cpb][KM]
+    if (which == KERNEL_CELL_A)
+        b = cpb * KM * 8 + (model == MODEL_NDC ? cpb * (K + 1) * (size_t)M * 8 : 0) + cpb * KM * 8;
     if (which == KERNEL_CELL_B && model != MODEL_SW)
         b = model == MODEL_NDC ? cpb * (10 * KM + (K + 1) * (size_t)M) * 8 : cpb * KM * 8;
     return coltab_round(b);
@@ -307,24 +310,10 @@ template <int L> __device__ __forceinline__ ColLane col_lane(const StageArgs &a,
     return c;
 }
 
-// Sequential sums over LDS with the loads issued four at a time (the adds
-// keep their order): sum_{q=q0}^{q1-1} p[q*stride], and the same downwards.
-__device__ __forceinline__ double lds_sum_up(const double *p, int stride, int q0, int q1) {
-    double s = 0.0;
-    int q = q0;
-    for (; q + 4 <= q1; q += 4) {
-        const double a0 = p[q * stride], a1 = p[(q + 1) * stride], a2 = p[(q + 2) * stride], a3 = p[(q + 3) * stride];
-        s += a0;
-        s += a1;
-        s += a2;
-        s += a3;
-    }
-    for (; q < q1; q++) s += p[q * stride];
-    return s;
-}
+// Sequential sum over LDS with the loads issued four at a time (the adds
+// keep their order): s0 + sum over q = q_hi, q_hi-1, ..., q_lo+1, in precision T.
 template <typename T>
 __device__ __forceinline__ T lds_sum_down(const double *p, int stride, int q_hi, int q_lo, T s0) {
-    // s0 + sum over q = q_hi, q_hi-1, ..., q_lo+1 (in that order), in precision T
     T s = s0;
     int q = q_hi;
     for (; q - 4 >= q_lo; q -= 4) {
@@ -495,28 +484,38 @@ k_cell_a(StageArgs a) {
             for (int j = 0; j < L; j++) sD[lc * KM + km0 + j] = D[j];
         }
         __syncthreads();
+        // The prefix sums over k of each column (and member) come from a
+        // parallel scan in LDS (Hillis-Steele, double buffered, ceil(log2 K)
+        // steps: after the step with distance d each entry holds the sum of the
+        // 2d entries ending at it), far fewer LDS reads than a sequential sum
+        // per lane.  The sums depend on k only, not on the launch shape.
+        const double *scan = sD;
+        {
+            double *src = sD, *dst = sD + a.cpb * KM + (MODEL == MODEL_NDC ? a.cpb * (K + 1) * M : 0);
+            for (int d = 1; d < K; d *= 2) {
+                if (cl.valid) {
+#pragma unroll
+                    for (int j = 0; j < L; j++) {
+                        const int o = lc * KM + v.k[j] * M + v.mm0 + (M1 ? 0 : j);
+                        const double lo = src[o - (v.k[j] >= d ? d * M : 0)];   // clamped: unused below d
+                        dst[o] = v.k[j] >= d ? src[o] + lo : src[o];
+                    }
+                }
+                __syncthreads();
+                double *tmp = src;
+                src = dst;
+                dst = tmp;
+            }
+            scan = src;
+        }
         double mdot_b[L];
         if (cl.valid) {
             const long K1M = (long)(K + 1) * M;
-            // M == 1: the L values are consecutive levels of one column, so the
-            // column sum is shared and each prefix extends the previous one
-            double tot = 0.0, pre = 0.0;
-            if constexpr (M1) {
-                tot = lds_sum_up(sD + lc * KM, 1, 0, K);
-                pre = lds_sum_up(sD + lc * KM, 1, 0, v.k0);
-            }
 #pragma unroll
             for (int j = 0; j < L; j++) {
                 const int mm = v.mm0 + (M1 ? 0 : j);
-                double dps, acc;
-                if constexpr (M1) {
-                    pre += sD[lc * KM + v.k[j]];
-                    dps = -tot;
-                    acc = pre;
-                } else {
-                    dps = -lds_sum_up(sD + lc * KM + mm, M, 0, K);
-                    acc = lds_sum_up(sD + lc * KM + mm, M, 0, v.k[j] + 1);
-                }
+                const double dps = -scan[lc * KM + (K - 1) * M + mm];
+                const double acc = scan[lc * KM + v.k[j] * M + mm];
                 mdot_b[j] = (v.k[j] == K - 1) ? 0.0 : -acc - sgb[j] * dps;
                 a.mdot[(long)i * K1M + (long)(v.k[j] + 1) * M + mm] = mdot_b[j];
                 if (v.k[j] == 0) {

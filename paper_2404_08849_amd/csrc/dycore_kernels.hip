@@ -165,7 +165,8 @@ __host__ __device__ inline size_t col_lds_bytes(int model, int which, int cpb, i
     if (which == KERNEL_CELL_A)
         b = cpb * KM * 8 + (model == MODEL_NDC ? cpb * (K + 1) * (size_t)M * 8 : 0) + cpb * KM * 8;
     if (which == KERNEL_CELL_B && model != MODEL_SW)
-        b = model == MODEL_NDC ? cpb * (10 * KM + (K + 1) * (size_t)M) * 8 : cpb * KM * 8;
+        // NDC: the column solve's arrays; HDC: alpha dpi, and for M > 1 the scan's second buffer
+        b = model == MODEL_NDC ? cpb * (10 * KM + (K + 1) * (size_t)M) * 8 : (M > 1 ? 2 : 1) * cpb * KM * 8;
     return coltab_round(b);
 }
 
@@ -310,8 +311,8 @@ template <int L> __device__ __forceinline__ ColLane col_lane(const StageArgs &a,
     return c;
 }
 
-// Sequential sum over LDS with the loads issued four at a time (the adds
-// keep their order): s0 + sum over q = q_hi, q_hi-1, ..., q_lo+1, in precision T.
+// Sequential sum over LDS with the loads issued four at a time (the adds keep
+// their order): s0 + sum over q = q_hi, q_hi-1, ..., q_lo+1, in precision T.
 template <typename T>
 __device__ __forceinline__ T lds_sum_down(const double *p, int stride, int q_hi, int q_lo, T s0) {
     T s = s0;
@@ -1059,11 +1060,16 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                     if (v.k[j] == 0) a.ps_o[(long)i * M + v.mm0 + (M1 ? 0 : j)] = ps_new[j];
             }
             __syncthreads();
-            if (cl.valid) {
-                // hydrostatic geopotential from the surface upwards (Eq. 8)
-                Pack<double, L> alp, php;
-                if constexpr (M1) {
-                    // consecutive levels: the deepest value's partial sum is extended upwards
+            // hydrostatic geopotential from the surface upwards (Eq. 8).  One
+            // member: a lane's L values are consecutive levels and the deepest
+            // one's sequential sum is extended upwards.  Several members: suffix
+            // sums over k of alpha dpi by a parallel scan in LDS (Hillis-Steele,
+            // double buffered; in the precision RP of the diagnostics), the same
+            // sums whatever the launch shape (measured faster for the ensemble,
+            // slower for one member at G6).
+            if constexpr (M1) {
+                if (cl.valid) {
+                    Pack<double, L> alp, php;
                     RP acc = lds_sum_down<RP>(sA + lc * KM, 1, K - 1, v.k[L - 1], (RP)phs);
 #pragma unroll
                     for (int j = L - 1; j >= 0; j--) {
@@ -1072,18 +1078,45 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                         php.v[j] = (RP)0.5 * (phit + acc);
                         acc = phit;
                     }
-                } else {
+                    stp<double, L>(a.alpha + (long)i * KM + km0, alp);
+                    stp<double, L>(a.phim + (long)i * KM + km0, php);
+                }
+            } else {
+                const double *usum;
+                {
+                    double *src = sA, *dst = sA + a.cpb * KM;
+                    for (int d = 1; d < K; d *= 2) {
+                        if (cl.valid) {
+#pragma unroll
+                            for (int j = 0; j < L; j++) {
+                                const int o = lc * KM + v.k[j] * M + v.mm0 + (M1 ? 0 : j);
+                                const bool in = v.k[j] + d < K;
+                                const double hi = src[o + (in ? d * M : 0)];   // clamped: unused at the bottom
+                                dst[o] = in ? (double)((RP)src[o] + (RP)hi) : src[o];
+                            }
+                        }
+                        __syncthreads();
+                        double *tmp = src;
+                        src = dst;
+                        dst = tmp;
+                    }
+                    usum = src;
+                }
+                if (cl.valid) {
+                    Pack<double, L> alp, php;
 #pragma unroll
                     for (int j = 0; j < L; j++) {
-                        const int mm = v.mm0 + j;
-                        const RP acc = lds_sum_down<RP>(sA + lc * KM + mm, M, K - 1, v.k[j], (RP)phs);
-                        const RP phit = acc + (RP)sA[lc * KM + v.k[j] * M + mm];
+                        const int o = lc * KM + v.k[j] * M + v.mm0 + (M1 ? 0 : j);
+                        const bool top = v.k[j] < K - 1;
+                        const RP below = (RP)usum[o + (top ? M : 0)];   // clamped: unused in the lowest layer
+                        const RP phit = (RP)phs + (RP)usum[o];           // top of the layer
+                        const RP phib = top ? (RP)phs + below : (RP)phs;  // bottom of the layer
                         alp.v[j] = al[j];
-                        php.v[j] = (RP)0.5 * (phit + acc);
+                        php.v[j] = (RP)0.5 * (phit + phib);
                     }
+                    stp<double, L>(a.alpha + (long)i * KM + km0, alp);
+                    stp<double, L>(a.phim + (long)i * KM + km0, php);
                 }
-                stp<double, L>(a.alpha + (long)i * KM + km0, alp);
-                stp<double, L>(a.phim + (long)i * KM + km0, php);
             }
         } else {
             // ---- implicit vertical acoustic solve of the column (FP64) ----

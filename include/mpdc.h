@@ -171,6 +171,7 @@ typedef struct {
     double min, max;      /* of the field named in mpdc_diagnostics                         */
     double l1, l2, linf;  /* area-weighted normalised errors vs the reference (if given)    */
     int64_t nonfinite;    /* NaN/Inf count over every prognostic field                      */
+    double cfl_max;       /* dycore: largest |u_e| dt / d_e (NaN if u holds one); tracer: 0    */
 } mpdc_diag;
 
 typedef struct mpdc_mesh mpdc_mesh;

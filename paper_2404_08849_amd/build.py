@@ -30,6 +30,10 @@ def build(verbose=False):
            # the launch shape (bitwise-reproducible across shapes and the autotuner)
            "-ffp-contract=off",
            "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+           # every change of floating-point kind is written out (the mixed-kind
+           # hazard of Section 2.2 (ii)): implicit float <-> double and
+           # integer -> float conversions are errors
+           "-Werror=double-promotion", "-Werror=implicit-float-conversion",
            "-x", "hip"] + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)

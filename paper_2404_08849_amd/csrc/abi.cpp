@@ -932,7 +932,7 @@ int mpdc_time_kernel(mpdc_state *st, int kernel_id, int nreps, void *stream, dou
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        *ms_avg = ms / nreps;
+        *ms_avg = (double)ms / nreps;
         return MPDC_OK;
     }
     StageArgs a = stage_args(st, 0);
@@ -948,13 +948,13 @@ int mpdc_time_kernel(mpdc_state *st, int kernel_id, int nreps, void *stream, dou
     HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    *ms_avg = ms / nreps;
+    *ms_avg = (double)ms / nreps;
     return MPDC_OK;
 }
 
 // Algorithmic bytes: every array a kernel must touch, read or written once.
 static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
-    const double N = st->N, E = st->E, V = st->V, K = st->K, M = st->M;
+    const double N = (double)st->N, E = (double)st->E, V = (double)st->V, K = st->K, M = st->M;
     const double KM = K * M, K1M = (K + 1) * M;
     const double r = (double)rsize(st->policy);
     const bool mix = st->policy != MPDC_POLICY_DBL;
@@ -1025,7 +1025,7 @@ static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
 // the tracer's vertical step, once per step: q and dpi in and out, the interface flux in
 static double vertical_bytes(const mpdc_state *st) {
     if (st->model != MPDC_MODEL_TRACER || !st->has_vflux) return 0;
-    const double N = st->N, K = st->K, T = st->T, r = (double)rsize(st->policy);
+    const double N = (double)st->N, K = st->K, T = st->T, r = (double)rsize(st->policy);
     return 2 * N * K * T * r + 2 * N * K * 8 + N * (K + 1) * 8;
 }
 
@@ -1082,7 +1082,7 @@ int mpdc_profile_steps(mpdc_state *st, int nsteps, void *stream, double *ms_tota
         for (size_t j = 0; j < kid.size(); j++) {
             float ms = 0;
             HIP_TRY(hipEventElapsedTime(&ms, ev[j], ev[j + 1]));
-            ms_total[kid[j]] += ms;
+            ms_total[kid[j]] += (double)ms;
             launches[kid[j]] += 1;
         }
         if (tr) st->parity = 1 - st->parity;
@@ -1159,7 +1159,7 @@ int mpdc_diagnostics(mpdc_state *st, int f, const void *ref_dev, mpdc_diag *out,
         HIP_TRY(launch_diag(a, kDiagBlocks, s));
         HIP_TRY(hipMemcpyAsync(part.data(), st->partial, part.size() * 8, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        r9[0] = 0; r9[1] = INFINITY; r9[2] = -INFINITY;
+        r9[0] = 0; r9[1] = (double)INFINITY; r9[2] = -(double)INFINITY;
         for (int v = 3; v < 9; v++) r9[v] = 0;
         for (int b = 0; b < kDiagBlocks; b++) {       // fixed order
             const double *p = &part[(size_t)b * 9];
@@ -1232,6 +1232,16 @@ int mpdc_diagnostics(mpdc_state *st, int f, const void *ref_dev, mpdc_diag *out,
             d.l2 = std::sqrt(r9[5] / r9[6]);
             d.linf = r9[7] / r9[8];
         }
+    }
+    // largest advective Courant number of the dycore's velocity
+    if (st->model != MPDC_MODEL_TRACER) {
+        std::vector<double> cp(kDiagBlocks);
+        HIP_TRY(launch_cfl(st->set[0].u, st->mesh->dev.e_dinv, st->E, st->K * st->M, st->cfg.dt, st->partial,
+                           kDiagBlocks, s));
+        HIP_TRY(hipMemcpyAsync(cp.data(), st->partial, cp.size() * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        d.cfl_max = 0.0;
+        for (double c : cp) d.cfl_max = (c > d.cfl_max || c != c) ? c : d.cfl_max;
     }
     // non-finite count over the prognostic fields
     {

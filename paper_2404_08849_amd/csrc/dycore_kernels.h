@@ -176,5 +176,7 @@ struct DiagArgs {
 hipError_t launch_diag(const DiagArgs &a, int nblocks, hipStream_t s);
 hipError_t launch_nonfinite(const double *x, const float *x32, long n, unsigned long long *partial, int nblocks,
                             hipStream_t s);
+hipError_t launch_cfl(const double *u, const double *dinv, long E, long inner, double dt, double *partial,
+                      int nblocks, hipStream_t s);
 
 }  // namespace mpdc

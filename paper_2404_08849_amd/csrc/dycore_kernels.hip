@@ -1074,8 +1074,8 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
 #pragma unroll
                     for (int j = L - 1; j >= 0; j--) {
                         const RP phit = acc + (RP)sA[lc * KM + v.k[j]];
-                        alp.v[j] = al[j];
-                        php.v[j] = (RP)0.5 * (phit + acc);
+                        alp.v[j] = (double)al[j];
+                        php.v[j] = (double)((RP)0.5 * (phit + acc));
                         acc = phit;
                     }
                     stp<double, L>(a.alpha + (long)i * KM + km0, alp);
@@ -1111,8 +1111,8 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                         const RP below = (RP)usum[o + (top ? M : 0)];   // clamped: unused in the lowest layer
                         const RP phit = (RP)phs + (RP)usum[o];           // top of the layer
                         const RP phib = top ? (RP)phs + below : (RP)phs;  // bottom of the layer
-                        alp.v[j] = al[j];
-                        php.v[j] = (RP)0.5 * (phit + phib);
+                        alp.v[j] = (double)al[j];
+                        php.v[j] = (double)((RP)0.5 * (phit + phib));
                     }
                     stp<double, L>(a.alpha + (long)i * KM + km0, alp);
                     stp<double, L>(a.phim + (long)i * KM + km0, php);

@@ -605,4 +605,32 @@ hipError_t launch_nonfinite(const double *x, const float *x32, long n, unsigned 
     return hipGetLastError();
 }
 
+// largest advective Courant number max |u_e| dt / d_e over the edge field
+// u [E][inner]; per-block maxima (a NaN anywhere gives a NaN maximum)
+__global__ void __launch_bounds__(kDiagThreads) k_cfl(const double *u, const double *dinv, long E, long inner,
+                                                      double dt, double *partial) {
+    __shared__ double s[kDiagThreads];
+    double c = 0.0;
+    for (long idx = (long)blockIdx.x * kDiagThreads + threadIdx.x; idx < E * inner; idx += (long)gridDim.x * kDiagThreads) {
+        const double v = fabs(u[idx]) * dt * dinv[idx / inner];
+        c = (v > c || v != v) ? v : c;
+    }
+    s[threadIdx.x] = c;
+    __syncthreads();
+    for (int h = kDiagThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            const double o = s[threadIdx.x + h];
+            if (o > s[threadIdx.x] || o != o) s[threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+}
+
+hipError_t launch_cfl(const double *u, const double *dinv, long E, long inner, double dt, double *partial,
+                      int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_cfl, dim3(nblocks), dim3(kDiagThreads), 0, s, u, dinv, E, inner, dt, partial);
+    return hipGetLastError();
+}
+
 }  // namespace mpdc

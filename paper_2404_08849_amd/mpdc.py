@@ -57,7 +57,7 @@ class Config(ctypes.Structure):
 class Diag(ctypes.Structure):
     _fields_ = [("mass", ctypes.c_double), ("mass_tracer", ctypes.c_double * 16), ("min", ctypes.c_double),
                 ("max", ctypes.c_double), ("l1", ctypes.c_double), ("l2", ctypes.c_double),
-                ("linf", ctypes.c_double), ("nonfinite", ctypes.c_int64)]
+                ("linf", ctypes.c_double), ("nonfinite", ctypes.c_int64), ("cfl_max", ctypes.c_double)]
 
 
 def _load():
@@ -235,7 +235,7 @@ class State:
         if rc != MPDC_OK and (check or rc != -5):
             _check(rc)
         return dict(mass=d.mass, mass_tracer=list(d.mass_tracer)[:max(self.T, 0)], min=d.min, max=d.max,
-                    l1=d.l1, l2=d.l2, linf=d.linf, nonfinite=d.nonfinite, rc=rc)
+                    l1=d.l1, l2=d.l2, linf=d.linf, nonfinite=d.nonfinite, cfl_max=d.cfl_max, rc=rc)
 
     def set_graph(self, enable):
         _check(lib.mpdc_set_graph(self.h, int(bool(enable))))

@@ -125,3 +125,28 @@ def test_error_paths(mpdc, mesh_cache):
     hdc.state_write(mpdc.FIELD_U, np.zeros((g.E, K, 1)))
     hdc.dycore_step(1)
     assert np.isfinite(hdc.state_read(mpdc.FIELD_PS)).all()
+
+
+def test_instability_is_flagged(mpdc, mesh_cache):
+    # a stable step reports finite fields and a Courant number below one; fifty
+    # times that step makes the run blow up, which the diagnostics flag (a
+    # Courant number above one, or MPDC_E_NUMERIC once values are no longer finite)
+    m = mesh_cache(3)
+    K = 6
+    s = ic.hdc_jet(m, K, seed=2000)
+    g = mpdc.Mesh(m)
+    for dt in (900.0, 50 * 900.0):
+        st2 = mpdc.State(g, mpdc.MODEL_HDC, mpdc.POLICY_MIX, K=K, dt=dt, sigma=ic.sigma_interfaces(K))
+        st2.state_write(mpdc.FIELD_PS, s["ps"][:, None])
+        st2.state_write(mpdc.FIELD_THETA, s["Theta"][:, :, None])
+        st2.state_write(mpdc.FIELD_U, s["u"][:, :, None])
+        st2.dycore_step(40)
+        d = st2.diagnostics(mpdc.FIELD_PS, check=False)
+        _say("hdc G3x%d MIX dt %.0f s, 40 steps: rc %d nonfinite %d cfl_max %.3g" % (K, dt, d["rc"], d["nonfinite"],
+                                                                                d["cfl_max"]))
+        if dt == 900.0:
+            assert d["rc"] == 0 and d["nonfinite"] == 0 and 0.0 < d["cfl_max"] < 1.0
+        else:
+            assert d["rc"] == -5 or d["cfl_max"] > 1.0
+            if d["rc"] == -5:
+                assert d["nonfinite"] > 0

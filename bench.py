@@ -435,8 +435,8 @@ def coupled_main(args, torch, mpdc):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the design for sharding members and subdomains is in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(ensemble members and subdomains would be sharded one per GPU)", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2404_08849_amd.mpdc as mpdc

@@ -13,8 +13,9 @@ resident in HBM; the all-FP64 rate, the mixed/FP64 speedup, the accuracy gate
 20 steps), the roofline of the dominant kernel (algorithmic bytes / HIP-event
 duration) and the FP64 oracle timed on the host cores.
 
-Other workloads (--workload): sw-g5, hdc-g6 (default), tracer-g8, ndc-g8,
-ens-g7 (16 members), hdc-g9.
+Other workloads (--workload): sw-g5, hdc-g6 (default), tracer-g8,
+tracer3d-g8 (with the vertical step), coupled-g6 (dycore, flux hand-over and
+tracer step), ndc-g8, ens-g7 (16 members), hdc-g9.
 """
 import argparse
 import json

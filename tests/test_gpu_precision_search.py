@@ -3,7 +3,9 @@
 * the relative-vorticity diagnostic (MPDC_FIELD_VORT) equals the oracle's
   curl of the same velocity, and its area-weighted norms against a reference
   equal the oracle's norms with the dual-cell areas;
-* E of a run against itself is zero; the search accepts MIX at the paper's
+* E of a run against itself is zero; an FP64 run perturbed by the FP32
+  unit roundoff departs further than one perturbed by 1e-14; the search
+  accepts MIX at the paper's
   alpha = 0.05 and goes on to the reductions built on it; with an alpha below
   MIX's error it rejects MIX and skips what builds on it;
 * on the G6 jet over 4 days the search keeps the paper's split and rejects
@@ -62,16 +64,18 @@ def test_vorticity_matches_oracle(mpdc, mesh_cache):
 def test_search_accepts_and_rejects(mpdc):
     from paper_2404_08849_amd import precision_search as ps
     trials, accepted = ps.search(level=4, K=10, days=2.0, alpha=0.05, log=_say)
-    assert [t["policy"] for t in trials] == ["DBL+1e-14", "MIX", "MIX_F32_DIV", "MIX_PGF32", "SGL"]
-    spread, cand = trials[0], trials[1:]
+    assert [t["policy"] for t in trials] == ["DBL+1e-14", "DBL+6e-8", "MIX", "MIX_F32_DIV", "MIX_PGF32", "SGL"]
+    spread, spread32, cand = trials[0], trials[1], trials[2:]
     assert spread["spread"] and spread["E"] > 0.0
+    # an FP32-sized initial perturbation moves the run more than a 1e-14 one
+    assert spread32["spread"] and spread32["E"] > 100.0 * spread["E"]
     assert cand[0]["accepted"] and "MIX" in accepted
     assert all(not t.get("skipped") for t in cand)
     assert 0.0 < cand[0]["E"] < 0.05
     # alpha below MIX's own error: MIX is rejected and the reductions built on it are skipped
     trials2, accepted2 = ps.search(level=4, K=10, days=2.0, alpha=0.1 * cand[0]["E"], log=_say)
-    assert not trials2[1]["accepted"] and accepted2 == ["DBL"]
-    assert all(t.get("skipped") for t in trials2[2:])
+    assert not trials2[2]["accepted"] and accepted2 == ["DBL"]
+    assert all(t.get("skipped") for t in trials2[3:])
 
 
 def test_error_measure_of_a_run_against_itself_is_zero(mpdc, mesh_cache):

@@ -10,7 +10,8 @@
   MIX's error it rejects MIX and skips what builds on it;
 * on the G6 jet over 4 days the search keeps the paper's split and rejects
   the FP32 pressure-gradient term: the paper's finding that this term must
-  stay in FP64, reproduced at small scale.
+  stay in FP64, reproduced at small scale; the split's error is that of an
+  FP64 run whose initial state carries an FP32-sized perturbation.
 """
 import numpy as np
 import pytest
@@ -102,3 +103,9 @@ def test_search_keeps_fp64_pressure_gradient(mpdc):
     assert not E["MIX_PGF32"]["accepted"] and not E["SGL"]["accepted"]
     assert E["MIX_PGF32"]["E"] > 10.0 * E["MIX"]["E"] and E["SGL"]["E"] > 10.0 * E["MIX"]["E"]
     assert accepted == ["DBL", "MIX", "MIX_F32_DIV"]
+    # the split moves the run as much as an FP32-sized perturbation of the
+    # initial state does (measured 9.2e-3 against 8.6e-3); the FP32 pressure
+    # gradient and SGL move it far more
+    ref32 = E["DBL+6e-8"]["E"]
+    assert 0.5 * ref32 < E["MIX"]["E"] < 2.0 * ref32
+    assert E["MIX_PGF32"]["E"] > 10.0 * ref32 and E["SGL"]["E"] > 10.0 * ref32

@@ -94,10 +94,13 @@ def summarize(d, out):
         commands = fh.read().strip()
     rf = bench["roofline"]
     kernel = rf["kernel"]
-    names = ["k_cell_a", "k_vertex", "k_cell_b", "k_edge"]
-    if bench["config"]["tracers"]:
-        names = ["k_tr_low", "k_tr_limit", "k_tr_update"]
-    vpl, group = bench["launch_shapes"]["mix"][names.index(kernel)]
+    dycore = ["k_cell_a", "k_vertex", "k_cell_b", "k_edge"]
+    tracer = ["k_tr_low", "k_tr_limit", "k_tr_update"]
+    names = tracer if kernel in tracer else dycore
+    shapes = bench["launch_shapes"]["mix"]
+    if isinstance(shapes, dict):   # coupled runs: shapes per model
+        shapes = shapes["tracer" if kernel in tracer else "dycore"]
+    vpl, group = shapes[names.index(kernel)]
     inst = kernel_instance(kernel, "float", vpl)
 
     stats = _csv(os.path.join(d, "trace", "**", "*kernel_stats.csv"))

@@ -75,7 +75,8 @@ def parse():
                    help="only run a plain device copy of this many MiB (HBM counter calibration)")
     p.add_argument("--shapes", default=None, metavar="JSON",
                    help='fixed launch shapes instead of autotuning, e.g. {"mix": [[2,16],[2,256],[2,16],[2,512]], '
-                        '"dbl": [...]}: (values per lane, cells or threads per work-group) per kernel')
+                        '"dbl": [...]}: (values per lane, cells or threads per work-group) per kernel; '
+                        'for coupled-g6 each policy holds {"dycore": [...], "tracer": [...]}')
     return p.parse_args()
 
 
@@ -291,9 +292,11 @@ def copy_calibration(torch, mib):
     print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 3}), flush=True)
 
 
-def coupled_states(torch, mpdc, g, mesh, w, pol, stream, autotune):
+def coupled_states(torch, mpdc, g, mesh, w, pol, stream, autotune, shapes=None):
     """Dycore (accumulating its mass fluxes) and tracer states of the coupled
-    workload; one coupling round is run so the tracer has its fluxes."""
+    workload; one coupling round is run so the tracer has its fluxes.
+    shapes, if given ({"dycore": [[values per lane, group], ...], "tracer":
+    [...]}), fixes the launch shapes instead of autotuning them."""
     from paper_2404_08849_amd.inputs import initial as ic
     K, T, n = w["K"], w["T"], w["nsub"]
     s = ic.hdc_jet(mesh, K, seed=2000)
@@ -307,12 +310,17 @@ def coupled_states(torch, mpdc, g, mesh, w, pol, stream, autotune):
     trs = mpdc.State(g, mpdc.MODEL_TRACER, pol, K=K, T=T, dt=n * w["dt"])
     trs.state_write(mpdc.FIELD_TR_DPI, dpi0)
     trs.state_write(mpdc.FIELD_TR_Q, tr["q"])
+    if shapes:
+        for k, (v, grp) in enumerate(shapes["dycore"]):
+            dy.set_kernel_launch(k, v, grp)
+        for k, (v, grp) in enumerate(shapes["tracer"]):
+            trs.set_kernel_launch(k, v, grp)
     with torch.cuda.stream(stream):
-        if autotune:
+        if autotune and not shapes:
             dy.autotune(stream=stream)
         dy.dycore_step(n, stream=stream)
         trs.couple(dy, stream=stream)
-        if autotune:
+        if autotune and not shapes:
             trs.autotune(stream=stream)
         trs.tracer_step(1, stream=stream)
         torch.cuda.synchronize()
@@ -337,10 +345,12 @@ def coupled_main(args, torch, mpdc):
     stream = torch.cuda.Stream()
     N, K, T, n = mesh["nCells"], w["K"], w["T"], w["nsub"]
     res = {}
+    fixed = json.loads(args.shapes) if args.shapes else {}
     copy_gbs = copy_ceiling(torch, stream)
     for name in ("MIX", "DBL"):
         pol = getattr(mpdc, "POLICY_" + name)
-        dy, trs, s, tr, dpi0 = coupled_states(torch, mpdc, g, mesh, w, pol, stream, not args.no_autotune)
+        dy, trs, s, tr, dpi0 = coupled_states(torch, mpdc, g, mesh, w, pol, stream, not args.no_autotune,
+                                              fixed.get(name.lower()))
         with torch.cuda.stream(stream):
             for _ in range(args.warmup):
                 coupled_step(dy, trs, n, stream)

@@ -317,6 +317,15 @@ int mpdc_autotune(mpdc_state *st, void *stream, int *cells_per_block, int *flat_
 double mpdc_kernel_bytes(const mpdc_state *st, int kernel_id);
 double mpdc_step_bytes(const mpdc_state *st);
 
+/* Algorithmic HBM bytes of one launch of a kernel class in RK stage `stage`
+ * (0, 1 or 2; the tracer's vertical step: its once-per-step figure for any
+ * stage).  Stages differ where one reads or writes arrays the others do not:
+ * the first reads the step-start state once for both roles, and the mixed
+ * policies that read only FP32 shadows (MIX, MIX_F32_DIV, MIX_PGF32, SGL)
+ * store the FP64 u and Theta in the last stage only.  mpdc_time_kernel times
+ * the launch of stage 0.  Returns 0 for a bad id or stage. */
+double mpdc_stage_kernel_bytes(const mpdc_state *st, int kernel_id, int stage);
+
 void mpdc_state_destroy(mpdc_state *st);
 
 const char *mpdc_strerror(int code);

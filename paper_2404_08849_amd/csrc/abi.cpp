@@ -262,6 +262,17 @@ int cpb_of(const mpdc_state *st, int k) {
     return cpb;
 }
 
+// Whether stage s stores its FP64 u and Theta.  The last stage's output is
+// the new state.  In the mixed policies whose kernels read only the FP32
+// shadows of a stage's u and Theta (MIX, MIX_F32_DIV, MIX_PGF32, SGL), the
+// FP64 values of the first two stages are never read, so only their shadows
+// are stored; the all-FP64 policy and the variants that read the FP64 stage
+// state (MIX_BOX, MIX_DBL_MASS) store every stage.
+bool stage_stores_fp64(const mpdc_state *st, int s) {
+    return s == 2 || st->policy == MPDC_POLICY_DBL || st->policy == MPDC_POLICY_MIX_BOX ||
+           st->policy == MPDC_POLICY_MIX_DBL_MASS;
+}
+
 StageArgs stage_args(const mpdc_state *st, int s) {
     StageArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -291,6 +302,7 @@ StageArgs stage_args(const mpdc_state *st, int s) {
     a.u32_s = in.u32; a.th32_s = in.th32;
     a.ps_o = out.ps; a.Th_o = out.Th; a.u_o = out.u; a.w_o = out.w; a.phi_o = out.phi;
     a.u32_o = out.u32; a.th32_o = out.th32;
+    a.store64 = stage_stores_fp64(st, s) ? 1 : 0;
     a.b = st->b;
     a.phis = st->phis;
     a.dps = st->dps;
@@ -961,6 +973,7 @@ static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
     const bool box = st->policy == MPDC_POLICY_MIX_BOX;
     const bool u64 = box || st->policy == MPDC_POLICY_MIX_DBL_MASS;   // cell_a reads the FP64 velocity
     const bool first = (stage == 0);
+    const bool st64 = st->model != MPDC_MODEL_TRACER && stage_stores_fp64(st, stage);   // FP64 u, Theta out
     if (st->model == MPDC_MODEL_TRACER) {
         const double T = st->T, nq = N * K * T;
         const double tabc = N * kCellSlots * (4 + 4 + r);              // c_edge, c_nbr, c_div
@@ -1002,7 +1015,7 @@ static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
         // theta transport and update: e_cell, hdir, d2, theta, hth, mdot, dps, Th_n, ps_n
         b += E * 8 + E * 6 * r + E * r + th_s + 3 * N * KM * r + N * K1M * 8 + ps;
         b += (first && !mix) ? 0 : N * KM * 8 + ps;       // Th_n, ps_n (stage 1 FP64: same arrays as _s)
-        b += N * KM * 8 + ps + 2 * N * KM * 8 + (mix ? N * KM * 4 : 0);   // Th_o, ps_o, alpha, phim, th32_o
+        b += (st64 ? N * KM * 8 : 0) + ps + 2 * N * KM * 8 + (mix ? N * KM * 4 : 0);   // Th_o, ps_o, alpha, phim, th32_o
         if (!nh) b += N * 8;                               // surface geopotential
         if (nh) b += 2 * N * K1M * 8 /*w*, phi* */ + 2 * N * K1M * 8 /*w_o, phi_o*/ + 2 * N * KM * 8 /*pm, mum*/;
         return b;
@@ -1011,7 +1024,7 @@ static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
         // e_cell, e_dinv, qh, u_n -> u_o (+u32_o)
         double b = E * (2 * 4 + 8) + 2 * E * KM * r;
         b += (first && !mix) ? 0 : E * KM * 8;             // u_n
-        b += E * KM * 8 + (mix ? E * KM * 4 : 0);           // u_o, u32_o
+        b += (st64 ? E * KM * 8 : 0) + (mix ? E * KM * 4 : 0);   // u_o, u32_o
         if (sw) return b + ps /*h_o*/ + N * 8 /*b*/;
         b += u_s + ps + N * K1M * 8 + 2 * N * KM * 8 + ps; // u_s, ps_s, mdot, alpha, phim, ps_o
         if (box) b += N * KM * 8 - u_s + (first ? 0 : E * KM * 8);   // FP64 K; FP64 u_s (= u_n at stage 1)
@@ -1027,6 +1040,12 @@ static double vertical_bytes(const mpdc_state *st) {
     if (st->model != MPDC_MODEL_TRACER || !st->has_vflux) return 0;
     const double N = (double)st->N, K = st->K, T = st->T, r = (double)rsize(st->policy);
     return 2 * N * K * T * r + 2 * N * K * 8 + N * (K + 1) * 8;
+}
+
+double mpdc_stage_kernel_bytes(const mpdc_state *st, int id, int stage) {
+    if (!st || stage < 0 || stage > 2) return 0;
+    if (st->model == MPDC_MODEL_TRACER && id == 3) return vertical_bytes(st);
+    return kernel_bytes_stage(st, id, stage);
 }
 
 double mpdc_kernel_bytes(const mpdc_state *st, int id) {

@@ -53,6 +53,7 @@ struct StageArgs {
     int cpb;          // cells per work-group of the column kernels
     int flat_block;   // threads per work-group of the flat kernels
     int vpl;          // (k, m) values per lane of this launch (1, 2; flat kernels also 4)
+    int store64;      // 1: store the FP64 u and Theta of this stage (0: only their FP32 shadows)
     double dts, grav, rd, cp, p0, ptop, kappa, gamma, inv_p0;
     const double *dsig;  // [K]
     const double *sig;   // [K+1]

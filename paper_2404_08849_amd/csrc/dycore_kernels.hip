@@ -1053,7 +1053,7 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                     }
                     th32.v[j] = (float)th;
                 }
-                stp<double, L>(a.Th_o + (long)i * KM + km0, tho);
+                if (a.store64) stp<double, L>(a.Th_o + (long)i * KM + km0, tho);
                 if (a.th32_o) stp<float, L>(a.th32_o + (long)i * KM + km0, th32);
 #pragma unroll
                 for (int j = 0; j < L; j++)
@@ -1151,7 +1151,7 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                     sP[base + km0 + j] = p;
                     sC[base + km0 + j] = a.gamma * a.grav * a.dts * p / dphi;
                 }
-                stp<double, L>(a.Th_o + (long)i * KM + km0, tho);
+                if (a.store64) stp<double, L>(a.Th_o + (long)i * KM + km0, tho);
                 if (a.th32_o) stp<float, L>(a.th32_o + (long)i * KM + km0, th32);
 #pragma unroll
                 for (int j = 0; j < L; j++)
@@ -1446,7 +1446,7 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
         else uo.v[j] = un.v[j] + a.dts * ((double)adv[j] + pgf[j]);
         u32.v[j] = (float)uo.v[j];
     }
-    stp<double, L>(a.u_o + base, uo);
+    if (a.store64) stp<double, L>(a.u_o + base, uo);
     if (a.u32_o) stp<float, L>(a.u32_o + base, u32);
 }
 

@@ -87,6 +87,7 @@ def _load():
                                                   ctypes.POINTER(ctypes.c_int)]),
         "mpdc_time_kernel": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double)]),
         "mpdc_kernel_bytes": (ctypes.c_double, [_vp, ctypes.c_int]),
+        "mpdc_stage_kernel_bytes": (ctypes.c_double, [_vp, ctypes.c_int, ctypes.c_int]),
         "mpdc_profile_steps": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_int)]),
         "mpdc_autotune": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
@@ -270,6 +271,9 @@ class State:
 
     def kernel_bytes(self, kernel_id):
         return lib.mpdc_kernel_bytes(self.h, kernel_id)
+
+    def stage_kernel_bytes(self, kernel_id, stage):
+        return lib.mpdc_stage_kernel_bytes(self.h, kernel_id, stage)
 
     def step_bytes(self):
         return lib.mpdc_step_bytes(self.h)

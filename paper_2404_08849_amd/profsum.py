@@ -154,7 +154,8 @@ def summarize(d, out):
     in_step = rf.get("ms_per_launch_in_step")
     L.append("Dominant kernel of the mixed step: `%s` (values per lane %d, group %d).  "
              "Profiler average %.2f us over %d dispatches (trace: min %.2f, max %.2f us); the benchmark's "
-             "HIP-event average in the same run: %.2f us over back-to-back launches (used for `achieved`)%s."
+             "HIP-event average in the same run: %.2f us over back-to-back launches of the first RK stage "
+             "(used for `achieved`)%s."
              % (_short(stat[0]["Name"]), vpl, group, avg_ms * 1e3, len(durs), min(durs) * 1e3, max(durs) * 1e3,
                 rf["ms_per_launch"] * 1e3,
                 ", %.2f us between the launches of whole steps (event and launch overhead included)"
@@ -183,10 +184,12 @@ def summarize(d, out):
         L.append("| %s | %.0f | %.0f | %.2f | %.2f |" % (k, fm, wm, fm * 1024 / f_factor / 1e6,
                                                         wm * 1024 / w_factor / 1e6))
     L.append("")
-    L.append("Dominant kernel: algorithmic bytes per launch %.3f MB; measured HBM traffic per launch %.3f MB "
+    alg = rf.get("bytes_per_launch_mean", rf["bytes_per_launch"])   # the dispatches span all RK stages
+    L.append("Dominant kernel: algorithmic bytes per launch %.3f MB (mean over the RK stages; %.3f MB in the "
+             "first stage, the one timed back to back); measured HBM traffic per launch %.3f MB "
              "(read %.3f + write %.3f), ratio %.2f."
-             % (rf["bytes_per_launch"] / 1e6, traffic / 1e6, fetch_b / 1e6, write_b / 1e6,
-                traffic / rf["bytes_per_launch"]))
+             % (alg / 1e6, rf["bytes_per_launch"] / 1e6, traffic / 1e6, fetch_b / 1e6, write_b / 1e6,
+                traffic / alg))
     L.append("")
     L.append("```record")
     L.append("workload: %s" % bench["config"]["workload"])

@@ -150,3 +150,30 @@ def test_instability_is_flagged(mpdc, mesh_cache):
             assert d["rc"] == -5 or d["cfl_max"] > 1.0
             if d["rc"] == -5:
                 assert d["nonfinite"] > 0
+
+
+def test_stage_byte_counts(mpdc, mesh_cache):
+    # the byte model per RK stage: its mean is mpdc_kernel_bytes; the mixed
+    # policy stores the FP64 u (edge kernel) and Theta (second cell kernel) in
+    # the last stage only, the all-FP64 policy in every stage
+    m = mesh_cache(3)
+    K = 6
+    g = mpdc.Mesh(m)
+    E, N = g.E, g.N
+    for name in ("DBL", "MIX", "MIX_BOX"):
+        st = mpdc.State(g, mpdc.MODEL_HDC, getattr(mpdc, "POLICY_" + name), K=K, dt=600.0,
+                        sigma=ic.sigma_interfaces(K))
+        for kid in range(4):
+            b = [st.stage_kernel_bytes(kid, s) for s in range(3)]
+            assert all(x > 0 for x in b)
+            assert abs(sum(b) / 3.0 - st.kernel_bytes(kid)) <= 1e-9 * st.kernel_bytes(kid)
+        assert st.stage_kernel_bytes(0, 3) == 0.0 and st.stage_kernel_bytes(0, -1) == 0.0
+        skip = {3: E * K * 8, 2: N * K * 8}
+        for kid in (0, 1, 2, 3):
+            d = st.stage_kernel_bytes(kid, 2) - st.stage_kernel_bytes(kid, 1)
+            if name == "MIX" and kid in skip:
+                assert d == skip[kid], (name, kid, d)
+            else:
+                assert d == 0.0, (name, kid, d)
+        assert abs(st.step_bytes() - sum(st.stage_kernel_bytes(k, s) for k in range(4) for s in range(3))) \
+            <= 1e-9 * st.step_bytes()

@@ -323,7 +323,7 @@ double mpdc_step_bytes(const mpdc_state *st);
  * the first reads the step-start state once for both roles, and the mixed
  * policies that read only FP32 shadows (MIX, MIX_F32_DIV, MIX_PGF32, SGL)
  * store the FP64 u and Theta in the last stage only.  mpdc_time_kernel times
- * the launch of stage 0.  Returns 0 for a bad id or stage. */
+ * the first stage's launch (stage = 0 here).  Returns 0 for a bad id or stage. */
 double mpdc_stage_kernel_bytes(const mpdc_state *st, int kernel_id, int stage);
 
 void mpdc_state_destroy(mpdc_state *st);

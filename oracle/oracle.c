@@ -777,8 +777,8 @@ static double iface_mass(const double *dpi_col, int K, int k)
  * bottom), m_k the layer mean of the interface mass fluxes; missing layers
  * contribute nothing.
  */
-static void iface_advection(const or_mesh *h, int K, const double *F, const double *dpi, const double *mdot,
-                            const double *X, double *out)
+void or_iface_advection(const or_mesh *h, int K, const double *F, const double *dpi, const double *mdot,
+                        const double *X, double *out)
 {
     const or_mesh_in *m = &h->m;
     const int K1 = K + 1;
@@ -927,8 +927,8 @@ static void ndc_run(const or_mesh *h, const or_params *p, double *ps, double *Th
             for (size_t x = 0; x < NK; x++) theta[x] = Theta[x] / dpi[x];
             theta_tendency(h, p, F, theta, mdot, dTh, we, wc);
             momentum_adv(h, p, u, F, dpi, mdot, adv, ke, zeta, dpiv, qv, Q);
-            iface_advection(h, K, F, dpi, mdot, w, aw);
-            iface_advection(h, K, F, dpi, mdot, phi, aphi);
+            or_iface_advection(h, K, F, dpi, mdot, w, aw);
+            or_iface_advection(h, K, F, dpi, mdot, phi, aphi);
             if (s == 2 && Facc) {
                 accumulate(EK, F, Facc);
                 accumulate(NK1, mdot, Macc);

@@ -76,6 +76,12 @@ void or_edge_value3(const or_mesh *m, int K, const double *q, const double *F, d
 void or_edge_value3_formula(int n, const double *qc1, const double *qc2,
                             const double *h1, const double *h2, const double *d,
                             const double *F, double *out);
+/* Advection V.grad X + eta_dot dX/deta of an interface field X [N][K+1]
+ * (the w and phi equations, Eqs. 6-7) by the layer mass flux F [E][K] and
+ * the interface vertical mass flux mdot [N][K+1], with layer masses dpi
+ * [N][K]; out [N][K+1]. */
+void or_iface_advection(const or_mesh *m, int K, const double *F, const double *dpi, const double *mdot,
+                        const double *X, double *out);
 int or_thomas(int n, const double *sub, const double *diag, const double *sup,
               const double *rhs, double *x);
 

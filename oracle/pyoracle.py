@@ -53,6 +53,7 @@ def oracle_lib():
         lib.or_edge_value3.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp]
         lib.or_edge_value3_formula.argtypes = [ctypes.c_int] + [_dp] * 7
         lib.or_thomas.argtypes = [ctypes.c_int] + [_dp] * 5
+        lib.or_iface_advection.argtypes = [ctypes.c_void_p, ctypes.c_int] + [_dp] * 5
         lib.or_table_sizes.argtypes = [ctypes.c_void_p, _ip]
         lib.or_get_cells_on_cell.argtypes = [ctypes.c_void_p, _ip]
         lib.or_get_edge_sign.argtypes = [ctypes.c_void_p, _dp]
@@ -188,6 +189,17 @@ class OracleMesh:
         out = np.empty((self.E, K))
         self.lib.or_edge_value3(self.h, K, _d(q), _d(F), _d(out))
         return out.squeeze()
+
+    def iface_advection(self, F, dpi, mdot, X):
+        """V.grad X + eta_dot dX/deta of the interface field X [N][K+1] (Eqs. 6-7)
+        for layer mass fluxes F [E][K], layer masses dpi [N][K] and interface
+        vertical mass fluxes mdot [N][K+1]; returns [N][K+1]."""
+        F, dpi, mdot, X = [np.ascontiguousarray(a, dtype=np.float64) for a in (F, dpi, mdot, X)]
+        K = dpi.shape[1]
+        assert F.shape == (self.E, K) and mdot.shape == (self.N, K + 1) and X.shape == (self.N, K + 1)
+        out = np.empty((self.N, K + 1))
+        self.lib.or_iface_advection(self.h, K, _d(F), _d(dpi), _d(mdot), _d(X), _d(out))
+        return out
 
     # ---- models (copies; inputs untouched) ----
     def params(self, K, dt, T=0, fct=1, sigma=None, phis=None):

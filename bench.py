@@ -1,21 +1,27 @@
 """Benchmark of the mixed-precision icosahedral dycore on one MI355X.
 
-Default workload: the hydrostatic dry dycore (continuity, theta_m transport,
-momentum with TRiSK Coriolis and FP64 pressure gradient; RK3 forward-backward)
-on the G6 icosahedral mesh (40,962 cells) x 30 sigma levels, isothermal jet
-plus a seeded wind perturbation, dt = 300 s -- run in the mixed policy (the
-paper's term split) and in all-FP64.  One "step" is one full RK3 dycore step
-(three stages, four kernels each) replayed from a HIP graph.
+Default workload: the batched ensemble of the hydrostatic dry dycore
+(continuity, theta_m transport, momentum with TRiSK Coriolis and FP64
+pressure gradient; RK3 forward-backward): 16 members on the G7 icosahedral
+mesh (163,842 cells) x 30 sigma levels, isothermal jet plus a seeded wind
+perturbation with N(0, 0.1 m/s) member perturbations, dt = 150 s -- run in
+the mixed policy (the paper's term split) and in all-FP64.  One "step" is
+one full RK3 dycore step of all members (three stages, four kernels each,
+one launch per operator for all members) replayed from a HIP graph.
 
 Prints ONE JSON line: value = mixed-policy cell-level-steps/s with inputs
-resident in HBM; the all-FP64 rate, the mixed/FP64 speedup, the accuracy gate
-(mixed vs FP64 oracle, normalised L2 of surface pressure after the workload's
-20 steps), the roofline of the dominant kernel (algorithmic bytes / HIP-event
-duration) and the FP64 oracle timed on the host cores.
+resident in HBM (cells x levels x members per second); the all-FP64 rate,
+the mixed/FP64 speedup, the accuracy gate (mixed vs all-FP64 after the
+workload's steps, and both against the FP64 oracle's stored 10-step
+results), the roofline of the dominant kernel (algorithmic bytes / HIP-event
+duration, against the 8 TB/s peak and against the library's own streaming
+kernels), the median of five further timed repetitions, a secondary line for
+the cache-resident G6 workload, and the FP64 oracle timed on the host cores
+(N threads and 1 thread).
 
-Other workloads (--workload): sw-g5, hdc-g6 (default), tracer-g8,
-tracer3d-g8 (with the vertical step), coupled-g6 (dycore, flux hand-over and
-tracer step), ndc-g8, ens-g7 (16 members), hdc-g9.
+Other workloads (--workload): sw-g5, hdc-g6, tracer-g8, tracer3d-g8 (with the
+vertical step), coupled-g6 (dycore, flux hand-over and tracer step), ndc-g8,
+ens-g7 (default), hdc-g9.
 """
 import argparse
 import json
@@ -29,6 +35,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# MI355X last-level (MALL / Infinity Cache) capacity: a launch whose
+# algorithmic bytes fit here is cache-resident, not HBM-bound
+MALL_BYTES = 256 * 2 ** 20
+# the workloads whose FP64 oracle results after 10 steps are stored (sampled)
+STORED_REFS = {"ens-g7": "ens_g7x30x16", "ndc-g8": "ndc_g8x60", "tracer-g8": "tracer_g8x30x8",
+               "hdc-g9": "hdc_g9x30"}
 KERNEL_NAMES = {
     "dycore": ["k_cell_a", "k_vertex", "k_cell_b", "k_edge"],
     "tracer": ["k_tr_low", "k_tr_limit", "k_tr_update", "k_tr_vert"],
@@ -60,9 +72,11 @@ WORKLOADS = {
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--steps", type=int, default=100)
     p.add_argument("--warmup", type=int, default=10)
-    p.add_argument("--workload", default="hdc-g6", choices=sorted(WORKLOADS))
+    p.add_argument("--workload", default="ens-g7", choices=sorted(WORKLOADS))
+    p.add_argument("--no-secondary", action="store_true", help="skip the cache-resident G6 secondary line")
+    p.add_argument("--repeats", type=int, default=5, help="further timed repetitions of --steps steps (median)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-dbl", action="store_true", help="skip the all-FP64 timing")
     p.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
@@ -266,23 +280,23 @@ def recorded_traffic(workload, kernel, shape, digest):
     return float(rec["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT) + note
 
 
-def copy_ceiling(torch, stream, mib=2048, reps=10):
-    """Streaming-copy ceiling of the device: GB/s (bytes read + written) of a
-    plain device-to-device copy of mib MiB, HIP events on the stream."""
-    n = mib * (1 << 20) // 4
+def stream_ceilings(torch, mpdc, stream, mib=2048, reps=10):
+    """Bandwidth of the library's hand-written streaming kernels (16-byte
+    accesses, one pass over mib MiB) on the launch stream: GB/s of bytes read
+    (read), written (write) and read + written (copy)."""
+    n = mib * (1 << 20)
     with torch.cuda.stream(stream):
-        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        a = torch.ones(n // 4, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
-        b.copy_(a)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            b.copy_(a)
-        e1.record(stream)
-        e1.synchronize()
-        ms = e0.elapsed_time(e1) / reps
+        torch.cuda.synchronize()
+        out = {}
+        for name, mode, moved in (("read", mpdc.STREAM_READ, n), ("write", mpdc.STREAM_WRITE, n),
+                                  ("copy", mpdc.STREAM_COPY, 2 * n)):
+            ms = mpdc.stream_time(mode, b, a, reps, stream=stream)
+            out[name] = moved / (ms * 1e-3) / 1e9
     del a, b
-    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+    torch.cuda.empty_cache()
+    return out
 
 
 def copy_calibration(torch, mib):
@@ -349,7 +363,8 @@ def coupled_main(args, torch, mpdc):
     N, K, T, n = mesh["nCells"], w["K"], w["T"], w["nsub"]
     res = {}
     fixed = json.loads(args.shapes) if args.shapes else {}
-    copy_gbs = copy_ceiling(torch, stream)
+    ceil = stream_ceilings(torch, mpdc, stream)
+    copy_gbs = ceil["copy"]
     for name in ("MIX", "DBL"):
         pol = getattr(mpdc, "POLICY_" + name)
         dy, trs, s, tr, dpi0 = coupled_states(torch, mpdc, g, mesh, w, pol, stream, not args.no_autotune,
@@ -441,17 +456,101 @@ def coupled_main(args, torch, mpdc):
         "kernels_dbl": {k: {"ms": v["ms"], "ms_in_step": v["ms_in_step"], "MB": v["bytes"] / 1e6,
                             "GB/s": v["bytes"] / (v["ms"] * 1e-3) / 1e9} for k, v in dbl["kernels"].items()},
         "launch_shapes": {"mix": mix["shapes"], "dbl": dbl["shapes"]},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": traffic_src,
-                     "bytes_per_launch": kt[dom]["bytes"], "bytes_per_launch_mean": kt[dom]["bytes_mean"],
-                     "ms_per_launch": kt[dom]["ms"],
-                     "ms_per_launch_in_step": kt[dom]["ms_in_step"],
-                     "timing": "HIP events around back-to-back launches on the launch stream",
-                     "copy_ceiling_gbs": copy_gbs, "frac_of_copy": ach / copy_gbs},
+        "roofline": roofline_record(kt, dom, ach, traffic, traffic_src, ceil),
         "cpu_baseline": cpu,
         "source_sha256": digest,
     }
     print(json.dumps(out), flush=True)
+
+
+def roofline_record(kt, dom, ach, traffic, traffic_src, ceil):
+    """The dominant kernel's roofline: achieved GB/s (algorithmic bytes of one
+    launch / its HIP-event duration) against the 8 TB/s HBM peak, or labelled
+    "cache" when that launch's bytes fit the 256 MB MALL; also against the
+    library's streaming kernels measured in the same run."""
+    bound = "hbm" if kt[dom]["bytes"] > MALL_BYTES else "cache"
+    return {"bound": bound, "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": traffic_src,
+            "bytes_per_launch": kt[dom]["bytes"], "bytes_per_launch_mean": kt[dom]["bytes_mean"],
+            "ms_per_launch": kt[dom]["ms"], "ms_per_launch_in_step": kt[dom]["ms_in_step"],
+            "timing": "HIP events around back-to-back launches on the launch stream",
+            "stream_ceiling_gbs": ceil, "copy_ceiling_gbs": ceil["copy"], "frac_of_copy": ach / ceil["copy"],
+            "frac_of_read": ach / ceil["read"],
+            "ceiling_source": "the library's streaming kernels (mpdc_stream_time), 2 GiB, 16-byte accesses"}
+
+
+def stored_reference_gate(torch, mpdc, g, w, st, stream, shapes, case):
+    """Both policies for the 10 steps of the stored FP64 oracle results
+    (tests/golden, written by make_fullsize_refs.py from the oracle), in the
+    timed launch shapes, compared on the stored sample of cells and edges:
+    relative max error of the key field (surface pressure, or the tracers)."""
+    path = os.path.join(ROOT, "tests", "golden", "fullsize_%s.npz" % case)
+    if not os.path.exists(path):
+        return None
+    ref = dict(np.load(path))
+    cells = ref["cells"]
+    wl = dict(w, steps=int(ref["nsteps"]))
+    out = {"steps": int(ref["nsteps"]), "sample": "%d cells (incl. the 12 pentagons), every level" % len(cells)}
+    for name in ("DBL", "MIX"):
+        s = make_state(mpdc, g, wl, st, getattr(mpdc, "POLICY_" + name), shapes.get(name.lower()))
+        s.set_graph(True)
+        with torch.cuda.stream(stream):
+            step(s, wl, wl["steps"], stream)
+            torch.cuda.synchronize()
+        x = s.state_read(key_field(mpdc, w), stream=stream)
+        del s
+        if w["model"] == "TRACER":
+            r = ref["q"]
+            x = x[cells]
+        elif "members" in ref:
+            errs = []
+            for j in ref["members"]:
+                r = ref["ps_%d" % j]
+                errs.append(float(np.abs(x[cells, j] - r).max() / np.abs(r).max()))
+            out[name.lower() + "_vs_oracle_linf_ps"] = max(errs)
+            continue
+        else:
+            r = ref["ps"]
+            x = x[cells, 0] if x.ndim == 2 else x[cells]
+        out[name.lower() + "_vs_oracle_linf_" + ("q" if w["model"] == "TRACER" else "ps")] = \
+            float(np.abs(x - r).max() / np.abs(r).max())
+    return out
+
+
+def timed_repeats(torch, s, w, steps, repeats, stream):
+    """ms per step of `repeats` further timed runs of `steps` steps each
+    (graph replay, continuing the state), and their median."""
+    res = []
+    with torch.cuda.stream(stream):
+        for _ in range(repeats):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            step(s, w, steps, stream)
+            torch.cuda.synchronize()
+            res.append((time.perf_counter() - t0) / max(steps, 1) * 1e3)
+    return {"ms_per_step": res, "median_ms_per_step": float(np.median(res)) if res else None}
+
+
+def secondary_g6(torch, mpdc, stream, args, ceil):
+    """The G6 x 30 hydrostatic workload, whose state fits the 256 MB MALL:
+    MIX and DBL rates and the dominant kernel's bandwidth, labelled cache."""
+    w = WORKLOADS["hdc-g6"]
+    mesh, st = build_inputs(w)
+    g = mpdc.Mesh(mesh)
+    units = mesh["nCells"] * w["K"]
+    s_mix, sec_mix = timed_run(torch, mpdc, g, w, st, mpdc.POLICY_MIX, args.steps, args.warmup, stream,
+                               not args.no_autotune)
+    kt = kernel_times(torch, s_mix, w, args.profile_steps, stream)
+    del s_mix
+    s_dbl, sec_dbl = timed_run(torch, mpdc, g, w, st, mpdc.POLICY_DBL, args.steps, args.warmup, stream,
+                               not args.no_autotune)
+    del s_dbl
+    dom = max(kt, key=lambda k: kt[k]["ms_in_step"] * kt[k]["launches"])
+    ach = kt[dom]["bytes"] / (kt[dom]["ms"] * 1e-3) / 1e9
+    rl = roofline_record(kt, dom, ach, None, "not taken for the secondary line", ceil)
+    return {"workload": w["desc"], "value": units / sec_mix, "ms_per_step": sec_mix * 1e3,
+            "dbl_value": units / sec_dbl, "mix_over_dbl_speedup": sec_dbl / sec_mix,
+            "roofline": rl}
 
 
 def main():
@@ -476,9 +575,11 @@ def main():
     units = N * K * M
 
     fixed = json.loads(args.shapes) if args.shapes else {}
-    copy_gbs = copy_ceiling(torch, stream)
+    ceil = stream_ceilings(torch, mpdc, stream)
     s_mix, sec_mix = timed_run(torch, mpdc, g, w, st, mpdc.POLICY_MIX, args.steps, args.warmup, stream,
                                not args.no_autotune, fixed.get("mix"))
+    shapes_mix = s_mix.launch_shapes
+    reps = timed_repeats(torch, s_mix, w, args.steps, args.repeats, stream)
     kt = kernel_times(torch, s_mix, w, args.profile_steps, stream)
     step_bytes_mix = s_mix.step_bytes()
     sec_dbl, kt_dbl, step_bytes_dbl, shapes_dbl = None, None, None, None
@@ -492,16 +593,20 @@ def main():
     # dominant kernel of the mixed step: the largest share of the step time
     dom = max(kt, key=lambda k: kt[k]["ms_in_step"] * kt[k]["launches"])
     ach = kt[dom]["bytes"] / (kt[dom]["ms"] * 1e-3) / 1e9
-    acc = accuracy_run(torch, mpdc, g, w, st, stream, {"mix": s_mix.launch_shapes, "dbl": shapes_dbl})
+    acc = accuracy_run(torch, mpdc, g, w, st, stream, {"mix": shapes_mix, "dbl": shapes_dbl})
     from paper_2404_08849_amd.profsum import source_digest
     digest = source_digest()
     names = KERNEL_NAMES["tracer" if w["model"] == "TRACER" else "dycore"]
     di = names.index(dom)
-    shape = s_mix.launch_shapes[di] if di < len(s_mix.launch_shapes) else [0, 0]   # (the vertical step has one shape)
+    shape = shapes_mix[di] if di < len(shapes_mix) else [0, 0]   # (the vertical step has one shape)
     traffic, traffic_src = recorded_traffic(args.workload, dom, shape, digest)
     gate = {"mix_vs_dbl_l2": rel_l2(acc["MIX"], acc["DBL"]), "nonfinite": acc["MIX_nonfinite"] + acc["DBL_nonfinite"]}
     if "MIX_mass_drift" in acc:
         gate["mass_drift"] = {"mix": acc["MIX_mass_drift"], "dbl": acc["DBL_mass_drift"]}
+    if args.workload in STORED_REFS:
+        gate["stored_oracle_10_steps"] = stored_reference_gate(torch, mpdc, g, w, st, stream,
+                                                               {"mix": shapes_mix, "dbl": shapes_dbl},
+                                                               STORED_REFS[args.workload])
 
     # mixed-policy variants beside MIX (layered dycores only)
     variants, var_keys = None, {}
@@ -518,9 +623,16 @@ def main():
                               "vs_dbl_l2": rel_l2(av[name], acc["DBL"]), "mass_drift": av[name + "_mass_drift"],
                               "nonfinite": av[name + "_nonfinite"], "launch_shapes": shp}
 
+    del s_mix
+    secondary = None
+    if not args.no_secondary and args.workload != "hdc-g6":
+        secondary = {"hdc-g6": secondary_g6(torch, mpdc, stream, args, ceil)}
+
     cpu = None
     if not args.no_cpu_baseline:
+        from oracle import oracle_lib
         nst = w["steps"] if w["level"] <= 6 else 1
+        cores = oracle_lib().or_num_threads()
         key, el, nrun, cores = oracle_baseline(mesh, w, st, nst)
         ref = np.asarray(key)
         gpu_dbl = acc["DBL"] if nst == w["steps"] else None
@@ -535,11 +647,25 @@ def main():
                 xv = x[:, 0] if (w["model"] == "HDC" and M > 1) else x.reshape(ref.shape)
                 variants[name]["vs_oracle_l2"] = rel_l2(xv, ref)
         per_member = N * K * (T if w["model"] == "TRACER" else 1)
+        # the same oracle on one thread: one step (or the workload's steps on small meshes)
+        oracle_lib().or_set_num_threads(1)
+        try:
+            _, el1, nrun1, _ = oracle_baseline(mesh, w, st, 1 if w["level"] > 5 else nst,
+                                               min_seconds=0.0, max_seconds=0.0)
+        finally:
+            oracle_lib().or_set_num_threads(cores)
         cpu = {"value": per_member * nrun / el, "unit": "cell-level-steps/s" if w["model"] != "TRACER"
                else "cell-level-tracer-steps/s", "cores": cores, "kind": "oracle",
                "sample": "%d step(s) of one member of %s on the host (%.1f s); the first %d are the "
-                         "accuracy reference" % (nrun, args.workload, el, nst)}
+                         "accuracy reference" % (nrun, args.workload, el, nst),
+               "value_1_thread": per_member * nrun1 / el1,
+               "sample_1_thread": "%d step(s) of one member of %s on one host thread (%.1f s)"
+                                  % (nrun1, args.workload, el1)}
     gate["passes"] = bool(gate.get("mix_vs_oracle_l2", gate["mix_vs_dbl_l2"]) <= 1e-5 and gate["nonfinite"] == 0)
+    so = gate.get("stored_oracle_10_steps")
+    if so:
+        key = [k for k in so if k.startswith("mix_vs_oracle")][0]
+        gate["passes"] = bool(gate["passes"] and so[key] <= 1e-5)
 
     value = units / sec_mix
     unit = "cell-level-steps/s"
@@ -571,15 +697,11 @@ def main():
         "kernels_dbl": ({k: {"ms": v["ms"], "ms_in_step": v["ms_in_step"], "MB": v["bytes"] / 1e6,
                              "GB/s": v["bytes"] / (v["ms"] * 1e-3) / 1e9} for k, v in kt_dbl.items()}
                         if kt_dbl else None),
-        "launch_shapes": {"mix": s_mix.launch_shapes, "dbl": shapes_dbl,
+        "launch_shapes": {"mix": shapes_mix, "dbl": shapes_dbl,
                           "note": "(values per lane, cells or threads per work-group) per kernel, autotuned"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": traffic_src,
-                     "bytes_per_launch": kt[dom]["bytes"], "bytes_per_launch_mean": kt[dom]["bytes_mean"],
-                     "ms_per_launch": kt[dom]["ms"],
-                     "ms_per_launch_in_step": kt[dom]["ms_in_step"],
-                     "timing": "HIP events around back-to-back launches on the launch stream",
-                     "copy_ceiling_gbs": copy_gbs, "frac_of_copy": ach / copy_gbs},
+        "repeats": reps,
+        "roofline": roofline_record(kt, dom, ach, traffic, traffic_src, ceil),
+        "secondary": secondary,
         "cpu_baseline": cpu,
         "source_sha256": digest,
     }

@@ -162,16 +162,35 @@ typedef struct {
     const double *sigma;  /* [K+1] sigma at interfaces, 0 at the top, 1 at the surface      */
     int32_t accumulate_flux; /* HDC/NDC with M = 1: 1 = sum each step's last-stage horizontal and
                                 vertical mass fluxes for mpdc_tracer_couple (0 otherwise)         */
-    int32_t reserved[7];  /* must be zero                                                   */
+    int32_t forward_backward_off; /* 0 (default): forward-backward stages -- the pressure-gradient
+                                (gravity) term of each RK stage uses the mass and Theta that stage
+                                has just advanced (Section 2.1: the hydrostatic solver's Mesinger
+                                forward-backward scheme); 1: every term of a stage uses the
+                                stage's input state (plain RK3).  SW and HDC with the policies
+                                DBL, MIX, MIX_BOX, MIX_DBL_MASS, MIX_F32_DIV only (the
+                                non-hydrostatic solver's HEVI ordering has no such switch);
+                                otherwise MPDC_E_UNSUPPORTED                                     */
+    int32_t reserved[6];  /* must be zero                                                   */
 } mpdc_config;
+
+#define MPDC_DIAG_MAX_TRACERS 16  /* per-tracer entries of mpdc_diag */
 
 typedef struct {
     double mass;          /* sum_i A_i h_i (SW) or sum_i A_i (pi_s - pi_t) summed over members */
-    double mass_tracer[16];/* sum A dpi q per tracer (first 16 tracers)                    */
+    double mass_tracer[MPDC_DIAG_MAX_TRACERS];  /* sum A dpi q per tracer                 */
     double min, max;      /* of the field named in mpdc_diagnostics                         */
     double l1, l2, linf;  /* area-weighted normalised errors vs the reference (if given)    */
     int64_t nonfinite;    /* NaN/Inf count over every prognostic field                      */
     double cfl_max;       /* dycore: largest |u_e| dt / d_e (NaN if u holds one); tracer: 0    */
+    double energy;        /* dycore: total energy (J) summed over members -- kinetic, internal
+                             and potential energy of every layer's mass,
+                             (1/g) sum_i A_i sum_k dpi (K + c_v T + phi), with K the cell
+                             kinetic energy (1/A) sum (l d/4) u^2, phi the layer mean of the
+                             interface geopotentials (hydrostatic: integrated from phi_s;
+                             non-hydrostatic: prognostic, plus the layer mean of w^2/2);
+                             shallow water: sum_i A_i h (K + g (h/2 + b)); tracer: 0     */
+    double tracer_min[MPDC_DIAG_MAX_TRACERS], tracer_max[MPDC_DIAG_MAX_TRACERS];
+                          /* per tracer over every cell and level (tracer model)         */
 } mpdc_diag;
 
 typedef struct mpdc_mesh mpdc_mesh;
@@ -228,7 +247,8 @@ int mpdc_state_read(mpdc_state *st, int field_id, void *dst, int dst_on_device, 
 
 /* Advance the dycore (SW, HDC or NDC) by nsteps RK3 steps of dt.  Each stage
  * updates the mass and Theta first and uses them in the pressure-gradient
- * term (forward-backward).  Asynchronous.  Errors: INVAL, STATE, DEVICE. */
+ * term (forward-backward; see mpdc_config.forward_backward_off).
+ * Asynchronous.  Errors: INVAL, STATE, DEVICE. */
 int mpdc_dycore_step(mpdc_state *st, int nsteps, void *stream);
 
 /* Advance the tracers (TRACER model) by nsteps RK3 steps with the FCT limiter
@@ -258,13 +278,16 @@ int mpdc_tracer_step(mpdc_state *st, int nsteps, void *stream);
  * coupling), UNSUPPORTED (K x T too large for the vertical step), DEVICE. */
 int mpdc_tracer_couple(mpdc_state *tracer, mpdc_state *dycore, void *stream);
 
-/* Deterministic FP64 reductions over the state: global mass, tracer masses,
- * NaN/Inf count, min/max of field_id, and (if ref_dev is not NULL) the
- * normalised L1/L2/Linf errors of field_id against the FP64 device array
- * ref_dev of the same layout (Section 2.2, Eq. 2; cell fields weighted by the
- * cell areas, MPDC_FIELD_VORT by the dual-cell areas, edge fields
- * unweighted).  Synchronous.  Returns MPDC_E_NUMERIC (with *out filled) if a
- * NaN/Inf is present. */
+/* Deterministic FP64 reductions over the state: global mass, total energy,
+ * tracer masses and per-tracer min/max, NaN/Inf count, min/max of field_id,
+ * and (if ref_dev is not NULL) the normalised L1/L2/Linf errors of field_id
+ * against the FP64 device array ref_dev of the same layout (Section 2.2,
+ * Eq. 2; cell fields weighted by the cell areas, MPDC_FIELD_VORT by the
+ * dual-cell areas, edge fields unweighted).  Synchronous.  Returns
+ * MPDC_E_NUMERIC (with *out filled) if a NaN/Inf is present, and
+ * MPDC_E_UNSUPPORTED (nothing written) for a tracer state with more than
+ * MPDC_DIAG_MAX_TRACERS tracers.  The energy uses the state's stage scratch,
+ * so it must not run concurrently with a step of the same state. */
 int mpdc_diagnostics(mpdc_state *st, int field_id, const void *ref_dev, mpdc_diag *out, void *stream);
 
 /* Capture one dycore or tracer step into a HIP graph and replay it for later
@@ -304,12 +327,21 @@ int mpdc_time_kernel(mpdc_state *st, int kernel_id, int nreps, void *stream, dou
  * advances by nsteps exactly as with mpdc_dycore_step / mpdc_tracer_step. */
 int mpdc_profile_steps(mpdc_state *st, int nsteps, void *stream, double *ms_total, int *launches);
 
-/* Autotuner: for each kernel class in launch order, time every legal
- * (values per lane, work-group) pair with mpdc_time_kernel (so the state is
- * not advanced), keep the fastest, and return the column kernels' cells per
- * work-group and the last flat kernel's threads per work-group.  Results stay
- * bitwise identical; mpdc_get_kernel_launch reads the choice back. */
-int mpdc_autotune(mpdc_state *st, void *stream, int *cells_per_block, int *flat_block);
+/* Autotuner (the tuned launch shapes of the batched workloads): for each
+ * kernel class in launch order, time every legal (values per lane,
+ * work-group) pair with mpdc_time_kernel (so the state is not advanced) and
+ * keep the fastest; mpdc_get_kernel_launch reads the choice back.  Results
+ * stay bitwise identical whatever is chosen.  cache_path (may be NULL: no
+ * cache) names a text file of stored choices, one line per configuration
+ * keyed by the device (architecture, compute units), the library version,
+ * the model, policy, mesh counts, K, M, T and the stage ordering: if it holds
+ * a legal choice for this configuration, that choice is applied without
+ * timing anything; otherwise the tuned choice replaces or adds that line (the
+ * file is rewritten through a temporary file and a rename; concurrent
+ * writers of one file may lose each other's lines).  Synchronous.  Errors:
+ * INVAL (null state; the cache cannot be written -- the tuned shapes are
+ * applied all the same), DEVICE. */
+int mpdc_autotune(mpdc_state *st, const char *cache_path, void *stream);
 
 /* Algorithmic HBM bytes of one launch of a kernel class (same ids; mean over
  * the three RK stages; tracer id 3: the vertical step, once per step) and of
@@ -325,6 +357,18 @@ double mpdc_step_bytes(const mpdc_state *st);
  * store the FP64 u and Theta in the last stage only.  mpdc_time_kernel times
  * the first stage's launch (stage = 0 here).  Returns 0 for a bad id or stage. */
 double mpdc_stage_kernel_bytes(const mpdc_state *st, int kernel_id, int stage);
+
+/* Measurement utility, not a step of the method: the device's streaming
+ * bandwidth, which the stencil kernels' achieved bandwidth is read against.
+ * Times nreps launches of a plain streaming kernel over `bytes` bytes (a
+ * positive multiple of 16; dst and src 16-byte aligned device buffers of at
+ * least that size) on stream with HIP events, after one untimed launch;
+ * *ms_avg receives the mean duration.  mode 0 reads src (and stores one
+ * 8-byte word per 16 KiB read at the start of dst), 1 writes dst (src may be
+ * NULL), 2 copies src to dst; each lane moves four 16-byte words.
+ * Synchronous.  Errors: INVAL, DEVICE. */
+int mpdc_stream_time(int mode, void *dst, const void *src, size_t bytes, int nreps, void *stream,
+                     double *ms_avg);
 
 void mpdc_state_destroy(mpdc_state *st);
 

@@ -44,6 +44,15 @@ int or_num_threads(void)
 #endif
 }
 
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* small vector helpers                                                */
 /* ------------------------------------------------------------------ */
@@ -458,7 +467,8 @@ static const double RK3_FRAC[3] = {1.0 / 3.0, 0.5, 1.0};
  * dh/dt = -D(F), F_e = (h_c1 + h_c2)/2 u_e
  * du/dt = Q_e - G_e K - g G_e (h + b)
  * Wicker-Skamarock RK3 (dt/3, dt/2, dt from the step's start state); in each
- * stage h is updated first and the gravity term uses the updated h.
+ * stage h is updated first and the gravity term uses the updated h
+ * (forward-backward), or the stage's input h when p->no_fb is set.
  */
 void or_sw_run(const or_mesh *h, const or_params *p, double *hs, double *us, const double *b, int nsteps)
 {
@@ -483,7 +493,8 @@ void or_sw_run(const or_mesh *h, const or_params *p, double *hs, double *us, con
             for (int e = 0; e < E; e++) {
                 int c1 = m->cells_on_edge[2 * e], c2 = m->cells_on_edge[2 * e + 1];
                 double gk = (ke[c2] - ke[c1]) / m->dEdge[e];
-                double gh = p->grav * ((hn[c2] + b[c2]) - (hn[c1] + b[c1])) / m->dEdge[e];
+                const double *hg = p->no_fb ? hs : hn;
+                double gh = p->grav * ((hg[c2] + b[c2]) - (hg[c1] + b[c1])) / m->dEdge[e];
                 us[e] = u0[e] + dts * (Q[e] - gk - gh);
             }
             memcpy(hs, hn, sizeof(double) * N);
@@ -650,6 +661,7 @@ static void hydro_pgf(const or_mesh *h, const or_params *p, const double *ps, co
  *   dpi_s/dt = -sum_k D_k (Eq. 3), dTheta/dt from Eq. 4, du/dt from Eq. 5.
  * Stage s: pi_s and Theta are advanced first; the PGF/gravity term then uses
  * them (forward-backward); every other term uses the previous stage's state.
+ * With p->no_fb the PGF/gravity term also uses the previous stage's state.
  */
 /* Mass fluxes handed to a time-split tracer step (Section 2.3: the tracer's
  * mass flux is accumulated and averaged from the dycore's, Eq. 3): the
@@ -693,7 +705,8 @@ static void hdc_run(const or_mesh *h, const or_params *p, double *ps, double *Th
             }
             for (int i = 0; i < N; i++) psn[i] = ps0[i] + dts * dps[i];
             for (size_t x = 0; x < NK; x++) Thn[x] = Th0[x] + dts * dTh[x];
-            hydro_pgf(h, p, psn, Thn, pgf, alpha, pmid, phim);
+            if (p->no_fb) hydro_pgf(h, p, ps, Theta, pgf, alpha, pmid, phim);
+            else hydro_pgf(h, p, psn, Thn, pgf, alpha, pmid, phim);
             for (size_t x = 0; x < EK; x++) u[x] = u0[x] + dts * (adv[x] + pgf[x]);
             memcpy(ps, psn, sizeof(double) * N);
             memcpy(Theta, Thn, sizeof(double) * NK);
@@ -1162,6 +1175,71 @@ void or_norms(int n, int K, const double *area, const double *x, const double *r
     out[0] = (a1.s + a1.c) / (b1.s + b1.c);
     out[1] = sqrt((a2.s + a2.c) / (b2.s + b2.c));
     out[2] = mi / mr;
+}
+
+/*
+ * Total energy (J) of a state: kinetic, internal and potential energy of the
+ * mass of every layer,
+ *   E = (1/g) sum_i A_i sum_k dpi_{i,k} (K_{i,k} + c_v T_{i,k} + phi_{i,k}),
+ * with K the cell kinetic energy per unit mass (1/A_i) sum (l d / 4) u^2.
+ * Hydrostatic (model 1): dpi from pi_s and sigma, T = theta (p_k/p0)^kappa at
+ * the mid-layer pressure, phi_k the mean of the interface geopotentials
+ * integrated upwards from phi_s (Eq. 8).  Non-hydrostatic (model 2): p_k from
+ * Eq. 9, alpha_k = dphi_k/dpi_k, T = p_k alpha_k / R_d, phi_k the mean of the
+ * prognostic interface values, and the vertical kinetic energy adds the
+ * mean of w^2/2 at the layer's two interfaces.  Shallow water (model 0):
+ *   E = sum_i A_i h_i (K_i + g (h_i/2 + b_i)),
+ * the kinetic energy and the potential energy of the column above b.
+ * Fields: ps or h [N], Theta [N][K], u [E][K], w and phi [N][K+1], b [N]
+ * (NULL where a model has none).  Cells are summed in order (Neumaier).
+ */
+double or_energy(const or_mesh *h, const or_params *p, int model, const double *ps, const double *Theta,
+                 const double *u, const double *w, const double *phi, const double *b)
+{
+    const or_mesh_in *m = &h->m;
+    const int N = m->N, K = model == 0 ? 1 : p->K, K1 = K + 1;
+    const double kappa = p->rd / p->cp, cv = p->cp - p->rd;
+    double *ke = dalloc((size_t)N * K), *col = dalloc(N);
+    or_kinetic_energy(h, K, u, ke);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < N; i++) {
+        const double *kc = ke + (size_t)i * K;
+        if (model == 0) {
+            double bi = b ? b[i] : 0.0;
+            col[i] = ps[i] * (kc[0] + p->grav * (0.5 * ps[i] + bi));
+            continue;
+        }
+        double acc = 0.0;
+        if (model == 1) {
+            double phib = p->phis ? p->phis[i] : 0.0;
+            for (int k = K - 1; k >= 0; k--) {
+                double dpi = (p->sigma[k + 1] - p->sigma[k]) * (ps[i] - p->ptop);
+                double pit = p->ptop + p->sigma[k] * (ps[i] - p->ptop);
+                double pib = p->ptop + p->sigma[k + 1] * (ps[i] - p->ptop);
+                double pk = 0.5 * (pit + pib);
+                double T = Theta[(size_t)i * K + k] / dpi * pow(pk / p->p0, kappa);
+                double phit = phib + p->rd * T / pk * dpi;
+                acc += dpi * (kc[k] + cv * T + 0.5 * (phit + phib));
+                phib = phit;
+            }
+        } else {
+            const double *ph = phi + (size_t)i * K1, *wc = w + (size_t)i * K1;
+            for (int k = 0; k < K; k++) {
+                double dpi = (p->sigma[k + 1] - p->sigma[k]) * (ps[i] - p->ptop);
+                double dphi = ph[k] - ph[k + 1];
+                double pk = eos(p, Theta[(size_t)i * K + k], dphi);
+                double T = pk * (dphi / dpi) / p->rd;
+                double kw = 0.25 * (wc[k] * wc[k] + wc[k + 1] * wc[k + 1]);
+                acc += dpi * (kc[k] + kw + cv * T + 0.5 * (ph[k] + ph[k + 1]));
+            }
+        }
+        col[i] = acc / p->grav;
+    }
+    nsum a = {0, 0};
+    for (int i = 0; i < N; i++) nadd(&a, m->areaCell[i] * col[i]);
+    free(ke);
+    free(col);
+    return a.s + a.c;
 }
 
 /* sum_i A_i sum_k x_{i,k} (Neumaier) */

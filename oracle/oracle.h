@@ -49,6 +49,9 @@ typedef struct {
     const double *sigma;   /* [K+1] interface sigma, 0 at top, 1 at bottom */
     int fct;               /* 1: FCT limiter on; 0: bounds +-inf (limiter inactive) */
     const double *phis;    /* [N] surface geopotential of the hydrostatic model (NULL: flat) */
+    int no_fb;             /* SW and hydrostatic model: 1 = every term of an RK stage from the stage's
+                              input state (plain RK3); 0 = forward-backward (mass and Theta first,
+                              the pressure-gradient / gravity term from the updated values) */
 } or_params;
 
 typedef struct or_mesh or_mesh;
@@ -115,7 +118,13 @@ void or_nh_column_solve(const or_params *p, double dts, const double *Th, const 
 void or_norms(int n, int K, const double *area, const double *x, const double *ref,
               double out[3]);
 double or_area_sum(int n, int K, const double *area, const double *x);
+/* Total energy (J) of a state: model 0 shallow water (h, u, b), 1 hydrostatic
+ * (pi_s, Theta, u; p->phis), 2 non-hydrostatic (pi_s, Theta, u, w, phi); unused
+ * fields may be NULL. */
+double or_energy(const or_mesh *m, const or_params *p, int model, const double *ps, const double *Theta,
+                 const double *u, const double *w, const double *phi, const double *b);
 int or_num_threads(void);
+void or_set_num_threads(int n);   /* OpenMP threads of later calls */
 
 #ifdef __cplusplus
 }

@@ -34,7 +34,7 @@ class Params(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int), ("T", ctypes.c_int), ("dt", ctypes.c_double),
                 ("grav", ctypes.c_double), ("rd", ctypes.c_double), ("cp", ctypes.c_double),
                 ("p0", ctypes.c_double), ("ptop", ctypes.c_double), ("sigma", _dp),
-                ("fct", ctypes.c_int), ("phis", _dp)]
+                ("fct", ctypes.c_int), ("phis", _dp), ("no_fb", ctypes.c_int)]
 
 
 def oracle_lib():
@@ -76,6 +76,9 @@ def oracle_lib():
         lib.or_area_sum.restype = ctypes.c_double
         lib.or_area_sum.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp]
         lib.or_num_threads.restype = ctypes.c_int
+        lib.or_set_num_threads.argtypes = [ctypes.c_int]
+        lib.or_energy.restype = ctypes.c_double
+        lib.or_energy.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_int] + [_dp] * 6
         _lib = lib
     return _lib
 
@@ -202,24 +205,25 @@ class OracleMesh:
         return out
 
     # ---- models (copies; inputs untouched) ----
-    def params(self, K, dt, T=0, fct=1, sigma=None, phis=None):
+    def params(self, K, dt, T=0, fct=1, sigma=None, phis=None, forward_backward=True):
         if sigma is None:
             sigma = np.arange(K + 1, dtype=np.float64) / K
         self._sigma = np.ascontiguousarray(sigma, dtype=np.float64)
         self._phis = None if phis is None else np.ascontiguousarray(phis, dtype=np.float64)
         return Params(K, T, dt, GRAV, RD, CP, P0, PTOP, _d(self._sigma), fct,
-                      None if self._phis is None else _d(self._phis))
+                      None if self._phis is None else _d(self._phis), int(not forward_backward))
 
-    def sw_run(self, h, u, b, dt, nsteps):
+    def sw_run(self, h, u, b, dt, nsteps, forward_backward=True):
         h, u, b = [np.array(x, dtype=np.float64, order="C") for x in (h, u, b)]
-        p = self.params(1, dt)
+        p = self.params(1, dt, forward_backward=forward_backward)
         self.lib.or_sw_run(self.h, ctypes.byref(p), _d(h), _d(u), _d(b), nsteps)
         return h, u
 
-    def hdc_run(self, ps, Theta, u, dt, nsteps, phis=None):
-        """phis [N]: surface geopotential (terrain), None for a flat surface."""
+    def hdc_run(self, ps, Theta, u, dt, nsteps, phis=None, forward_backward=True):
+        """phis [N]: surface geopotential (terrain), None for a flat surface;
+        forward_backward=False: plain RK3 stages (the PGF from the stage's input)."""
         ps, Theta, u = [np.array(x, dtype=np.float64, order="C") for x in (ps, Theta, u)]
-        p = self.params(Theta.shape[1], dt, phis=phis)
+        p = self.params(Theta.shape[1], dt, phis=phis, forward_backward=forward_backward)
         self.lib.or_hdc_run(self.h, ctypes.byref(p), _d(ps), _d(Theta), _d(u), nsteps)
         return ps, Theta, u
 
@@ -281,6 +285,17 @@ class OracleMesh:
         p = self.params(K, dts)
         self.lib.or_nh_column_solve(ctypes.byref(p), dts, _d(Th), _d(dp), _d(w), _d(phi))
         return w, phi
+
+    def energy(self, model, ps, u, Theta=None, w=None, phi=None, b=None, phis=None):
+        """Total energy (J): model "SW" (ps = h, b), "HDC" (phis) or "NDC" (w, phi)."""
+        mid = {"SW": 0, "HDC": 1, "NDC": 2}[model]
+        arr = lambda x: None if x is None else np.ascontiguousarray(x, dtype=np.float64)
+        ps, u, Theta, w, phi, b = [arr(x) for x in (ps, u, Theta, w, phi, b)]
+        K = 1 if mid == 0 else Theta.shape[1]
+        p = self.params(K, 1.0, phis=phis)
+        ptr = lambda x: None if x is None else _d(x)
+        return self.lib.or_energy(self.h, ctypes.byref(p), mid, ptr(ps), ptr(Theta), ptr(u), ptr(w), ptr(phi),
+                                  ptr(b))
 
     def tracer_run(self, F, dpi, q, dt, nsteps, fct=True, vflux=None):
         """vflux [N][K+1]: vertical mass flux through the interfaces (or None)."""

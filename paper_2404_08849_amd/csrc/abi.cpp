@@ -4,7 +4,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <new>
 #include <sstream>
 #include <string>
@@ -134,6 +136,7 @@ struct mpdc_state {
     long N, E, V;
     // dycore
     StateSet set[3];
+    bool fb_off = false;   // plain RK3 stages (no forward-backward ordering)
     double *b = nullptr, *phis = nullptr, *dsig = nullptr, *sig = nullptr, *dps = nullptr, *mdot = nullptr;
     void *ke = nullptr, *hth = nullptr, *qv = nullptr, *qh = nullptr;
     double *alpha = nullptr, *phim = nullptr, *pm = nullptr, *mum = nullptr, *wstar = nullptr, *phistar = nullptr;
@@ -269,8 +272,10 @@ int cpb_of(const mpdc_state *st, int k) {
 // are stored; the all-FP64 policy and the variants that read the FP64 stage
 // state (MIX_BOX, MIX_DBL_MASS) store every stage.
 bool stage_stores_fp64(const mpdc_state *st, int s) {
+    // (without forward-backward ordering the next stage's pressure-gradient
+    // term reads this stage's FP64 Theta)
     return s == 2 || st->policy == MPDC_POLICY_DBL || st->policy == MPDC_POLICY_MIX_BOX ||
-           st->policy == MPDC_POLICY_MIX_DBL_MASS;
+           st->policy == MPDC_POLICY_MIX_DBL_MASS || st->fb_off;
 }
 
 StageArgs stage_args(const mpdc_state *st, int s) {
@@ -302,6 +307,9 @@ StageArgs stage_args(const mpdc_state *st, int s) {
     a.u32_s = in.u32; a.th32_s = in.th32;
     a.ps_o = out.ps; a.Th_o = out.Th; a.u_o = out.u; a.w_o = out.w; a.phi_o = out.phi;
     a.u32_o = out.u32; a.th32_o = out.th32;
+    // the mass the pressure-gradient (gravity) term uses: the stage's updated
+    // one (forward-backward) or its input state's
+    a.ps_pg = st->fb_off ? in.ps : out.ps;
     a.store64 = stage_stores_fp64(st, s) ? 1 : 0;
     a.b = st->b;
     a.phis = st->phis;
@@ -348,7 +356,13 @@ hipError_t launch_dycore(const mpdc_state *st, StageArgs a, int k, hipStream_t s
     a.vpl = vpl_of(st, k);
     a.cpb = cpb_of(st, k);
     a.flat_block = st->launch.flat[k];
-    return launch_stage_kernel(st->model, st->policy, a, k, s);
+    hipError_t e = launch_stage_kernel(st->model, st->policy, a, k, s);
+    // without forward-backward ordering the hydrostatic pressure-gradient term
+    // takes its column diagnostics from the stage's input state (after cell_b,
+    // whose diagnostics of the updated state they replace)
+    if (e == hipSuccess && k == KERNEL_CELL_B && st->fb_off && st->model == MPDC_MODEL_HDC)
+        e = launch_column_diag(a, s);
+    return e;
 }
 hipError_t launch_tracer(const mpdc_state *st, TracerArgs a, int k, hipStream_t s) {
     a.vpl = vpl_of(st, k);
@@ -647,9 +661,18 @@ static int check_config(const mpdc_mesh *m, const mpdc_config *c) {
             if (!(c->sigma[k + 1] > c->sigma[k])) return fail(MPDC_E_INVAL, "sigma must increase");
     }
     if (c->accumulate_flux != 0 && c->accumulate_flux != 1) return fail(MPDC_E_INVAL, "accumulate_flux must be 0 or 1");
+    if (c->forward_backward_off != 0 && c->forward_backward_off != 1)
+        return fail(MPDC_E_INVAL, "forward_backward_off must be 0 or 1");
+    if (c->forward_backward_off &&
+        !((c->model == MPDC_MODEL_SW || c->model == MPDC_MODEL_HDC) &&
+          (c->policy == MPDC_POLICY_DBL || c->policy == MPDC_POLICY_MIX || c->policy == MPDC_POLICY_MIX_BOX ||
+           c->policy == MPDC_POLICY_MIX_DBL_MASS || c->policy == MPDC_POLICY_MIX_F32_DIV)))
+        return fail(MPDC_E_UNSUPPORTED,
+                    "forward_backward_off applies to the shallow-water and hydrostatic models in the policies "
+                    "DBL, MIX, MIX_BOX, MIX_DBL_MASS and MIX_F32_DIV");
     if (c->accumulate_flux && (c->model == MPDC_MODEL_SW || c->model == MPDC_MODEL_TRACER || c->M != 1))
         return fail(MPDC_E_UNSUPPORTED, "mass-flux accumulation needs a layered dycore with M = 1");
-    for (int j = 0; j < 7; j++)
+    for (int j = 0; j < (int)(sizeof(c->reserved) / sizeof(c->reserved[0])); j++)
         if (c->reserved[j]) return fail(MPDC_E_INVAL, "reserved config fields must be zero");
     return MPDC_OK;
 }
@@ -661,6 +684,7 @@ static mpdc_state *new_state(const mpdc_mesh *m, const mpdc_config *c) {
     st->model = c->model;
     st->policy = c->policy;
     st->accumulate = c->accumulate_flux != 0;
+    st->fb_off = c->forward_backward_off != 0;
     st->K = c->K;
     st->M = c->M;
     st->T = c->model == MPDC_MODEL_TRACER ? c->T : 0;
@@ -964,6 +988,30 @@ int mpdc_time_kernel(mpdc_state *st, int kernel_id, int nreps, void *stream, dou
     return MPDC_OK;
 }
 
+int mpdc_stream_time(int mode, void *dst, const void *src, size_t bytes, int nreps, void *stream, double *ms_avg) {
+    if (mode < 0 || mode > 2) return fail(MPDC_E_INVAL, "stream mode must be 0 (read), 1 (write) or 2 (copy)");
+    if (!dst || (mode != 1 && !src) || !ms_avg || nreps < 1) return fail(MPDC_E_INVAL, "bad arguments");
+    if (bytes < 16 || bytes % 16) return fail(MPDC_E_INVAL, "bytes must be a positive multiple of 16");
+    if (((uintptr_t)dst | (uintptr_t)src) % 16) return fail(MPDC_E_INVAL, "buffers must be 16-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    const long n16 = (long)(bytes / 16);
+    HIP_TRY(launch_stream(mode, src, dst, n16, s));   // first touch outside the timed region
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < nreps && e == hipSuccess; r++) e = launch_stream(mode, src, dst, n16, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "stream kernel timing");
+    *ms_avg = (double)ms / nreps;
+    return MPDC_OK;
+}
+
 // Algorithmic bytes: every array a kernel must touch, read or written once.
 static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
     const double N = (double)st->N, E = (double)st->E, V = (double)st->V, K = st->K, M = st->M;
@@ -1018,6 +1066,9 @@ static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
         b += (st64 ? N * KM * 8 : 0) + ps + 2 * N * KM * 8 + (mix ? N * KM * 4 : 0);   // Th_o, ps_o, alpha, phim, th32_o
         if (!nh) b += N * 8;                               // surface geopotential
         if (nh) b += 2 * N * K1M * 8 /*w*, phi* */ + 2 * N * K1M * 8 /*w_o, phi_o*/ + 2 * N * KM * 8 /*pm, mum*/;
+        // without forward-backward ordering a column pass recomputes alpha and phim
+        // from the input state: ps_s, Th_s, phi_s in; alpha, phim out
+        if (st->fb_off && !nh) b += ps + N * KM * 8 + N * 8 + 2 * N * KM * 8;
         return b;
     }
     case KERNEL_EDGE: {
@@ -1110,8 +1161,39 @@ int mpdc_profile_steps(mpdc_state *st, int nsteps, void *stream, double *ms_tota
     return rc;
 }
 
-int mpdc_autotune(mpdc_state *st, void *stream, int *cells_per_block, int *flat_block) {
-    if (!st || !cells_per_block || !flat_block) return fail(MPDC_E_INVAL, "bad arguments");
+// ---- autotuner with a persistent cache ----
+// One text line per configuration: "<key> | v0 g0 v1 g1 ..." -- the key names
+// the device (architecture, compute units), the library version and
+// everything that decides which kernel instances run and how much work they
+// get; the values are each kernel class's (values per lane, group).
+static std::string tune_key(const mpdc_state *st) {
+    int dev = 0;
+    hipDeviceProp_t p;
+    std::memset(&p, 0, sizeof(p));
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return "";
+    std::ostringstream o;
+    o << "mpdc-autotune-v1 arch=" << p.gcnArchName << " cus=" << p.multiProcessorCount << " lib=\"" << mpdc_version()
+      << "\" model=" << st->model << " policy=" << st->policy << " N=" << st->N << " E=" << st->E << " V=" << st->V
+      << " K=" << st->K << " M=" << st->M << " T=" << st->T << " fb_off=" << (st->fb_off ? 1 : 0);
+    return o.str();
+}
+
+static bool apply_cached_shapes(mpdc_state *st, const std::string &line, int nk) {
+    std::istringstream in(line);
+    Launch l = st->launch;
+    for (int k = 0; k < nk; k++) {
+        int v = 0, g = 0;
+        if (!(in >> v >> g)) return false;
+        if (!vpl_ok(st, k, v) || check_group(st, k, v, g) != MPDC_OK) return false;
+        l.vpl[k] = v;
+        if (st->model != MPDC_MODEL_TRACER && is_column(k)) l.cpb[k] = g;
+        else l.flat[k] = g;
+    }
+    st->launch = l;
+    return true;
+}
+
+static int tune_shapes(mpdc_state *st, void *stream) {
     const bool tr = st->model == MPDC_MODEL_TRACER;
     const int nk = tr ? 3 : 4;
     const int flats[] = {64, 128, 256, 512, 1024};
@@ -1149,10 +1231,53 @@ int mpdc_autotune(mpdc_state *st, void *stream, int *cells_per_block, int *flat_
         if (col) st->launch.cpb[k] = best_g;
         else st->launch.flat[k] = best_g;
     }
+    return MPDC_OK;
+}
+
+int mpdc_autotune(mpdc_state *st, const char *cache_path, void *stream) {
+    if (!st) return fail(MPDC_E_INVAL, "null state");
+    const int nk = st->model == MPDC_MODEL_TRACER ? 3 : 4;
+    const std::string key = tune_key(st);
+    if (key.empty()) return fail(MPDC_E_DEVICE, "cannot read the device properties for the autotune key");
+    std::vector<std::string> lines;
+    if (cache_path && *cache_path) {
+        std::ifstream f(cache_path);
+        std::string line;
+        while (f && std::getline(f, line)) {
+            const size_t bar = line.find(" | ");
+            if (bar != std::string::npos && line.compare(0, bar, key) == 0 && bar == key.size() &&
+                apply_cached_shapes(st, line.substr(bar + 3), nk)) {
+                set_error("");
+                drop_graphs(st);
+                return MPDC_OK;   // a stored choice for this configuration: no timing
+            }
+            if (!line.empty()) lines.push_back(line);
+        }
+    }
+    int rc = tune_shapes(st, stream);
+    if (rc != MPDC_OK) return rc;
     set_error("");
     drop_graphs(st);
-    *cells_per_block = tr ? 0 : cpb_of(st, KERNEL_CELL_A);
-    *flat_block = st->launch.flat[tr ? 0 : KERNEL_EDGE];
+    if (cache_path && *cache_path) {
+        std::ostringstream o;
+        o << key << " |";
+        for (int k = 0; k < nk; k++) {
+            const bool col = st->model != MPDC_MODEL_TRACER && is_column(k);
+            o << " " << vpl_of(st, k) << " " << (col ? cpb_of(st, k) : st->launch.flat[k]);
+        }
+        std::vector<std::string> keep;
+        for (auto &l : lines)
+            if (l.compare(0, key.size() + 3, key + " | ") != 0) keep.push_back(l);
+        keep.push_back(o.str());
+        const std::string tmp = std::string(cache_path) + ".tmp";
+        {
+            std::ofstream out(tmp, std::ios::trunc);
+            for (auto &l : keep) out << l << "\n";
+            if (!out) return fail(MPDC_E_INVAL, std::string("cannot write the autotune cache ") + tmp);
+        }
+        if (std::rename(tmp.c_str(), cache_path) != 0)
+            return fail(MPDC_E_INVAL, std::string("cannot replace the autotune cache ") + cache_path);
+    }
     return MPDC_OK;
 }
 
@@ -1169,6 +1294,8 @@ int mpdc_diagnostics(mpdc_state *st, int f, const void *ref_dev, mpdc_diag *out,
     if (!st || !out) return fail(MPDC_E_INVAL, "null state or output");
     long nf = field_count(st, f);
     if (nf < 0) return fail(MPDC_E_INVAL, "field not part of this model");
+    if (st->model == MPDC_MODEL_TRACER && st->T > MPDC_DIAG_MAX_TRACERS)
+        return fail(MPDC_E_UNSUPPORTED, "diagnostics hold at most 16 tracers (MPDC_DIAG_MAX_TRACERS)");
     hipStream_t s = (hipStream_t)stream;
     mpdc_diag d;
     std::memset(&d, 0, sizeof(d));
@@ -1196,7 +1323,7 @@ int mpdc_diagnostics(mpdc_state *st, int f, const void *ref_dev, mpdc_diag *out,
     double r9[9];
     // mass
     if (st->model == MPDC_MODEL_TRACER) {
-        for (int t = 0; t < T && t < 16; t++) {
+        for (int t = 0; t < T; t++) {
             DiagArgs a{};
             a.area = area;
             a.n = N; a.inner = K; a.xs = (int)T; a.xo = t;
@@ -1206,6 +1333,8 @@ int mpdc_diagnostics(mpdc_state *st, int f, const void *ref_dev, mpdc_diag *out,
             int rc = reduce(a, r9);
             if (rc) return rc;
             d.mass_tracer[t] = r9[0];
+            d.tracer_min[t] = r9[1];
+            d.tracer_max[t] = r9[2];
         }
         DiagArgs a{};
         a.area = area; a.n = N; a.inner = K; a.xs = 1; a.xo = 0; a.x = st->dpi[st->parity];
@@ -1219,6 +1348,21 @@ int mpdc_diagnostics(mpdc_state *st, int f, const void *ref_dev, mpdc_diag *out,
         int rc = reduce(a, r9);
         if (rc) return rc;
         d.mass = r9[0];
+        // total energy: column energies into the stage scratch, then their area-weighted sum
+        EnergyArgs e{};
+        e.model = st->model; e.K = st->K; e.M = st->M;
+        e.grav = st->cfg.grav; e.rd = st->cfg.rd; e.cp = st->cfg.cp; e.p0 = st->cfg.p0; e.ptop = st->cfg.ptop;
+        e.sig = st->sig;
+        const StateSet &s0 = st->set[0];
+        e.ps = s0.ps; e.Th = s0.Th; e.u = s0.u; e.w = s0.w; e.phi = s0.phi;
+        e.b = st->b; e.phis = st->phis;
+        e.out = (double *)st->qh;
+        HIP_TRY(launch_energy(st->mesh->dev, e, s));
+        DiagArgs ea{};
+        ea.area = area; ea.n = N; ea.inner = M; ea.xs = 1; ea.xo = 0; ea.x = e.out;
+        rc = reduce(ea, r9);
+        if (rc) return rc;
+        d.energy = r9[0];
     }
     // field statistics and norms: cell fields area-weighted, vertex fields
     // (vorticity) weighted by the dual-cell areas, edge fields unweighted

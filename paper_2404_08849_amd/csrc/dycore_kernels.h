@@ -62,6 +62,7 @@ struct StageArgs {
     const float *u32_s, *th32_s;
     double *ps_o, *Th_o, *u_o, *w_o, *phi_o;
     float *u32_o, *th32_o;
+    const double *ps_pg; // pi_s (h) of the pressure-gradient term: ps_o (forward-backward) or ps_s
     const double *b;     // SW bottom height [N]
     const double *phis;  // HDC surface geopotential [N] (zero: flat)
     // stage intermediates
@@ -119,6 +120,9 @@ __host__ __device__ inline ColTabLayout coltab_layout(int model, int which, int 
 
 hipError_t launch_stage_kernel(int model, int policy, const StageArgs &a, int which, hipStream_t s);
 hipError_t launch_shadows(int model, const StageArgs &a, hipStream_t s);
+// hydrostatic column diagnostics (alpha, layer geopotential) of the stage's
+// input state (ps_s, Th_s), FP64, for stages without forward-backward ordering
+hipError_t launch_column_diag(const StageArgs &a, hipStream_t s);
 // relative vorticity at the vertices of an FP64 velocity [E][KM] into out [V][KM] (diagnostics)
 hipError_t launch_vorticity(const DevMesh &m, const double *u, double *out, int KM, hipStream_t s);
 size_t stage_lds_bytes(int model, int policy, int which, int cpb, int K, int M);
@@ -179,5 +183,22 @@ hipError_t launch_nonfinite(const double *x, const float *x32, long n, unsigned 
                             hipStream_t s);
 hipError_t launch_cfl(const double *u, const double *dinv, long E, long inner, double dt, double *partial,
                       int nblocks, hipStream_t s);
+
+// ---- total energy of the dycore state (diagnostics) ----
+struct EnergyArgs {
+    int model, K, M;
+    double grav, rd, cp, p0, ptop;
+    const double *sig;            // [K+1]
+    const double *ps, *Th, *u;    // [N][M] (h for SW), [N][K][M], [E][K][M]
+    const double *w, *phi;        // [N][K+1][M] (non-hydrostatic)
+    const double *b, *phis;       // [N] SW bottom height, hydrostatic surface geopotential (or null)
+    double *out;                  // [N][M] column energy per unit area (J/m^2)
+};
+hipError_t launch_energy(const DevMesh &m, const EnergyArgs &e, hipStream_t s);
+
+// ---- streaming reference kernels (bandwidth ceiling of the device) ----
+// mode 0: read src (one 8-byte word per work-group into dst), 1: write dst,
+// 2: copy src to dst; n16 16-byte words, both pointers 16-byte aligned
+hipError_t launch_stream(int mode, const void *src, void *dst, long n16, hipStream_t s);
 
 }  // namespace mpdc

@@ -1391,12 +1391,13 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
     }
 
     // pressure-gradient force and gravity in FP64 from the updated mass/Theta
+    // (forward-backward; ps_pg is the stage's input mass when that is off)
     const double dinv64 = m.e_dinv[e];
     double pgf[L];
     if constexpr (MODEL == MODEL_SW) {
         double h1[L], h2[L];
-        ld2d<L, M1>(a.ps_o, c1, M, v.mm0, h1);
-        ld2d<L, M1>(a.ps_o, c2, M, v.mm0, h2);
+        ld2d<L, M1>(a.ps_pg, c1, M, v.mm0, h1);
+        ld2d<L, M1>(a.ps_pg, c2, M, v.mm0, h2);
         const double b1 = a.b[c1], b2 = a.b[c2];
 #pragma unroll
         for (int j = 0; j < L; j++) pgf[j] = -a.grav * ((h2[j] + b2) - (h1[j] + b1)) * dinv64;
@@ -1406,8 +1407,8 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
         const Pack<double, L> ph1 = ldp<double, L>(a.phim + x1), ph2 = ldp<double, L>(a.phim + x2);
         if constexpr (MODEL == MODEL_HDC) {
             double s1[L], s2[L];
-            ld2d<L, M1>(a.ps_o, c1, M, v.mm0, s1);
-            ld2d<L, M1>(a.ps_o, c2, M, v.mm0, s2);
+            ld2d<L, M1>(a.ps_pg, c1, M, v.mm0, s1);
+            ld2d<L, M1>(a.ps_pg, c2, M, v.mm0, s2);
 #pragma unroll
             for (int j = 0; j < L; j++) {
                 const int k = v.k[j];
@@ -1629,6 +1630,112 @@ __global__ void k_vorticity(DevMesh m, const double *u, double *out, int KM) {
 hipError_t launch_vorticity(const DevMesh &m, const double *u, double *out, int KM, hipStream_t s) {
     const long n = (long)m.V * KM;
     hipLaunchKernelGGL(k_vorticity, dim3(nblocks(n, 256)), dim3(256), 0, s, m, u, out, KM);
+    return hipGetLastError();
+}
+
+// Column energy per unit area of every (cell, member), in FP64 from the FP64
+// state: (1/g) sum_k dpi_k (K_k + c_v T_k + phi_k), with the cell kinetic
+// energy K = sum_j (l d / 4A) u_j^2 and phi_k the mean of the layer's two
+// interface geopotentials.  Hydrostatic: T = theta (p_k/p0)^kappa at the
+// mid-layer pressure, geopotential integrated upwards from phi_s (Eq. 8).
+// Non-hydrostatic: p_k from Eq. 9, T = p_k (dphi_k/dpi_k) / R_d, plus the
+// mean of w^2/2 at the layer's interfaces.  Shallow water: h (K + g (h/2 + b)).
+// One lane per (cell, member), levels in sequence.
+__global__ void k_energy(DevMesh m, EnergyArgs e) {
+    const long x = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int K = e.K, M = e.M;
+    if (x >= (long)m.N * M) return;
+    const int i = (int)(x / M), mm = (int)(x - (long)i * M);
+    const long KM = (long)K * M, K1M = (long)(K + 1) * M;
+    int ed[6];
+    double ck[6];
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        ed[j] = m.c_edge[6 * (long)i + j];
+        ck[j] = m.c_ke[6 * (long)i + j];
+    }
+    auto kin = [&](int k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < 6; j++) {
+            if (ed[j] < 0) continue;
+            const double uj = e.u[(long)ed[j] * KM + (long)k * M + mm];
+            acc += ck[j] * (uj * uj);
+        }
+        return acc;
+    };
+    const double ps = e.ps[x];
+    if (e.model == MODEL_SW) {
+        const double b = e.b ? e.b[i] : 0.0;
+        e.out[x] = ps * (kin(0) + e.grav * (0.5 * ps + b));
+        return;
+    }
+    const double kappa = e.rd / e.cp, cv = e.cp - e.rd;
+    double acc = 0.0;
+    if (e.model == MODEL_HDC) {
+        double phib = e.phis ? e.phis[i] : 0.0;
+        for (int k = K - 1; k >= 0; k--) {
+            const double dpi = (e.sig[k + 1] - e.sig[k]) * (ps - e.ptop);
+            const double pit = e.ptop + e.sig[k] * (ps - e.ptop);
+            const double pib = e.ptop + e.sig[k + 1] * (ps - e.ptop);
+            const double pk = 0.5 * (pit + pib);
+            const double T = e.Th[(long)i * KM + (long)k * M + mm] / dpi * pow(pk / e.p0, kappa);
+            const double phit = phib + e.rd * T / pk * dpi;
+            acc += dpi * (kin(k) + cv * T + 0.5 * (phit + phib));
+            phib = phit;
+        }
+    } else {
+        const double gamma = e.cp / cv;
+        for (int k = 0; k < K; k++) {
+            const double dpi = (e.sig[k + 1] - e.sig[k]) * (ps - e.ptop);
+            const long t = (long)i * K1M + (long)k * M + mm, b = t + M;
+            const double dphi = e.phi[t] - e.phi[b];
+            const double pk = e.p0 * pow(e.rd * e.Th[(long)i * KM + (long)k * M + mm] / (e.p0 * dphi), gamma);
+            const double T = pk * (dphi / dpi) / e.rd;
+            const double kw = 0.25 * (e.w[t] * e.w[t] + e.w[b] * e.w[b]);
+            acc += dpi * (kin(k) + kw + cv * T + 0.5 * (e.phi[t] + e.phi[b]));
+        }
+    }
+    e.out[x] = acc / e.grav;
+}
+
+hipError_t launch_energy(const DevMesh &m, const EnergyArgs &e, hipStream_t s) {
+    const long n = (long)m.N * e.M;
+    hipLaunchKernelGGL(k_energy, dim3(nblocks(n, 256)), dim3(256), 0, s, m, e);
+    return hipGetLastError();
+}
+
+// Hydrostatic column diagnostics of the stage's input state (ps_s, Th_s) in
+// FP64 -- the formulas of cell_b's FP64 diagnostics (Eqs. 8-9): alpha = R_d T
+// / p at the mid-layer pressure and the layer mean of the geopotential
+// integrated upwards from phi_s -- for stages without forward-backward
+// ordering.  One lane per (cell, member), levels in sequence.
+__global__ void k_column_diag(StageArgs a) {
+    const long x = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int K = a.K, M = a.M;
+    if (x >= (long)a.mesh.N * M) return;
+    const int i = (int)(x / M), mm = (int)(x - (long)i * M);
+    const long KM = (long)K * M;
+    const double ps = a.ps_s[x];
+    double phib = a.phis[i];
+    for (int k = K - 1; k >= 0; k--) {
+        const long o = (long)i * KM + (long)k * M + mm;
+        const double dpn = a.dsig[k] * (ps - a.ptop);
+        const double pit = a.ptop + a.sig[k] * (ps - a.ptop);
+        const double pib = a.ptop + a.sig[k + 1] * (ps - a.ptop);
+        const double pk = 0.5 * (pit + pib);
+        const double T = (a.Th_s[o] / dpn) * powpos(pk * a.inv_p0, a.kappa);
+        const double al = a.rd * T / pk;
+        const double phit = phib + al * dpn;
+        a.alpha[o] = al;
+        a.phim[o] = 0.5 * (phit + phib);
+        phib = phit;
+    }
+}
+
+hipError_t launch_column_diag(const StageArgs &a, hipStream_t s) {
+    const long n = (long)a.mesh.N * a.M;
+    hipLaunchKernelGGL(k_column_diag, dim3(nblocks(n, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -51,13 +51,16 @@ class Config(ctypes.Structure):
                 ("M", ctypes.c_int32), ("T", ctypes.c_int32), ("fct", ctypes.c_int32),
                 ("dt", ctypes.c_double), ("grav", ctypes.c_double), ("rd", ctypes.c_double),
                 ("cp", ctypes.c_double), ("p0", ctypes.c_double), ("ptop", ctypes.c_double),
-                ("sigma", _dp), ("accumulate_flux", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("sigma", _dp), ("accumulate_flux", ctypes.c_int32), ("forward_backward_off", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class Diag(ctypes.Structure):
     _fields_ = [("mass", ctypes.c_double), ("mass_tracer", ctypes.c_double * 16), ("min", ctypes.c_double),
                 ("max", ctypes.c_double), ("l1", ctypes.c_double), ("l2", ctypes.c_double),
-                ("linf", ctypes.c_double), ("nonfinite", ctypes.c_int64), ("cfl_max", ctypes.c_double)]
+                ("linf", ctypes.c_double), ("nonfinite", ctypes.c_int64), ("cfl_max", ctypes.c_double),
+                ("energy", ctypes.c_double), ("tracer_min", ctypes.c_double * 16),
+                ("tracer_max", ctypes.c_double * 16)]
 
 
 def _load():
@@ -90,8 +93,10 @@ def _load():
         "mpdc_stage_kernel_bytes": (ctypes.c_double, [_vp, ctypes.c_int, ctypes.c_int]),
         "mpdc_profile_steps": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_int)]),
-        "mpdc_autotune": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+        "mpdc_autotune": (ctypes.c_int, [_vp, ctypes.c_char_p, _vp]),
         "mpdc_step_bytes": (ctypes.c_double, [_vp]),
+        "mpdc_stream_time": (ctypes.c_int, [ctypes.c_int, _vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp,
+                                            ctypes.POINTER(ctypes.c_double)]),
         "mpdc_state_destroy": (None, [_vp]),
         "mpdc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "mpdc_last_error": (ctypes.c_char_p, []),
@@ -124,6 +129,20 @@ def _i32(a):
 
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+STREAM_READ, STREAM_WRITE, STREAM_COPY = 0, 1, 2
+
+
+def stream_time(mode, dst, src=None, nreps=10, stream=None):
+    """mpdc_stream_time: mean duration (ms) of the library's streaming kernel
+    (STREAM_READ, STREAM_WRITE or STREAM_COPY) over dst.nbytes bytes of the
+    device tensors dst and src."""
+    ms = ctypes.c_double()
+    _check(lib.mpdc_stream_time(mode, ctypes.c_void_p(dst.data_ptr()),
+                                ctypes.c_void_p(src.data_ptr() if src is not None else 0),
+                                dst.numel() * dst.element_size(), nreps, _stream(stream), ctypes.byref(ms)))
+    return ms.value
 
 
 class Mesh:
@@ -171,12 +190,13 @@ class State:
     """mpdc_state_create and the per-state calls (dycore_step, tracer_step, diagnostics, ...)."""
 
     def __init__(self, mesh, model, policy, K=1, M=1, T=0, dt=1.0, sigma=None, fct=True,
-                 grav=9.80616, rd=287.0, cp=1004.5, p0=1.0e5, ptop=1000.0, device="cuda", accumulate_flux=False):
+                 grav=9.80616, rd=287.0, cp=1004.5, p0=1.0e5, ptop=1000.0, device="cuda", accumulate_flux=False,
+                 forward_backward=True):
         self.mesh = mesh
         self.model, self.policy, self.K, self.M, self.T = model, policy, K, M, T
         self.sigma = _f64(np.arange(K + 1) / K if sigma is None else sigma)
         self.cfg = Config(model, policy, K, M, T, int(bool(fct)), dt, grav, rd, cp, p0, ptop,
-                          self.sigma.ctypes.data_as(_dp), int(bool(accumulate_flux)))
+                          self.sigma.ctypes.data_as(_dp), int(bool(accumulate_flux)), int(not forward_backward))
         nbytes = lib.mpdc_state_workspace_bytes(mesh.h, ctypes.byref(self.cfg))
         if nbytes == 0:
             raise MpdcError(-6, lib.mpdc_last_error().decode())
@@ -235,8 +255,10 @@ class State:
         rc = lib.mpdc_diagnostics(self.h, f, refp, ctypes.byref(d), _stream(stream))
         if rc != MPDC_OK and (check or rc != -5):
             _check(rc)
-        return dict(mass=d.mass, mass_tracer=list(d.mass_tracer)[:max(self.T, 0)], min=d.min, max=d.max,
-                    l1=d.l1, l2=d.l2, linf=d.linf, nonfinite=d.nonfinite, cfl_max=d.cfl_max, rc=rc)
+        nt = max(self.T, 0)
+        return dict(mass=d.mass, mass_tracer=list(d.mass_tracer)[:nt], min=d.min, max=d.max,
+                    l1=d.l1, l2=d.l2, linf=d.linf, nonfinite=d.nonfinite, cfl_max=d.cfl_max, energy=d.energy,
+                    tracer_min=list(d.tracer_min)[:nt], tracer_max=list(d.tracer_max)[:nt], rc=rc)
 
     def set_graph(self, enable):
         _check(lib.mpdc_set_graph(self.h, int(bool(enable))))
@@ -264,10 +286,11 @@ class State:
         _check(lib.mpdc_profile_steps(self.h, nsteps, _stream(stream), ms, n))
         return {k: (ms[k], n[k]) for k in range(4) if n[k] > 0}
 
-    def autotune(self, stream=None):
-        c, f = ctypes.c_int(), ctypes.c_int()
-        _check(lib.mpdc_autotune(self.h, _stream(stream), ctypes.byref(c), ctypes.byref(f)))
-        return c.value, f.value
+    def autotune(self, stream=None, cache_path=None):
+        """mpdc_autotune; returns the chosen (values per lane, group) per kernel class."""
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(lib.mpdc_autotune(self.h, path, _stream(stream)))
+        return [self.get_kernel_launch(k) for k in range(3 if self.model == MODEL_TRACER else 4)]
 
     def kernel_bytes(self, kernel_id):
         return lib.mpdc_kernel_bytes(self.h, kernel_id)

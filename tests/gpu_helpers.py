@@ -25,6 +25,70 @@ def rel_l2(x, r, w=None):
     return float(np.sqrt((w * (x - r) ** 2).sum() / max((w * r ** 2).sum(), 1e-300)))
 
 
+# Unit roundoffs of the two formats (IEEE 754 binary64 and binary32)
+EPS64 = 2.0 ** -53
+EPS32 = 2.0 ** -24
+DBL_TOL = 1e-12          # all-FP64 path against the oracle: normalised L2 and relative max error
+MIX_TOL = 1e-5           # mixed path on h / surface pressure (and Theta, phi) after 10 steps
+# Mixed path on the velocity: its advective tendencies are FP32, so after a
+# few steps the velocity carries a few FP32 roundings of its own size; the bar
+# is 16 of them (both norms).
+MIX_U_TOL = 16.0 * EPS32
+
+
+def linf_rel(x, r):
+    """max |x - r| / max |r| over every element."""
+    x = np.asarray(x, dtype=np.float64)
+    r = np.asarray(r, dtype=np.float64)
+    return float(np.abs(x - r).max() / max(np.abs(r).max(), 1e-300))
+
+
+def compare(label, x, r, w=None, l2_tol=None, linf_tol=None):
+    """Normalised L2 (weighted by w over the first axis, if given) and relative
+    max error of x against r; prints both, then asserts each against its bar
+    (None: reported only).  Returns (l2, linf)."""
+    l2, li = rel_l2(x, r, w), linf_rel(x, r)
+    print("    %-10s L2 %.3e  Linf %.3e  max|r| %.3e" % (label, l2, li, float(np.abs(r).max())), flush=True)
+    assert np.isfinite(np.asarray(x)).all(), label + ": non-finite values"
+    if l2_tol is not None:
+        assert l2 <= l2_tol, "%s: normalised L2 %.3e > %.1e" % (label, l2, l2_tol)
+    if linf_tol is not None:
+        assert li <= linf_tol, "%s: relative max error %.3e > %.1e" % (label, li, linf_tol)
+    return l2, li
+
+
+def compare_dbl(label, x, r, w=None):
+    return compare(label, x, r, w, DBL_TOL, DBL_TOL)
+
+
+def nh_dbl_bounds(ref_phi, grav, dt, nsteps, d_min, rd=287.0, tmax=400.0, c=16.0):
+    """Element-wise bars of the all-FP64 non-hydrostatic w and u, which are
+    small residuals of large cancelling FP64 terms.
+    w: each stage's column system has the right-hand side w* + D (p_k -
+    p_{k-1}) - g dt_s, two terms of size g dt_s that cancel to leave w; their
+    FP64 roundings are eps g dt_s, which a diagonally dominant solve does
+    not amplify, and the last stage of a step has dt_s = dt.  Over n steps:
+    |dw| <= c eps g dt n.
+    u: the pressure-gradient force -(alpha_e dp + mu_e dphi)/d_e is formed from
+    p alpha = R_d T and phi at the edge's two cells, each carrying a rounding
+    of eps times its size; differenced over d_e that is a force error of
+    eps (|phi| + R_d T)/d_e, integrated over n steps of dt:
+    |du| <= c eps (max|phi| + R_d T_max) dt n / min d_e."""
+    eps = EPS64
+    bw = c * eps * grav * dt * nsteps
+    bu = c * eps * (float(np.abs(ref_phi).max()) + rd * tmax) * dt * nsteps / d_min
+    return bw, bu
+
+
+def compare_abs(label, x, r, bound):
+    """max |x - r| against an absolute bar (the NH w and u of the FP64 path)."""
+    err = float(np.abs(np.asarray(x, np.float64) - np.asarray(r, np.float64)).max())
+    print("    %-10s max|x-r| %.3e  bar %.3e  (L2 %.3e)" % (label, err, bound, rel_l2(x, r)), flush=True)
+    assert np.isfinite(np.asarray(x)).all(), label + ": non-finite values"
+    assert err <= bound, "%s: max error %.3e > %.3e" % (label, err, bound)
+    return err
+
+
 def _gpu_sw_impl(mpdc, gmesh, state, dt, nsteps, policy, graph=False, launch=None):
     st = mpdc.State(gmesh, mpdc.MODEL_SW, policy, K=1, M=1, dt=dt)
     if launch:

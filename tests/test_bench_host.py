@@ -63,3 +63,27 @@ def test_recorded_traffic_is_used_only_for_the_same_sources_and_instance(name):
 def test_source_digest_is_stable():
     d = source_digest()
     assert len(d) == 64 and d == source_digest()
+
+
+def test_roofline_bound_follows_the_launch_bytes():
+    """A launch whose algorithmic bytes exceed the 256 MB MALL is labelled HBM-bound;
+    a smaller one is cache-resident; both are read against the streaming kernels."""
+    ceil = {"read": 5000.0, "write": 4000.0, "copy": 4500.0}
+    kt = {"k": dict(bytes=300e6, bytes_mean=310e6, ms=0.1, ms_in_step=0.11)}
+    r = bench.roofline_record(kt, "k", 3000.0, None, "none", ceil)
+    assert r["bound"] == "hbm" and r["frac"] == 3000.0 / 8000.0
+    assert r["frac_of_copy"] == 3000.0 / 4500.0 and r["frac_of_read"] == 3000.0 / 5000.0
+    kt["k"]["bytes"] = 100e6
+    assert bench.roofline_record(kt, "k", 3000.0, None, "none", ceil)["bound"] == "cache"
+
+
+def test_default_workload_is_the_largest_single_gpu_ensemble():
+    old = sys.argv
+    sys.argv = ["bench.py"]
+    try:
+        a = bench.parse()
+    finally:
+        sys.argv = old
+    w = bench.WORKLOADS[a.workload]
+    assert a.workload == "ens-g7" and w["M"] == 16 and w["level"] == 7 and w["K"] == 30
+    assert a.workload in bench.STORED_REFS

@@ -1,20 +1,24 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
-Bars (stated in the workload definitions): the all-FP64 path within 1e-12
-normalised L2 of the oracle on every prognostic field; the mixed path within
-1e-5 normalised L2 on h / surface pressure after 10 steps (every other field
-reported and bounded loosely); integer mesh tables bit-exact.
+Bars (the workload definitions, plus element-wise forms of them):
+ - all-FP64 path: every prognostic field within 1e-12 of the oracle in
+   normalised L2 and in relative max error (max|x - r| / max|r|); the
+   non-hydrostatic w and u, small residuals of large cancelling FP64 terms,
+   element-wise within 16 unit roundoffs of those terms' size, integrated
+   over the steps (gpu_helpers.nh_dbl_bounds);
+ - mixed path: h / surface pressure (and Theta, phi) within 1e-5 after 10
+   steps in both norms; the velocity within 16 FP32 unit roundoffs (its
+   advective tendencies are FP32);
+ - integer mesh tables bit-exact.
 """
 import numpy as np
 import pytest
 
 from paper_2404_08849_amd.inputs import initial as ic
-from gpu_helpers import gpu_hdc, gpu_ndc, gpu_sw, gpu_tracer, rel_l2
+from gpu_helpers import (DBL_TOL, MIX_TOL, MIX_U_TOL, compare, compare_abs, compare_dbl, gpu_hdc, gpu_ndc, gpu_sw,
+                         gpu_tracer, nh_dbl_bounds, rel_l2)
 
 pytestmark = pytest.mark.gpu
-
-DBL_TOL = 1e-12
-MIX_TOL = 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -62,14 +66,17 @@ def test_sw_parity_g5(mpdc, oracle_mod, mesh_cache, policy):
     pol = getattr(mpdc, "POLICY_" + policy)
     _say("sw G5 10 steps", policy)
     st, h, u = gpu_sw(mpdc, g, s, 600.0, 10, pol)
-    eh, eu = rel_l2(h, h_o, m["areaCell"]), rel_l2(u, u_o)
     # the bump's signal (h - h0) must also agree, not only the mean depth
     eb = rel_l2(h - s["h"], h_o - s["h"], m["areaCell"])
-    _say("  h %.3e  u %.3e  dh %.3e" % (eh, eu, eb))
+    _say("  dh %.3e" % eb)
     if policy == "DBL":
-        assert eh <= DBL_TOL and eu <= DBL_TOL and eb <= 1e-9
+        compare_dbl("h", h, h_o, m["areaCell"])
+        compare_dbl("u", u, u_o)
+        assert eb <= 1e-9
     else:
-        assert eh <= MIX_TOL and eu <= 1e-3 and eb <= 1e-2
+        compare("h", h, h_o, m["areaCell"], MIX_TOL, MIX_TOL)
+        compare("u", u, u_o, None, MIX_U_TOL, MIX_U_TOL)
+        assert eb <= 1e-2
 
 
 @pytest.mark.parametrize("policy", ["DBL", "MIX"])
@@ -83,13 +90,16 @@ def test_hdc_parity_g4(mpdc, oracle_mod, mesh_cache, policy):
     pol = getattr(mpdc, "POLICY_" + policy)
     _say("hdc G4x30 10 steps", policy)
     st, (ps, Th, u) = gpu_hdc(mpdc, g, s, K, 600.0, 10, pol)
-    e = (rel_l2(ps, ps_o, m["areaCell"]), rel_l2(Th, Th_o, m["areaCell"]), rel_l2(u, u_o))
     du = rel_l2(u - s["u"], u_o - s["u"])
-    _say("  ps %.3e  Theta %.3e  u %.3e  du %.3e" % (e + (du,)))
+    _say("  du %.3e" % du)
     if policy == "DBL":
-        assert max(e) <= DBL_TOL and du <= 1e-9
+        for n, x, r, w in (("ps", ps, ps_o, m["areaCell"]), ("Theta", Th, Th_o, m["areaCell"]), ("u", u, u_o, None)):
+            compare_dbl(n, x, r, w)
+        assert du <= 1e-9
     else:
-        assert e[0] <= MIX_TOL and e[1] <= MIX_TOL and e[2] <= 1e-3
+        compare("ps", ps, ps_o, m["areaCell"], MIX_TOL, MIX_TOL)
+        compare("Theta", Th, Th_o, m["areaCell"], MIX_TOL, MIX_TOL)
+        compare("u", u, u_o, None, MIX_U_TOL, MIX_U_TOL)
 
 
 @pytest.mark.parametrize("policy", ["DBL", "MIX"])
@@ -103,27 +113,22 @@ def test_ndc_parity_g4(mpdc, oracle_mod, mesh_cache, policy):
     pol = getattr(mpdc, "POLICY_" + policy)
     _say("ndc G4x20 10 steps", policy)
     st, out = gpu_ndc(mpdc, g, s, K, 60.0, 10, pol)
-    names = ["ps", "Theta", "u", "w", "phi"]
-    errs = {}
-    for n, x, r in zip(names, out, ref):
-        errs[n] = rel_l2(x, r)
-    errs["dphi"] = rel_l2(out[4] - s["phi"], ref[4] - s["phi"])
-    _say("  " + "  ".join("%s %.3e" % kv for kv in errs.items()))
+    ps, Th, u, w, phi = out
+    _say("  dphi L2 %.3e" % rel_l2(phi - s["phi"], ref[4] - s["phi"]))
     assert np.abs(ref[3]).max() > 1e-4          # the bubble produces vertical motion
     if policy == "DBL":
-        # w and u are small residuals of cancelling FP64 terms (the acoustic
-        # balance g dt (dp/dpi - 1)); their bar is the oracle's own sensitivity
-        # to a 1e-15 relative perturbation of Theta (a few ulps), times 10
-        r = np.random.default_rng(9)
-        Thp = s["Theta"] * (1.0 + 1e-15 * r.standard_normal(s["Theta"].shape))
-        refp = om.ndc_run(s["ps"], Thp, s["u"], s["w"], s["phi"], 60.0, 10)
-        sens = {n: rel_l2(a, b) for n, a, b in zip(names, refp, ref)}
-        _say("  oracle sensitivity " + "  ".join("%s %.3e" % kv for kv in sens.items()))
-        for n in names:
-            assert errs[n] <= max(DBL_TOL, 10.0 * sens[n]), n
+        compare_dbl("ps", ps, ref[0], m["areaCell"])
+        compare_dbl("Theta", Th, ref[1], m["areaCell"])
+        compare_dbl("phi", phi, ref[4], m["areaCell"])
+        bw, bu = nh_dbl_bounds(ref[4], 9.80616, 60.0, 10, float(m["dEdge"].min()))
+        compare_abs("w", w, ref[3], bw)
+        compare_abs("u", u, ref[2], bu)
     else:
-        assert errs["ps"] <= MIX_TOL and errs["Theta"] <= MIX_TOL and errs["phi"] <= MIX_TOL
-        assert rel_l2(out[3], ref[3]) <= 1e-2
+        compare("ps", ps, ref[0], m["areaCell"], MIX_TOL, MIX_TOL)
+        compare("Theta", Th, ref[1], m["areaCell"], MIX_TOL, MIX_TOL)
+        compare("phi", phi, ref[4], m["areaCell"], MIX_TOL, MIX_TOL)
+        compare("u", u, ref[2], None, MIX_U_TOL, MIX_U_TOL)
+        compare("w", w, ref[3], m["areaCell"], MIX_U_TOL, MIX_U_TOL)
 
 
 @pytest.mark.parametrize("policy", ["DBL", "MIX"])
@@ -137,14 +142,14 @@ def test_tracer_parity_g4(mpdc, oracle_mod, mesh_cache, policy):
     pol = getattr(mpdc, "POLICY_" + policy)
     _say("tracer G4x5x4 6 steps", policy)
     st, dpi, q = gpu_tracer(mpdc, g, tr, dt, 6, pol)
-    eq = max(rel_l2(q[:, :, t], q_o[:, :, t], m["areaCell"]) for t in range(q.shape[2]))
-    ed = rel_l2(dpi, dpi_o, m["areaCell"])
-    _say("  q %.3e  dpi %.3e  min %.3e max %.3e" % (eq, ed, q.min(), q.max()))
-    assert ed <= DBL_TOL
-    if policy == "DBL":
-        assert eq <= DBL_TOL
-    else:
-        assert eq <= MIX_TOL
+    _say("  min %.3e max %.3e" % (q.min(), q.max()))
+    compare_dbl("dpi", dpi, dpi_o, m["areaCell"])
+    for t in range(q.shape[2]):
+        if policy == "DBL":
+            compare_dbl("q%d" % t, q[:, :, t], q_o[:, :, t], m["areaCell"])
+        else:
+            compare("q%d" % t, q[:, :, t], q_o[:, :, t], m["areaCell"], MIX_TOL, MIX_TOL)
+    if policy != "DBL":
         assert q.min() >= -1e-6 and q.max() <= 1.0 + 1e-6
 
 
@@ -159,9 +164,9 @@ def test_hdc_ensemble_members_match_single_runs(mpdc, oracle_mod, mesh_cache):
     st, (ps, Th, u) = gpu_hdc(mpdc, g, ens, K, 900.0, 5, mpdc.POLICY_DBL, M=M)
     for j in range(M):
         ps_o, Th_o, u_o = om.hdc_run(ens["ps"][:, j], ens["Theta"][:, :, j], ens["u"][:, :, j], 900.0, 5)
-        assert rel_l2(ps[:, j], ps_o) <= DBL_TOL
-        assert rel_l2(Th[:, :, j], Th_o) <= DBL_TOL
-        assert rel_l2(u[:, :, j], u_o) <= DBL_TOL
+        compare_dbl("ps m%d" % j, ps[:, j], ps_o)
+        compare_dbl("Theta m%d" % j, Th[:, :, j], Th_o)
+        compare_dbl("u m%d" % j, u[:, :, j], u_o)
 
 
 def test_graph_replay_and_launch_shapes_are_bitwise_identical(mpdc, mesh_cache):

@@ -14,12 +14,9 @@ import numpy as np
 import pytest
 
 from paper_2404_08849_amd.inputs import initial as ic
-from gpu_helpers import rel_l2
+from gpu_helpers import MIX_TOL, MIX_U_TOL, compare, compare_dbl, rel_l2
 
 pytestmark = pytest.mark.gpu
-
-DBL_TOL = 1e-12
-MIX_TOL = 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -69,12 +66,15 @@ def test_terrain_parity_g4(mpdc, oracle_mod, mesh_cache, policy):
     g = mpdc.Mesh(m)
     _say("hdc G4x%d over a 3 km mountain, %d steps" % (K, n), policy)
     ps, Th, u = _run(mpdc, g, s, K, dt, n, getattr(mpdc, "POLICY_" + policy), phis)
-    e = (rel_l2(ps, ref[0], m["areaCell"]), rel_l2(Th, ref[1], m["areaCell"]), rel_l2(u, ref[2]))
-    _say("  ps %.3e  Theta %.3e  u %.3e" % e)
+    A = m["areaCell"]
     if policy == "DBL":
-        assert max(e) <= DBL_TOL
+        compare_dbl("ps", ps, ref[0], A)
+        compare_dbl("Theta", Th, ref[1], A)
+        compare_dbl("u", u, ref[2])
     else:
-        assert e[0] <= MIX_TOL and e[1] <= MIX_TOL and e[2] <= 1e-3
+        compare("ps", ps, ref[0], A, MIX_TOL, MIX_TOL)
+        compare("Theta", Th, ref[1], A, MIX_TOL, MIX_TOL)
+        compare("u", u, ref[2], None, MIX_U_TOL, MIX_U_TOL)
     # the terrain acted: the same run on a flat surface differs
     flat = _run(mpdc, g, s, K, dt, n, getattr(mpdc, "POLICY_" + policy), np.zeros(m["nCells"]))
     assert rel_l2(flat[2], u) > 1e-3
@@ -91,8 +91,9 @@ def test_terrain_members_share_the_surface(mpdc, oracle_mod, mesh_cache):
     ps, Th, u = _run(mpdc, g, ens, K, dt, n, mpdc.POLICY_DBL, phis, M=M)
     for j in range(M):
         r = om.hdc_run(ens["ps"][:, j], ens["Theta"][:, :, j], ens["u"][:, :, j], dt, n, phis=phis)
-        assert rel_l2(ps[:, j], r[0]) <= DBL_TOL and rel_l2(Th[:, :, j], r[1]) <= DBL_TOL
-        assert rel_l2(u[:, :, j], r[2]) <= DBL_TOL
+        compare_dbl("ps m%d" % j, ps[:, j], r[0], m["areaCell"])
+        compare_dbl("Theta m%d" % j, Th[:, :, j], r[1], m["areaCell"])
+        compare_dbl("u m%d" % j, u[:, :, j], r[2])
 
 
 def test_fp32_pressure_gradient_is_less_accurate(mpdc, oracle_mod, mesh_cache):
@@ -109,10 +110,13 @@ def test_fp32_pressure_gradient_is_less_accurate(mpdc, oracle_mod, mesh_cache):
         res = {}
         for pol in ("MIX", "MIX_PGF32"):
             ps, Th, u = _run(mpdc, g, s, K, dt, n, getattr(mpdc, "POLICY_" + pol), phis)
+            if pol == "MIX":
+                ps_mix, u_mix = ps, u
             res[pol] = (rel_l2(ps, ref[0], m["areaCell"]), rel_l2(u, ref[2]))
             _say("hdc G5x%d %s, %d steps, %s: ps %.3e  u %.3e" % ((K, case, n, pol) + res[pol]))
-        # the mixed policy passes its bar; the FP32 force is over 8x less accurate
-        assert res["MIX"][0] <= MIX_TOL and res["MIX"][1] <= 1e-3
+        # the mixed policy passes its bars; the FP32 force is over 8x less accurate
+        compare("ps MIX", ps_mix, ref[0], m["areaCell"], MIX_TOL, MIX_TOL)
+        compare("u MIX", u_mix, ref[2], None, MIX_U_TOL, MIX_U_TOL)
         assert res["MIX_PGF32"][0] > 8.0 * res["MIX"][0] and res["MIX_PGF32"][1] > 8.0 * res["MIX"][1]
 
 
@@ -131,5 +135,9 @@ def test_sgl_parity_and_ordering(mpdc, oracle_mod, mesh_cache):
         assert np.isfinite(ps).all() and np.isfinite(u).all()
         err[pol] = (rel_l2(ps, ref[0], m["areaCell"]), rel_l2(u, ref[2]))
         _say("hdc G5x%d jet, %d steps, %s: ps %.3e  u %.3e" % ((K, n, pol) + err[pol]))
-    assert err["SGL"][0] <= MIX_TOL and err["SGL"][1] <= 1e-3
+    # SGL computes the pressure-gradient term and everything else in FP32: it is
+    # held to the surface-pressure bar only (both norms); its wind is checked to
+    # be worse than MIX's, as the paper finds
+    compare("ps SGL", ps, ref[0], m["areaCell"], MIX_TOL, MIX_TOL)
+    assert err["SGL"][1] <= 1e-3
     assert err["SGL"][1] > 8.0 * err["MIX"][1]

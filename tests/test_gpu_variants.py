@@ -5,8 +5,9 @@ advection, pressure-gradient operator) in FP64 with one FP32 rounding as a
 tendency; MIX_DBL_MASS forms the continuity mass flux in FP64 (the local mass
 switch of Section 2.3); MIX_F32_DIV accumulates the cell divergence of the
 FP32 mass flux in FP32 (the literal reading of Section 2.3).  All three are
-held to the mixed policy's bars (1e-5 normalised L2 on the surface pressure
-and Theta, 1e-3 on u); the global mass sum tells MIX_F32_DIV apart: the
+held to the mixed policy's bars (1e-5 on the surface pressure, Theta and
+phi, 16 FP32 unit roundoffs on u and w, each in normalised L2 and relative
+max error); the global mass sum tells MIX_F32_DIV apart: the
 other policies conserve it to FP64 rounding, the FP32 divergence does not.
 """
 import ctypes
@@ -15,11 +16,9 @@ import numpy as np
 import pytest
 
 from paper_2404_08849_amd.inputs import initial as ic
-from gpu_helpers import gpu_hdc, gpu_ndc, rel_l2
+from gpu_helpers import MIX_TOL, MIX_U_TOL, compare, gpu_hdc, gpu_ndc, rel_l2
 
 pytestmark = pytest.mark.gpu
-
-MIX_TOL = 1e-5
 VARIANTS = ["MIX_BOX", "MIX_DBL_MASS", "MIX_F32_DIV"]
 
 
@@ -60,11 +59,12 @@ def test_variant_hdc_parity_g4(mpdc, hdc_g4, policy):
     _say("hdc G4x30 10 steps", policy)
     st, out = gpu_hdc(mpdc, g, s, K, 600.0, 10, getattr(mpdc, "POLICY_" + policy))
     ps, Th, u = out
-    e = (rel_l2(ps, ps_o, m["areaCell"]), rel_l2(Th, Th_o, m["areaCell"]), rel_l2(u, u_o))
     em = (rel_l2(mix[0], ps_o, m["areaCell"]), rel_l2(mix[1], Th_o, m["areaCell"]), rel_l2(mix[2], u_o))
     du = rel_l2(u - s["u"], u_o - s["u"])
-    _say("  ps %.3e  Theta %.3e  u %.3e  du %.3e   (MIX: %.3e %.3e %.3e)" % (e + (du,) + em))
-    assert e[0] <= MIX_TOL and e[1] <= MIX_TOL and e[2] <= 1e-3
+    _say("  du %.3e   (MIX: ps %.3e Theta %.3e u %.3e)" % ((du,) + em))
+    compare("ps", ps, ps_o, m["areaCell"], MIX_TOL, MIX_TOL)
+    compare("Theta", Th, Th_o, m["areaCell"], MIX_TOL, MIX_TOL)
+    compare("u", u, u_o, None, MIX_U_TOL, MIX_U_TOL)
     # the variant ran its own arithmetic: it differs from MIX somewhere
     assert any(not np.array_equal(a, b) for a, b in zip(out, mix))
 
@@ -78,12 +78,10 @@ def test_variant_ndc_parity_g4(mpdc, oracle_mod, mesh_cache, policy):
     g = mpdc.Mesh(m)
     _say("ndc G4x20 10 steps", policy)
     st, out = gpu_ndc(mpdc, g, s, K, 60.0, 10, getattr(mpdc, "POLICY_" + policy))
-    names = ["ps", "Theta", "u", "w", "phi"]
-    errs = {n: rel_l2(x, r) for n, x, r in zip(names, out, ref)}
-    _say("  " + "  ".join("%s %.3e" % kv for kv in errs.items()))
-    assert all(np.isfinite(x).all() for x in out)
-    assert errs["ps"] <= MIX_TOL and errs["Theta"] <= MIX_TOL and errs["phi"] <= MIX_TOL
-    assert errs["w"] <= 1e-2
+    A = m["areaCell"]
+    for n, x, r, w, tol in zip(["ps", "Theta", "u", "w", "phi"], out, ref, [A, A, None, A, A],
+                               [MIX_TOL, MIX_TOL, MIX_U_TOL, MIX_U_TOL, MIX_TOL]):
+        compare(n, x, r, w, tol, tol)
 
 
 @pytest.mark.parametrize("policy", VARIANTS)
@@ -99,9 +97,9 @@ def test_variant_ensemble_members(mpdc, oracle_mod, mesh_cache, policy):
     st, (ps, Th, u) = gpu_hdc(mpdc, g, ens, K, 900.0, 5, getattr(mpdc, "POLICY_" + policy), M=M)
     for j in range(M):
         ps_o, Th_o, u_o = om.hdc_run(ens["ps"][:, j], ens["Theta"][:, :, j], ens["u"][:, :, j], 900.0, 5)
-        e = (rel_l2(ps[:, j], ps_o), rel_l2(Th[:, :, j], Th_o), rel_l2(u[:, :, j], u_o))
-        _say("  member %d: ps %.3e  Theta %.3e  u %.3e" % ((j,) + e))
-        assert e[0] <= MIX_TOL and e[1] <= MIX_TOL and e[2] <= 1e-3
+        compare("ps m%d" % j, ps[:, j], ps_o, m["areaCell"], MIX_TOL, MIX_TOL)
+        compare("Theta m%d" % j, Th[:, :, j], Th_o, m["areaCell"], MIX_TOL, MIX_TOL)
+        compare("u m%d" % j, u[:, :, j], u_o, None, MIX_U_TOL, MIX_U_TOL)
 
 
 @pytest.mark.parametrize("policy", VARIANTS)

@@ -358,6 +358,23 @@ double mpdc_step_bytes(const mpdc_state *st);
  * the first stage's launch (stage = 0 here).  Returns 0 for a bad id or stage. */
 double mpdc_stage_kernel_bytes(const mpdc_state *st, int kernel_id, int stage);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the error
+ * norms of mpdc_diagnostics without a state or a workspace.  Over the FP64
+ * device arrays x and ref [n][inner] and the optional weights [n] (NULL:
+ * unweighted), out[0..4] receives the normalised L1, L2 and Linf of x
+ * against ref (sum w|x - r| / sum w|r|, sqrt(sum w (x - r)^2 / sum w r^2),
+ * max|x - r| / max|r|) and the min and max of x.  The per-work-group partial
+ * sums live in a static device array of 1024 x 9 doubles (72 KiB), which
+ * each GPU the library runs on holds until the process ends; the reduction
+ * strides over any n x inner with at most 1024 work-groups, so every size
+ * fits it.  Nothing is allocated on the device.  Every call on one GPU shares
+ * that array: calls that overlap on one GPU (several streams or threads)
+ * race.  Synchronous on stream.  Errors: INVAL (null pointer, n or inner
+ * zero, n x inner overflowing), DEVICE. */
+int mpdc_error_norms_noalloc(const double *x, const double *ref, const double *weight, size_t n, size_t inner,
+                             double *out, void *stream);
+
 /* Measurement utility, not a step of the method: the device's streaming
  * bandwidth, which the stencil kernels' achieved bandwidth is read against.
  * Times nreps launches of a plain streaming kernel over `bytes` bytes (a

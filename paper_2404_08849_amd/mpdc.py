@@ -95,6 +95,8 @@ def _load():
                                               ctypes.POINTER(ctypes.c_int)]),
         "mpdc_autotune": (ctypes.c_int, [_vp, ctypes.c_char_p, _vp]),
         "mpdc_step_bytes": (ctypes.c_double, [_vp]),
+        "mpdc_error_norms_noalloc": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_size_t, ctypes.c_size_t,
+                                                    ctypes.POINTER(ctypes.c_double), _vp]),
         "mpdc_stream_time": (ctypes.c_int, [ctypes.c_int, _vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp,
                                             ctypes.POINTER(ctypes.c_double)]),
         "mpdc_state_destroy": (None, [_vp]),
@@ -129,6 +131,18 @@ def _i32(a):
 
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def error_norms_noalloc(x, ref, weight=None, stream=None):
+    """mpdc_error_norms_noalloc over the FP64 device tensors x and ref ([n][...])
+    and optional weights [n]: (l1, l2, linf, min, max)."""
+    out = (ctypes.c_double * 5)()
+    n = x.shape[0]
+    inner = x.numel() // n if n else 0
+    _check(lib.mpdc_error_norms_noalloc(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(ref.data_ptr()),
+                                        ctypes.c_void_p(weight.data_ptr() if weight is not None else 0), n, inner,
+                                        out, _stream(stream)))
+    return tuple(out)
 
 
 STREAM_READ, STREAM_WRITE, STREAM_COPY = 0, 1, 2

@@ -81,8 +81,8 @@ def parse():
     p.add_argument("--no-dbl", action="store_true", help="skip the all-FP64 timing")
     p.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     p.add_argument("--no-variants", action="store_true",
-                   help="skip the mixed-policy variants (MIX_BOX, MIX_DBL_MASS, MIX_F32_DIV; MIX_PGF32 for HDC) of "
-                             "the layered dycores")
+                   help="skip the policy variants (MIX_BOX, MIX_DBL_MASS, MIX_F32_DIV, MIX_PGF32 and SGL of the "
+                        "layered dycores; SGL of the tracer transport)")
     p.add_argument("--profile-steps", type=int, default=20,
                    help="steps run with HIP events between launches for per-kernel durations")
     p.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -610,9 +610,12 @@ def main():
 
     # mixed-policy variants beside MIX (layered dycores only)
     variants, var_keys = None, {}
-    if w["model"] in ("HDC", "NDC") and not args.no_variants:
+    if w["model"] in ("HDC", "NDC", "TRACER") and not args.no_variants:
         variants = {}
-        for name in ("MIX_BOX", "MIX_DBL_MASS", "MIX_F32_DIV") + (("MIX_PGF32", "SGL") if w["model"] == "HDC" else ()):
+        # (the all-FP32 tracer policy has no vertical step)
+        names = ((() if w.get("vflux") else ("SGL",)) if w["model"] == "TRACER" else
+                 ("MIX_BOX", "MIX_DBL_MASS", "MIX_F32_DIV", "MIX_PGF32", "SGL"))
+        for name in names:
             s_v, sec_v = timed_run(torch, mpdc, g, w, st, getattr(mpdc, "POLICY_" + name), args.steps, args.warmup,
                                    stream, not args.no_autotune, fixed.get(name.lower()))
             shp = s_v.launch_shapes
@@ -620,7 +623,7 @@ def main():
             av = accuracy_run(torch, mpdc, g, w, st, stream, {name.lower(): shp}, names=(name,))
             var_keys[name] = av[name]
             variants[name] = {"value": units / sec_v, "ms_per_step": sec_v * 1e3, "speed_vs_mix": sec_mix / sec_v,
-                              "vs_dbl_l2": rel_l2(av[name], acc["DBL"]), "mass_drift": av[name + "_mass_drift"],
+                              "vs_dbl_l2": rel_l2(av[name], acc["DBL"]), "mass_drift": av.get(name + "_mass_drift"),
                               "nonfinite": av[name + "_nonfinite"], "launch_shapes": shp}
 
     del s_mix

@@ -85,20 +85,48 @@ extern "C" {
 #define MPDC_POLICY_MIX_BOX 2
 #define MPDC_POLICY_MIX_DBL_MASS 3
 #define MPDC_POLICY_MIX_F32_DIV 4
-/* MIX_PGF32 (hydrostatic dycore only): the precision-sensitive terms of
- * Section 2.3 -- the column diagnostics of Eqs. 8-9 (pressure, specific
- * volume, geopotential) and the pressure-gradient and gravity term of Eq. 5
- * -- in FP32, as a single-precision model computes them, the rest as MIX.
- * Over terrain these two large terms nearly cancel (Section 4), which is
- * where FP32 fails. */
+/* MIX_PGF32 (hydrostatic and non-hydrostatic dycore): the precision-sensitive
+ * terms of Section 2.3 -- the column diagnostics of Eqs. 8-9 (pressure,
+ * specific volume, geopotential; non-hydrostatic: the equation of state,
+ * the implicit column system and its solution, mu) and the pressure-gradient
+ * and gravity term of Eq. 5 -- in FP32, as a single-precision model computes
+ * them, the rest as MIX.  Over terrain these two large terms nearly cancel
+ * (Section 4), which is where FP32 fails. */
 #define MPDC_POLICY_MIX_PGF32 5
-/* SGL (hydrostatic dycore only): every term in FP32 -- the reductions of
- * MIX, the FP32 cell divergence of MIX_F32_DIV, the FP32 diagnostics and
- * pressure-gradient term of MIX_PGF32, and the vertex mass and potential
- * vorticity in FP32 -- the single-precision configuration the paper starts
- * from (Section 2.2) and finds unacceptable (Section 4.1).  The prognostic
- * state is still stored in FP64 and updated with the FP32 tendencies. */
+/* SGL (hydrostatic and non-hydrostatic dycore, tracer transport): every term
+ * in FP32 -- the dycores: the reductions of MIX, the FP32 cell divergence of
+ * MIX_F32_DIV, the FP32 diagnostics, column solve and pressure-gradient term
+ * of MIX_PGF32, and the vertex mass and potential vorticity in FP32; the
+ * tracer transport: also the layer-mass continuity, with the mass flux read
+ * as FP32 (no vertical tracer step: MPDC_E_UNSUPPORTED for a vertical flux)
+ * -- the single-precision configuration the paper starts from (Section 2.2),
+ * finds unacceptable (Section 4.1) and times for all three solvers
+ * (Table 2).  The dycores' prognostic state is still stored in FP64 and
+ * updated with the FP32 tendencies. */
 #define MPDC_POLICY_SGL 6
+/* TERMS (hydrostatic dycore, one member): the per-term precision table of
+ * the iterative precision reduction (Section 2.2, Eqs. 1-2).  Each term of
+ * the stage runs in FP32 if its bit is set in mpdc_config.term_fp32, else in
+ * FP64: a term in FP32 takes its inputs rounded to FP32 and its result is
+ * kept rounded from FP32; the prognostic state stays FP64.  The terms run
+ * as separate, unfused kernels (a tool for choosing a split, not the timed
+ * path).  No bit set: an all-FP64 stage; the bits of MIX's FP32 terms
+ * (MPDC_TERMS_MIX) reproduce the mixed split to FP32 rounding. */
+#define MPDC_POLICY_TERMS 7
+#define MPDC_TERM_MASS_FLUX 0           /* F = dpi_e u (Eq. 3)                                  */
+#define MPDC_TERM_DIVERGENCE 1          /* cell divergence, dpi_s/dt, vertical mass flux (Eq. 3) */
+#define MPDC_TERM_KINETIC_ENERGY 2      /* K and -grad K (Eq. 5)                                */
+#define MPDC_TERM_VORTICITY 3           /* zeta at the vertices (Eq. 5)                        */
+#define MPDC_TERM_VERTEX_MASS 4         /* kite-weighted dpi_v and q = (zeta + f)/dpi_v         */
+#define MPDC_TERM_CORIOLIS 5            /* TRiSK PV flux (Eq. 5)                               */
+#define MPDC_TERM_THETA_FLUX 6          /* third-order theta_m flux and its divergence (Eq. 4) */
+#define MPDC_TERM_VERTICAL_ADVECTION 7  /* vertical advection of u and theta (Eqs. 4-5)        */
+#define MPDC_TERM_COLUMN_DIAG 8         /* pressure, specific volume, geopotential (Eqs. 8-9)  */
+#define MPDC_TERM_PRESSURE_GRADIENT 9   /* pressure-gradient force and gravity (Eq. 5)         */
+#define MPDC_TERM_COUNT 10
+#define MPDC_TERMS_MIX ((1u << MPDC_TERM_MASS_FLUX) | (1u << MPDC_TERM_KINETIC_ENERGY) | \
+                        (1u << MPDC_TERM_VORTICITY) | (1u << MPDC_TERM_CORIOLIS) |           \
+                        (1u << MPDC_TERM_THETA_FLUX) | (1u << MPDC_TERM_VERTICAL_ADVECTION))
 
 /* ---- state fields for mpdc_state_write / mpdc_state_read (FP64 in and out) ---- */
 #define MPDC_FIELD_H 0           /* SW fluid depth h          [N][M]        */
@@ -170,7 +198,9 @@ typedef struct {
                                 DBL, MIX, MIX_BOX, MIX_DBL_MASS, MIX_F32_DIV only (the
                                 non-hydrostatic solver's HEVI ordering has no such switch);
                                 otherwise MPDC_E_UNSUPPORTED                                     */
-    int32_t reserved[6];  /* must be zero                                                   */
+    int32_t term_fp32;    /* MPDC_POLICY_TERMS: bit MPDC_TERM_* set = that term in FP32; must be
+                             zero for every other policy                                    */
+    int32_t reserved[5];  /* must be zero                                                   */
 } mpdc_config;
 
 #define MPDC_DIAG_MAX_TRACERS 16  /* per-tracer entries of mpdc_diag */

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpdc.so")
 SOURCES = ["abi.cpp", "mesh.cpp", "dycore_kernels.hip", "tracer_kernels.hip", "stream_kernels.hip",
-           "norms_static.hip"]
+           "norms_static.hip", "term_kernels.hip"]
 ARCH = os.environ.get("MPDC_OFFLOAD_ARCH", "gfx950")
 
 

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <new>
@@ -137,6 +138,8 @@ struct mpdc_state {
     // dycore
     StateSet set[3];
     bool fb_off = false;   // plain RK3 stages (no forward-backward ordering)
+    unsigned term_mask = 0;                       // POLICY_TERMS: terms in FP32
+    double *tF = nullptr, *tD = nullptr, *ttheta = nullptr, *tpmid = nullptr;   // POLICY_TERMS arrays
     double *b = nullptr, *phis = nullptr, *dsig = nullptr, *sig = nullptr, *dps = nullptr, *mdot = nullptr;
     void *ke = nullptr, *hth = nullptr, *qv = nullptr, *qh = nullptr;
     double *alpha = nullptr, *phim = nullptr, *pm = nullptr, *mum = nullptr, *wstar = nullptr, *phistar = nullptr;
@@ -166,14 +169,17 @@ namespace {
 
 constexpr int kDiagBlocks = 1024;
 
-size_t rsize(int policy) { return policy == MPDC_POLICY_DBL ? sizeof(double) : sizeof(float); }
+// FP64 intermediates and no FP32 shadows: the all-FP64 policy and the per-term
+// engine (whose FP32 terms keep their results rounded, in FP64 storage)
+bool fp64_storage(int policy) { return policy == MPDC_POLICY_DBL || policy == MPDC_POLICY_TERMS; }
+size_t rsize(int policy) { return fp64_storage(policy) ? sizeof(double) : sizeof(float); }
 
 // lay out (or measure) a state's workspace
 size_t state_layout(mpdc_state *st, void *base) {
     Carver c(base);
     const long N = st->N, E = st->E, V = st->V, K = st->K, M = st->M, T = st->T;
     const long KM = K * M, K1M = (K + 1) * M;
-    const bool mix = st->policy != MPDC_POLICY_DBL;
+    const bool mix = !fp64_storage(st->policy);
     const size_t r = rsize(st->policy);
     st->partial = c.take<double>((size_t)kDiagBlocks * 9);
     st->nfpartial = c.take<unsigned long long>(kDiagBlocks);
@@ -228,6 +234,12 @@ size_t state_layout(mpdc_state *st, void *base) {
         st->Facc = c.take<double>(E * K);
         st->Macc = c.take<double>(N * (K + 1));
     }
+    if (st->policy == MPDC_POLICY_TERMS) {
+        st->tF = c.take<double>(E * K);
+        st->tD = c.take<double>(N * K);
+        st->ttheta = c.take<double>(N * K);
+        st->tpmid = c.take<double>(N * K);
+    }
     return c.off;
 }
 
@@ -274,7 +286,7 @@ int cpb_of(const mpdc_state *st, int k) {
 bool stage_stores_fp64(const mpdc_state *st, int s) {
     // (without forward-backward ordering the next stage's pressure-gradient
     // term reads this stage's FP64 Theta)
-    return s == 2 || st->policy == MPDC_POLICY_DBL || st->policy == MPDC_POLICY_MIX_BOX ||
+    return s == 2 || fp64_storage(st->policy) || st->policy == MPDC_POLICY_MIX_BOX ||
            st->policy == MPDC_POLICY_MIX_DBL_MASS || st->fb_off;
 }
 
@@ -371,6 +383,14 @@ hipError_t launch_tracer(const mpdc_state *st, TracerArgs a, int k, hipStream_t 
 }
 
 int run_dycore_step(mpdc_state *st, hipStream_t s) {
+    if (st->policy == MPDC_POLICY_TERMS) {
+        TermArgs x{st->tF, st->tD, st->ttheta, st->tpmid, st->term_mask};
+        for (int stage = 0; stage < 3; stage++) {
+            hipError_t e = launch_term_stage(stage_args(st, stage), x, s);
+            if (e != hipSuccess) return hip_fail(e, "per-term stage launch");
+        }
+        return MPDC_OK;
+    }
     for (int stage = 0; stage < 3; stage++) {
         StageArgs a = stage_args(st, stage);
         for (int k = KERNEL_CELL_A; k <= KERNEL_EDGE; k++) {
@@ -641,10 +661,18 @@ void mpdc_mesh_destroy(mpdc_mesh *m) { delete m; }
 static int check_config(const mpdc_mesh *m, const mpdc_config *c) {
     if (!m || !c) return fail(MPDC_E_INVAL, "null mesh or config");
     if (c->model < MPDC_MODEL_SW || c->model > MPDC_MODEL_TRACER) return fail(MPDC_E_INVAL, "unknown model");
-    if (c->policy < MPDC_POLICY_DBL || c->policy > MPDC_POLICY_SGL) return fail(MPDC_E_INVAL, "unknown policy");
-    if ((c->policy == MPDC_POLICY_MIX_PGF32 || c->policy == MPDC_POLICY_SGL) && c->model != MPDC_MODEL_HDC)
-        return fail(MPDC_E_UNSUPPORTED, "the FP32 pressure-gradient variants are built for the hydrostatic dycore only");
-    if (c->policy > MPDC_POLICY_MIX && c->model != MPDC_MODEL_HDC && c->model != MPDC_MODEL_NDC)
+    if (c->policy < MPDC_POLICY_DBL || c->policy > MPDC_POLICY_TERMS) return fail(MPDC_E_INVAL, "unknown policy");
+    if (c->policy == MPDC_POLICY_TERMS &&
+        (c->model != MPDC_MODEL_HDC || c->M != 1 || c->accumulate_flux || c->forward_backward_off))
+        return fail(MPDC_E_UNSUPPORTED, "the per-term precision engine is built for one member of the hydrostatic "
+                                        "dycore, with forward-backward stages and no flux accumulation");
+    if (c->term_fp32 != 0 && c->policy != MPDC_POLICY_TERMS)
+        return fail(MPDC_E_INVAL, "term_fp32 is for MPDC_POLICY_TERMS only");
+    if ((unsigned)c->term_fp32 >> MPDC_TERM_COUNT) return fail(MPDC_E_INVAL, "term_fp32 has bits beyond the terms");
+    const bool layered = c->model == MPDC_MODEL_HDC || c->model == MPDC_MODEL_NDC;
+    if (c->policy == MPDC_POLICY_SGL && !layered && c->model != MPDC_MODEL_TRACER)
+        return fail(MPDC_E_UNSUPPORTED, "the all-FP32 policy is built for the layered dycores and the tracer transport");
+    if (c->policy > MPDC_POLICY_MIX && c->policy != MPDC_POLICY_SGL && !layered)
         return fail(MPDC_E_UNSUPPORTED, "the mixed-policy variants are built for the layered dycores only");
     if (c->K < 1 || c->M < 1 || c->K > 512 || c->M > 64) return fail(MPDC_E_INVAL, "K must be 1..512 and M 1..64");
     if (c->model == MPDC_MODEL_SW && c->K != 1) return fail(MPDC_E_UNSUPPORTED, "shallow water needs K = 1");
@@ -685,6 +713,7 @@ static mpdc_state *new_state(const mpdc_mesh *m, const mpdc_config *c) {
     st->policy = c->policy;
     st->accumulate = c->accumulate_flux != 0;
     st->fb_off = c->forward_backward_off != 0;
+    st->term_mask = (unsigned)c->term_fp32;
     st->K = c->K;
     st->M = c->M;
     st->T = c->model == MPDC_MODEL_TRACER ? c->T : 0;
@@ -724,6 +753,19 @@ int mpdc_state_create(const mpdc_mesh *m, const mpdc_config *c, void *dev_ws, si
     std::vector<double> dsig(st->K);
     for (int k = 0; k < st->K; k++) dsig[k] = st->sigma[k + 1] - st->sigma[k];
     hipError_t e = hipMemsetAsync(dev_ws, 0, need, s);
+    // Test switch: MPDC_POISON_STAGE_SETS=1 fills the FP64 u and Theta of the two
+    // stage-output sets with NaN.  Under the mixed policies whose stages store
+    // only FP32 shadows (stage_stores_fp64) those arrays are written by no
+    // stage, so a kernel that read them would turn the state into NaN; with the
+    // switch the results must stay finite and bitwise unchanged.
+    const char *poison = std::getenv("MPDC_POISON_STAGE_SETS");
+    if (e == hipSuccess && poison && poison[0] == '1' && st->model != MPDC_MODEL_TRACER) {
+        const size_t nu = (size_t)st->E * st->K * st->M * 8, nt = (size_t)st->N * st->K * st->M * 8;
+        for (int j = 1; j < 3 && e == hipSuccess; j++) {
+            e = hipMemsetAsync(st->set[j].u, 0xff, nu, s);
+            if (e == hipSuccess && st->set[j].Th) e = hipMemsetAsync(st->set[j].Th, 0xff, nt, s);
+        }
+    }
     if (e == hipSuccess) e = hipMemcpyAsync(st->dsig, dsig.data(), dsig.size() * 8, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(st->sig, st->sigma.data(), st->sigma.size() * 8, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -750,6 +792,8 @@ int mpdc_state_write(mpdc_state *st, int f, const void *src, int src_on_device, 
     if (f == MPDC_FIELD_TR_VFLUX) {
         if (tracer_vert_columns(st->K, st->T) < 1)
             return fail(MPDC_E_UNSUPPORTED, "a column of K x T tracers does not fit the vertical step's LDS");
+        if (st->policy == MPDC_POLICY_SGL)
+            return fail(MPDC_E_UNSUPPORTED, "the all-FP32 tracer policy has no vertical step (its column solve is FP64)");
         if (!st->has_vflux) drop_graphs(st);   // the step gains its vertical kernel
         st->has_vflux = true;
     }
@@ -767,7 +811,7 @@ int mpdc_state_write(mpdc_state *st, int f, const void *src, int src_on_device, 
                            (float *)st->q[st->parity], n);
         HIP_TRY(hipGetLastError());
     }
-    if (st->policy != MPDC_POLICY_DBL && st->model != MPDC_MODEL_TRACER) {
+    if (!fp64_storage(st->policy) && st->model != MPDC_MODEL_TRACER) {
         StageArgs a = stage_args(st, 0);
         // regenerate the FP32 shadows of the current state (set 0)
         a.u_o = st->set[0].u;
@@ -937,6 +981,8 @@ int mpdc_tracer_couple(mpdc_state *tracer, mpdc_state *dycore, void *stream) {
         return fail(MPDC_E_INVAL, "the tracer step must span the accumulated dycore steps (dt_tracer = n dt)");
     if (tracer_vert_columns(tracer->K, tracer->T) < 1)
         return fail(MPDC_E_UNSUPPORTED, "a column of K x T tracers does not fit the vertical step's LDS");
+    if (tracer->policy == MPDC_POLICY_SGL)
+        return fail(MPDC_E_UNSUPPORTED, "the all-FP32 tracer policy has no vertical step (its column solve is FP64)");
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(launch_couple(dycore->Facc, dycore->Macc, tracer->F, tracer->vflux, tracer->E * tracer->K,
                           tracer->N * (tracer->K + 1), dycore->acc_steps, s));
@@ -948,6 +994,8 @@ int mpdc_tracer_couple(mpdc_state *tracer, mpdc_state *dycore, void *stream) {
 
 int mpdc_time_kernel(mpdc_state *st, int kernel_id, int nreps, void *stream, double *ms_avg) {
     if (!st || !ms_avg || nreps < 1) return fail(MPDC_E_INVAL, "bad arguments");
+    if (st->policy == MPDC_POLICY_TERMS)
+        return fail(MPDC_E_UNSUPPORTED, "the per-term precision engine has no fused kernel classes to time");
     hipStream_t s = (hipStream_t)stream;
     const bool tr = st->model == MPDC_MODEL_TRACER;
     const int nk = tr ? 3 : 4;
@@ -1016,8 +1064,9 @@ int mpdc_stream_time(int mode, void *dst, const void *src, size_t bytes, int nre
 static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
     const double N = (double)st->N, E = (double)st->E, V = (double)st->V, K = st->K, M = st->M;
     const double KM = K * M, K1M = (K + 1) * M;
+    if (st->policy == MPDC_POLICY_TERMS) return 0;   // (the per-term engine has no byte model)
     const double r = (double)rsize(st->policy);
-    const bool mix = st->policy != MPDC_POLICY_DBL;
+    const bool mix = !fp64_storage(st->policy);
     const bool box = st->policy == MPDC_POLICY_MIX_BOX;
     const bool u64 = box || st->policy == MPDC_POLICY_MIX_DBL_MASS;   // cell_a reads the FP64 velocity
     const bool first = (stage == 0);
@@ -1107,6 +1156,8 @@ double mpdc_kernel_bytes(const mpdc_state *st, int id) {
 
 int mpdc_profile_steps(mpdc_state *st, int nsteps, void *stream, double *ms_total, int *launches) {
     if (!st || !ms_total || !launches || nsteps < 0) return fail(MPDC_E_INVAL, "bad arguments");
+    if (st->policy == MPDC_POLICY_TERMS)
+        return fail(MPDC_E_UNSUPPORTED, "the per-term precision engine has no fused kernel classes to profile");
     hipStream_t s = (hipStream_t)stream;
     const bool tr = st->model == MPDC_MODEL_TRACER;
     const int nk = tr ? 3 : 4;
@@ -1236,6 +1287,7 @@ static int tune_shapes(mpdc_state *st, void *stream) {
 
 int mpdc_autotune(mpdc_state *st, const char *cache_path, void *stream) {
     if (!st) return fail(MPDC_E_INVAL, "null state");
+    if (st->policy == MPDC_POLICY_TERMS) return MPDC_OK;   // fixed shapes: nothing to tune
     const int nk = st->model == MPDC_MODEL_TRACER ? 3 : 4;
     const std::string key = tune_key(st);
     if (key.empty()) return fail(MPDC_E_DEVICE, "cannot read the device properties for the autotune key");

@@ -184,6 +184,30 @@ hipError_t launch_nonfinite(const double *x, const float *x32, long n, unsigned 
 hipError_t launch_cfl(const double *u, const double *dinv, long E, long inner, double dt, double *partial,
                       int nblocks, hipStream_t s);
 
+// ---- per-term precision engine of the hydrostatic dycore ----
+// bit t of the term mask: term t in FP32 (the MPDC_TERM_* bits of mpdc.h)
+enum {
+    TERM_MASS_FLUX = MPDC_TERM_MASS_FLUX,
+    TERM_DIVERGENCE = MPDC_TERM_DIVERGENCE,
+    TERM_KINETIC_ENERGY = MPDC_TERM_KINETIC_ENERGY,
+    TERM_VORTICITY = MPDC_TERM_VORTICITY,
+    TERM_VERTEX_MASS = MPDC_TERM_VERTEX_MASS,
+    TERM_CORIOLIS = MPDC_TERM_CORIOLIS,
+    TERM_THETA_FLUX = MPDC_TERM_THETA_FLUX,
+    TERM_VERTICAL_ADVECTION = MPDC_TERM_VERTICAL_ADVECTION,
+    TERM_COLUMN_DIAG = MPDC_TERM_COLUMN_DIAG,
+    TERM_PRESSURE_GRADIENT = MPDC_TERM_PRESSURE_GRADIENT
+};
+struct TermArgs {
+    double *F;       // [E][K] mass flux, then the momentum's advective sum
+    double *D;       // [N][K] prefix sums of the divergence, then the theta flux divergence
+    double *theta;   // [N][K] theta of the stage's input
+    double *pmid;    // [N][K] mid-layer pressure of the updated state
+    unsigned mask;   // bit t set: term t in FP32
+};
+// one RK stage of the hydrostatic model (M = 1) in the per-term precisions
+hipError_t launch_term_stage(const StageArgs &a, const TermArgs &x, hipStream_t s);
+
 // ---- total energy of the dycore state (diagnostics) ----
 struct EnergyArgs {
     int model, K, M;

@@ -76,6 +76,7 @@ __device__ __forceinline__ double fmar(double a, double b, double c) { return __
 // x^y for x > 0 as exp(y log x) (the exponents here are fixed gas constants
 // and x a pressure ratio near 1, so this stays within a few ulps of pow)
 __device__ __forceinline__ double powpos(double x, double y) { return exp(y * log(x)); }
+__device__ __forceinline__ float powpos(float x, float y) { return expf(y * logf(x)); }
 
 template <typename R> __device__ __forceinline__ const R *u_prev_ptr(const StageArgs &a) {
     if constexpr (sizeof(R) == 8) return a.u_s;
@@ -1120,6 +1121,12 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
             }
         } else {
             // ---- implicit vertical acoustic solve of the column (FP64) ----
+            // The variant VAR_PGF32 (and so SGL) computes the equation of
+            // state, the column system and its solution, the specific volume,
+            // the geopotential and mu in FP32 (RS); every value is still kept in
+            // the FP64 arrays, rounded from its FP32 result.
+            constexpr bool P32 = VAR == VAR_PGF32;
+            using RS = typename std::conditional<P32, float, double>::type;
             const int K1 = K + 1;
             const long K1M = (long)K1 * M;
             const long cb = (long)i * K1M;
@@ -1146,10 +1153,10 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                     tho.v[j] = Th_new[j];
                     dpn[j] = dsg[j] * (ps_new[j] - a.ptop);
                     th32.v[j] = (float)(Th_new[j] / dpn[j]);
-                    const double dphi = phs_k[j] - phs_k1[j];
-                    const double p = a.p0 * powpos(a.rd * Th_new[j] / (a.p0 * dphi), a.gamma);
-                    sP[base + km0 + j] = p;
-                    sC[base + km0 + j] = a.gamma * a.grav * a.dts * p / dphi;
+                    const RS dphi = (RS)phs_k[j] - (RS)phs_k1[j];
+                    const RS p = (RS)a.p0 * powpos((RS)a.rd * (RS)Th_new[j] / ((RS)a.p0 * dphi), (RS)a.gamma);
+                    sP[base + km0 + j] = (double)p;
+                    sC[base + km0 + j] = (double)((RS)a.gamma * (RS)a.grav * (RS)a.dts * p / dphi);
                 }
                 if (a.store64) stp<double, L>(a.Th_o + (long)i * KM + km0, tho);
                 if (a.th32_o) stp<float, L>(a.th32_o + (long)i * KM + km0, th32);
@@ -1165,13 +1172,14 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                     if (k < 1) continue;
                     // row r = k-1 for interior interface k (between layers k-1 and k)
                     const double dpm = a.dsig[k - 1] * (ps_new[j] - a.ptop);
-                    const double D = a.grav * a.dts / (0.5 * (dpm + dpn[j]));
-                    const double Cm = sC[base + (k - 1) * M + mm], Ck = sC[base + k * M + mm];
+                    const RS D = (RS)a.grav * (RS)a.dts / ((RS)0.5 * ((RS)dpm + (RS)dpn[j]));
+                    const RS Cm = (RS)sC[base + (k - 1) * M + mm], Ck = (RS)sC[base + k * M + mm];
                     const int r = (k - 1) * M + mm;
-                    sSub[base + r] = -D * Cm;
-                    sDia[base + r] = 1.0 + D * (Cm + Ck);
-                    sSup[base + r] = -D * Ck;
-                    sRhs[base + r] = ws_k[j] + D * (sP[base + k * M + mm] - sP[base + (k - 1) * M + mm]) - a.grav * a.dts;
+                    sSub[base + r] = (double)(-D * Cm);
+                    sDia[base + r] = (double)((RS)1 + D * (Cm + Ck));
+                    sSup[base + r] = (double)(-D * Ck);
+                    sRhs[base + r] = (double)((RS)ws_k[j] + D * ((RS)sP[base + k * M + mm] - (RS)sP[base + (k - 1) * M + mm]) -
+                                              (RS)a.grav * (RS)a.dts);
                 }
             }
             __syncthreads();
@@ -1192,25 +1200,25 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                         const int k = v.k[j], mm = v.mm0 + (M1 ? 0 : j);
                         if (k < 1) continue;
                         const int r = k - 1, o = base + r * M + mm;
-                        double bb = cur[1][o], dd = cur[3][o], na = 0.0, nc = 0.0;
+                        RS bb = (RS)cur[1][o], dd = (RS)cur[3][o], na = 0, nc = 0;
                         if (r - st >= 0) {
                             const int q = o - st * M;
-                            const double f = cur[0][o] / cur[1][q];
-                            bb = fmar(-cur[2][q], f, bb);
-                            dd = fmar(-cur[3][q], f, dd);
-                            na = -cur[0][q] * f;
+                            const RS f = (RS)cur[0][o] / (RS)cur[1][q];
+                            bb = fmar(-(RS)cur[2][q], f, bb);
+                            dd = fmar(-(RS)cur[3][q], f, dd);
+                            na = -(RS)cur[0][q] * f;
                         }
                         if (r + st < n) {
                             const int q = o + st * M;
-                            const double f = cur[2][o] / cur[1][q];
-                            bb = fmar(-cur[0][q], f, bb);
-                            dd = fmar(-cur[3][q], f, dd);
-                            nc = -cur[2][q] * f;
+                            const RS f = (RS)cur[2][o] / (RS)cur[1][q];
+                            bb = fmar(-(RS)cur[0][q], f, bb);
+                            dd = fmar(-(RS)cur[3][q], f, dd);
+                            nc = -(RS)cur[2][q] * f;
                         }
-                        nxt[0][o] = na;
-                        nxt[1][o] = bb;
-                        nxt[2][o] = nc;
-                        nxt[3][o] = dd;
+                        nxt[0][o] = (double)na;
+                        nxt[1][o] = (double)bb;
+                        nxt[2][o] = (double)nc;
+                        nxt[3][o] = (double)dd;
                     }
                 }
                 __syncthreads();
@@ -1227,8 +1235,9 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
 #pragma unroll
                 for (int j = 0; j < L; j++) {
                     const int k = v.k[j], mm = v.mm0 + (M1 ? 0 : j);
-                    wk[j] = (k == 0) ? 0.0 : cur[3][base + (k - 1) * M + mm] / cur[1][base + (k - 1) * M + mm];
-                    phk[j] = phs_k[j] + a.grav * a.dts * wk[j];
+                    const RS wr = (k == 0) ? (RS)0 : (RS)cur[3][base + (k - 1) * M + mm] / (RS)cur[1][base + (k - 1) * M + mm];
+                    wk[j] = (double)wr;
+                    phk[j] = (double)((RS)phs_k[j] + (RS)a.grav * (RS)a.dts * wr);
                     sPhi[lc * K1 * M + k * M + mm] = phk[j];
                     if (k == K - 1) sPhi[lc * K1 * M + K * M + mm] = phs_k1[j];   // surface: w = 0
                 }
@@ -1250,12 +1259,12 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                 for (int j = 0; j < L; j++) {
                     const int k = v.k[j], mm = v.mm0 + (M1 ? 0 : j);
                     const double phb = sPhi[lc * K1 * M + (k + 1) * M + mm];
-                    const double dphi = phk[j] - phb;
-                    const double pk = a.p0 * powpos(a.rd * Th_new[j] / (a.p0 * dphi), a.gamma);
-                    sPn[base + k * M + mm] = pk;
-                    alp.v[j] = dphi / dpn[j];
-                    pmp.v[j] = pk;
-                    php.v[j] = 0.5 * (phk[j] + phb);
+                    const RS dphi = (RS)phk[j] - (RS)phb;
+                    const RS pk = (RS)a.p0 * powpos((RS)a.rd * (RS)Th_new[j] / ((RS)a.p0 * dphi), (RS)a.gamma);
+                    sPn[base + k * M + mm] = (double)pk;
+                    alp.v[j] = (double)(dphi / (RS)dpn[j]);
+                    pmp.v[j] = (double)pk;
+                    php.v[j] = (double)((RS)0.5 * ((RS)phk[j] + (RS)phb));
                 }
                 stp<double, L>(a.alpha + (long)i * KM + km0, alp);
                 stp<double, L>(a.pm + (long)i * KM + km0, pmp);
@@ -1269,15 +1278,16 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                 for (int j = 0; j < L; j++) {
                     const int mm = v.mm0 + (M1 ? 0 : j);
                     const double psj = ps_new[j];
-                    auto mu_at = [&](int kk) -> double {
-                        if (K == 1) return 1.0;
+                    auto mu_at = [&](int kk) -> RS {
+                        if (K == 1) return (RS)1;
                         if (kk < 1) kk = 1;
                         if (kk > K - 1) kk = K - 1;
                         const double dp_a = a.dsig[kk - 1] * (psj - a.ptop);
                         const double dp_b = a.dsig[kk] * (psj - a.ptop);
-                        return (sPn[base + kk * M + mm] - sPn[base + (kk - 1) * M + mm]) / (0.5 * (dp_a + dp_b));
+                        return ((RS)sPn[base + kk * M + mm] - (RS)sPn[base + (kk - 1) * M + mm]) /
+                               ((RS)0.5 * ((RS)dp_a + (RS)dp_b));
                     };
-                    mup.v[j] = 0.5 * (mu_at(v.k[j]) + mu_at(v.k[j] + 1));
+                    mup.v[j] = (double)((RS)0.5 * (mu_at(v.k[j]) + mu_at(v.k[j] + 1)));
                 }
                 stp<double, L>(a.mum + (long)i * KM + km0, mup);
             }
@@ -1432,6 +1442,14 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
             const Pack<double, L> u1 = ldp<double, L>(a.mum + x1), u2 = ldp<double, L>(a.mum + x2);
 #pragma unroll
             for (int j = 0; j < L; j++) {
+                if constexpr (VAR == VAR_PGF32) {
+                    // the single-precision pressure-gradient term of the FP32 variant
+                    const float ae = 0.5f * ((float)al1.v[j] + (float)al2.v[j]);
+                    const float me = 0.5f * ((float)u1.v[j] + (float)u2.v[j]);
+                    pgf[j] = (double)(-(ae * ((float)q2.v[j] - (float)q1.v[j]) + me * ((float)ph2.v[j] - (float)ph1.v[j])) *
+                                      (float)dinv64);
+                    continue;
+                }
                 const double ae = 0.5 * (al1.v[j] + al2.v[j]);
                 const double me = 0.5 * (u1.v[j] + u2.v[j]);
                 pgf[j] = -(ae * (q2.v[j] - q1.v[j]) + me * (ph2.v[j] - ph1.v[j])) * dinv64;
@@ -1568,12 +1586,8 @@ hipError_t launch_stage_kernel(int model, int policy, const StageArgs &a, int wh
     case POLICY_MIX_BOX: return launch_variant<VAR_BOX>(model, a, which, s);
     case POLICY_MIX_DBL_MASS: return launch_variant<VAR_DBL_MASS>(model, a, which, s);
     case POLICY_MIX_F32_DIV: return launch_variant<VAR_F32_DIV>(model, a, which, s);
-    case POLICY_MIX_PGF32:   // hydrostatic model only
-        if (model == MODEL_HDC) return launch_stage_r<MODEL_HDC, float, VAR_PGF32>(a, which, s);
-        return hipErrorInvalidValue;
-    case POLICY_SGL:         // hydrostatic model only
-        if (model == MODEL_HDC) return launch_stage_r<MODEL_HDC, float, VAR_SGL>(a, which, s);
-        return hipErrorInvalidValue;
+    case POLICY_MIX_PGF32: return launch_variant<VAR_PGF32>(model, a, which, s);
+    case POLICY_SGL: return launch_variant<VAR_SGL>(model, a, which, s);
     }
     return hipErrorInvalidValue;
 }

@@ -13,7 +13,9 @@
 //           neighbours; P+-, Q+-, R+-
 //   update  C = min(R+ receiver, R- donor); q^(s) = [dpi q^n - dt_s D(F^L + C A)]/dpi_new
 // R = double (all-FP64 policy) or float (mixed policy: q, fluxes and limiter
-// in FP32, layer-mass continuity in FP64).
+// in FP32, layer-mass continuity in FP64).  SG (the all-FP32 policy, float
+// only): the layer-mass continuity too is FP32 -- the mass flux is read as an
+// FP32 number everywhere and the new layer mass is formed in FP32.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -86,12 +88,26 @@ template <typename R> struct Stencil {
     double F[6];
     double dpi_n, dpin;
 };
-template <typename R>
+template <typename R, bool SG = false>
 __device__ __forceinline__ void load_stencil(const TracerArgs &a, int i, int k, Stencil<R> &st) {
     const DevMesh &m = a.mesh;
     tld6<int>(m.c_edge + (long)i * kCellSlots, st.ce);
     tld6<int>(m.c_nbr + (long)i * kCellSlots, st.cn);
     tld6<R>(tpick<R>(m.c_div, m.c_div32) + (long)i * kCellSlots, st.cdiv);
+    if constexpr (SG) {
+        // all-FP32: the flux as an FP32 number, FP32 continuity
+        float d = 0.0f;
+#pragma unroll
+        for (int s = 0; s < kCellSlots; s++) {
+            const float f = (float)a.F[(long)(st.ce[s] < 0 ? 0 : st.ce[s]) * a.K + k];
+            st.F[s] = (st.ce[s] >= 0) ? (double)f : 0.0;
+            d = fmar((float)st.cdiv[s], (float)st.F[s], d);
+        }
+        const float dn = (float)a.dpi_n[(long)i * a.K + k];
+        st.dpi_n = (double)dn;
+        st.dpin = (double)(dn - (float)a.dts * d);
+        return;
+    }
     double c64[6];
     tld6<double>(m.c_div + (long)i * kCellSlots, c64);
     double d = 0.0;
@@ -176,7 +192,7 @@ __device__ __forceinline__ void edge_fluxes(const TracerArgs &a, const Stencil<R
     }
 }
 
-template <typename R, int L>
+template <typename R, int L, bool SG>
 __global__ void __launch_bounds__(kTracerThreads) k_tr_low(TracerArgs a) {
     const TLane ln = tracer_lane<L>(a);
     if (!ln.ok) return;
@@ -184,7 +200,7 @@ __global__ void __launch_bounds__(kTracerThreads) k_tr_low(TracerArgs a) {
     const int KT = a.K * a.T;
     const int i = ln.i, k = ln.k, t0 = ln.t0;
     Stencil<R> st;
-    load_stencil<R>(a, i, k, st);
+    load_stencil<R, SG>(a, i, k, st);
     const R *qn = (const R *)a.q_n;
     const R *qs = (const R *)a.q_s;
     R ch[3][6];
@@ -243,14 +259,14 @@ __device__ __forceinline__ void load_own(const TracerArgs &a, const TLane &ln, R
     }
 }
 
-template <typename R, int L>
+template <typename R, int L, bool SG>
 __global__ void __launch_bounds__(kTracerThreads) k_tr_limit(TracerArgs a) {
     const TLane ln = tracer_lane<L>(a);
     if (!ln.ok) return;
     const int KT = a.K * a.T;
     const int i = ln.i, k = ln.k, t0 = ln.t0;
     Stencil<R> st;
-    load_stencil<R>(a, i, k, st);
+    load_stencil<R, SG>(a, i, k, st);
     R qn_i[L], qs_i[L], Hi[3][L];
     load_own<R, L>(a, ln, qn_i, qs_i, Hi);
     const R *qn = (const R *)a.q_n;
@@ -295,14 +311,14 @@ __global__ void __launch_bounds__(kTracerThreads) k_tr_limit(TracerArgs a) {
     tst<R, L>((R *)a.rm + ln.x, rm);
 }
 
-template <typename R, int L>
+template <typename R, int L, bool SG>
 __global__ void __launch_bounds__(kTracerThreads) k_tr_update(TracerArgs a) {
     const TLane ln = tracer_lane<L>(a);
     if (!ln.ok) return;
     const int KT = a.K * a.T;
     const int i = ln.i, k = ln.k, t0 = ln.t0;
     Stencil<R> st;
-    load_stencil<R>(a, i, k, st);
+    load_stencil<R, SG>(a, i, k, st);
     R qn_i[L], qs_i[L], Hi[3][L];
     load_own<R, L>(a, ln, qn_i, qs_i, Hi);
     const R *rp = (const R *)a.rp;
@@ -336,32 +352,34 @@ __global__ void __launch_bounds__(kTracerThreads) k_tr_update(TracerArgs a) {
 
 namespace {
 inline unsigned tblocks(long n, int b) { return (unsigned)((n + b - 1) / b); }
-template <typename R, int L>
+template <typename R, int L, bool SG>
 hipError_t launch_tr_l(const TracerArgs &a, int which, hipStream_t s) {
     const long n = (long)a.mesh.N * a.K * (a.T / L);
     TracerArgs ab = a;
     ab.cpb = a.cpb > 0 ? a.cpb : 256;   // the kernels read the work-group size from here
     const int b = ab.cpb;
     switch (which) {
-    case TKERNEL_LOW: hipLaunchKernelGGL((k_tr_low<R, L>), dim3(tblocks(n, b)), dim3(b), 0, s, ab); break;
-    case TKERNEL_LIMIT: hipLaunchKernelGGL((k_tr_limit<R, L>), dim3(tblocks(n, b)), dim3(b), 0, s, ab); break;
-    case TKERNEL_UPDATE: hipLaunchKernelGGL((k_tr_update<R, L>), dim3(tblocks(n, b)), dim3(b), 0, s, ab); break;
+    case TKERNEL_LOW: hipLaunchKernelGGL((k_tr_low<R, L, SG>), dim3(tblocks(n, b)), dim3(b), 0, s, ab); break;
+    case TKERNEL_LIMIT: hipLaunchKernelGGL((k_tr_limit<R, L, SG>), dim3(tblocks(n, b)), dim3(b), 0, s, ab); break;
+    case TKERNEL_UPDATE: hipLaunchKernelGGL((k_tr_update<R, L, SG>), dim3(tblocks(n, b)), dim3(b), 0, s, ab); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
-template <typename R>
+template <typename R, bool SG>
 hipError_t launch_tr(const TracerArgs &a, int which, hipStream_t s) {
     if constexpr (sizeof(R) == 4)
-        if (a.vpl == 8) return launch_tr_l<R, 8>(a, which, s);
-    if (a.vpl == 4) return launch_tr_l<R, 4>(a, which, s);
-    if (a.vpl == 2) return launch_tr_l<R, 2>(a, which, s);
-    return launch_tr_l<R, 1>(a, which, s);
+        if (a.vpl == 8) return launch_tr_l<R, 8, SG>(a, which, s);
+    if (a.vpl == 4) return launch_tr_l<R, 4, SG>(a, which, s);
+    if (a.vpl == 2) return launch_tr_l<R, 2, SG>(a, which, s);
+    return launch_tr_l<R, 1, SG>(a, which, s);
 }
 }  // namespace
 
 hipError_t launch_tracer_kernel(int policy, const TracerArgs &a, int which, hipStream_t s) {
-    return policy == POLICY_DBL ? launch_tr<double>(a, which, s) : launch_tr<float>(a, which, s);
+    if (policy == POLICY_DBL) return launch_tr<double, false>(a, which, s);
+    if (policy == POLICY_SGL) return launch_tr<float, true>(a, which, s);
+    return launch_tr<float, false>(a, which, s);
 }
 
 // ---------------------------------------------------------------------------

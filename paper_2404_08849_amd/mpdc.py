@@ -21,6 +21,13 @@ ERRORS = {-1: "INVAL", -2: "MESH", -3: "NOMEM", -4: "DEVICE", -5: "NUMERIC", -6:
 MODEL_SW, MODEL_HDC, MODEL_NDC, MODEL_TRACER = 0, 1, 2, 3
 POLICY_DBL, POLICY_MIX, POLICY_MIX_BOX, POLICY_MIX_DBL_MASS, POLICY_MIX_F32_DIV, POLICY_MIX_PGF32, POLICY_SGL = \
     0, 1, 2, 3, 4, 5, 6
+POLICY_TERMS = 7
+# per-term precision bits of POLICY_TERMS (mpdc.h MPDC_TERM_*)
+TERMS = ["mass flux", "divergence", "kinetic energy", "vorticity", "vertex mass", "Coriolis", "theta flux",
+         "vertical advection", "column diagnostics", "pressure gradient"]
+TERM_BIT = {name: i for i, name in enumerate(TERMS)}
+TERMS_MIX = sum(1 << TERM_BIT[t] for t in ("mass flux", "kinetic energy", "vorticity", "Coriolis", "theta flux",
+                                            "vertical advection"))
 FIELD_H, FIELD_PS, FIELD_THETA, FIELD_U, FIELD_W, FIELD_PHI, FIELD_B = 0, 1, 2, 3, 4, 5, 6
 FIELD_TR_FLUX, FIELD_TR_DPI, FIELD_TR_Q, FIELD_TR_VFLUX, FIELD_PHIS, FIELD_VORT = 7, 8, 9, 10, 11, 12
 TABLE_CELLS_ON_CELL, TABLE_EDGE_SIGN, TABLE_VERTEX_SIGN = 0, 1, 2
@@ -52,7 +59,7 @@ class Config(ctypes.Structure):
                 ("dt", ctypes.c_double), ("grav", ctypes.c_double), ("rd", ctypes.c_double),
                 ("cp", ctypes.c_double), ("p0", ctypes.c_double), ("ptop", ctypes.c_double),
                 ("sigma", _dp), ("accumulate_flux", ctypes.c_int32), ("forward_backward_off", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("term_fp32", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class Diag(ctypes.Structure):
@@ -205,12 +212,13 @@ class State:
 
     def __init__(self, mesh, model, policy, K=1, M=1, T=0, dt=1.0, sigma=None, fct=True,
                  grav=9.80616, rd=287.0, cp=1004.5, p0=1.0e5, ptop=1000.0, device="cuda", accumulate_flux=False,
-                 forward_backward=True):
+                 forward_backward=True, term_fp32=0):
         self.mesh = mesh
         self.model, self.policy, self.K, self.M, self.T = model, policy, K, M, T
         self.sigma = _f64(np.arange(K + 1) / K if sigma is None else sigma)
         self.cfg = Config(model, policy, K, M, T, int(bool(fct)), dt, grav, rd, cp, p0, ptop,
-                          self.sigma.ctypes.data_as(_dp), int(bool(accumulate_flux)), int(not forward_backward))
+                          self.sigma.ctypes.data_as(_dp), int(bool(accumulate_flux)), int(not forward_backward),
+                          int(term_fp32))
         nbytes = lib.mpdc_state_workspace_bytes(mesh.h, ctypes.byref(self.cfg))
         if nbytes == 0:
             raise MpdcError(-6, lib.mpdc_last_error().decode())

@@ -174,9 +174,15 @@ def test_variants_rejected_where_not_built(mpdc, mesh_cache):
             assert out.value is None
     cfg, sig = _config(mpdc, mpdc.MODEL_HDC, 7, 4)                  # no such policy
     assert lib.mpdc_state_workspace_bytes(g.h, ctypes.byref(cfg)) == 0
-    for pol in (mpdc.POLICY_MIX_PGF32, mpdc.POLICY_SGL):                # hydrostatic only
-        cfg, sig = _config(mpdc, mpdc.MODEL_NDC, pol, 4)
-        assert lib.mpdc_state_workspace_bytes(g.h, ctypes.byref(cfg)) == 0
+    # MIX_PGF32 is built for the layered dycores, SGL for them and the tracer
+    cfg, sig = _config(mpdc, mpdc.MODEL_TRACER, mpdc.POLICY_MIX_PGF32, 4, 2)
+    assert lib.mpdc_state_workspace_bytes(g.h, ctypes.byref(cfg)) == 0
+    cfg, sig = _config(mpdc, mpdc.MODEL_SW, mpdc.POLICY_SGL, 1)
+    assert lib.mpdc_state_workspace_bytes(g.h, ctypes.byref(cfg)) == 0
+    for model, pol, K, T in ((mpdc.MODEL_NDC, mpdc.POLICY_MIX_PGF32, 4, 0), (mpdc.MODEL_NDC, mpdc.POLICY_SGL, 4, 0),
+                             (mpdc.MODEL_TRACER, mpdc.POLICY_SGL, 4, 2)):
+        cfg, sig = _config(mpdc, model, pol, K, T)
+        assert lib.mpdc_state_workspace_bytes(g.h, ctypes.byref(cfg)) > 0
     # the boxed variant keeps the kinetic energy in FP64
     b = {}
     for pol in (mpdc.POLICY_MIX, mpdc.POLICY_MIX_BOX, mpdc.POLICY_MIX_DBL_MASS):

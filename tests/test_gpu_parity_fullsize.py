@@ -5,7 +5,8 @@ The G6 x 30 hydrostatic jet runs its 20 steps against the oracle run live.
 The G8 and G7 workloads run 10 steps against the oracle's results stored by
 `tests/golden/make_fullsize_refs.py` (a committed script that calls only the
 oracle and the input generators): every level of the 12 pentagons, of their
-edges and of 500 random cells and edges.  The test rebuilds the same seeded
+edges, of 500 random cells and edges and of the 500 cells and edges where
+the oracle's state changed most over the steps.  The test rebuilds the same seeded
 input (signatures checked), runs the GPU path and compares those samples
 element by element, with the bars of the small-mesh parity tests:
  - all-FP64: 1e-12 in normalised L2 over the samples and in relative max

@@ -208,7 +208,7 @@ typedef struct {
 typedef struct {
     double mass;          /* sum_i A_i h_i (SW) or sum_i A_i (pi_s - pi_t) summed over members */
     double mass_tracer[MPDC_DIAG_MAX_TRACERS];  /* sum A dpi q per tracer                 */
-    double min, max;      /* of the field named in mpdc_diagnostics                         */
+    double min, max;      /* of ref_field, the field named in mpdc_diagnostics              */
     double l1, l2, linf;  /* area-weighted normalised errors vs the reference (if given)    */
     int64_t nonfinite;    /* NaN/Inf count over every prognostic field                      */
     double cfl_max;       /* dycore: largest |u_e| dt / d_e (NaN if u holds one); tracer: 0    */
@@ -309,16 +309,17 @@ int mpdc_tracer_step(mpdc_state *st, int nsteps, void *stream);
 int mpdc_tracer_couple(mpdc_state *tracer, mpdc_state *dycore, void *stream);
 
 /* Deterministic FP64 reductions over the state: global mass, total energy,
- * tracer masses and per-tracer min/max, NaN/Inf count, min/max of field_id,
- * and (if ref_dev is not NULL) the normalised L1/L2/Linf errors of field_id
- * against the FP64 device array ref_dev of the same layout (Section 2.2,
- * Eq. 2; cell fields weighted by the cell areas, MPDC_FIELD_VORT by the
- * dual-cell areas, edge fields unweighted).  Synchronous.  Returns
- * MPDC_E_NUMERIC (with *out filled) if a NaN/Inf is present, and
- * MPDC_E_UNSUPPORTED (nothing written) for a tracer state with more than
- * MPDC_DIAG_MAX_TRACERS tracers.  The energy uses the state's stage scratch,
- * so it must not run concurrently with a step of the same state. */
-int mpdc_diagnostics(mpdc_state *st, int field_id, const void *ref_dev, mpdc_diag *out, void *stream);
+ * tracer masses and per-tracer min/max, NaN/Inf count, min/max of the field
+ * ref_field, and (if ref_dev is not NULL) the normalised L1/L2/Linf errors of
+ * ref_field against the FP64 device array ref_dev of the same layout
+ * (Section 2.2, Eq. 2; cell fields weighted by the cell areas,
+ * MPDC_FIELD_VORT by the dual-cell areas, edge fields unweighted).  ref_dev
+ * is borrowed for the call.  Synchronous.  Returns MPDC_E_NUMERIC (with *out
+ * filled) if a NaN/Inf is present, and MPDC_E_UNSUPPORTED (nothing written)
+ * for a tracer state with more than MPDC_DIAG_MAX_TRACERS tracers.  The
+ * energy uses the state's stage scratch, so it must not run concurrently
+ * with a step of the same state. */
+int mpdc_diagnostics(mpdc_state *st, const void *ref_dev, int ref_field, mpdc_diag *out, void *stream);
 
 /* Capture one dycore or tracer step into a HIP graph and replay it for later
  * steps (enable != 0), or go back to direct launches (enable == 0).  Results

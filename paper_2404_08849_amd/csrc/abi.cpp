@@ -1342,7 +1342,7 @@ double mpdc_step_bytes(const mpdc_state *st) {
     return b + vertical_bytes(st);
 }
 
-int mpdc_diagnostics(mpdc_state *st, int f, const void *ref_dev, mpdc_diag *out, void *stream) {
+int mpdc_diagnostics(mpdc_state *st, const void *ref_dev, int f, mpdc_diag *out, void *stream) {
     if (!st || !out) return fail(MPDC_E_INVAL, "null state or output");
     long nf = field_count(st, f);
     if (nf < 0) return fail(MPDC_E_INVAL, "field not part of this model");

@@ -89,7 +89,7 @@ def _load():
         "mpdc_dycore_step": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
         "mpdc_tracer_step": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
         "mpdc_tracer_couple": (ctypes.c_int, [_vp, _vp, _vp]),
-        "mpdc_diagnostics": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.POINTER(Diag), _vp]),
+        "mpdc_diagnostics": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(Diag), _vp]),
         "mpdc_set_graph": (ctypes.c_int, [_vp, ctypes.c_int]),
         "mpdc_set_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
         "mpdc_set_kernel_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
@@ -274,7 +274,7 @@ class State:
             ref = ref.to(torch.float64).contiguous() if isinstance(ref, torch.Tensor) else \
                 torch.from_numpy(_f64(ref)).cuda()
             refp = ctypes.c_void_p(ref.data_ptr())
-        rc = lib.mpdc_diagnostics(self.h, f, refp, ctypes.byref(d), _stream(stream))
+        rc = lib.mpdc_diagnostics(self.h, refp, f, ctypes.byref(d), _stream(stream))
         if rc != MPDC_OK and (check or rc != -5):
             _check(rc)
         nt = max(self.T, 0)

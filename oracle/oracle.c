@@ -826,7 +826,11 @@ void or_iface_advection(const or_mesh *h, int K, const double *F, const double *
  * interfaces k = 1..K-1 satisfy
  *   -D_k C_{k-1} w_{k-1} + [1 + D_k (C_{k-1} + C_k)] w_k - D_k C_k w_{k+1}
  *       = w*_k + D_k (p*_k - p*_{k-1}) - g dt,
- * with w_0 = w_K = 0 (rigid lid, flat surface); then phi = phi* + g dt w.
+ * with w_0 = 0 at the rigid lid; then phi = phi* + g dt w above the surface.
+ * The surface interface keeps its geopotential (phi_s: the bottom of every
+ * layer-thickness difference) and the w given on entry (its kinematic value,
+ * surface_w), which the system does not couple to: with phi_K fixed the
+ * bottom layer's thickness changes only through w_{K-1}.
  */
 static void vertical_solve(const or_params *p, int K, double dts, const double *Th, const double *dpi,
                            double *w, double *phi, double *ws)
@@ -850,13 +854,40 @@ static void vertical_solve(const or_params *p, int K, double dts, const double *
     }
     if (n > 0) or_thomas(n, sub, dia, sup, rhs, x);
     w[0] = 0.0;
-    w[K] = 0.0;
     for (int r = 0; r < n; r++) w[r + 1] = x[r];
-    for (int k = 0; k <= K; k++) phi[k] = phi[k] + g * dts * w[k];
+    for (int k = 0; k < K; k++) phi[k] = phi[k] + g * dts * w[k];
+}
+
+/*
+ * Kinematic vertical velocity at the surface (Eq. 7 at the lower boundary,
+ * where the vertical mass flux vanishes and phi = phi_s does not change):
+ * g w_s = V.grad phi_s, with V.grad phi_s the horizontal part of the interface
+ * advection operator at the surface interface (the bottom layer's mass flux
+ * at half weight, over half the bottom layer's mass):
+ *   w_s,i = sum_e s l_e F_{e,K-1} (phi_s,nb - phi_s,i) / (2 g A_i dpi_{i,K-1}).
+ * Zero over a flat surface.  phi [N][K+1] (its bottom interface is phi_s),
+ * F [E][K], dpi [N][K]; writes w[i][K].
+ */
+void or_nh_surface_w(const or_mesh *h, const or_params *p, const double *F, const double *dpi, const double *phi,
+                     double *w)
+{
+    const or_mesh_in *m = &h->m;
+    const int K = p->K, K1 = K + 1;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < m->N; i++) {
+        double acc = 0.0;
+        for (int j = m->eoc_offset[i]; j < m->eoc_offset[i + 1]; j++) {
+            int e = m->edges_on_cell[j];
+            acc += h->sgn[j] * m->lEdge[e] * F[(size_t)e * K + K - 1] *
+                   (phi[(size_t)h->coc[j] * K1 + K] - phi[(size_t)i * K1 + K]);
+        }
+        w[(size_t)i * K1 + K] = acc / (2.0 * p->grav * m->areaCell[i] * dpi[(size_t)i * K + K - 1]);
+    }
 }
 
 /* One column of the vertical solve (exported for tests): w, phi [K+1] hold
- * w*, phi* on entry and the implicit solution on return. */
+ * w*, phi* on entry and the implicit solution on return (w_K and phi_K as
+ * given). */
 void or_nh_column_solve(const or_params *p, double dts, const double *Th, const double *dpi, double *w, double *phi)
 {
     double *ws = dalloc((size_t)7 * p->K);
@@ -905,10 +936,12 @@ static void nh_pgf(const or_mesh *h, const or_params *p, const double *Th, const
 
 /*
  * One RK3 step of the non-hydrostatic dycore, state (pi_s, Theta, u, w, phi).
- * Stage s: (1) pi_s and Theta advance with tendencies of the previous stage;
- * (2) w and phi take their explicit advective step w* = w^n + dt_s adv, phi*
- * likewise; (3) the implicit column solve turns (w*, phi*) into the stage's w
- * and phi using the new Theta and dpi; (4) u advances with the previous
+ * Stage s: (0) the surface w takes its kinematic value from the stage's
+ * mass flux and phi_s (or_nh_surface_w); (1) pi_s and Theta advance with
+ * tendencies of the previous stage; (2) w and phi take their explicit
+ * advective step w* = w^n + dt_s adv, phi* likewise (the surface keeps phi_s
+ * and its w); (3) the implicit column solve turns (w*, phi*) into the stage's
+ * w and phi using the new Theta and dpi; (4) u advances with the previous
  * stage's advective terms and the PGF of the new (dpi, Theta, phi).
  */
 static void ndc_run(const or_mesh *h, const or_params *p, double *ps, double *Theta, double *u, double *w,
@@ -940,6 +973,7 @@ static void ndc_run(const or_mesh *h, const or_params *p, double *ps, double *Th
             for (size_t x = 0; x < NK; x++) theta[x] = Theta[x] / dpi[x];
             theta_tendency(h, p, F, theta, mdot, dTh, we, wc);
             momentum_adv(h, p, u, F, dpi, mdot, adv, ke, zeta, dpiv, qv, Q);
+            or_nh_surface_w(h, p, F, dpi, phi, w);
             or_iface_advection(h, K, F, dpi, mdot, w, aw);
             or_iface_advection(h, K, F, dpi, mdot, phi, aphi);
             if (s == 2 && Facc) {
@@ -955,7 +989,7 @@ static void ndc_run(const or_mesh *h, const or_params *p, double *ps, double *Th
                 double *wc_ = wn + (size_t)i * K1, *pc = phin + (size_t)i * K1;
                 for (int k = 0; k <= K; k++) {
                     size_t x = (size_t)i * K1 + k;
-                    wc_[k] = (k == 0 || k == K) ? 0.0 : w0[x] - dts * aw[x];
+                    wc_[k] = k == 0 ? 0.0 : k == K ? w[x] : w0[x] - dts * aw[x];
                     pc[k] = (k == K) ? phi0[x] : phi0[x] - dts * aphi[x];
                 }
                 vertical_solve(p, K, dts, Thn + (size_t)i * K, dpin + (size_t)i * K, wc_, pc, wsp);

@@ -113,6 +113,11 @@ void or_hdc_tendency(const or_mesh *m, const or_params *p, const double *ps, con
                      const double *u, double *dps, double *dTh, double *du_adv, double *mdot);
 void or_nh_column_solve(const or_params *p, double dts, const double *Th, const double *dpi,
                         double *w, double *phi);
+/* Kinematic surface w of the non-hydrostatic model (Eq. 7 at the surface):
+ * w[i][K] = V.grad phi_s / g from the layer mass flux F [E][K], layer masses
+ * dpi [N][K] and the surface geopotential phi[i][K] (phi [N][K+1]). */
+void or_nh_surface_w(const or_mesh *m, const or_params *p, const double *F, const double *dpi, const double *phi,
+                     double *w);
 
 /* Diagnostics. */
 void or_norms(int n, int K, const double *area, const double *x, const double *ref,

@@ -72,6 +72,7 @@ def oracle_lib():
         lib.or_hdc_tendency.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params)] + [_dp] * 7
         lib.or_hdc_pgf.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _dp, _dp, _dp]
         lib.or_nh_column_solve.argtypes = [ctypes.POINTER(Params), ctypes.c_double, _dp, _dp, _dp, _dp]
+        lib.or_nh_surface_w.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _dp, _dp, _dp, _dp]
         lib.or_norms.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp]
         lib.or_area_sum.restype = ctypes.c_double
         lib.or_area_sum.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp]
@@ -285,6 +286,18 @@ class OracleMesh:
         p = self.params(K, dts)
         self.lib.or_nh_column_solve(ctypes.byref(p), dts, _d(Th), _d(dp), _d(w), _d(phi))
         return w, phi
+
+    def nh_surface_w(self, F, dpi, phi):
+        """Kinematic surface w [N] (g w_s = V.grad phi_s, Eq. 7 at the surface) for
+        layer mass fluxes F [E][K], layer masses dpi [N][K] and phi [N][K+1],
+        whose bottom interface is the surface geopotential."""
+        F, dpi, phi = [np.ascontiguousarray(a, dtype=np.float64) for a in (F, dpi, phi)]
+        K = dpi.shape[1]
+        assert F.shape == (self.E, K) and phi.shape == (self.N, K + 1)
+        w = np.zeros((self.N, K + 1))
+        p = self.params(K, 1.0)
+        self.lib.or_nh_surface_w(self.h, ctypes.byref(p), _d(F), _d(dpi), _d(phi), _d(w))
+        return w[:, K].copy()
 
     def energy(self, model, ps, u, Theta=None, w=None, phi=None, b=None, phis=None):
         """Total energy (J): model "SW" (ps = h, b), "HDC" (phis) or "NDC" (w, phi)."""

@@ -112,6 +112,79 @@ def hdc_jet(mesh, K, u0=35.0, T0=300.0, pert=1.0, seed=2000):
     return dict(ps=ps, Theta=dpi * theta, u=np.ascontiguousarray(u))
 
 
+def baroclinic_jet_profile(x, x_jet=np.log(4.0)):
+    """Vertical shape s(x) of the baroclinic jet, x = ln(p0/p): zero at the
+    surface, 1 at the jet level x_jet, decaying above; returns (s, ds/dln p)."""
+    c = np.exp(0.5) / x_jet
+    g = np.exp(-0.5 * (x / x_jet) ** 2)
+    s = c * x * g
+    ds_dx = c * g * (1.0 - (x / x_jet) ** 2)
+    return s, -ds_dx
+
+
+def baroclinic_jet_terms(lat, a, om, u0):
+    """Gamma(lat) = int_0^lat 2 Omega a sin U and Delta(lat) = int_0^lat U^2 tan
+    for U = u0 sin^2(2 lat), in closed form (c = cos lat)."""
+    c = np.cos(lat)
+    gam = 2.0 * om * a * 4.0 * u0 * (-c ** 3 / 3.0 + c ** 5 / 5.0 + 2.0 / 15.0)
+    dlt = 16.0 * u0 * u0 * (-(c ** 4 / 4.0 - c ** 6 / 3.0 + c ** 8 / 8.0) + 1.0 / 24.0)
+    return gam, dlt
+
+
+def baroclinic_reference_temperature(p, T_s=288.0, lapse=0.005, T_trop=220.0, p_s=1.0e5):
+    """Latitude-independent reference profile T_0(p): a constant lapse rate
+    (K/m) from T_s at p_s, isothermal at T_trop above the tropopause."""
+    return np.maximum(T_s * (p / p_s) ** (RD * lapse / GRAV), T_trop)
+
+
+def baroclinic_jet_temperature(lat, p, a, om, u0=30.0, p_s=1.0e5):
+    """Temperature of the baroclinic jet u = u0 sin^2(2 lat) s(ln(p_s/p)) in
+    gradient-wind and hydrostatic balance over a flat surface at p_s.
+
+    On pressure surfaces the geopotential is Phi = Phi_0(p) - Gamma s
+    - Delta s^2 (Phi_0: the reference profile's geopotential, independent of
+    latitude), whose latitude derivative is minus the gradient-wind term
+    (2 Omega a sin lat u + u^2 tan lat); the hydrostatic relation
+    dPhi/dln p = -R_d T then gives T = T_0(p) + (ds/dln p)(Gamma + 2 s Delta)/R_d."""
+    s, sl = baroclinic_jet_profile(np.log(p_s / p))
+    gam, dlt = baroclinic_jet_terms(lat, a, om, u0)
+    return baroclinic_reference_temperature(p, p_s=p_s) + sl * (gam + 2.0 * s * dlt) / RD
+
+
+def hdc_baroclinic_jet(mesh, K, u0=30.0, pert=1.0, seed=2000):
+    """Hydrostatic baroclinic jet: zonal wind u0 sin^2(2 lat) s(p), zero at the
+    surface and strongest near 250 hPa, in gradient-wind and thermal-wind
+    balance with the temperature of baroclinic_jet_temperature over a flat
+    surface at 1000 hPa (so pi_s is uniform; the reference profile has a
+    5 K/km lapse rate from 288 K up to a 220 K tropopause), plus a seeded zonal wind bump
+    pert*exp(-(r/(a/10))^2) scaled by s(p), which starts the baroclinic wave.
+    Mid-latitude jets of both hemispheres; the poles are cold at the surface.
+
+    Returns dict(ps[N], Theta[N][K], u[E][K])."""
+    a, om = mesh["radius"], mesh["omega"]
+    N = mesh["nCells"]
+    _, latc = lonlat(mesh["xCell"])
+    _, latv = lonlat(mesh["xVertex"])
+    ps = np.full(N, P0)
+    sig = sigma_interfaces(K)
+    smid = 0.5 * (sig[:-1] + sig[1:])
+    dpi = np.outer(ps - PTOP, np.diff(sig))
+    p = PTOP + np.outer(ps - PTOP, smid)
+    T = baroclinic_jet_temperature(latc[:, None], p, a, om, u0, P0)
+    theta = T * (P0 / p) ** KAPPA
+    # U = u0 sin^2(2 lat) = u0 (1 - cos 4 lat)/2 from psi = -a int U
+    psi = -a * u0 * (0.5 * latv - np.sin(4.0 * latv) / 8.0)
+    u1 = velocity_from_streamfunction(mesh, psi)
+    if pert:
+        lon0, lat0 = _seeded_centre(seed, 60.0)
+        xe = mesh["xEdge"]
+        r = a * _great_circle(xe, lon0, lat0)
+        u1 = u1 + pert * np.exp(-(r / (a / 10.0)) ** 2) * np.einsum("ij,ij->i", _east(xe), _edge_normal(mesh))
+    s_k, _ = baroclinic_jet_profile(np.log(P0 / (PTOP + (P0 - PTOP) * smid)))
+    u = np.outer(u1, s_k)
+    return dict(ps=ps, Theta=dpi * theta, u=np.ascontiguousarray(u))
+
+
 def ensemble(state, M, sigma=0.1, seed=5000, relative=None):
     """Stack M copies of a hydrostatic state member-innermost, with independent
     N(0, sigma) perturbations on every u_{e,k} of member m (seed + m), or, if
@@ -157,6 +230,39 @@ def nh_warm_bubble(mesh, K, T0=300.0, dtheta=1.0, rh=2.0e5, zc=2.0e3, rz=2.0e3, 
         bub = np.where(rho <= 1.0, dtheta * np.cos(0.5 * np.pi * rho) ** 2, 0.0)
         Theta = Theta + dpi * bub
     return dict(ps=ps, Theta=Theta, u=np.zeros((E, K)), w=np.zeros((N, K + 1)), phi=phi)
+
+
+def ndc_rest_over_terrain(mesh, K, phis, T0=300.0, p_ref=1.0e5):
+    """Non-hydrostatic isothermal atmosphere at rest over terrain, in discrete
+    hydrostatic balance: pi_s and Theta as hdc_rest_over_terrain, the
+    geopotential integrated upwards from the surface value phis with
+    delta phi_k = (R_d T0 / p_k) delta pi_k (so the equation of state returns
+    the hydrostatic mid-layer pressure p_k), w = 0.  The bottom interface of
+    phi is the surface geopotential.
+    Returns dict(ps, Theta, u, w[N][K+1], phi[N][K+1])."""
+    s = hdc_rest_over_terrain(mesh, K, phis, T0, p_ref)
+    ps = s["ps"]
+    sig = sigma_interfaces(K)
+    dpi = np.outer(ps - PTOP, np.diff(sig))
+    p = PTOP + np.outer(ps - PTOP, 0.5 * (sig[:-1] + sig[1:]))
+    dphi = RD * T0 / p * dpi
+    N = mesh["nCells"]
+    phi = np.zeros((N, K + 1))
+    phi[:, K] = phis
+    for k in range(K - 1, -1, -1):
+        phi[:, k] = phi[:, k + 1] + dphi[:, k]
+    return dict(ps=ps, Theta=s["Theta"], u=s["u"], w=np.zeros((N, K + 1)), phi=phi)
+
+
+def solid_body_wind(mesh, K, u0=20.0, axis=(0.0, 0.0, 1.0)):
+    """Solid-body rotation of speed u0 at the equator of the rotation axis,
+    the same at every level, as normal velocities [E][K] from its
+    streamfunction psi = -a u0 (axis . x) at the vertices (nondivergent)."""
+    ax = np.asarray(axis, dtype=np.float64)
+    ax = ax / np.linalg.norm(ax)
+    psi = -mesh["radius"] * u0 * (mesh["xVertex"] @ ax)
+    u1 = velocity_from_streamfunction(mesh, psi)
+    return np.ascontiguousarray(np.repeat(u1[:, None], K, axis=1))
 
 
 def _harmonics_deg3(x):

@@ -133,8 +133,13 @@ extern "C" {
 #define MPDC_FIELD_PS 1          /* surface pressure pi_s     [N][M]        */
 #define MPDC_FIELD_THETA 2       /* Theta = dpi theta_m       [N][K][M]     */
 #define MPDC_FIELD_U 3           /* normal velocity u         [E][K][M]     */
-#define MPDC_FIELD_W 4           /* vertical velocity w       [N][K+1][M]   */
-#define MPDC_FIELD_PHI 5         /* geopotential phi          [N][K+1][M]   */
+#define MPDC_FIELD_W 4           /* vertical velocity w       [N][K+1][M]: 0 at the lid (k = 0); at
+                                    the surface (k = K) each stage sets the kinematic value
+                                    V.grad phi_s / g of its flow (Eq. 7 at the surface, where the
+                                    vertical mass flux vanishes), zero over a flat surface */
+#define MPDC_FIELD_PHI 5         /* geopotential phi          [N][K+1][M]: its surface entry (k = K)
+                                    is the surface geopotential phi_s (NDC terrain), which the steps
+                                    keep fixed */
 #define MPDC_FIELD_B 6           /* SW bottom height b        [N]           */
 #define MPDC_FIELD_TR_FLUX 7     /* tracer mass flux F        [E][K]        */
 #define MPDC_FIELD_TR_DPI 8      /* tracer layer mass dpi     [N][K]        */

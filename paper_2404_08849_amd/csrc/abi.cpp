@@ -143,6 +143,7 @@ struct mpdc_state {
     double *b = nullptr, *phis = nullptr, *dsig = nullptr, *sig = nullptr, *dps = nullptr, *mdot = nullptr;
     void *ke = nullptr, *hth = nullptr, *qv = nullptr, *qh = nullptr;
     double *alpha = nullptr, *phim = nullptr, *pm = nullptr, *mum = nullptr, *wstar = nullptr, *phistar = nullptr;
+    int *nh_terrain = nullptr;                    // NDC: the surface geopotential varies (device flag)
     // dycore: last-stage mass fluxes summed over the steps since the last coupling
     bool accumulate = false;
     double *Facc = nullptr, *Macc = nullptr;
@@ -229,6 +230,7 @@ size_t state_layout(mpdc_state *st, void *base) {
         st->mum = c.take<double>(N * KM);
         st->wstar = c.take<double>(N * K1M);
         st->phistar = c.take<double>(N * K1M);
+        st->nh_terrain = c.take<int>(1);   // zero (the workspace is cleared): flat
     }
     if (st->accumulate) {
         st->Facc = c.take<double>(E * K);
@@ -333,6 +335,7 @@ StageArgs stage_args(const mpdc_state *st, int s) {
     a.qh = st->qh;
     a.alpha = st->alpha; a.phim = st->phim; a.pm = st->pm; a.mum = st->mum;
     a.wstar = st->wstar; a.phistar = st->phistar;
+    a.nh_terrain = st->nh_terrain;
     return a;
 }
 
@@ -811,6 +814,8 @@ int mpdc_state_write(mpdc_state *st, int f, const void *src, int src_on_device, 
                            (float *)st->q[st->parity], n);
         HIP_TRY(hipGetLastError());
     }
+    if (st->model == MPDC_MODEL_NDC && f == MPDC_FIELD_PHI)   // does the surface have terrain?
+        HIP_TRY(launch_surface_check(dst, st->N, st->K, st->M, st->nh_terrain, s));
     if (!fp64_storage(st->policy) && st->model != MPDC_MODEL_TRACER) {
         StageArgs a = stage_args(st, 0);
         // regenerate the FP32 shadows of the current state (set 0)

@@ -74,6 +74,8 @@ struct StageArgs {
     void *qh;            // [E][2][K][M]   (R) each cell's share of Coriolis - grad K per edge
     double *alpha, *phim, *pm, *mum;   // [N][K][M]
     double *wstar, *phistar;           // [N][K+1][M]
+    const int *nh_terrain;   // NDC: nonzero once the surface geopotential varies between cells
+                             // (then k_cell_a forms the kinematic surface w; else it is 0)
 
     template <typename R> __device__ R *ke_out() const { return (R *)ke; }
     template <typename R> __device__ const R *ke_in() const { return (const R *)ke; }
@@ -224,5 +226,8 @@ hipError_t launch_energy(const DevMesh &m, const EnergyArgs &e, hipStream_t s);
 // mode 0: read src (one 8-byte word per work-group into dst), 1: write dst,
 // 2: copy src to dst; n16 16-byte words, both pointers 16-byte aligned
 hipError_t launch_stream(int mode, const void *src, void *dst, long n16, hipStream_t s);
+// nh_terrain[0] = 1 if the bottom interface of phi [N][K+1][M] differs between
+// cells for any member, else 0 (one work-group; stream-ordered)
+hipError_t launch_surface_check(const double *phi, long N, int K, int M, int *flag, hipStream_t s);
 
 }  // namespace mpdc

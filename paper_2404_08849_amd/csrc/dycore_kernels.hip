@@ -567,9 +567,16 @@ k_cell_a(StageArgs a) {
                 ld_iface<L, M1>(a.w_s, cb, v, M, 0, wi);
                 ld_iface<L, M1>(a.phi_s, cb, v, M, 0, pi_);
                 const R *us = u_prev_ptr<R>(a);
-                R aw[L], ap[L];
+                R aw[L], ap[L], asf[L];
 #pragma unroll
-                for (int j = 0; j < L; j++) aw[j] = ap[j] = 0;
+                for (int j = 0; j < L; j++) aw[j] = ap[j] = asf[j] = 0;
+                // lanes holding the bottom layer also form the kinematic surface w
+                // (g w_s = V.grad phi_s: the horizontal advection of phi at the
+                // surface interface, the bottom layer's flux at half weight); over
+                // a flat surface it is zero and the gathers are skipped
+                const bool bottom = (M1 ? v.k0 + L - 1 : v.k0) >= K - 1 && *a.nh_terrain != 0;
+                double pd[L];
+                ld_iface<L, M1>(a.phi_s, cb, v, M, 1, pd);
                 double cdiv[6];
                 ld6<double>(tb.div64 + lc * kCellSlots, cdiv);
                 // slots grouped per basic block and no load under a condition,
@@ -619,12 +626,28 @@ k_cell_a(StageArgs a) {
                         aw[j] += c * (R)(wn_[j] - wi[j]);
                         ap[j] += c * (R)(pn_[j] - pi_[j]);
                     }
+                    if (bottom) {
+                        double pnK[L];
+                        ld_iface<L, M1>(a.phi_s, (long)nb * K1M, v, M, 1, pnK);
+#pragma unroll
+                        for (int j = 0; j < L; j++) {
+                            const R c = (R)cdiv[s] * ((R)0.5 * Fs[s][j]) * (R)0.5;
+                            asf[j] += c * (R)(pnK[j] - pd[j]);
+                        }
+                    }
                 }
-                double wu[L], wd[L], pu[L], pd[L], wn0[L], pn0[L], ws_[L], ps_[L];
+                // surface w of the lanes at layer K-1 (1/(half the bottom layer's mass))
+                double wsf[L];
+#pragma unroll
+                for (int j = 0; j < L; j++)
+                    wsf[j] = (double)(asf[j] * (R)(1.0 / (0.5 * dpi_i[j]))) / a.grav;
+                double wu[L], wd[L], pu[L], wn0[L], pn0[L], ws_[L], ps_[L];
                 ld_iface<L, M1>(a.w_n, cb, v, M, 0, wn0);
                 ld_iface<L, M1>(a.phi_n, cb, v, M, 0, pn0);
                 ld_iface<L, M1>(a.w_s, cb, v, M, 1, wd);
-                ld_iface<L, M1>(a.phi_s, cb, v, M, 1, pd);
+#pragma unroll
+                for (int j = 0; j < L; j++)
+                    if (v.k[j] == K - 1) wd[j] = wsf[j];   // the surface: this stage's kinematic w
                 // the interface above each value (none above the top interface)
                 if constexpr (M1) {
 #pragma unroll
@@ -660,12 +683,12 @@ k_cell_a(StageArgs a) {
                 }
                 st_iface<L, M1>(a.wstar, cb, v, M, 0, ws_);
                 st_iface<L, M1>(a.phistar, cb, v, M, 0, ps_);
-                // surface interface: w = 0, phi fixed
+                // surface interface: the kinematic w, phi fixed at phi_s
 #pragma unroll
                 for (int j = 0; j < L; j++) {
                     if (v.k[j] == K - 1) {
                         const int mm = v.mm0 + (M1 ? 0 : j);
-                        a.wstar[cb + (long)K * M + mm] = 0.0;
+                        a.wstar[cb + (long)K * M + mm] = wsf[j];
                         a.phistar[cb + (long)K * M + mm] = a.phi_n[cb + (long)K * M + mm];
                     }
                 }
@@ -1239,7 +1262,7 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                     wk[j] = (double)wr;
                     phk[j] = (double)((RS)phs_k[j] + (RS)a.grav * (RS)a.dts * wr);
                     sPhi[lc * K1 * M + k * M + mm] = phk[j];
-                    if (k == K - 1) sPhi[lc * K1 * M + K * M + mm] = phs_k1[j];   // surface: w = 0
+                    if (k == K - 1) sPhi[lc * K1 * M + K * M + mm] = phs_k1[j];   // surface: phi_s
                 }
                 st_iface<L, M1>(a.w_o, cb, v, M, 0, wk);
                 st_iface<L, M1>(a.phi_o, cb, v, M, 0, phk);
@@ -1247,7 +1270,7 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                 for (int j = 0; j < L; j++) {
                     if (v.k[j] == K - 1) {
                         const int mm = v.mm0 + (M1 ? 0 : j);
-                        a.w_o[cb + (long)K * M + mm] = 0.0;
+                        a.w_o[cb + (long)K * M + mm] = a.wstar[cb + (long)K * M + mm];   // kinematic
                         a.phi_o[cb + (long)K * M + mm] = phs_k1[j];
                     }
                 }
@@ -1760,6 +1783,26 @@ hipError_t launch_shadows(int model, const StageArgs &args, hipStream_t s) {
     if (model == MODEL_SW) hipLaunchKernelGGL(k_shadows<MODEL_SW>, dim3(nblocks(n, 256)), dim3(256), 0, s, a);
     else if (model == MODEL_HDC) hipLaunchKernelGGL(k_shadows<MODEL_HDC>, dim3(nblocks(n, 256)), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_shadows<MODEL_NDC>, dim3(nblocks(n, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// whether the non-hydrostatic surface geopotential varies (terrain)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) k_surface_check(const double *phi, long N, int K, int M, int *flag) {
+    int any = 0;
+    const long n = N * M, K1M = (long)(K + 1) * M;
+    for (long x = threadIdx.x; x < n; x += blockDim.x) {
+        const long i = x / M;
+        const int mm = (int)(x - i * M);
+        any |= phi[i * K1M + (long)K * M + mm] != phi[(long)K * M + mm];
+    }
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) flag[0] = any != 0;
+}
+
+hipError_t launch_surface_check(const double *phi, long N, int K, int M, int *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_surface_check, dim3(1), dim3(1024), 0, s, phi, N, K, M, flag);
     return hipGetLastError();
 }
 

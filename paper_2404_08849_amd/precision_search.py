@@ -17,20 +17,28 @@ burden), the precision-sensitive ones last.  Every run, the norms and the
 vorticity are computed on the GPU through the C ABI (``mpdc_diagnostics``
 with ``MPDC_FIELD_VORT``).
 
-The window.  The paper runs 10 days of a dry baroclinic wave in a model with
-its own dissipation.  This dry core has none, and on the unstable jet any
-rounding difference grows: after 10 days even an FP64 run whose initial
-Theta is perturbed by the FP32 unit roundoff is far outside alpha, so a
-10-day window would reject every FP32 term, whatever its accuracy.  The
-window is therefore set from the FP64 model alone, before any FP32 term is
-tried: the longest whole number of days, up to 10, over which an FP64 run
-with Theta perturbed by 2^-24 (an FP32-sized uncertainty of the initial
-state) stays within alpha/2 of the unperturbed run -- the horizon over
-which the model can tell FP32-level differences apart at all.  Beside the
-search the tool reports E of the mixed policy's split and of all-FP32, and
-of FP64 runs perturbed by 1e-14 and 2^-24.
+The test state.  The paper searches on a dry baroclinic wave.  The default
+state here is a baroclinic jet of its own (``inputs.initial.hdc_baroclinic_jet``:
+zonal wind u0 sin^2(2 lat), zero at the surface and strongest near 250 hPa,
+in gradient-wind and thermal-wind balance over a flat surface, plus a local
+wind bump that starts the wave); the isothermal barotropic jet u0 cos^2(lat)
+is the alternative (``--state barotropic``).
+
+The window.  The paper runs 10 days in a model with its own dissipation.
+This dry core has none, and on either jet any rounding difference grows:
+after 10 days even an FP64 run whose initial Theta is perturbed by the FP32
+unit roundoff is far outside alpha, so a 10-day window would reject every
+FP32 term, whatever its accuracy.  The window is therefore set from the
+FP64 model alone, before any FP32 term is tried: the longest whole number
+of days, up to 10, over which an FP64 run with Theta perturbed by 2^-24 (an
+FP32-sized uncertainty of the initial state) stays within alpha/2 of the
+unperturbed run -- the horizon over which the model can tell FP32-level
+differences apart at all.  Beside the search the tool reports E of the
+mixed policy's split and of all-FP32, and of FP64 runs perturbed by 1e-14
+and 2^-24.
 
 Usage: python -m paper_2404_08849_amd.precision_search [--level 6] [--days D] [--alpha 0.05]
+       [--state baroclinic|barotropic] [--terrain]
 """
 import argparse
 import json
@@ -103,15 +111,31 @@ def predictability_window(mpdc, g, s, K, dt, alpha, phis=None, max_days=10, eps=
     return max(days, 1), Es
 
 
-def search(level=6, K=30, days=None, dt=None, alpha=0.05, terrain=False, order=ORDER, log=print):
-    """The per-term search on the hydrostatic jet (optionally over a mountain);
+STATES = ("baroclinic", "barotropic")
+
+
+def initial_state(mesh, K, state):
+    """The search's test state: the baroclinic jet (zonal wind u0 sin^2(2 lat)
+    growing from zero at the surface to a maximum near 250 hPa, in thermal-wind
+    balance, with a local wind bump that starts a baroclinic wave) or the
+    isothermal barotropic jet u0 cos^2(lat) with the same kind of bump."""
+    if state == "baroclinic":
+        return ic.hdc_baroclinic_jet(mesh, K, seed=2000)
+    if state == "barotropic":
+        return ic.hdc_jet(mesh, K, seed=2000)
+    raise ValueError("state must be one of %s" % (STATES,))
+
+
+def search(level=6, K=30, days=None, dt=None, alpha=0.05, terrain=False, order=ORDER, state="baroclinic",
+           log=print):
+    """The per-term search on a hydrostatic jet (optionally over a mountain);
     returns a dict: the window, every trial, the accepted FP32 terms and mask."""
     import paper_2404_08849_amd.mpdc as mpdc
     from .inputs.meshgen import icosahedral_mesh
     mesh = icosahedral_mesh(level)
     if dt is None:
         dt = 300.0 * 2 ** (6 - level)          # the G6 workload's step, scaled with the mesh spacing
-    s = ic.hdc_jet(mesh, K, seed=2000)
+    s = initial_state(mesh, K, state)
     phis = None
     if terrain:
         phis = ic.mountain(mesh)
@@ -120,7 +144,7 @@ def search(level=6, K=30, days=None, dt=None, alpha=0.05, terrain=False, order=O
     g = mpdc.Mesh(mesh)
     window_log = None
     if days is None:
-        log("window: FP64 predictability at FP32 level, G%d x %d, dt %.1f s" % (level, K, dt))
+        log("window: FP64 predictability at FP32 level, %s jet, G%d x %d, dt %.1f s" % (state, level, K, dt))
         days, window_log = predictability_window(mpdc, g, s, K, dt, alpha, phis, log=log)
     nsteps = int(round(days * 86400.0 / dt))
     log("reference: DBL, G%d x %d, %d steps of %.1f s (%.1f days)" % (level, K, nsteps, dt, nsteps * dt / 86400.0))
@@ -152,7 +176,7 @@ def search(level=6, K=30, days=None, dt=None, alpha=0.05, terrain=False, order=O
         log("%-34s E = %.3e (L(ps) %.3e, L(vor) %.3e)  [reference]" % (name, E, n["ps"], n["vor"]))
         trials.append(dict(name=name, mask=mask, E=E, L_ps=n["ps"], L_vor=n["vor"], reference=True))
     fp32 = [t for t in mpdc.TERMS if accepted & (1 << mpdc.TERM_BIT[t])]
-    return dict(days=days, dt=dt, steps=nsteps, window_log=window_log, alpha=alpha, trials=trials,
+    return dict(state=state, days=days, dt=dt, steps=nsteps, window_log=window_log, alpha=alpha, trials=trials,
                 accepted_mask=accepted, fp32_terms=fp32,
                 fp64_terms=[t for t in mpdc.TERMS if t not in fp32])
 
@@ -165,8 +189,9 @@ def main():
     p.add_argument("--dt", type=float, default=None)
     p.add_argument("--alpha", type=float, default=0.05)
     p.add_argument("--terrain", action="store_true", help="the jet over a 3 km mountain")
+    p.add_argument("--state", default="baroclinic", choices=STATES)
     a = p.parse_args()
-    print(json.dumps(search(a.level, a.levels, a.days, a.dt, a.alpha, a.terrain)))
+    print(json.dumps(search(a.level, a.levels, a.days, a.dt, a.alpha, a.terrain, state=a.state)))
 
 
 if __name__ == "__main__":

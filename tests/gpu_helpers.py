@@ -43,6 +43,17 @@ def mix_u_tol(nsteps):
     return MIX_U_TOL * max(1.0, nsteps / 10.0)
 
 
+def mix_w_bar(u_ref, w_ref, nsteps):
+    """Absolute mixed bar of the non-hydrostatic w where w is much weaker than
+    the horizontal flow (a wind over terrain): the FP32 roundings that reach w
+    are those of the momentum tendencies, relative to the flow speed, carried
+    into w by the divergence of u; so the velocity bar is taken of the speed
+    scale max(|u|, |w|), not of |w| alone: 16 FP32 unit roundoffs of it per
+    10 steps, element-wise."""
+    scale = max(float(np.abs(u_ref).max()), float(np.abs(w_ref).max()))
+    return mix_u_tol(nsteps) * scale
+
+
 def linf_rel(x, r):
     """max |x - r| / max |r| over every element."""
     x = np.asarray(x, dtype=np.float64)

@@ -7,12 +7,15 @@
   the search lowers every term, with an alpha below the smallest it lowers
   none; an FP64 run perturbed by the FP32 unit roundoff departs further than
   one perturbed by 1e-14;
-* on the G6 jet, over the window the FP64 model itself sets (the longest run,
-  up to 10 days, over which an FP32-sized perturbation of its initial state
-  stays within alpha/2), the per-term search lowers the advective terms to
-  FP32 and keeps the column diagnostics and the pressure-gradient term in
-  FP64, and all-FP32 is rejected: the paper's finding, reproduced at small
-  scale without a window chosen for the mixed split.
+* on the G6 barotropic jet and on the G6 baroclinic jet (a mid-latitude jet
+  in thermal-wind balance whose wave a local wind bump starts), over the
+  window the FP64 model itself sets (the longest run, up to 10 days, over
+  which an FP32-sized perturbation of its initial state stays within
+  alpha/2), the per-term search lowers the advective terms to FP32 and keeps
+  the column diagnostics and the pressure-gradient term in FP64, each of
+  which alone moves the run over ten times more than all the accepted terms
+  together: the paper's finding, reproduced at small scale without a window
+  chosen for the mixed split.
 """
 import numpy as np
 import pytest
@@ -65,7 +68,7 @@ def test_vorticity_matches_oracle(mpdc, mesh_cache):
 
 def test_search_accepts_and_rejects(mpdc):
     from paper_2404_08849_amd import precision_search as ps
-    r = ps.search(level=4, K=10, days=2.0, alpha=10.0, log=_say)
+    r = ps.search(level=4, K=10, days=2.0, alpha=10.0, state="barotropic", log=_say)
     refs = [t for t in r["trials"] if t.get("reference")]
     cand = [t for t in r["trials"] if not t.get("reference")]
     assert [t["name"] for t in cand] == ps.ORDER
@@ -76,7 +79,7 @@ def test_search_accepts_and_rejects(mpdc):
     assert [t["mask"] for t in cand] == [sum(1 << mpdc.TERM_BIT[x] for x in ps.ORDER[:j + 1])
                                          for j in range(len(ps.ORDER))]
     # alpha below every error: nothing is lowered, and each trial is its term alone on FP64
-    r2 = ps.search(level=4, K=10, days=2.0, alpha=1e-30, log=_say)
+    r2 = ps.search(level=4, K=10, days=2.0, alpha=1e-30, state="barotropic", log=_say)
     cand2 = [t for t in r2["trials"] if not t.get("reference")]
     assert r2["accepted_mask"] == 0 and not any(t["accepted"] for t in cand2)
     assert [t["mask"] for t in cand2] == [1 << mpdc.TERM_BIT[x] for x in ps.ORDER]
@@ -98,7 +101,7 @@ def test_error_measure_of_a_run_against_itself_is_zero(mpdc, mesh_cache):
 @pytest.mark.timeout(900)
 def test_search_keeps_fp64_pressure_gradient(mpdc):
     from paper_2404_08849_amd import precision_search as ps
-    r = ps.search(level=6, K=30, alpha=0.05, log=_say)
+    r = ps.search(level=6, K=30, alpha=0.05, state="barotropic", log=_say)
     _say("window %d days; FP32: %s; FP64: %s" % (r["days"], r["fp32_terms"], r["fp64_terms"]))
     # the window comes from the FP64 model alone (E of the 2^-24-perturbed run per day)
     assert 1 <= r["days"] <= 10 and len(r["window_log"]) >= r["days"]
@@ -108,4 +111,21 @@ def test_search_keeps_fp64_pressure_gradient(mpdc):
         assert T[term]["accepted"], term
     assert not T["column diagnostics"]["accepted"] and not T["pressure gradient"]["accepted"]
     assert "pressure gradient" in r["fp64_terms"] and "column diagnostics" in r["fp64_terms"]
+    assert T["all terms FP32"]["E"] > 0.05
+
+
+@pytest.mark.timeout(900)
+def test_search_on_the_baroclinic_jet(mpdc):
+    from paper_2404_08849_amd import precision_search as ps
+    r = ps.search(level=6, K=30, alpha=0.05, state="baroclinic", log=_say)
+    _say("window %d days; FP32: %s; FP64: %s" % (r["days"], r["fp32_terms"], r["fp64_terms"]))
+    assert r["state"] == "baroclinic" and 2 <= r["days"] <= 10
+    assert all(E <= 0.025 for E in r["window_log"][:r["days"]])
+    T = {t["name"]: t for t in r["trials"]}
+    advective = ("Coriolis", "theta flux", "kinetic energy", "vertical advection", "mass flux", "vorticity")
+    for term in advective:
+        assert T[term]["accepted"], term
+    assert not T["column diagnostics"]["accepted"] and not T["pressure gradient"]["accepted"]
+    E_acc = max(t["E"] for t in r["trials"] if t.get("accepted"))
+    assert T["column diagnostics"]["E"] > 10.0 * E_acc and T["pressure gradient"]["E"] > 10.0 * E_acc
     assert T["all terms FP32"]["E"] > 0.05

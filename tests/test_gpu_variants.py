@@ -172,7 +172,15 @@ def test_variants_rejected_where_not_built(mpdc, mesh_cache):
             assert lib.mpdc_state_create(g.h, ctypes.byref(cfg), ctypes.c_void_p(256), 1 << 40,
                                          ctypes.byref(out)) == -6
             assert out.value is None
-    cfg, sig = _config(mpdc, mpdc.MODEL_HDC, 7, 4)                  # no such policy
+    cfg, sig = _config(mpdc, mpdc.MODEL_HDC, 8, 4)                  # no such policy
+    assert lib.mpdc_state_workspace_bytes(g.h, ctypes.byref(cfg)) == 0
+    # the per-term engine: the hydrostatic dycore with one member only
+    for model, K, T in ((mpdc.MODEL_SW, 1, 0), (mpdc.MODEL_NDC, 4, 0), (mpdc.MODEL_TRACER, 4, 2)):
+        cfg, sig = _config(mpdc, model, mpdc.POLICY_TERMS, K, T)
+        assert lib.mpdc_state_workspace_bytes(g.h, ctypes.byref(cfg)) == 0
+    cfg, sig = _config(mpdc, mpdc.MODEL_HDC, mpdc.POLICY_TERMS, 4)
+    assert lib.mpdc_state_workspace_bytes(g.h, ctypes.byref(cfg)) > 0
+    cfg.M = 2
     assert lib.mpdc_state_workspace_bytes(g.h, ctypes.byref(cfg)) == 0
     # MIX_PGF32 is built for the layered dycores, SGL for them and the tracer
     cfg, sig = _config(mpdc, mpdc.MODEL_TRACER, mpdc.POLICY_MIX_PGF32, 4, 2)

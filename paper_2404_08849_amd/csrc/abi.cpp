@@ -1097,9 +1097,10 @@ static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
     const double th_s = sw ? 0 : N * KM * (mix ? 4 : 8);
     switch (id) {
     case KERNEL_CELL_A: {
-        // tables, u, ps, theta -> K (+ second derivatives, mdot, dps; NDC: w*, phi*)
+        // tables, u, ps, theta -> second derivatives, mdot, dps (FP64 and boxed: K; NDC: w*, phi*)
+        // K: FP64 in the boxed variant, R in FP64 (r = 8); formed in cell_b otherwise
         double b = cellI + N * kCellSlots * (8 + r) + (u64 ? E * KM * 8 : u_s) + ps + th_s +
-                   N * KM * (box ? 8 : r) /*ke*/ + (box ? N * kCellSlots * 8 : 0) /*FP64 c_ke*/;
+                   (box ? N * KM * 8 + N * kCellSlots * 8 : r == 8 ? N * KM * r : 0);
         if (sw) return b + ps /*h_n*/ + ps /*h_o*/;
         b += N * 3 * kCellSlots * r + 3 * N * KM * r /*hth*/ + N * K1M * 8 /*mdot*/ + ps /*dps*/;
         if (nh) b += 4 * N * K1M * 8 /*w_s, phi_s, w_n, phi_n*/ + 2 * N * K1M * 8 /*w*, phi* */ -
@@ -1109,9 +1110,9 @@ static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
     case KERNEL_VERTEX:
         return V * 4 * 8 + V * 4 * (r + 8) + V * 8 + u_s + ps + V * KM * r;
     case KERNEL_CELL_B: {
-        // Coriolis/KE shares: c_vert, c_div, c_gk, c_tk, q_v, K, u, ps -> qh
-        double b = cellI + N * kCellSlots * 4 + N * kCellSlots * 2 * r + N * 36 * r + V * KM * r +
-                   (box ? 0 : N * KM * r) + u_s + ps + 2 * E * KM * r;
+        // Coriolis/KE shares: c_vert, c_div, c_gk, c_tk, c_ke, q_v, u, ps (FP64: K) -> qh
+        double b = cellI + N * kCellSlots * 4 + N * kCellSlots * 3 * r + N * 36 * r + V * KM * r +
+                   (r == 8 ? N * KM * r : 0) /*K from cell_a*/ + u_s + ps + 2 * E * KM * r;
         if (sw) return b;
         if (box && !first) b += N * KM * 8;                // FP64 Theta_s for the vertical flux
         // theta transport and update: e_cell, hdir, d2, theta, hth, mdot, dps, Th_n, ps_n

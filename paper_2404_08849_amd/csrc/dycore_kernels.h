@@ -95,7 +95,7 @@ struct ColTabLayout {
     size_t ce, cn, cv;    // int [cpb][6]: edges, neighbours, vertices
     size_t ps;            // double [cpb][7][M]: ps_s of the cell (slot 0), then of its neighbours
     size_t psn, dps;      // double [cpb][M]: ps_n and the column mass tendency (cell_b)
-    size_t r;             // cell_a: c_div (FP64), c_ke, c_hess; cell_b: c_div, c_gk, c_tk
+    size_t r;             // cell_a: c_div (FP64), c_ke, c_hess; cell_b: c_div, c_gk, c_tk, c_ke
     size_t hd;            // cell_b: c_hd [cpb][6][8]
     size_t bytes;
 };
@@ -110,9 +110,9 @@ __host__ __device__ inline ColTabLayout coltab_layout(int model, int which, int 
     t.psn = o; o += coltab_round((size_t)cpb * M * 8);
     t.dps = o; o += coltab_round((size_t)cpb * M * 8);
     t.r = o;
-    // cell_a: c_div in FP64, c_ke and c_hess in R; cell_b: c_div, c_gk, c_tk in R
+    // cell_a: c_div in FP64, c_ke and c_hess in R; cell_b: c_div, c_gk, c_tk, c_ke in R
     if (which == KERNEL_CELL_A) o += (size_t)cpb * (6 * 8 + (6 + (model == MODEL_SW ? 0 : 18)) * rsize);
-    else o += (size_t)cpb * (6 + 6 + 36) * rsize;
+    else o += (size_t)cpb * (6 + 6 + 36 + 6) * rsize;
     o = coltab_round(o);
     t.hd = o;
     if (which == KERNEL_CELL_B && model != MODEL_SW) o += (size_t)cpb * 6 * 8 * rsize;

@@ -196,7 +196,8 @@ template <typename R> struct ColTab {
         } else {
             gk = div + (size_t)cpb * 6;
             tk = gk + (size_t)cpb * 6;
-            ke = hs = nullptr;
+            ke = tk + (size_t)cpb * 36;
+            hs = nullptr;
         }
     }
 };
@@ -261,9 +262,11 @@ __device__ __forceinline__ void stage_columns(const StageArgs &a, const ColTab<R
                 t.psn[xm] = pn;
                 t.dps[xm] = dp;
             }
+            const Pack<R, 2> k2 = ldp<R, 2>(pick<R>(m.c_ke, m.c_ke32) + o6);
             stp<int, 2>(t.cv + 2 * x6, c2);
             stp<R, 2>(t.div + 2 * x6, d2);
             stp<R, 2>(t.gk + 2 * x6, g2);
+            stp<R, 2>(t.ke + 2 * x6, k2);
             stp<R, VW>(t.tk + VW * x36, t4);
         }
         const double pv = a.ps_s[(psl == 0 ? i0 + pc : (long)nbr) * M + pmm];
@@ -295,6 +298,13 @@ template <int WHICH, typename R> constexpr int slot_group() {
     if constexpr (WHICH == KERNEL_CELL_A) return sizeof(R) == 8 ? 2 : 3;
     else return sizeof(R) == 8 ? 1 : 2;
 }
+
+// Where the kinetic energy K_i of a cell is formed.  Both column kernels load
+// the cell's six edge velocities; in the FP32 policies cell_b forms K itself
+// (saving cell_a's store and cell_b's load of K); in FP64 the four extra
+// registers would cost cell_b a wave per SIMD, so cell_a forms and stores it;
+// the boxed variant forms it in FP64 in cell_a.  Same sum either way.
+template <typename R, int VAR> constexpr bool ke_in_cell_b() { return sizeof(R) == 4 && VAR != VAR_BOX; }
 
 // column-kernel lane setup: work-group = cpb cells x (K*M/L) lanes
 struct ColLane {
@@ -373,9 +383,9 @@ k_cell_a(StageArgs a) {
         for (int j = 0; j < L; j++) {
             dsg[j] = (MODEL == MODEL_SW) ? 1.0 : a.dsig[v.k[j]];
             dpi_i[j] = lmass<MODEL>(dsg[j], psi[j], a.ptop);
+            ke[j] = 0;
             D[j] = 0.0;
             Df[j] = 0.0f;
-            ke[j] = 0;
             ke64[j] = 0.0;
             h0[j] = h1[j] = h2[j] = 0;
         }
@@ -384,7 +394,7 @@ k_cell_a(StageArgs a) {
         double cdiv[6];
         R cke[6], ch0[6], ch1[6], ch2[6];
         ld6<double>(tb.div64 + lc * kCellSlots, cdiv);
-        ld6<R>(tb.ke + lc * kCellSlots, cke);
+        if constexpr (!ke_in_cell_b<R, VAR>()) ld6<R>(tb.ke + lc * kCellSlots, cke);
         double cked[6];   // FP64 kinetic-energy weights of the boxed variant
         if constexpr (VAR == VAR_BOX) ld6<double>(m.c_ke + (long)i * kCellSlots, cked);
         if constexpr (MODEL != MODEL_SW) {
@@ -437,7 +447,7 @@ k_cell_a(StageArgs a) {
                     else D[j] += cdiv[s] * (double)Fs[s][j];
                 }
                 if constexpr (VAR == VAR_BOX) ke64[j] += cked[s] * ud[j] * ud[j];
-                else ke[j] += cke[s] * ur[j] * ur[j];
+                else if constexpr (!ke_in_cell_b<R, VAR>()) ke[j] += cke[s] * ur[j] * ur[j];
             }
             if constexpr (MODEL != MODEL_SW) {
                 R th_n[L];
@@ -460,7 +470,7 @@ k_cell_a(StageArgs a) {
 #pragma unroll
             for (int j = 0; j < L; j++) kp.v[j] = ke64[j];
             stp<double, L>((double *)a.ke + (long)i * KM + km0, kp);
-        } else {
+        } else if constexpr (!ke_in_cell_b<R, VAR>()) {
             Pack<R, L> kp;
 #pragma unroll
             for (int j = 0; j < L; j++) kp.v[j] = ke[j];
@@ -817,10 +827,11 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                 Hi2[j] = a2.v[j];
             }
         }
-        // fluxes of the six edges and the theta flux divergence
-        R Fs[kCellSlots][L] = {}, hdiv[L];
+        // fluxes of the six edges, the theta flux divergence and the kinetic
+        // energy K_i = sum (l d / 4 A) u^2 of the cell (Eq. 5)
+        R Fs[kCellSlots][L] = {}, hdiv[L], ke[L];
 #pragma unroll
-        for (int j = 0; j < L; j++) hdiv[j] = 0;
+        for (int j = 0; j < L; j++) hdiv[j] = ke[j] = 0;
 #pragma unroll
         for (int s = 0; s < kCellSlots; s++) {
             // slot_group() slots per basic block: the gathers of a block are
@@ -837,6 +848,7 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
             double psn[L];
             ld2d_s<L, M1>(cps + (1 + s) * M, v.mm0, psn);
             const Pack<R, L> u = ldp<R, L>(us + (long)e * KM + km0);
+            const R ck = tb.ke[lc * kCellSlots + s];   // kinetic-energy weight (zero on a pad slot)
 #pragma unroll
             for (int j = 0; j < L; j++) {
                 const double dpe = 0.5 * (dpi_i[j] + lmass<MODEL>(dsg[j], psn[j], a.ptop));
@@ -844,6 +856,7 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                 if constexpr (sizeof(R) == 8) f = dpe * u.v[j];
                 else f = (float)dpe * u.v[j];
                 Fs[s][j] = pad ? (R)0 : f;
+                if constexpr (ke_in_cell_b<R, VAR>()) ke[j] += ck * u.v[j] * u.v[j];
             }
             if constexpr (MODEL != MODEL_SW) {
                 // Third-order upwind edge value: with the upwind weight 1 the two
@@ -903,8 +916,11 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                     }
             }
             // (the boxed variant adds -grad K in FP64 on the edge instead)
-            Pack<R, L> kp;
-            if constexpr (VAR != VAR_BOX) kp = ldp<R, L>(a.ke_in<R>() + (long)i * KM + km0);
+            if constexpr (!ke_in_cell_b<R, VAR>() && VAR != VAR_BOX) {
+                const Pack<R, L> kp = ldp<R, L>(a.ke_in<R>() + (long)i * KM + km0);
+#pragma unroll
+                for (int j = 0; j < L; j++) ke[j] = kp.v[j];
+            }
             const R *tk = tb.tk + lc * kCellSlots * kCellSlots;
             R *qh = a.qh_out<R>();
 #pragma unroll
@@ -925,7 +941,7 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                         B = fmar(w[sp], G[sp][j], B);
                     }
                     if constexpr (VAR == VAR_BOX) out.v[j] = fmar(Q[s][j], A, B);
-                    else out.v[j] = fmar(cgk[s], kp.v[j], fmar(Q[s][j], A, B));
+                    else out.v[j] = fmar(cgk[s], ke[j], fmar(Q[s][j], A, B));
                 }
                 const int side = (cdiv[s] > (R)0) ? 0 : 1;
                 stp<R, L>(qh + ((long)e * 2 + side) * KM + km0, out);

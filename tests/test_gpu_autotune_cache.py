@@ -81,3 +81,25 @@ def test_autotune_cache_unwritable_is_an_error(mpdc, mesh_cache, tmp_path):
     with pytest.raises(mpdc.MpdcError) as e:
         st.autotune(cache_path=str(tmp_path / "no_such_dir" / "tune.txt"))
     assert e.value.code == -1 and "autotune cache" in str(e.value)
+
+
+@pytest.mark.parametrize("policy", ["MIX", "DBL", "MIX_DBL_MASS"])
+def test_autotune_leaves_the_state_unchanged(mpdc, mesh_cache, policy):
+    """Tuning (the timed launches write only the stage scratch set, also when
+    they store the FP64 state as the last stage does) changes neither the
+    state nor, after it, the steps' results."""
+    m = mesh_cache(4)
+    K = 10
+    s = ic.hdc_jet(m, K, seed=2000)
+    g = mpdc.Mesh(m)
+    fields = (mpdc.FIELD_PS, mpdc.FIELD_THETA, mpdc.FIELD_U)
+    pol = getattr(mpdc, "POLICY_" + policy)
+    st = _state(mpdc, g, s, K, pol)
+    before = [st.state_read(f) for f in fields]
+    st.autotune()
+    after = [st.state_read(f) for f in fields]
+    assert all(np.array_equal(x, y) for x, y in zip(before, after))
+    ref = _state(mpdc, g, s, K, pol)
+    st.dycore_step(3)
+    ref.dycore_step(3)
+    assert all(np.array_equal(st.state_read(f), ref.state_read(f)) for f in fields)

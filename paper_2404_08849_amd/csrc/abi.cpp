@@ -141,6 +141,7 @@ struct mpdc_state {
     unsigned term_mask = 0;                       // POLICY_TERMS: terms in FP32
     double *tF = nullptr, *tD = nullptr, *ttheta = nullptr, *tpmid = nullptr;   // POLICY_TERMS arrays
     double *b = nullptr, *phis = nullptr, *dsig = nullptr, *sig = nullptr, *dps = nullptr, *mdot = nullptr;
+    float *mdot32 = nullptr;                      // mixed policies: mdot in FP32 for its advective users
     void *ke = nullptr, *hth = nullptr, *qv = nullptr, *qh = nullptr;
     double *alpha = nullptr, *phim = nullptr, *pm = nullptr, *mum = nullptr, *wstar = nullptr, *phistar = nullptr;
     int *nh_terrain = nullptr;                    // NDC: the surface geopotential varies (device flag)
@@ -217,6 +218,7 @@ size_t state_layout(mpdc_state *st, void *base) {
     if (st->model == MPDC_MODEL_HDC) st->phis = c.take<double>(N);   // zero (the workspace is cleared): flat
     st->dps = c.take<double>(N * M);
     if (!sw) st->mdot = c.take<double>(N * K1M);
+    if (!sw && mix && st->policy != MPDC_POLICY_MIX_BOX) st->mdot32 = c.take<float>(N * K1M);
     st->ke = c.take<char>(N * KM * (st->policy == MPDC_POLICY_MIX_BOX ? sizeof(double) : r));
     if (!sw) st->hth = c.take<char>(3 * N * KM * r);
     st->qv = c.take<char>(V * KM * r);
@@ -329,6 +331,8 @@ StageArgs stage_args(const mpdc_state *st, int s) {
     a.phis = st->phis;
     a.dps = st->dps;
     a.mdot = st->mdot;
+    a.mdot32 = st->mdot32;
+    a.mdot64 = st->accumulate ? 1 : 0;
     a.ke = st->ke;
     a.hth = st->hth;
     a.qv = st->qv;
@@ -1085,6 +1089,7 @@ static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
     const bool mix = !fp64_storage(st->policy);
     const bool box = st->policy == MPDC_POLICY_MIX_BOX;
     const bool u64 = box || st->policy == MPDC_POLICY_MIX_DBL_MASS;   // cell_a reads the FP64 velocity
+    const bool m32 = mix && !box;   // the vertical mass flux's advective users read its FP32 copy
     const bool first = (stage == 0);
     const bool st64 = st->model != MPDC_MODEL_TRACER && stage_stores_fp64(st, stage);   // FP64 u, Theta out
     if (st->model == MPDC_MODEL_TRACER) {
@@ -1113,7 +1118,9 @@ static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
         double b = cellI + N * kCellSlots * (8 + r) + (u64 ? E * KM * 8 : u_s) + ps + th_s +
                    (box ? N * KM * 8 + N * kCellSlots * 8 : r == 8 ? N * KM * r : 0);
         if (sw) return b + ps /*h_n*/ + ps /*h_o*/;
-        b += N * 3 * kCellSlots * r + 3 * N * KM * r /*hth*/ + N * K1M * 8 /*mdot*/ + ps /*dps*/;
+        // mdot: FP64 (FP32 policies: an FP32 copy, and FP64 only for the tracer accumulation)
+        b += N * 3 * kCellSlots * r + 3 * N * KM * r /*hth*/ + ps /*dps*/ +
+             (m32 ? N * K1M * 4 + (st->accumulate ? N * K1M * 8 : 0) : N * K1M * 8);
         if (nh) b += 4 * N * K1M * 8 /*w_s, phi_s, w_n, phi_n*/ + 2 * N * K1M * 8 /*w*, phi* */ -
                      (first ? 2 * N * K1M * 8 : 0);
         return b;
@@ -1127,7 +1134,7 @@ static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
         if (sw) return b;
         if (box && !first) b += N * KM * 8;                // FP64 Theta_s for the vertical flux
         // theta transport and update: e_cell, hdir, d2, theta, hth, mdot, dps, Th_n, ps_n
-        b += E * 8 + E * 6 * r + E * r + th_s + 3 * N * KM * r + N * K1M * 8 + ps;
+        b += E * 8 + E * 6 * r + E * r + th_s + 3 * N * KM * r + N * K1M * (m32 ? 4 : 8) + ps;
         b += (first && !mix) ? 0 : N * KM * 8 + ps;       // Th_n, ps_n (stage 1 FP64: same arrays as _s)
         b += (st64 ? N * KM * 8 : 0) + ps + 2 * N * KM * 8 + (mix ? N * KM * 4 : 0);   // Th_o, ps_o, alpha, phim, th32_o
         if (!nh) b += N * 8;                               // surface geopotential
@@ -1143,7 +1150,7 @@ static double kernel_bytes_stage(const mpdc_state *st, int id, int stage) {
         b += (first && !mix) ? 0 : E * KM * 8;             // u_n
         b += (st64 ? E * KM * 8 : 0) + (mix ? E * KM * 4 : 0);   // u_o, u32_o
         if (sw) return b + ps /*h_o*/ + N * 8 /*b*/;
-        b += u_s + ps + N * K1M * 8 + 2 * N * KM * 8 + ps; // u_s, ps_s, mdot, alpha, phim, ps_o
+        b += u_s + ps + N * K1M * (m32 ? 4 : 8) + 2 * N * KM * 8 + ps; // u_s, ps_s, mdot, alpha, phim, ps_o
         if (box) b += N * KM * 8 - u_s + (first ? 0 : E * KM * 8);   // FP64 K; FP64 u_s (= u_n at stage 1)
         if (nh) b += 2 * N * KM * 8;                        // pm, mum
         return b;

@@ -68,6 +68,10 @@ struct StageArgs {
     // stage intermediates
     double *dps;         // [N][M]
     double *mdot;        // [N][K+1][M]
+    float *mdot32;       // [N][K+1][M] mixed policies: mdot rounded to FP32 for its advective
+                         // users (the vertical theta flux of cell_b, the vertical advection of u)
+    int mdot64;          // with mdot32: whether cell_a also stores the FP64 mdot (read only by
+                         // the tracer mass-flux accumulation)
     void *ke;            // [N][K][M]      (R; FP64 in the boxed variant)
     void *hth;           // [N][3][K][M]   (R)
     void *qv;            // [V][K][M]      (R)

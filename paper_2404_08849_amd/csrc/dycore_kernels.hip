@@ -299,6 +299,13 @@ template <int WHICH, typename R> constexpr int slot_group() {
     else return sizeof(R) == 8 ? 1 : 2;
 }
 
+// The FP32 policies (except the boxed variant, which forms the vertical
+// advection in FP64) give the vertical mass flux's advective users, cell_b's
+// vertical theta flux and edge's vertical advection of u, an FP32 copy of it
+// written by cell_a: half the bytes and loads of the FP64 flux, which then
+// is stored only for the tracer mass-flux accumulation.
+template <typename R, int VAR> constexpr bool mdot32_used() { return sizeof(R) == 4 && VAR != VAR_BOX; }
+
 // Where the kinetic energy K_i of a cell is formed.  Both column kernels load
 // the cell's six edge velocities; in the FP32 policies cell_b forms K itself
 // (saving cell_a's store and cell_b's load of K); in FP64 the four extra
@@ -358,6 +365,7 @@ k_cell_a(StageArgs a) {
     // mixed-policy variants: the boxed kinetic energy and the FP64 mass flux
     // read the FP64 velocity instead of its FP32 shadow
     constexpr bool U64 = VAR == VAR_BOX || VAR == VAR_DBL_MASS;
+    constexpr bool MDOT32 = mdot32_used<R, VAR>();
     extern __shared__ double lds[];
     const DevMesh &m = a.mesh;
     const int K = a.K, M = M1 ? 1 : a.M, KM = K * M;
@@ -529,9 +537,14 @@ k_cell_a(StageArgs a) {
                 const double dps = -scan[lc * KM + (K - 1) * M + mm];
                 const double acc = scan[lc * KM + v.k[j] * M + mm];
                 mdot_b[j] = (v.k[j] == K - 1) ? 0.0 : -acc - sgb[j] * dps;
-                a.mdot[(long)i * K1M + (long)(v.k[j] + 1) * M + mm] = mdot_b[j];
+                // FP32 policies: the FP32 copy for the advective users, and the FP64
+                // flux only where the tracer accumulation reads it
+                const bool st64 = !MDOT32 || a.mdot64;
+                if (st64) a.mdot[(long)i * K1M + (long)(v.k[j] + 1) * M + mm] = mdot_b[j];
+                if constexpr (MDOT32) a.mdot32[(long)i * K1M + (long)(v.k[j] + 1) * M + mm] = (float)mdot_b[j];
                 if (v.k[j] == 0) {
-                    a.mdot[(long)i * K1M + mm] = 0.0;
+                    if (st64) a.mdot[(long)i * K1M + mm] = 0.0;
+                    if constexpr (MDOT32) a.mdot32[(long)i * K1M + mm] = 0.0f;
                     a.dps[(long)i * M + mm] = dps;
                 }
             }
@@ -1037,6 +1050,12 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                 R vd;
                 if constexpr (VAR == VAR_BOX) {
                     vd = (R)vb[j];   // FP64 compute, one rounding as a tendency
+                } else if constexpr (mdot32_used<R, VAR>()) {
+                    const float *m32 = a.mdot32 + (long)i * K1M;
+                    const R mt = m32[(long)v.k[j] * M + mm], mb = m32[(long)(v.k[j] + 1) * M + mm];
+                    const R top = (v.k[j] > 0 ? (R)1 : (R)0) * (mt * ((R)0.5 * (thu[j] + th_i[j])));
+                    const R bot = (v.k[j] < K - 1 ? (R)1 : (R)0) * (mb * ((R)0.5 * (th_i[j] + thd[j])));
+                    vd = bot - top;
                 } else {
                     const R mt = (R)md[(long)v.k[j] * M + mm], mb = (R)md[(long)(v.k[j] + 1) * M + mm];
                     const R top = (v.k[j] > 0 ? (R)1 : (R)0) * (mt * ((R)0.5 * (thu[j] + th_i[j])));
@@ -1386,7 +1405,12 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
         for (int j = 0; j < L; j++) dsg[j] = a.dsig[v.k[j]];
         const Pack<RU, L> uk = ldp<RU, L>(us + base);
         RU uup[L], udn[L];
-        double mt[L], mb[L];
+        // the interface mass flux: its FP32 copy in the FP32 policies
+        using MT = typename std::conditional<mdot32_used<R, VAR>(), float, double>::type;
+        const MT *mdp;
+        if constexpr (sizeof(MT) == 4) mdp = a.mdot32;
+        else mdp = a.mdot;
+        MT mt[L], mb[L];
         // the levels above and below are read from clamped indices (no load
         // under a condition); the values past the lid and the surface are unused
         if constexpr (M1) {
@@ -1397,8 +1421,8 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
                 uup[j] = (j > 0) ? uk.v[j - 1] : ua;   // ua, ub: unused at the lid and the surface
                 udn[j] = (j < L - 1) ? uk.v[j + 1] : ub;
             }
-            const double *m1p = a.mdot + (long)c1 * K1M + v.k0, *m2p = a.mdot + (long)c2 * K1M + v.k0;
-            double i1[L + 1], i2[L + 1];
+            const MT *m1p = mdp + (long)c1 * K1M + v.k0, *m2p = mdp + (long)c2 * K1M + v.k0;
+            MT i1[L + 1], i2[L + 1];
 #pragma unroll
             for (int j = 0; j <= L; j++) {
                 i1[j] = m1p[j];
@@ -1406,22 +1430,22 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
             }
 #pragma unroll
             for (int j = 0; j < L; j++) {
-                mt[j] = 0.5 * (i1[j] + i2[j]);
-                mb[j] = 0.5 * (i1[j + 1] + i2[j + 1]);
+                mt[j] = (MT)0.5 * (i1[j] + i2[j]);
+                mb[j] = (MT)0.5 * (i1[j + 1] + i2[j + 1]);
             }
         } else {
             const Pack<RU, L> pu = ldp<RU, L>(us + base - (v.k0 > 0 ? M : 0));
             const Pack<RU, L> pd = ldp<RU, L>(us + base + (v.k0 < K - 1 ? M : 0));
-            const Pack<double, L> t1 = ldp<double, L>(a.mdot + (long)c1 * K1M + (long)v.k0 * M + v.mm0);
-            const Pack<double, L> t2 = ldp<double, L>(a.mdot + (long)c2 * K1M + (long)v.k0 * M + v.mm0);
-            const Pack<double, L> b1 = ldp<double, L>(a.mdot + (long)c1 * K1M + (long)(v.k0 + 1) * M + v.mm0);
-            const Pack<double, L> b2 = ldp<double, L>(a.mdot + (long)c2 * K1M + (long)(v.k0 + 1) * M + v.mm0);
+            const Pack<MT, L> t1 = ldp<MT, L>(mdp + (long)c1 * K1M + (long)v.k0 * M + v.mm0);
+            const Pack<MT, L> t2 = ldp<MT, L>(mdp + (long)c2 * K1M + (long)v.k0 * M + v.mm0);
+            const Pack<MT, L> b1 = ldp<MT, L>(mdp + (long)c1 * K1M + (long)(v.k0 + 1) * M + v.mm0);
+            const Pack<MT, L> b2 = ldp<MT, L>(mdp + (long)c2 * K1M + (long)(v.k0 + 1) * M + v.mm0);
 #pragma unroll
             for (int j = 0; j < L; j++) {
                 uup[j] = pu.v[j];
                 udn[j] = pd.v[j];
-                mt[j] = 0.5 * (t1.v[j] + t2.v[j]);
-                mb[j] = 0.5 * (b1.v[j] + b2.v[j]);
+                mt[j] = (MT)0.5 * (t1.v[j] + t2.v[j]);
+                mb[j] = (MT)0.5 * (b1.v[j] + b2.v[j]);
             }
         }
 #pragma unroll

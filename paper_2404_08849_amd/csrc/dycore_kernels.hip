@@ -723,36 +723,91 @@ k_cell_a(StageArgs a) {
 // ---------------------------------------------------------------------------
 // vertex: vorticity, FP64 vertex mass, potential vorticity
 // ---------------------------------------------------------------------------
-template <int MODEL, typename R, int L, bool M1, int VAR>
+// LDS of the vertex kernel: per vertex of the work-group its f, three kite
+// weights, three curl weights, three edges and the three cells' surface
+// pressures [3][M]; then dsig [K].  Doubles throughout (the curl weights and
+// edge indices are exact in them).  Shapes whose vertices would not fit
+// 64 KiB (a vertex of very few lanes in a large work-group) read their
+// tables directly instead.
+__host__ __device__ inline int vertex_stage_max(int flat_block, int lanes) { return flat_block / lanes + 2; }
+__host__ __device__ inline size_t vertex_lds_bytes(int flat_block, int lanes, int K, int M) {
+    return ((size_t)vertex_stage_max(flat_block, lanes) * (10 + 3 * (size_t)M) + (size_t)K) * 8;
+}
+constexpr size_t kVertexLdsMax = 65536;
+
+// One vertex's constants: f, kite weights, curl weights, edges (as doubles).
+__device__ __forceinline__ void vertex_row(const DevMesh &m, long vx, bool f32curl, double t[10]) {
+    const Pack<int, 4> ve = ldp<int, 4>(m.v_edge + 4 * vx);
+    const Pack<double, 2> k0 = ldp<double, 2>(m.v_kite + 4 * vx), k1 = ldp<double, 2>(m.v_kite + 4 * vx + 2);
+    t[0] = m.v_f[vx];
+    t[1] = k0.v[0]; t[2] = k0.v[1]; t[3] = k1.v[0];
+    if (f32curl) {
+        const Pack<float, 4> c = ldp<float, 4>(m.v_curl32 + 4 * vx);
+        t[4] = (double)c.v[0]; t[5] = (double)c.v[1]; t[6] = (double)c.v[2];
+    } else {
+        const Pack<double, 2> c0 = ldp<double, 2>(m.v_curl + 4 * vx), c1 = ldp<double, 2>(m.v_curl + 4 * vx + 2);
+        t[4] = c0.v[0]; t[5] = c0.v[1]; t[6] = c1.v[0];
+    }
+    t[7] = (double)ve.v[0]; t[8] = (double)ve.v[1]; t[9] = (double)ve.v[2];
+}
+
+template <int MODEL, typename R, int L, bool M1, int VAR, bool STAGED>
 __global__ void __launch_bounds__(1024) k_vertex(StageArgs a) {
     // the all-FP32 variant forms the vertex mass and the potential vorticity in
     // FP32 (the paper keeps the vertex mass of zeta_p in FP64)
     constexpr bool S32 = VAR == VAR_SGL;
     using RM = typename std::conditional<S32, float, double>::type;
+    extern __shared__ double vlds[];
     const DevMesh &m = a.mesh;
     const int K = a.K, M = M1 ? 1 : a.M, KM = K * M;
     const int lanes = KM / L;
-    const long idx = (long)xcd_block() * a.flat_block + threadIdx.x;   // flat_block = threads per work-group
-    if (idx >= (long)m.V * lanes) return;
+    const long b0 = (long)xcd_block() * a.flat_block;
+    const long nall = (long)m.V * lanes;
+    const long idx = b0 + threadIdx.x;
+    // The work-group's vertices share their tables and cells' surface
+    // pressures among all K M / L lanes of each vertex: staged once in LDS,
+    // so the lanes issue only their three velocity gathers.
+    const int v0 = (int)(b0 / lanes);
+    const int nvm = vertex_stage_max(a.flat_block, lanes);
+    double *sT = vlds;                              // [nvm][10]: f, kite[3], curl[3], edge[3]
+    double *sP = sT + (long)nvm * 10;               // [nvm][3][M]
+    double *sD = sP + (long)nvm * 3 * M;            // [K]
+    if constexpr (STAGED) {
+        const long lastl = (b0 + a.flat_block < nall ? b0 + a.flat_block : nall) - 1;
+        const int nv = (int)(lastl / lanes) - v0 + 1;
+        const int nrow = nv * 3 * M;
+        for (int x = threadIdx.x; x < nv + nrow + K; x += blockDim.x) {
+            if (x < nv) {
+                vertex_row(m, v0 + x, sizeof(R) == 4, sT + (long)x * 10);
+            } else if (x < nv + nrow) {
+                const int y = x - nv, vs = y / (3 * M), r = (y - vs * 3 * M) / M, mm = y - vs * 3 * M - r * M;
+                const int c = m.v_cell[4 * (long)(v0 + vs) + r];
+                sP[y] = a.ps_s[(long)c * M + mm];
+            } else {
+                sD[x - nv - nrow] = a.dsig[x - nv - nrow];
+            }
+        }
+        __syncthreads();
+    }
+    if (idx >= nall) return;
     const int vx = (int)(idx / lanes);
     const int km0 = (int)(idx - (long)vx * lanes) * L;
     const Vals<L, M1> v(km0, M);
-    const Pack<int, 4> ve = ldp<int, 4>(m.v_edge + 4 * (long)vx);
-    const Pack<int, 4> vc = ldp<int, 4>(m.v_cell + 4 * (long)vx);
-    R cw[4];
-    if constexpr (sizeof(R) == 4) {
-        const Pack<float, 4> c = ldp<float, 4>(m.v_curl32 + 4 * (long)vx);
-#pragma unroll
-        for (int r = 0; r < 4; r++) cw[r] = c.v[r];
+    double trow[10];
+    const double *t;
+    Pack<int, 4> vc;
+    if constexpr (STAGED) {
+        t = sT + (long)(vx - v0) * 10;
     } else {
-        const Pack<double, 2> c0 = ldp<double, 2>(m.v_curl + 4 * (long)vx), c1 = ldp<double, 2>(m.v_curl + 4 * (long)vx + 2);
-        cw[0] = c0.v[0]; cw[1] = c0.v[1]; cw[2] = c1.v[0]; cw[3] = c1.v[1];
+        vertex_row(m, vx, sizeof(R) == 4, trow);
+        vc = ldp<int, 4>(m.v_cell + 4 * (long)vx);
+        t = trow;
     }
-    const Pack<double, 2> k0 = ldp<double, 2>(m.v_kite + 4 * (long)vx), k1 = ldp<double, 2>(m.v_kite + 4 * (long)vx + 2);
-    const RM kw[3] = {(RM)k0.v[0], (RM)k0.v[1], (RM)k1.v[0]};
+    const RM kw[3] = {(RM)t[1], (RM)t[2], (RM)t[3]};
+    const R cw[3] = {(R)t[4], (R)t[5], (R)t[6]};
     double dsg[L];
 #pragma unroll
-    for (int j = 0; j < L; j++) dsg[j] = (MODEL == MODEL_SW) ? 1.0 : a.dsig[v.k[j]];
+    for (int j = 0; j < L; j++) dsg[j] = (MODEL == MODEL_SW) ? 1.0 : STAGED ? sD[v.k[j]] : a.dsig[v.k[j]];
     R zeta[L];
     RM hv[L];
 #pragma unroll
@@ -763,16 +818,18 @@ __global__ void __launch_bounds__(1024) k_vertex(StageArgs a) {
     const R *us = u_prev_ptr<R>(a);
 #pragma unroll
     for (int r = 0; r < 3; r++) {
-        const Pack<R, L> u = ldp<R, L>(us + (long)ve.v[r] * KM + km0);
+        const int e = (int)t[7 + r];
+        const Pack<R, L> u = ldp<R, L>(us + (long)e * KM + km0);
         double ps[L];
-        ld2d<L, M1>(a.ps_s, vc.v[r], M, v.mm0, ps);
+        if constexpr (STAGED) ld2d_s<L, M1>(sP + ((long)(vx - v0) * 3 + r) * M, v.mm0, ps);
+        else ld2d<L, M1>(a.ps_s, vc.v[r], M, v.mm0, ps);
 #pragma unroll
         for (int j = 0; j < L; j++) {
             zeta[j] += cw[r] * u.v[j];
             hv[j] += kw[r] * (RM)lmass<MODEL>(dsg[j], ps[j], a.ptop);
         }
     }
-    const double f = m.v_f[vx];
+    const double f = t[0];
     Pack<R, L> q;
 #pragma unroll
     for (int j = 0; j < L; j++) {
@@ -1555,6 +1612,18 @@ __global__ void k_shadows(StageArgs a) {
 namespace {
 inline unsigned nblocks(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// the vertex kernel, its tables staged in LDS where the work-group's vertices fit
+template <int MODEL, typename R, int L, bool M1, int VV> void launch_vertex(const StageArgs &a, hipStream_t s) {
+    const int lanes = a.K * a.M / L, fb = a.flat_block;
+    const size_t lds = vertex_lds_bytes(fb, lanes, a.K, a.M);
+    if (lds <= kVertexLdsMax)
+        hipLaunchKernelGGL((k_vertex<MODEL, R, L, M1, VV, true>), dim3(nblocks((long)a.mesh.V * lanes, fb)), dim3(fb),
+                           lds, s, a);
+    else
+        hipLaunchKernelGGL((k_vertex<MODEL, R, L, M1, VV, false>), dim3(nblocks((long)a.mesh.V * lanes, fb)),
+                           dim3(fb), 0, s, a);
+}
+
 // VAR selects the mixed-policy variant of the FP32 instances; a kernel the
 // variant does not change runs its default instance
 template <int MODEL, typename R, int L, bool M1, int VAR>
@@ -1577,7 +1646,7 @@ hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
         hipLaunchKernelGGL((k_cell_a<MODEL, R, L, M1, VA>), dim3(colblocks), dim3(colthreads), lds_a, s, a);
         break;
     case KERNEL_VERTEX:
-        hipLaunchKernelGGL((k_vertex<MODEL, R, L, M1, VV>), dim3(nblocks((long)a.mesh.V * lanes, fb)), dim3(fb), 0, s, a);
+        launch_vertex<MODEL, R, L, M1, VV>(a, s);
         break;
     case KERNEL_CELL_B:
         hipLaunchKernelGGL((k_cell_b<MODEL, R, L, M1, VB>), dim3(colblocks), dim3(colthreads), lds_b, s, a);
@@ -1600,7 +1669,7 @@ hipError_t launch_flat4(const StageArgs &a, int which, hipStream_t s) {
     const int lanes = KM / 4;
     const int fb = a.flat_block;
     if (which == KERNEL_VERTEX)
-        hipLaunchKernelGGL((k_vertex<MODEL, R, 4, M1, VV>), dim3(nblocks((long)a.mesh.V * lanes, fb)), dim3(fb), 0, s, a);
+        launch_vertex<MODEL, R, 4, M1, VV>(a, s);
     else if (which == KERNEL_EDGE)
         hipLaunchKernelGGL((k_edge<MODEL, R, 4, M1, VB>), dim3(nblocks((long)a.mesh.E * lanes, fb)), dim3(fb), 0, s, a);
     else

@@ -1413,40 +1413,104 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
 // ---------------------------------------------------------------------------
 // edge: momentum
 // ---------------------------------------------------------------------------
-template <int MODEL, typename R, int L, bool M1, int VAR>
+// LDS of the edge kernel: per edge of the work-group its two cells and
+// 1/d_e, then the two cells' surface pressures of the stage input and of
+// the pressure-gradient term [4][M]; then sigma [K+1] and dsigma [K].
+// Shapes whose edges would not fit 64 KiB read them directly instead.
+__host__ __device__ inline size_t edge_lds_bytes(int flat_block, int lanes, int K, int M) {
+    return ((size_t)vertex_stage_max(flat_block, lanes) * (3 + 4 * (size_t)M) + 2 * (size_t)K + 1) * 8;
+}
+
+template <int MODEL, typename R, int L, bool M1, int VAR, bool STAGED>
 __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
     // boxed variant: -grad K and the vertical advection of u in FP64 (from the
     // FP64 kinetic energy and velocity), rounded to FP32 once with the
     // pressure-gradient term as one tendency
     constexpr bool BOX = VAR == VAR_BOX;
     using RU = typename std::conditional<BOX, double, R>::type;
+    extern __shared__ double elds[];
     const DevMesh &m = a.mesh;
     const int K = a.K, M = M1 ? 1 : a.M, KM = K * M;
     const int lanes = KM / L;
-    const long idx = (long)xcd_block() * a.flat_block + threadIdx.x;   // flat_block = threads per work-group
-    if (idx >= (long)m.E * lanes) return;
-    const int e = (int)(idx / lanes);
-    const int km0 = (int)(idx - (long)e * lanes) * L;
+    const long b0 = (long)xcd_block() * a.flat_block;   // flat_block = threads per work-group
+    const long nall = (long)m.E * lanes;
+    const long idx = b0 + threadIdx.x;
+    const bool valid = idx < nall;
+    const int e = (int)((valid ? idx : nall - 1) / lanes);
+    const int km0 = (int)((valid ? idx : nall - 1) - (long)e * lanes) * L;
     const long base = (long)e * KM + km0;
     const Vals<L, M1> v(km0, M);
-    const Pack<int, 2> cc = ldp<int, 2>(m.e_cell + 2 * (long)e);
-    const int c1 = cc.v[0], c2 = cc.v[1];
 
-    // Coriolis - grad K: the two cells' shares (Coriolis only when boxed)
+    // Coriolis - grad K: the two cells' shares (issued before the staging)
     R adv[L];
-    double box[L];
-    if constexpr (BOX) {
-        const double *ke = (const double *)a.ke;
-        const Pack<double, L> k1 = ldp<double, L>(ke + (long)c1 * KM + km0), k2 = ldp<double, L>(ke + (long)c2 * KM + km0);
-        const double di = m.e_dinv[e];
-#pragma unroll
-        for (int j = 0; j < L; j++) box[j] = -(k2.v[j] - k1.v[j]) * di;
-    }
     {
         const R *qh = a.qh_in<R>();
         const Pack<R, L> q1 = ldp<R, L>(qh + (long)e * 2 * KM + km0), q2 = ldp<R, L>(qh + ((long)e * 2 + 1) * KM + km0);
 #pragma unroll
         for (int j = 0; j < L; j++) adv[j] = q1.v[j] + q2.v[j];
+    }
+    // The work-group's edges share their cells, 1/d_e, the cells' surface
+    // pressures and the level fractions among all K M / L lanes of each edge:
+    // staged once in LDS, so the lanes gather only the fields of the levels.
+    const int e0 = (int)(b0 / lanes);
+    const int nem = vertex_stage_max(a.flat_block, lanes);
+    const int row_len = 3 + 4 * M;
+    double *sR = elds;                              // [nem][3 + 4 M]
+    double *sS = sR + (long)nem * row_len;          // sigma [K+1]
+    double *sD = sS + K + 1;                        // dsigma [K]
+    if constexpr (STAGED) {
+        const long lastl = (b0 + a.flat_block < nall ? b0 + a.flat_block : nall) - 1;
+        const int ne = (int)(lastl / lanes) - e0 + 1;
+        const int nps = ne * 4 * M;
+        for (int x = threadIdx.x; x < ne + nps + 2 * K + 1; x += blockDim.x) {
+            if (x < ne) {
+                const long ex = e0 + x;
+                const Pack<int, 2> cc = ldp<int, 2>(m.e_cell + 2 * ex);
+                double *r = sR + (long)x * row_len;
+                r[0] = (double)cc.v[0];
+                r[1] = (double)cc.v[1];
+                r[2] = m.e_dinv[ex];
+            } else if (x < ne + nps) {
+                const int y = x - ne, es = y / (4 * M), q = (y - es * 4 * M) / M, mm = y - es * 4 * M - q * M;
+                const int c = m.e_cell[2 * (long)(e0 + es) + (q & 1)];
+                sR[(long)es * row_len + 3 + q * M + mm] = (q < 2 ? a.ps_s : a.ps_pg)[(long)c * M + mm];
+            } else if (x < ne + nps + K + 1) {
+                sS[x - ne - nps] = a.sig[x - ne - nps];
+            } else {
+                sD[x - ne - nps - K - 1] = a.dsig[x - ne - nps - K - 1];
+            }
+        }
+        __syncthreads();
+    }
+    if (!valid) return;
+    const double *row = sR + (long)(e - e0) * row_len;
+    int c1, c2;
+    double dinv_e;
+    if constexpr (STAGED) {
+        c1 = (int)row[0];
+        c2 = (int)row[1];
+        dinv_e = row[2];
+    } else {
+        const Pack<int, 2> cc = ldp<int, 2>(m.e_cell + 2 * (long)e);
+        c1 = cc.v[0];
+        c2 = cc.v[1];
+        dinv_e = m.e_dinv[e];
+    }
+    // surface pressure q (0, 1: the stage input at c1, c2; 2, 3: the
+    // pressure-gradient term's at c1, c2) and the level fractions
+    auto cell_ps = [&](int q, double out[L]) {
+        if constexpr (STAGED) ld2d_s<L, M1>(row + 3 + q * M, v.mm0, out);
+        else ld2d<L, M1>(q < 2 ? a.ps_s : a.ps_pg, (q & 1) ? c2 : c1, M, v.mm0, out);
+    };
+    auto sig_at = [&](int k) { return STAGED ? sS[k] : a.sig[k]; };
+    auto dsig_at = [&](int k) { return STAGED ? sD[k] : a.dsig[k]; };
+
+    double box[L];
+    if constexpr (BOX) {
+        const double *ke = (const double *)a.ke;
+        const Pack<double, L> k1 = ldp<double, L>(ke + (long)c1 * KM + km0), k2 = ldp<double, L>(ke + (long)c2 * KM + km0);
+#pragma unroll
+        for (int j = 0; j < L; j++) box[j] = -(k2.v[j] - k1.v[j]) * dinv_e;
     }
 
     if constexpr (MODEL != MODEL_SW) {
@@ -1456,10 +1520,10 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
         else us = u_prev_ptr<R>(a);
         const long K1M = (long)(K + 1) * M;
         double p1[L], p2[L], dsg[L];
-        ld2d<L, M1>(a.ps_s, c1, M, v.mm0, p1);
-        ld2d<L, M1>(a.ps_s, c2, M, v.mm0, p2);
+        cell_ps(0, p1);
+        cell_ps(1, p2);
 #pragma unroll
-        for (int j = 0; j < L; j++) dsg[j] = a.dsig[v.k[j]];
+        for (int j = 0; j < L; j++) dsg[j] = dsig_at(v.k[j]);
         const Pack<RU, L> uk = ldp<RU, L>(us + base);
         RU uup[L], udn[L];
         // the interface mass flux: its FP32 copy in the FP32 policies
@@ -1522,12 +1586,12 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
 
     // pressure-gradient force and gravity in FP64 from the updated mass/Theta
     // (forward-backward; ps_pg is the stage's input mass when that is off)
-    const double dinv64 = m.e_dinv[e];
+    const double dinv64 = dinv_e;
     double pgf[L];
     if constexpr (MODEL == MODEL_SW) {
         double h1[L], h2[L];
-        ld2d<L, M1>(a.ps_pg, c1, M, v.mm0, h1);
-        ld2d<L, M1>(a.ps_pg, c2, M, v.mm0, h2);
+        cell_ps(2, h1);
+        cell_ps(3, h2);
         const double b1 = a.b[c1], b2 = a.b[c2];
 #pragma unroll
         for (int j = 0; j < L; j++) pgf[j] = -a.grav * ((h2[j] + b2) - (h1[j] + b1)) * dinv64;
@@ -1537,14 +1601,15 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
         const Pack<double, L> ph1 = ldp<double, L>(a.phim + x1), ph2 = ldp<double, L>(a.phim + x2);
         if constexpr (MODEL == MODEL_HDC) {
             double s1[L], s2[L];
-            ld2d<L, M1>(a.ps_pg, c1, M, v.mm0, s1);
-            ld2d<L, M1>(a.ps_pg, c2, M, v.mm0, s2);
+            cell_ps(2, s1);
+            cell_ps(3, s2);
 #pragma unroll
             for (int j = 0; j < L; j++) {
                 const int k = v.k[j];
+                const double sgk = sig_at(k), sgk1 = sig_at(k + 1);
                 if constexpr (VAR == VAR_PGF32) {
                     // the single-precision pressure-gradient term of the FP32 variant
-                    const float pt = (float)a.ptop, st_ = (float)a.sig[k], sb = (float)a.sig[k + 1];
+                    const float pt = (float)a.ptop, st_ = (float)sgk, sb = (float)sgk1;
                     const float f1 = (float)s1[j], f2 = (float)s2[j];
                     const float q1 = 0.5f * ((pt + st_ * (f1 - pt)) + (pt + sb * (f1 - pt)));
                     const float q2 = 0.5f * ((pt + st_ * (f2 - pt)) + (pt + sb * (f2 - pt)));
@@ -1552,8 +1617,8 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
                     pgf[j] = (double)(-(ae * (q2 - q1) + ((float)ph2.v[j] - (float)ph1.v[j])) * (float)dinv64);
                     continue;
                 }
-                const double q1 = 0.5 * ((a.ptop + a.sig[k] * (s1[j] - a.ptop)) + (a.ptop + a.sig[k + 1] * (s1[j] - a.ptop)));
-                const double q2 = 0.5 * ((a.ptop + a.sig[k] * (s2[j] - a.ptop)) + (a.ptop + a.sig[k + 1] * (s2[j] - a.ptop)));
+                const double q1 = 0.5 * ((a.ptop + sgk * (s1[j] - a.ptop)) + (a.ptop + sgk1 * (s1[j] - a.ptop)));
+                const double q2 = 0.5 * ((a.ptop + sgk * (s2[j] - a.ptop)) + (a.ptop + sgk1 * (s2[j] - a.ptop)));
                 const double ae = 0.5 * (al1.v[j] + al2.v[j]);
                 pgf[j] = -(ae * (q2 - q1) + (ph2.v[j] - ph1.v[j])) * dinv64;
             }
@@ -1624,6 +1689,18 @@ template <int MODEL, typename R, int L, bool M1, int VV> void launch_vertex(cons
                            dim3(fb), 0, s, a);
 }
 
+// the edge kernel, its per-edge values staged in LDS where the work-group's edges fit
+template <int MODEL, typename R, int L, bool M1, int VB> void launch_edge(const StageArgs &a, hipStream_t s) {
+    const int lanes = a.K * a.M / L, fb = a.flat_block;
+    const size_t lds = edge_lds_bytes(fb, lanes, a.K, a.M);
+    if (lds <= kVertexLdsMax)
+        hipLaunchKernelGGL((k_edge<MODEL, R, L, M1, VB, true>), dim3(nblocks((long)a.mesh.E * lanes, fb)), dim3(fb),
+                           lds, s, a);
+    else
+        hipLaunchKernelGGL((k_edge<MODEL, R, L, M1, VB, false>), dim3(nblocks((long)a.mesh.E * lanes, fb)), dim3(fb),
+                           0, s, a);
+}
+
 // VAR selects the mixed-policy variant of the FP32 instances; a kernel the
 // variant does not change runs its default instance
 template <int MODEL, typename R, int L, bool M1, int VAR>
@@ -1652,7 +1729,7 @@ hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
         hipLaunchKernelGGL((k_cell_b<MODEL, R, L, M1, VB>), dim3(colblocks), dim3(colthreads), lds_b, s, a);
         break;
     case KERNEL_EDGE:
-        hipLaunchKernelGGL((k_edge<MODEL, R, L, M1, VB>), dim3(nblocks((long)a.mesh.E * lanes, fb)), dim3(fb), 0, s, a);
+        launch_edge<MODEL, R, L, M1, VB>(a, s);
         break;
     default:
         return hipErrorInvalidValue;
@@ -1671,7 +1748,7 @@ hipError_t launch_flat4(const StageArgs &a, int which, hipStream_t s) {
     if (which == KERNEL_VERTEX)
         launch_vertex<MODEL, R, 4, M1, VV>(a, s);
     else if (which == KERNEL_EDGE)
-        hipLaunchKernelGGL((k_edge<MODEL, R, 4, M1, VB>), dim3(nblocks((long)a.mesh.E * lanes, fb)), dim3(fb), 0, s, a);
+        launch_edge<MODEL, R, 4, M1, VB>(a, s);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -1554,6 +1554,46 @@ __global__ void __launch_bounds__(1024) k_edge(StageArgs a) {
                 mt[j] = (MT)0.5 * (i1[j] + i2[j]);
                 mb[j] = (MT)0.5 * (i1[j + 1] + i2[j + 1]);
             }
+        } else if constexpr (sizeof(RU) == 4 && sizeof(MT) == 4) {
+            // Several members: the lane M / L further in the wave holds the same
+            // members one level down (of the same edge, or past the surface,
+            // where the value is unused), so the level above and below of u and
+            // the lower interface's flux come across the wave, not from memory;
+            // only the lanes whose partner is in the next or previous wave load.
+            const Pack<MT, L> t1 = ldp<MT, L>(mdp + (long)c1 * K1M + (long)v.k0 * M + v.mm0);
+            const Pack<MT, L> t2 = ldp<MT, L>(mdp + (long)c2 * K1M + (long)v.k0 * M + v.mm0);
+#pragma unroll
+            for (int j = 0; j < L; j++) mt[j] = (MT)0.5 * (t1.v[j] + t2.v[j]);
+            const int wl = (int)(threadIdx.x & 63), dl = M / L;
+#pragma unroll
+            for (int j = 0; j < L; j++) {
+                uup[j] = __shfl_up(uk.v[j], dl, 64);
+                udn[j] = __shfl_down(uk.v[j], dl, 64);
+                mb[j] = __shfl_down(mt[j], dl, 64);
+                // past the lid and the surface the partner may be another edge or
+                // an idle lane: the values the loads would give there (unused, but
+                // finite, as they are multiplied by zero)
+                if (v.k0 == 0) uup[j] = uk.v[j];
+                if (v.k0 == K - 1) {
+                    udn[j] = uk.v[j];
+                    mb[j] = (MT)0;
+                }
+            }
+            if (wl < dl) {
+                const Pack<RU, L> pu = ldp<RU, L>(us + base - (v.k0 > 0 ? M : 0));
+#pragma unroll
+                for (int j = 0; j < L; j++) uup[j] = pu.v[j];
+            }
+            if (wl + dl > 63) {
+                const Pack<RU, L> pd = ldp<RU, L>(us + base + (v.k0 < K - 1 ? M : 0));
+                const Pack<MT, L> b1 = ldp<MT, L>(mdp + (long)c1 * K1M + (long)(v.k0 + 1) * M + v.mm0);
+                const Pack<MT, L> b2 = ldp<MT, L>(mdp + (long)c2 * K1M + (long)(v.k0 + 1) * M + v.mm0);
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    udn[j] = pd.v[j];
+                    mb[j] = (MT)0.5 * (b1.v[j] + b2.v[j]);
+                }
+            }
         } else {
             const Pack<RU, L> pu = ldp<RU, L>(us + base - (v.k0 > 0 ? M : 0));
             const Pack<RU, L> pd = ldp<RU, L>(us + base + (v.k0 < K - 1 ? M : 0));

@@ -143,7 +143,7 @@ __device__ __forceinline__ void st_iface(double *X, long cbase, const Vals<L, M1
 
 // theta of the previous stage at cell c, values starting at km0 (R precision)
 template <int MODEL, typename R, int L>
-__device__ __forceinline__ void theta_prev(const StageArgs &a, int c, long KM, long km0, const double dsg[L],
+__device__ __forceinline__ void theta_prev(const StageArgs &a, int c, long KM, unsigned km0, const double dsg[L],
                                            const double psc[L], R out[L]) {
     if constexpr (sizeof(R) == 8) {
         const Pack<double, L> T = ldp<double, L>(a.Th_s + (long)c * KM + km0);
@@ -318,8 +318,17 @@ struct ColLane {
     int lc, km0, i;
     bool valid;
 };
-template <int L> __device__ __forceinline__ ColLane col_lane(const StageArgs &a, int KM) {
+template <int L, bool UNI = false> __device__ __forceinline__ ColLane col_lane(const StageArgs &a, int KM) {
     ColLane c;
+    if constexpr (UNI) {
+        // one cell per work-group (of exactly K M / L lanes): the cell, and so
+        // every value of its stencil tables, is the same in all lanes of a wave
+        c.lc = 0;
+        c.km0 = (int)threadIdx.x * L;
+        c.i = (int)xcd_block();
+        c.valid = c.i < a.mesh.N;
+        return c;
+    }
     const int lanes = KM / L;
     const int tid = threadIdx.x;
     c.lc = tid / lanes;
@@ -358,7 +367,7 @@ template <int WHICH, int MODEL, typename R, int L> constexpr int col_waves() {
     return 1;
 }
 
-template <int MODEL, typename R, int L, bool M1, int VAR>
+template <int MODEL, typename R, int L, bool M1, int VAR, bool UNI>
 __global__ void __launch_bounds__(kColumnThreads)
 __attribute__((amdgpu_waves_per_eu(col_waves<KERNEL_CELL_A, MODEL, R, L>())))
 k_cell_a(StageArgs a) {
@@ -369,9 +378,10 @@ k_cell_a(StageArgs a) {
     extern __shared__ double lds[];
     const DevMesh &m = a.mesh;
     const int K = a.K, M = M1 ? 1 : a.M, KM = K * M;
-    const ColLane cl = col_lane<L>(a, KM);
-    const int i = cl.i, km0 = cl.km0, lc = cl.lc;
-    const Vals<L, M1> v(km0, M);
+    const ColLane cl = col_lane<L, UNI>(a, KM);
+    const int i = cl.i, lc = cl.lc;
+    const unsigned km0 = (unsigned)cl.km0;   // unsigned lane offset in a row (see k_cell_b)
+    const Vals<L, M1> v((int)km0, M);
     double *sD = lds;                        // [cpb][KM]
     double *sMd = lds + a.cpb * KM;          // [cpb][(K+1) M]  (NDC)
     const ColTab<R> tb((char *)lds + col_lds_bytes(MODEL, KERNEL_CELL_A, a.cpb, K, a.M), MODEL, KERNEL_CELL_A, a.cpb, M);
@@ -843,14 +853,18 @@ __global__ void __launch_bounds__(1024) k_vertex(StageArgs a) {
 // cell_b: Coriolis/KE shares, theta transport, mass/Theta update, column
 // diagnostics or the NH column solve
 // ---------------------------------------------------------------------------
-template <int MODEL, typename R, int L, bool M1, int VAR>
+template <int MODEL, typename R, int L, bool M1, int VAR, bool UNI>
 __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
     extern __shared__ double lds[];
     const DevMesh &m = a.mesh;
     const int K = a.K, M = M1 ? 1 : a.M, KM = K * M;
-    const ColLane cl = col_lane<L>(a, KM);
-    const int i = cl.i, km0 = cl.km0, lc = cl.lc;
-    const Vals<L, M1> v(km0, M);
+    const ColLane cl = col_lane<L, UNI>(a, KM);
+    const int i = cl.i, lc = cl.lc;
+    // the lane's offset in a row of K M values: unsigned, so that a row's
+    // address (the same in every lane where the cell is) plus it is a
+    // scalar-base-plus-vector-offset access
+    const unsigned km0 = (unsigned)cl.km0;
+    const Vals<L, M1> v((int)km0, M);
     const ColTab<R> tb((char *)lds + col_lds_bytes(MODEL, KERNEL_CELL_B, a.cpb, K, a.M), MODEL, KERNEL_CELL_B, a.cpb, M);
     stage_columns<KERNEL_CELL_B, MODEL, R, M1>(a, tb, a.cpb * (KM / L));
     const double *cps = tb.ps + (long)lc * 7 * M;   // ps_s of this cell, then of its neighbours
@@ -950,8 +964,8 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                 const R *ds = hd, *dn = hd + 3;
                 // (the neighbour's second derivatives are loaded whether or not it
                 // is upwind: a load under a condition costs a wait where the paths join)
-                const long hb = (long)nb * 3 * KM + km0;
-                const Pack<R, L> b0 = ldp<R, L>(Hs + hb), b1 = ldp<R, L>(Hs + hb + KM), b2 = ldp<R, L>(Hs + hb + 2 * KM);
+                const R *hb = Hs + (long)nb * 3 * KM;
+                const Pack<R, L> b0 = ldp<R, L>(hb + km0), b1 = ldp<R, L>(hb + KM + km0), b2 = ldp<R, L>(hb + 2 * KM + km0);
                 const R m2c = hd[6];
 #pragma unroll
                 for (int j = 0; j < L; j++) {
@@ -1758,15 +1772,25 @@ hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
     const int pol = sizeof(R) == 8 ? POLICY_DBL : POLICY_MIX;
     const size_t lds_a = stage_lds_bytes(MODEL, pol, KERNEL_CELL_A, a.cpb, a.K, a.M);
     const size_t lds_b = stage_lds_bytes(MODEL, pol, KERNEL_CELL_B, a.cpb, a.K, a.M);
+    // One cell per work-group of an ensemble takes the uniform-cell instance of
+    // the column kernels, except the all-FP64 cell_b, which the uniform form
+    // does not bring below three waves per SIMD and which then runs slower.
+    constexpr bool UB = !M1 && sizeof(R) == 4;
     switch (which) {
     case KERNEL_CELL_A:
-        hipLaunchKernelGGL((k_cell_a<MODEL, R, L, M1, VA>), dim3(colblocks), dim3(colthreads), lds_a, s, a);
+        if (!M1 && a.cpb == 1)
+            hipLaunchKernelGGL((k_cell_a<MODEL, R, L, M1, VA, !M1>), dim3(colblocks), dim3(colthreads), lds_a, s, a);
+        else
+            hipLaunchKernelGGL((k_cell_a<MODEL, R, L, M1, VA, false>), dim3(colblocks), dim3(colthreads), lds_a, s, a);
         break;
     case KERNEL_VERTEX:
         launch_vertex<MODEL, R, L, M1, VV>(a, s);
         break;
     case KERNEL_CELL_B:
-        hipLaunchKernelGGL((k_cell_b<MODEL, R, L, M1, VB>), dim3(colblocks), dim3(colthreads), lds_b, s, a);
+        if (UB && a.cpb == 1)
+            hipLaunchKernelGGL((k_cell_b<MODEL, R, L, M1, VB, UB>), dim3(colblocks), dim3(colthreads), lds_b, s, a);
+        else
+            hipLaunchKernelGGL((k_cell_b<MODEL, R, L, M1, VB, false>), dim3(colblocks), dim3(colthreads), lds_b, s, a);
         break;
     case KERNEL_EDGE:
         launch_edge<MODEL, R, L, M1, VB>(a, s);

@@ -1,0 +1,153 @@
+"""Ensembles of the shallow-water and non-hydrostatic models, and the launch
+shapes of the column kernels on an ensemble.
+
+* every member of a shallow-water ensemble (G4, three members whose height
+  bumps sit at three seeded places) and of a non-hydrostatic one (G3 x 8
+  levels, three members with warm bubbles at three seeded places) equals the
+  FP64 oracle's run of that member alone, within the bars of the
+  single-member parity tests;
+* the hydrostatic and non-hydrostatic ensembles give bitwise the same results
+  whatever the launch shape of the column kernels: one cell per work-group
+  (where the cell, and so every value of its stencil tables, is the same in
+  all lanes of a wave) or several, with one or two values per lane, in both
+  policies.
+"""
+import numpy as np
+import pytest
+
+from paper_2404_08849_amd.inputs import initial as ic
+from gpu_helpers import (MIX_TOL, MIX_U_TOL, compare, compare_abs, compare_dbl, nh_dbl_bounds)
+
+pytestmark = pytest.mark.gpu
+
+GRAV = 9.80616
+
+
+@pytest.fixture(scope="module")
+def mpdc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_08849_amd.mpdc as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def oracle_mod():
+    import oracle
+    return oracle
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _stack(members, key):
+    """Stack the members' arrays of one field member-innermost."""
+    return np.stack([s[key] for s in members], axis=-1)
+
+
+def _ndc_members(m, K, M):
+    return [ic.nh_warm_bubble(m, K, rh=1.5e6, seed=4000 + j) for j in range(M)]
+
+
+@pytest.mark.parametrize("policy", ["DBL", "MIX"])
+def test_sw_ensemble_members_match_oracle(mpdc, oracle_mod, mesh_cache, policy):
+    m = mesh_cache(4)
+    M, dt, n = 3, 600.0, 5
+    mem = [ic.sw_geostrophic(m, seed=1000 + j) for j in range(M)]
+    g = mpdc.Mesh(m)
+    st = mpdc.State(g, mpdc.MODEL_SW, getattr(mpdc, "POLICY_" + policy), K=1, M=M, dt=dt)
+    st.state_write(mpdc.FIELD_H, _stack(mem, "h"))
+    st.state_write(mpdc.FIELD_U, _stack(mem, "u")[:, None, :])
+    st.state_write(mpdc.FIELD_B, mem[0]["b"])
+    _say("sw ensemble G4 x %d members, %d steps" % (M, n), policy)
+    st.dycore_step(n)
+    h, u = st.state_read(mpdc.FIELD_H), st.state_read(mpdc.FIELD_U)[:, 0, :]
+    om = oracle_mod.OracleMesh(m)
+    for j, s in enumerate(mem):
+        h_o, u_o = om.sw_run(s["h"], s["u"], s["b"], dt, n)
+        if policy == "DBL":
+            compare_dbl("h m%d" % j, h[:, j], h_o, m["areaCell"])
+            compare_dbl("u m%d" % j, u[:, j], u_o)
+        else:
+            compare("h m%d" % j, h[:, j], h_o, m["areaCell"], MIX_TOL, MIX_TOL)
+            compare("u m%d" % j, u[:, j], u_o, None, MIX_U_TOL, MIX_U_TOL)
+    # the members differ (each bump sits elsewhere)
+    assert np.abs(h[:, 0] - h[:, 1]).max() > 1e-3
+
+
+@pytest.mark.parametrize("policy", ["DBL", "MIX"])
+def test_ndc_ensemble_members_match_oracle(mpdc, oracle_mod, mesh_cache, policy):
+    m = mesh_cache(3)
+    K, M, dt, n = 8, 3, 60.0, 4
+    mem = _ndc_members(m, K, M)
+    g = mpdc.Mesh(m)
+    st = mpdc.State(g, mpdc.MODEL_NDC, getattr(mpdc, "POLICY_" + policy), K=K, M=M, dt=dt,
+                    sigma=ic.sigma_interfaces(K))
+    fields = (mpdc.FIELD_PS, mpdc.FIELD_THETA, mpdc.FIELD_U, mpdc.FIELD_W, mpdc.FIELD_PHI)
+    for f, key in zip(fields, ("ps", "Theta", "u", "w", "phi")):
+        st.state_write(f, _stack(mem, key))
+    _say("ndc ensemble G3 x %d x %d members, %d steps" % (K, M, n), policy)
+    st.dycore_step(n)
+    out = [st.state_read(f) for f in fields]
+    om = oracle_mod.OracleMesh(m)
+    A = m["areaCell"]
+    for j, s in enumerate(mem):
+        ref = om.ndc_run(s["ps"], s["Theta"], s["u"], s["w"], s["phi"], dt, n)
+        ps, Th, u, w, phi = (x[..., j] for x in out)
+        assert np.abs(ref[3]).max() > 1e-4          # the bubble drives vertical motion
+        if policy == "DBL":
+            compare_dbl("ps m%d" % j, ps, ref[0], A)
+            compare_dbl("Theta m%d" % j, Th, ref[1], A)
+            compare_dbl("phi m%d" % j, phi, ref[4], A)
+            bw, bu = nh_dbl_bounds(ref[4], GRAV, dt, n, float(m["dEdge"].min()))
+            compare_abs("w m%d" % j, w, ref[3], bw)
+            compare_abs("u m%d" % j, u, ref[2], bu)
+        else:
+            for name, x, r, wt, tol in zip(["ps", "Theta", "u", "w", "phi"], (ps, Th, u, w, phi), ref,
+                                           [A, A, None, A, A], [MIX_TOL, MIX_TOL, MIX_U_TOL, MIX_U_TOL, MIX_TOL]):
+                compare("%s m%d" % (name, j), x, r, wt, tol, tol)
+
+
+# (values per lane, cells per work-group) of both column kernels; the flat
+# kernels keep their defaults
+_SHAPES = [(2, 1), (2, 3), (1, 1), (1, 8), (2, 16)]
+
+
+@pytest.mark.parametrize("model", ["HDC", "NDC"])
+@pytest.mark.parametrize("policy", ["DBL", "MIX"])
+def test_ensemble_column_shapes_are_bitwise_identical(mpdc, mesh_cache, model, policy):
+    m = mesh_cache(3)
+    K, M = 8, 4
+    g = mpdc.Mesh(m)
+    if model == "HDC":
+        s = ic.ensemble(ic.hdc_jet(m, K, seed=2000), M, sigma=0.1, seed=5000)
+        fields = (mpdc.FIELD_PS, mpdc.FIELD_THETA, mpdc.FIELD_U)
+        keys = ("ps", "Theta", "u")
+        data = [s[k] for k in keys]
+        dt = 900.0
+    else:
+        mem = _ndc_members(m, K, M)
+        fields = (mpdc.FIELD_PS, mpdc.FIELD_THETA, mpdc.FIELD_U, mpdc.FIELD_W, mpdc.FIELD_PHI)
+        data = [_stack(mem, k) for k in ("ps", "Theta", "u", "w", "phi")]
+        dt = 60.0
+    ref = None
+    for vpl, cpb in _SHAPES:
+        _say("%s ensemble G3 x %d x %d, %s, column kernels %d values per lane, %d cells per work-group"
+             % (model, K, M, policy, vpl, cpb))
+        st = mpdc.State(g, getattr(mpdc, "MODEL_" + model), getattr(mpdc, "POLICY_" + policy), K=K, M=M, dt=dt,
+                        sigma=ic.sigma_interfaces(K))
+        for kid in (0, 2):   # cell_a, cell_b
+            st.set_kernel_launch(kid, vpl, cpb)
+        assert [st.get_kernel_launch(k) for k in (0, 2)] == [(vpl, cpb)] * 2
+        for f, x in zip(fields, data):
+            st.state_write(f, x)
+        st.dycore_step(4)
+        out = [st.state_read(f) for f in fields]
+        assert all(np.isfinite(x).all() for x in out)
+        if ref is None:
+            ref = out
+            assert np.abs(out[2] - data[2]).max() > 0.0   # the state moved
+        for a, b in zip(out, ref):
+            assert np.array_equal(a, b)

@@ -264,7 +264,9 @@ bool vpl_ok(const mpdc_state *st, int k, int L) {
     if (st->model == MPDC_MODEL_TRACER)   // eight FP32 tracers per lane; FP64 stops at four (registers)
         return (L == 1 || L == 2 || L == 4 || (L == 8 && st->policy == MPDC_POLICY_MIX)) && st->T % L == 0;
     if (L != 1 && L != 2 && L != 4) return false;
-    if (L == 4 && is_column(k)) return false;
+    // four values per lane in a column kernel: four members of an ensemble in
+    // the FP32 policies (with one cell per work-group, check_group)
+    if (L == 4 && is_column(k)) return st->M > 1 && st->M % 4 == 0 && st->policy != MPDC_POLICY_DBL;
     if (st->M == 1) return st->K % L == 0;
     return st->M % L == 0;
 }
@@ -872,6 +874,8 @@ static int check_group(const mpdc_state *st, int k, int L, int group) {
         const long lanes = (long)st->K * st->M / L;
         if (group < 1 || group * lanes > kColumnThreads)
             return fail(MPDC_E_INVAL, "cells per work-group times the column's lanes must be 1..512");
+        if (L == 4 && group != 1)
+            return fail(MPDC_E_INVAL, "four values per lane in a column kernel need one cell per work-group");
         if (stage_lds_bytes(st->model, st->policy, k, group, st->K, st->M) > 65536)
             return fail(MPDC_E_INVAL, "column work-group would need more than 64 KiB of LDS");
         return MPDC_OK;

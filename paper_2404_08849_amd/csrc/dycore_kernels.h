@@ -103,7 +103,8 @@ struct ColTabLayout {
     size_t hd;            // cell_b: c_hd [cpb][6][8]
     size_t bytes;
 };
-__host__ __device__ inline size_t coltab_round(size_t b) { return (b + 15) & ~(size_t)15; }
+// (32 bytes: a lane's four FP64 values of a row are one aligned 32-byte pack)
+__host__ __device__ inline size_t coltab_round(size_t b) { return (b + 31) & ~(size_t)31; }
 __host__ __device__ inline ColTabLayout coltab_layout(int model, int which, int cpb, int M, int rsize) {
     ColTabLayout t;
     size_t o = 0;

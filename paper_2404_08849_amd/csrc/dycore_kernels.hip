@@ -1801,20 +1801,34 @@ hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
     return hipGetLastError();
 }
 
-// flat kernels (vertex, edge) also take four values per lane
+// Four values per lane: the flat kernels (vertex, edge), and for an ensemble
+// (four members per lane, one cell per work-group) the uniform-cell column
+// kernels of the FP32 policies
 template <int MODEL, typename R, bool M1, int VAR>
 hipError_t launch_flat4(const StageArgs &a, int which, hipStream_t s) {
+    constexpr int VA = VAR == VAR_PGF32 ? VAR_MIX : VAR == VAR_SGL ? VAR_F32_DIV : VAR;
     constexpr int VB = (VAR == VAR_BOX || VAR == VAR_PGF32) ? VAR : VAR == VAR_SGL ? VAR_PGF32 : VAR_MIX;
     constexpr int VV = VAR == VAR_SGL ? VAR_SGL : VAR_MIX;
-    const int KM = a.K * a.M;
-    const int lanes = KM / 4;
-    const int fb = a.flat_block;
-    if (which == KERNEL_VERTEX)
+    constexpr bool C4 = !M1 && sizeof(R) == 4;
+    if (which == KERNEL_VERTEX) {
         launch_vertex<MODEL, R, 4, M1, VV>(a, s);
-    else if (which == KERNEL_EDGE)
+    } else if (which == KERNEL_EDGE) {
         launch_edge<MODEL, R, 4, M1, VB>(a, s);
-    else
+    } else if (C4 && a.cpb == 1 && (which == KERNEL_CELL_A || which == KERNEL_CELL_B)) {
+        if constexpr (C4) {
+            const int pol = POLICY_MIX;
+            const unsigned nb = a.mesh.N;
+            const int threads = a.K * a.M / 4;
+            if (which == KERNEL_CELL_A)
+                hipLaunchKernelGGL((k_cell_a<MODEL, R, 4, false, VA, true>), dim3(nb), dim3(threads),
+                                   stage_lds_bytes(MODEL, pol, KERNEL_CELL_A, 1, a.K, a.M), s, a);
+            else
+                hipLaunchKernelGGL((k_cell_b<MODEL, R, 4, false, VB, true>), dim3(nb), dim3(threads),
+                                   stage_lds_bytes(MODEL, pol, KERNEL_CELL_B, 1, a.K, a.M), s, a);
+        }
+    } else {
         return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -114,7 +114,13 @@ def test_error_paths(mpdc, mesh_cache):
     # launch shapes outside the legal set
     assert lib.mpdc_set_kernel_launch(hdc.h, 4, 0, 0) == -1          # kernel id
     assert lib.mpdc_set_kernel_launch(hdc.h, 0, 3, 0) == -1          # values per lane
-    assert lib.mpdc_set_kernel_launch(hdc.h, 0, 4, 0) == -1          # four per lane: flat kernels only
+    assert lib.mpdc_set_kernel_launch(hdc.h, 0, 4, 0) == -1          # four per lane in a column: ensembles only
+    ens = {p: mpdc.State(g, mpdc.MODEL_HDC, p, K=K, M=4, dt=600.0, sigma=ic.sigma_interfaces(K))
+           for p in (mpdc.POLICY_MIX, mpdc.POLICY_DBL)}
+    assert lib.mpdc_set_kernel_launch(ens[mpdc.POLICY_MIX].h, 2, 4, 1) == 0    # FP32, one cell per work-group
+    assert lib.mpdc_set_kernel_launch(ens[mpdc.POLICY_MIX].h, 2, 4, 2) == -1   # ... and only one
+    assert lib.mpdc_set_kernel_launch(ens[mpdc.POLICY_DBL].h, 0, 4, 1) == -1   # not in the all-FP64 policy
+    del ens
     assert lib.mpdc_set_kernel_launch(hdc.h, 0, 1, 1000) == -1       # column work-group over 512 lanes
     assert lib.mpdc_set_kernel_launch(hdc.h, 3, 2, 100) == -1        # not a multiple of 64
     assert lib.mpdc_set_kernel_launch(trs.h, 0, 4, 128) == -1        # 4 does not divide T = 2

@@ -78,6 +78,19 @@ __device__ __forceinline__ double fmar(double a, double b, double c) { return __
 __device__ __forceinline__ double powpos(double x, double y) { return exp(y * log(x)); }
 __device__ __forceinline__ float powpos(float x, float y) { return expf(y * logf(x)); }
 
+// Element o of a read-only mesh table through the scalar data cache: where
+// the address is the same in every lane (the row of a uniform-cell
+// work-group's own cell) the load is a scalar one, into scalar registers,
+// with no vector-memory instruction and no LDS.  Tables only (never written
+// by a kernel).
+template <typename T> __device__ __forceinline__ T sld(const T *p, long o) {
+    return ((const __attribute__((address_space(4))) T *)p)[o];
+}
+template <typename T> __device__ __forceinline__ void sld6(const T *p, long o, T out[6]) {
+#pragma unroll
+    for (int s = 0; s < 6; s++) out[s] = sld(p, o + s);
+}
+
 template <typename R> __device__ __forceinline__ const R *u_prev_ptr(const StageArgs &a) {
     if constexpr (sizeof(R) == 8) return a.u_s;
     else return a.u32_s;
@@ -205,7 +218,9 @@ template <typename R> struct ColTab {
 // Load the tables of the work-group's columns [i0, i0 + ncol) into LDS with
 // all its threads (contiguous rows; the neighbours' surface pressures through
 // c_nbr), then synchronise.
-template <int WHICH, int MODEL, typename R, bool M1>
+// (UNI: a uniform-cell work-group reads its tables with scalar loads, so only
+// the surface pressures, which differ between members, are staged.)
+template <int WHICH, int MODEL, typename R, bool M1, bool UNI = false>
 __device__ __forceinline__ void stage_columns(const StageArgs &a, const ColTab<R> &t, int nthr) {
     const DevMesh &m = a.mesh;
     const int M = M1 ? 1 : a.M;
@@ -221,6 +236,7 @@ __device__ __forceinline__ void stage_columns(const StageArgs &a, const ColTab<R
     if (CA && !SW && v18 > nmax) nmax = v18;
     if (!CA && v36 > nmax) nmax = v36;
     if (!CA && !SW && v48 > nmax) nmax = v48;
+    if constexpr (UNI) nmax = nps;   // >= nM
     // One pass moves one vector of every table per thread, branch-free: a
     // thread past the end of a table re-reads and re-writes its last vector
     // (the same value), so no load sits under a condition (the compiler would
@@ -233,6 +249,16 @@ __device__ __forceinline__ void stage_columns(const StageArgs &a, const ColTab<R
         const int pc = xp / (7 * M), pr = xp - pc * 7 * M;
         const int psl = pr / M, pmm = pr - psl * M;
         const int nbr = m.c_nbr[(i0 + pc) * kCellSlots + (psl > 0 ? psl - 1 : 0)];
+        if constexpr (UNI) {
+            if constexpr (!CA && !SW) {
+                const int xm = x < nM ? x : nM - 1;
+                const double pn = a.ps_n[i0 * M + xm], dp = a.dps[i0 * M + xm];
+                t.psn[xm] = pn;
+                t.dps[xm] = dp;
+            }
+            t.ps[xp] = a.ps_s[(psl == 0 ? i0 + pc : (long)nbr) * M + pmm];
+            continue;
+        }
         const int x6 = x < v6 ? x : v6 - 1;
         const long o6 = i0 * kCellSlots + 2 * (long)x6;
         const Pack<int, 2> e2 = ldp<int, 2>(m.c_edge + o6);
@@ -385,7 +411,8 @@ k_cell_a(StageArgs a) {
     double *sD = lds;                        // [cpb][KM]
     double *sMd = lds + a.cpb * KM;          // [cpb][(K+1) M]  (NDC)
     const ColTab<R> tb((char *)lds + col_lds_bytes(MODEL, KERNEL_CELL_A, a.cpb, K, a.M), MODEL, KERNEL_CELL_A, a.cpb, M);
-    stage_columns<KERNEL_CELL_A, MODEL, R, M1>(a, tb, a.cpb * (KM / L));
+    stage_columns<KERNEL_CELL_A, MODEL, R, M1, UNI>(a, tb, a.cpb * (KM / L));
+    const long r6 = (long)i * kCellSlots;   // the cell's row of the [N][6] tables (scalar loads, UNI)
     const double *cps = tb.ps + (long)lc * 7 * M;   // ps_s of this cell, then of its neighbours
 
     double dsg[L], psi[L], dpi_i[L], D[L], sgb[L], ke64[L];
@@ -407,19 +434,33 @@ k_cell_a(StageArgs a) {
             ke64[j] = 0.0;
             h0[j] = h1[j] = h2[j] = 0;
         }
-        ld6<int>(tb.ce + lc * kCellSlots, ce);
-        ld6<int>(tb.cn + lc * kCellSlots, cn);
         double cdiv[6];
         R cke[6], ch0[6], ch1[6], ch2[6];
-        ld6<double>(tb.div64 + lc * kCellSlots, cdiv);
-        if constexpr (!ke_in_cell_b<R, VAR>()) ld6<R>(tb.ke + lc * kCellSlots, cke);
+        if constexpr (UNI) {
+            sld6<int>(m.c_edge, r6, ce);
+            sld6<int>(m.c_nbr, r6, cn);
+            sld6<double>(m.c_div, r6, cdiv);
+            if constexpr (!ke_in_cell_b<R, VAR>()) sld6<R>(pick<R>(m.c_ke, m.c_ke32), r6, cke);
+        } else {
+            ld6<int>(tb.ce + lc * kCellSlots, ce);
+            ld6<int>(tb.cn + lc * kCellSlots, cn);
+            ld6<double>(tb.div64 + lc * kCellSlots, cdiv);
+            if constexpr (!ke_in_cell_b<R, VAR>()) ld6<R>(tb.ke + lc * kCellSlots, cke);
+        }
         double cked[6];   // FP64 kinetic-energy weights of the boxed variant
         if constexpr (VAR == VAR_BOX) ld6<double>(m.c_ke + (long)i * kCellSlots, cked);
         if constexpr (MODEL != MODEL_SW) {
-            const R *ch = tb.hs + lc * 3 * kCellSlots;
-            ld6<R>(ch, ch0);
-            ld6<R>(ch + kCellSlots, ch1);
-            ld6<R>(ch + 2 * kCellSlots, ch2);
+            if constexpr (UNI) {
+                const R *ch = pick<R>(m.c_hess, m.c_hess32);
+                sld6<R>(ch, 3 * r6, ch0);
+                sld6<R>(ch, 3 * r6 + kCellSlots, ch1);
+                sld6<R>(ch, 3 * r6 + 2 * kCellSlots, ch2);
+            } else {
+                const R *ch = tb.hs + lc * 3 * kCellSlots;
+                ld6<R>(ch, ch0);
+                ld6<R>(ch + kCellSlots, ch1);
+                ld6<R>(ch + 2 * kCellSlots, ch2);
+            }
             theta_prev<MODEL, R, L>(a, i, KM, km0, dsg, psi, th_i);
         }
         const R *us = u_prev_ptr<R>(a);
@@ -611,7 +652,8 @@ k_cell_a(StageArgs a) {
                 double pd[L];
                 ld_iface<L, M1>(a.phi_s, cb, v, M, 1, pd);
                 double cdiv[6];
-                ld6<double>(tb.div64 + lc * kCellSlots, cdiv);
+                if constexpr (UNI) sld6<double>(m.c_div, r6, cdiv);
+                else ld6<double>(tb.div64 + lc * kCellSlots, cdiv);
                 // slots grouped per basic block and no load under a condition,
                 // as in the horizontal part above (pad slot: edge 0, itself,
                 // zero flux and weight; the layer above the top: clamped index)
@@ -866,7 +908,8 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
     const unsigned km0 = (unsigned)cl.km0;
     const Vals<L, M1> v((int)km0, M);
     const ColTab<R> tb((char *)lds + col_lds_bytes(MODEL, KERNEL_CELL_B, a.cpb, K, a.M), MODEL, KERNEL_CELL_B, a.cpb, M);
-    stage_columns<KERNEL_CELL_B, MODEL, R, M1>(a, tb, a.cpb * (KM / L));
+    stage_columns<KERNEL_CELL_B, MODEL, R, M1, UNI>(a, tb, a.cpb * (KM / L));
+    const long r6 = (long)i * kCellSlots;   // the cell's row of the [N][6] tables (scalar loads, UNI)
     const double *cps = tb.ps + (long)lc * 7 * M;   // ps_s of this cell, then of its neighbours
 
     double Th_new[L], ps_new[L], dsg[L], sgt[L], sgb[L];
@@ -889,12 +932,20 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
             dpi_i[j] = lmass<MODEL>(dsg[j], psi[j], a.ptop);
         }
         int ce[6], cn[6], cv[6];
-        ld6<int>(tb.ce + lc * kCellSlots, ce);
-        ld6<int>(tb.cn + lc * kCellSlots, cn);
-        ld6<int>(tb.cv + lc * kCellSlots, cv);
         R cdiv[6], cgk[6];
-        ld6<R>(tb.div + lc * kCellSlots, cdiv);
-        ld6<R>(tb.gk + lc * kCellSlots, cgk);
+        if constexpr (UNI) {
+            sld6<int>(m.c_edge, r6, ce);
+            sld6<int>(m.c_nbr, r6, cn);
+            sld6<int>(m.c_vert, r6, cv);
+            sld6<R>(pick<R>(m.c_div, m.c_div32), r6, cdiv);
+            sld6<R>(pick<R>(m.c_gk, m.c_gk32), r6, cgk);
+        } else {
+            ld6<int>(tb.ce + lc * kCellSlots, ce);
+            ld6<int>(tb.cn + lc * kCellSlots, cn);
+            ld6<int>(tb.cv + lc * kCellSlots, cv);
+            ld6<R>(tb.div + lc * kCellSlots, cdiv);
+            ld6<R>(tb.gk + lc * kCellSlots, cgk);
+        }
         const R *us = u_prev_ptr<R>(a);
         const R *Hs = a.hth_in<R>();
 
@@ -932,7 +983,8 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
             double psn[L];
             ld2d_s<L, M1>(cps + (1 + s) * M, v.mm0, psn);
             const Pack<R, L> u = ldp<R, L>(us + (long)e * KM + km0);
-            const R ck = tb.ke[lc * kCellSlots + s];   // kinetic-energy weight (zero on a pad slot)
+            // kinetic-energy weight (zero on a pad slot)
+            const R ck = UNI ? sld(pick<R>(m.c_ke, m.c_ke32), r6 + s) : tb.ke[lc * kCellSlots + s];
 #pragma unroll
             for (int j = 0; j < L; j++) {
                 const double dpe = 0.5 * (dpi_i[j] + lmass<MODEL>(dsg[j], psn[j], a.ptop));
@@ -952,7 +1004,10 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                 theta_prev<MODEL, R, L>(a, nb, KM, km0, dsg, psn, th_n);
                 // neighbour direction in i's frame, i's direction in the neighbour's, -d^2/6
                 R hd[8];
-                {
+                if constexpr (UNI) {
+#pragma unroll
+                    for (int q = 0; q < 8; q++) hd[q] = sld(pick<R>(m.c_hd, m.c_hd32), (r6 + s) * 8 + q);
+                } else {
                     const R *p = tb.hd + (lc * kCellSlots + s) * 8;
 #pragma unroll
                     for (int q = 0; q < 8; q += 2) {
@@ -1012,7 +1067,8 @@ __global__ void __launch_bounds__(kColumnThreads) k_cell_b(StageArgs a) {
                 const int e = ce[s];
                 if (e < 0) continue;
                 R w[6];
-                ld6<R>(tk + s * kCellSlots, w);
+                if constexpr (UNI) sld6<R>(pick<R>(m.c_tk, m.c_tk32), (r6 + s) * kCellSlots, w);
+                else ld6<R>(tk + s * kCellSlots, w);
                 Pack<R, L> out;
 #pragma unroll
                 for (int j = 0; j < L; j++) {
@@ -1773,9 +1829,8 @@ hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
     const size_t lds_a = stage_lds_bytes(MODEL, pol, KERNEL_CELL_A, a.cpb, a.K, a.M);
     const size_t lds_b = stage_lds_bytes(MODEL, pol, KERNEL_CELL_B, a.cpb, a.K, a.M);
     // One cell per work-group of an ensemble takes the uniform-cell instance of
-    // the column kernels, except the all-FP64 cell_b, which the uniform form
-    // does not bring below three waves per SIMD and which then runs slower.
-    constexpr bool UB = !M1 && sizeof(R) == 4;
+    // the column kernels.
+    constexpr bool UB = !M1;
     switch (which) {
     case KERNEL_CELL_A:
         if (!M1 && a.cpb == 1)

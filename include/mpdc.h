@@ -345,8 +345,9 @@ int mpdc_set_launch(mpdc_state *st, int cells_per_block, int flat_block);
  * per work-group), 1, 2 or 4 for the flat kernels, 1, 2, 4 or (mixed policy) 8 tracers for the
  * tracer kernels; it must divide K (M == 1), M (M > 1) or T; 0 = default --
  * and group = cells per work-group (column kernels) or threads per
- * work-group (others), 0 = keep.  Results are bitwise identical for every
- * legal shape.  Errors: INVAL. */
+ * work-group (others; for the tracer kernels also 1: one cell per
+ * work-group, K T / values_per_lane <= 512 threads), 0 = keep.  Results are
+ * bitwise identical for every legal shape.  Errors: INVAL. */
 int mpdc_set_kernel_launch(mpdc_state *st, int kernel_id, int values_per_lane, int group);
 int mpdc_get_kernel_launch(const mpdc_state *st, int kernel_id, int *values_per_lane, int *group);
 

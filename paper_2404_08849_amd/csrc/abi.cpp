@@ -277,6 +277,7 @@ int col_lanes(const mpdc_state *st, int k) { return st->K * st->M / vpl_of(st, k
 int cpb_of(const mpdc_state *st, int k) {
     if (st->model == MPDC_MODEL_TRACER) return st->launch.flat[k];
     if (st->launch.cpb[k] > 0) return st->launch.cpb[k];
+    if (vpl_of(st, k) == 4) return 1;   // four members per lane: one cell per work-group
     // about 256 lanes, halved while the staged tables would take over 32 KiB of LDS
     int cpb = std::max(1, 256 / col_lanes(st, k));
     while (cpb > 1 && stage_lds_bytes(st->model, st->policy, k, cpb, st->K, st->M) > 32768) cpb /= 2;
@@ -880,6 +881,12 @@ static int check_group(const mpdc_state *st, int k, int L, int group) {
             return fail(MPDC_E_INVAL, "column work-group would need more than 64 KiB of LDS");
         return MPDC_OK;
     }
+    if (st->model == MPDC_MODEL_TRACER && group == 1) {
+        // one cell per work-group: K T / L threads
+        if ((long)st->K * (st->T / L) > kTracerThreads)
+            return fail(MPDC_E_INVAL, "one cell per work-group needs K T / values_per_lane <= 512");
+        return MPDC_OK;
+    }
     const int cap = (st->model == MPDC_MODEL_TRACER) ? kTracerThreads : 1024;
     if (group < 64 || group > cap || group % 64) return fail(MPDC_E_INVAL, "threads per work-group must be a multiple of 64 up to 512 (tracer) or 1024");
     return MPDC_OK;
@@ -932,6 +939,10 @@ int mpdc_set_kernel_launch(mpdc_state *st, int kernel_id, int values_per_lane_, 
     }
     if (col && L.cpb[kernel_id] > 0) {
         int rc = check_group(st, kernel_id, v, L.cpb[kernel_id]);
+        if (rc) return rc;
+    }
+    if (!col && L.flat[kernel_id] == 1) {   // one cell per work-group (tracer): K T / L threads
+        int rc = check_group(st, kernel_id, v, 1);
         if (rc) return rc;
     }
     drop_graphs(st);
@@ -1275,7 +1286,7 @@ static bool apply_cached_shapes(mpdc_state *st, const std::string &line, int nk)
 static int tune_shapes(mpdc_state *st, void *stream) {
     const bool tr = st->model == MPDC_MODEL_TRACER;
     const int nk = tr ? 3 : 4;
-    const int flats[] = {64, 128, 256, 512, 1024};
+    const int flats[] = {1, 64, 128, 256, 512, 1024};   // 1: one cell per work-group (tracer kernels)
     const int cpbs[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 64, 128, 256, 512};
     const int vpls[] = {1, 2, 4, 8};
     // kernels are tuned in launch order, each with the already tuned shapes of

@@ -44,6 +44,19 @@ __device__ __forceinline__ unsigned xcd_block() {
 #endif
 }
 
+// Element o of a read-only mesh table through the scalar data cache: where
+// the address is the same in every lane (the row of a uniform-cell
+// work-group's own cell or edge) the load is a scalar one, into scalar
+// registers, with no vector-memory instruction and no LDS.  Tables only
+// (never written by a kernel).
+template <typename T> __device__ __forceinline__ T sld(const T *p, long o) {
+    return ((const __attribute__((address_space(4))) T *)p)[o];
+}
+template <typename T> __device__ __forceinline__ void sld6(const T *p, long o, T out[6]) {
+#pragma unroll
+    for (int s = 0; s < 6; s++) out[s] = sld(p, o + s);
+}
+
 // Everything one dycore stage reads and writes.  Pointers of another model
 // or policy are null.  "_n": state at the start of the step; "_s": state of
 // the previous stage; "_o": output state of this stage.

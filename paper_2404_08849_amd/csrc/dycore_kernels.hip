@@ -78,19 +78,6 @@ __device__ __forceinline__ double fmar(double a, double b, double c) { return __
 __device__ __forceinline__ double powpos(double x, double y) { return exp(y * log(x)); }
 __device__ __forceinline__ float powpos(float x, float y) { return expf(y * logf(x)); }
 
-// Element o of a read-only mesh table through the scalar data cache: where
-// the address is the same in every lane (the row of a uniform-cell
-// work-group's own cell) the load is a scalar one, into scalar registers,
-// with no vector-memory instruction and no LDS.  Tables only (never written
-// by a kernel).
-template <typename T> __device__ __forceinline__ T sld(const T *p, long o) {
-    return ((const __attribute__((address_space(4))) T *)p)[o];
-}
-template <typename T> __device__ __forceinline__ void sld6(const T *p, long o, T out[6]) {
-#pragma unroll
-    for (int s = 0; s < 6; s++) out[s] = sld(p, o + s);
-}
-
 template <typename R> __device__ __forceinline__ const R *u_prev_ptr(const StageArgs &a) {
     if constexpr (sizeof(R) == 8) return a.u_s;
     else return a.u32_s;

@@ -65,9 +65,20 @@ struct TLane {
     long x;       // linear index of (i, k, t0)
     bool ok;
 };
-template <int L> __device__ __forceinline__ TLane tracer_lane(const TracerArgs &a) {
+// UNI: one cell per work-group of exactly K T / L lanes; the cell, and so
+// its stencil tables and its edges' tables, are the same in every lane, and
+// the kernels read them with scalar loads.
+template <int L, bool UNI> __device__ __forceinline__ TLane tracer_lane(const TracerArgs &a) {
     TLane r;
     const int lanes_k = a.T / L;
+    if constexpr (UNI) {
+        r.i = (int)xcd_block();
+        r.ok = r.i < a.mesh.N;
+        r.k = (int)threadIdx.x / lanes_k;
+        r.t0 = ((int)threadIdx.x - r.k * lanes_k) * L;
+        r.x = ((long)r.i * a.K + r.k) * a.T + r.t0;
+        return r;
+    }
     const int lanes = a.K * lanes_k;
     const long idx = (long)xcd_block() * a.cpb + threadIdx.x;   // a.cpb = threads per work-group
     r.ok = idx < (long)a.mesh.N * lanes;
@@ -88,12 +99,19 @@ template <typename R> struct Stencil {
     double F[6];
     double dpi_n, dpin;
 };
-template <typename R, bool SG = false>
+template <typename R, bool SG, bool UNI>
 __device__ __forceinline__ void load_stencil(const TracerArgs &a, int i, int k, Stencil<R> &st) {
     const DevMesh &m = a.mesh;
-    tld6<int>(m.c_edge + (long)i * kCellSlots, st.ce);
-    tld6<int>(m.c_nbr + (long)i * kCellSlots, st.cn);
-    tld6<R>(tpick<R>(m.c_div, m.c_div32) + (long)i * kCellSlots, st.cdiv);
+    const long r6 = (long)i * kCellSlots;
+    if constexpr (UNI) {
+        sld6<int>(m.c_edge, r6, st.ce);
+        sld6<int>(m.c_nbr, r6, st.cn);
+        sld6<R>(tpick<R>(m.c_div, m.c_div32), r6, st.cdiv);
+    } else {
+        tld6<int>(m.c_edge + r6, st.ce);
+        tld6<int>(m.c_nbr + r6, st.cn);
+        tld6<R>(tpick<R>(m.c_div, m.c_div32) + r6, st.cdiv);
+    }
     if constexpr (SG) {
         // all-FP32: the flux as an FP32 number, FP32 continuity
         float d = 0.0f;
@@ -109,7 +127,8 @@ __device__ __forceinline__ void load_stencil(const TracerArgs &a, int i, int k, 
         return;
     }
     double c64[6];
-    tld6<double>(m.c_div + (long)i * kCellSlots, c64);
+    if constexpr (UNI) sld6<double>(m.c_div, r6, c64);
+    else tld6<double>(m.c_div + r6, c64);
     double d = 0.0;
 #pragma unroll
     for (int s = 0; s < kCellSlots; s++) {
@@ -132,7 +151,7 @@ __device__ __forceinline__ void load_stencil(const TracerArgs &a, int i, int k, 
 // wait where the paths join).  The flux F_e is one FP64 number per
 // edge-level, so the upwind cell is the same for the L tracers of a lane.
 // qn_nb, if given, is q^n of the neighbour already loaded by the caller.
-template <typename R, int L, bool UPWIND_LOADS>
+template <typename R, int L, bool UPWIND_LOADS, bool UNI>
 __device__ __forceinline__ void edge_fluxes(const TracerArgs &a, const Stencil<R> &st, int s, int k, int t0,
                                             const R qn_i[L], const R qs_i[L], const R Hi[3][L],
                                             const TPack<R, L> *qn_nb, R FL[L], R Aa[L]) {
@@ -179,9 +198,25 @@ __device__ __forceinline__ void edge_fluxes(const TracerArgs &a, const Stencil<R
         }
     }
     // the neighbour direction in the upwind cell's frame (c1: first triple)
-    const R *dir = tpick<R>(m.e_hdir, m.e_hdir32) + (long)e * 6 + (fwd ? 0 : 3);
-    const R d0 = dir[0], d1 = dir[1], d2 = dir[2];
-    const R m2c = (R)-2 * tpick<R>(m.e_d2, m.e_d2_32)[e];
+    R d0, d1, d2, m2c;
+    if constexpr (UNI) {
+        // both triples by scalar loads (the edge is the same in every lane; the
+        // upwind side depends on the level's flux)
+        const R *hd = tpick<R>(m.e_hdir, m.e_hdir32);
+        const long o = (long)e * 6;
+        const R a0 = sld(hd, o), a1 = sld(hd, o + 1), a2 = sld(hd, o + 2);
+        const R b0 = sld(hd, o + 3), b1 = sld(hd, o + 4), b2 = sld(hd, o + 5);
+        d0 = fwd ? a0 : b0;
+        d1 = fwd ? a1 : b1;
+        d2 = fwd ? a2 : b2;
+        m2c = (R)-2 * sld(tpick<R>(m.e_d2, m.e_d2_32), (long)e);
+    } else {
+        const R *dir = tpick<R>(m.e_hdir, m.e_hdir32) + (long)e * 6 + (fwd ? 0 : 3);
+        d0 = dir[0];
+        d1 = dir[1];
+        d2 = dir[2];
+        m2c = (R)-2 * tpick<R>(m.e_d2, m.e_d2_32)[e];
+    }
     const R F = (R)Fd;
 #pragma unroll
     for (int j = 0; j < L; j++) {
@@ -192,22 +227,29 @@ __device__ __forceinline__ void edge_fluxes(const TracerArgs &a, const Stencil<R
     }
 }
 
-template <typename R, int L, bool SG>
+template <typename R, int L, bool SG, bool UNI>
 __global__ void __launch_bounds__(kTracerThreads) k_tr_low(TracerArgs a) {
-    const TLane ln = tracer_lane<L>(a);
+    const TLane ln = tracer_lane<L, UNI>(a);
     if (!ln.ok) return;
     const DevMesh &m = a.mesh;
     const int KT = a.K * a.T;
     const int i = ln.i, k = ln.k, t0 = ln.t0;
     Stencil<R> st;
-    load_stencil<R, SG>(a, i, k, st);
+    load_stencil<R, SG, UNI>(a, i, k, st);
     const R *qn = (const R *)a.q_n;
     const R *qs = (const R *)a.q_s;
     R ch[3][6];
-    const R *chp = tpick<R>(m.c_hess, m.c_hess32) + (long)i * 3 * kCellSlots;
-    tld6<R>(chp, ch[0]);
-    tld6<R>(chp + kCellSlots, ch[1]);
-    tld6<R>(chp + 2 * kCellSlots, ch[2]);
+    const R *chp = tpick<R>(m.c_hess, m.c_hess32);
+    const long r18 = (long)i * 3 * kCellSlots;
+    if constexpr (UNI) {
+        sld6<R>(chp, r18, ch[0]);
+        sld6<R>(chp, r18 + kCellSlots, ch[1]);
+        sld6<R>(chp, r18 + 2 * kCellSlots, ch[2]);
+    } else {
+        tld6<R>(chp + r18, ch[0]);
+        tld6<R>(chp + r18 + kCellSlots, ch[1]);
+        tld6<R>(chp + r18 + 2 * kCellSlots, ch[2]);
+    }
     const TPack<R, L> qni = tld<R, L>(qn + ln.x), qsi = tld<R, L>(qs + ln.x);
     R dL[L], h[3][L];
 #pragma unroll
@@ -259,14 +301,14 @@ __device__ __forceinline__ void load_own(const TracerArgs &a, const TLane &ln, R
     }
 }
 
-template <typename R, int L, bool SG>
+template <typename R, int L, bool SG, bool UNI>
 __global__ void __launch_bounds__(kTracerThreads) k_tr_limit(TracerArgs a) {
-    const TLane ln = tracer_lane<L>(a);
+    const TLane ln = tracer_lane<L, UNI>(a);
     if (!ln.ok) return;
     const int KT = a.K * a.T;
     const int i = ln.i, k = ln.k, t0 = ln.t0;
     Stencil<R> st;
-    load_stencil<R, SG>(a, i, k, st);
+    load_stencil<R, SG, UNI>(a, i, k, st);
     R qn_i[L], qs_i[L], Hi[3][L];
     load_own<R, L>(a, ln, qn_i, qs_i, Hi);
     const R *qn = (const R *)a.q_n;
@@ -285,7 +327,7 @@ __global__ void __launch_bounds__(kTracerThreads) k_tr_limit(TracerArgs a) {
         const long on = (long)st.cn[s] * KT + (long)k * a.T + t0;
         const TPack<R, L> qnn = tld<R, L>(qn + on), qtn = tld<R, L>(qtd + on);
         R FL[L], Aa[L];
-        edge_fluxes<R, L, kLimitUpwindLoads>(a, st, s, k, t0, qn_i, qs_i, Hi, &qnn, FL, Aa);
+        edge_fluxes<R, L, kLimitUpwindLoads, UNI>(a, st, s, k, t0, qn_i, qs_i, Hi, &qnn, FL, Aa);
 #pragma unroll
         for (int j = 0; j < L; j++) {
             qmax[j] = fmax(qmax[j], fmax(qnn.v[j], qtn.v[j]));
@@ -311,14 +353,14 @@ __global__ void __launch_bounds__(kTracerThreads) k_tr_limit(TracerArgs a) {
     tst<R, L>((R *)a.rm + ln.x, rm);
 }
 
-template <typename R, int L, bool SG>
+template <typename R, int L, bool SG, bool UNI>
 __global__ void __launch_bounds__(kTracerThreads) k_tr_update(TracerArgs a) {
-    const TLane ln = tracer_lane<L>(a);
+    const TLane ln = tracer_lane<L, UNI>(a);
     if (!ln.ok) return;
     const int KT = a.K * a.T;
     const int i = ln.i, k = ln.k, t0 = ln.t0;
     Stencil<R> st;
-    load_stencil<R, SG>(a, i, k, st);
+    load_stencil<R, SG, UNI>(a, i, k, st);
     R qn_i[L], qs_i[L], Hi[3][L];
     load_own<R, L>(a, ln, qn_i, qs_i, Hi);
     const R *rp = (const R *)a.rp;
@@ -333,7 +375,7 @@ __global__ void __launch_bounds__(kTracerThreads) k_tr_update(TracerArgs a) {
         const long on = (long)st.cn[s] * KT + (long)k * a.T + t0;
         const TPack<R, L> rpn = tld<R, L>(rp + on), rmn = tld<R, L>(rm + on);
         R FL[L], Aa[L];
-        edge_fluxes<R, L, kUpdateUpwindLoads>(a, st, s, k, t0, qn_i, qs_i, Hi, nullptr, FL, Aa);
+        edge_fluxes<R, L, kUpdateUpwindLoads, UNI>(a, st, s, k, t0, qn_i, qs_i, Hi, nullptr, FL, Aa);
         const bool self_c1 = st.cdiv[s] > (R)0;
 #pragma unroll
         for (int j = 0; j < L; j++) {
@@ -354,14 +396,26 @@ namespace {
 inline unsigned tblocks(long n, int b) { return (unsigned)((n + b - 1) / b); }
 template <typename R, int L, bool SG>
 hipError_t launch_tr_l(const TracerArgs &a, int which, hipStream_t s) {
+    if (a.cpb == 1) {
+        // one cell per work-group (K T / L <= 512 threads, checked by the host)
+        const unsigned nb = a.mesh.N;
+        const int b = a.K * (a.T / L);
+        switch (which) {
+        case TKERNEL_LOW: hipLaunchKernelGGL((k_tr_low<R, L, SG, true>), dim3(nb), dim3(b), 0, s, a); break;
+        case TKERNEL_LIMIT: hipLaunchKernelGGL((k_tr_limit<R, L, SG, true>), dim3(nb), dim3(b), 0, s, a); break;
+        case TKERNEL_UPDATE: hipLaunchKernelGGL((k_tr_update<R, L, SG, true>), dim3(nb), dim3(b), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     const long n = (long)a.mesh.N * a.K * (a.T / L);
     TracerArgs ab = a;
     ab.cpb = a.cpb > 0 ? a.cpb : 256;   // the kernels read the work-group size from here
     const int b = ab.cpb;
     switch (which) {
-    case TKERNEL_LOW: hipLaunchKernelGGL((k_tr_low<R, L, SG>), dim3(tblocks(n, b)), dim3(b), 0, s, ab); break;
-    case TKERNEL_LIMIT: hipLaunchKernelGGL((k_tr_limit<R, L, SG>), dim3(tblocks(n, b)), dim3(b), 0, s, ab); break;
-    case TKERNEL_UPDATE: hipLaunchKernelGGL((k_tr_update<R, L, SG>), dim3(tblocks(n, b)), dim3(b), 0, s, ab); break;
+    case TKERNEL_LOW: hipLaunchKernelGGL((k_tr_low<R, L, SG, false>), dim3(tblocks(n, b)), dim3(b), 0, s, ab); break;
+    case TKERNEL_LIMIT: hipLaunchKernelGGL((k_tr_limit<R, L, SG, false>), dim3(tblocks(n, b)), dim3(b), 0, s, ab); break;
+    case TKERNEL_UPDATE: hipLaunchKernelGGL((k_tr_update<R, L, SG, false>), dim3(tblocks(n, b)), dim3(b), 0, s, ab); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -342,7 +342,9 @@ int mpdc_set_launch(mpdc_state *st, int cells_per_block, int flat_block);
 /* Launch shape of one kernel class (ids as for mpdc_time_kernel):
  * values_per_lane = (level, member) values a lane computes -- 1 or 2 for the
  * column kernels (also 4 for an ensemble in the FP32 policies, with one cell
- * per work-group), 1, 2 or 4 for the flat kernels, 1, 2, 4 or (mixed policy) 8 tracers for the
+ * per work-group; the default for hydrostatic and shallow-water ensembles of
+ * a multiple of four members in those policies), 1, 2 or 4 for the flat
+ * kernels, 1, 2, 4 or (mixed policy) 8 tracers for the
  * tracer kernels; it must divide K (M == 1), M (M > 1) or T; 0 = default --
  * and group = cells per work-group (column kernels) or threads per
  * work-group (others; for the tracer kernels also 1: one cell per

@@ -256,6 +256,10 @@ int vpl_of(const mpdc_state *st, int k) {
         if (st->policy == MPDC_POLICY_MIX && st->T % 4 == 0) return 4;   // 16-byte FP32 loads
         return (st->T % 2 == 0) ? 2 : 1;
     }
+    // FP32 ensembles of the hydrostatic and shallow-water models: four members
+    // per lane (16-byte loads; the column kernels with one cell per work-group),
+    // the fastest measured on the G7 x 30 x 16 ensemble
+    if (st->M > 1 && st->M % 4 == 0 && st->policy != MPDC_POLICY_DBL && st->model != MPDC_MODEL_NDC) return 4;
     return values_per_lane(st->K, st->M);
 }
 

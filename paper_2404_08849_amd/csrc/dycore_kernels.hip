@@ -1816,12 +1816,14 @@ hipError_t launch_stage_t(const StageArgs &a, int which, hipStream_t s) {
     const size_t lds_a = stage_lds_bytes(MODEL, pol, KERNEL_CELL_A, a.cpb, a.K, a.M);
     const size_t lds_b = stage_lds_bytes(MODEL, pol, KERNEL_CELL_B, a.cpb, a.K, a.M);
     // One cell per work-group of an ensemble takes the uniform-cell instance of
-    // the column kernels.
+    // the column kernels (one member: measured slower at G8 x 60 and G9 x 30,
+    // whose columns of 30 to 60 lanes leave most of a wave idle or need no
+    // fewer registers than the autotuned general shapes).
     constexpr bool UB = !M1;
     switch (which) {
     case KERNEL_CELL_A:
-        if (!M1 && a.cpb == 1)
-            hipLaunchKernelGGL((k_cell_a<MODEL, R, L, M1, VA, !M1>), dim3(colblocks), dim3(colthreads), lds_a, s, a);
+        if (UB && a.cpb == 1)
+            hipLaunchKernelGGL((k_cell_a<MODEL, R, L, M1, VA, UB>), dim3(colblocks), dim3(colthreads), lds_a, s, a);
         else
             hipLaunchKernelGGL((k_cell_a<MODEL, R, L, M1, VA, false>), dim3(colblocks), dim3(colthreads), lds_a, s, a);
         break;

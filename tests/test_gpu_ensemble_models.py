@@ -1,8 +1,9 @@
 """Ensembles of the shallow-water and non-hydrostatic models, and the launch
 shapes of the column kernels on an ensemble.
 
-* every member of a shallow-water ensemble (G4, three members whose height
-  bumps sit at three seeded places) and of a non-hydrostatic one (G3 x 8
+* every member of a shallow-water ensemble (G4, three or four members --
+  four take four members per lane by default in the mixed policy -- whose
+  height bumps sit at seeded places) and of a non-hydrostatic one (G3 x 8
   levels, three members with warm bubbles at three seeded places) equals the
   FP64 oracle's run of that member alone, within the bars of the
   single-member parity tests;
@@ -10,7 +11,8 @@ shapes of the column kernels on an ensemble.
   whatever the launch shape of the column kernels: one cell per work-group
   (where the cell, and so every value of its stencil tables, is the same in
   all lanes of a wave) or several, with one or two values per lane, in both
-  policies, and four members per lane in the mixed policy.
+  policies, the mixed variants and SGL, and four members per lane in the
+  FP32 policies.
 """
 import numpy as np
 import pytest
@@ -51,13 +53,15 @@ def _ndc_members(m, K, M):
     return [ic.nh_warm_bubble(m, K, rh=1.5e6, seed=4000 + j) for j in range(M)]
 
 
+@pytest.mark.parametrize("M", [3, 4])
 @pytest.mark.parametrize("policy", ["DBL", "MIX"])
-def test_sw_ensemble_members_match_oracle(mpdc, oracle_mod, mesh_cache, policy):
+def test_sw_ensemble_members_match_oracle(mpdc, oracle_mod, mesh_cache, policy, M):
     m = mesh_cache(4)
-    M, dt, n = 3, 600.0, 5
+    dt, n = 600.0, 5
     mem = [ic.sw_geostrophic(m, seed=1000 + j) for j in range(M)]
     g = mpdc.Mesh(m)
     st = mpdc.State(g, mpdc.MODEL_SW, getattr(mpdc, "POLICY_" + policy), K=1, M=M, dt=dt)
+    _say("  launch shapes", [st.get_kernel_launch(k) for k in range(4)])
     st.state_write(mpdc.FIELD_H, _stack(mem, "h"))
     st.state_write(mpdc.FIELD_U, _stack(mem, "u")[:, None, :])
     st.state_write(mpdc.FIELD_B, mem[0]["b"])
@@ -116,8 +120,9 @@ def test_ndc_ensemble_members_match_oracle(mpdc, oracle_mod, mesh_cache, policy)
 _SHAPES = [(2, 1), (2, 3), (1, 1), (1, 8), (2, 16), (4, 1)]
 
 
-@pytest.mark.parametrize("model", ["HDC", "NDC"])
-@pytest.mark.parametrize("policy", ["DBL", "MIX"])
+@pytest.mark.parametrize("model,policy", [("HDC", p) for p in ("DBL", "MIX", "SGL", "MIX_BOX", "MIX_DBL_MASS",
+                                                                  "MIX_F32_DIV", "MIX_PGF32")] +
+                         [("NDC", p) for p in ("DBL", "MIX", "SGL")])
 def test_ensemble_column_shapes_are_bitwise_identical(mpdc, mesh_cache, model, policy):
     m = mesh_cache(3)
     K, M = 8, 4

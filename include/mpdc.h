@@ -30,8 +30,10 @@
  *    code; on error no output is modified and mpdc_last_error() (per thread)
  *    describes the failure.  No C++ exception crosses this boundary.
  *  - The library never allocates device memory: the caller passes device
- *    workspaces (pointer + size in bytes) that must outlive the handle that
- *    uses them.  Host arrays in descriptors are only read during the call.
+ *    workspaces (pointer + size in bytes, the pointer 256-byte aligned, as
+ *    hipMalloc's and torch's allocations are; INVAL otherwise) that must
+ *    outlive the handle that uses them.  Host arrays in descriptors are only
+ *    read during the call.
  *  - Streams are hipStream_t passed as void*; NULL is the default stream.
  *    Calls are asynchronous on that stream unless stated otherwise.
  *  - Layouts are level-innermost SoA: cell fields [N][K][M], edge fields

@@ -560,6 +560,7 @@ int mpdc_mesh_check(const mpdc_mesh_desc *d) {
 int mpdc_mesh_create(const mpdc_mesh_desc *d, void *dev_ws, size_t ws_bytes, void *stream, mpdc_mesh **out) {
     if (!d || !out) return fail(MPDC_E_INVAL, "null descriptor or output handle");
     if (!dev_ws) return fail(MPDC_E_INVAL, "null device workspace");
+    if ((uintptr_t)dev_ws % kAlign) return fail(MPDC_E_INVAL, "mesh workspace must be 256-byte aligned");
     try {
         std::string err = validate_mesh(d);
         if (!err.empty()) return fail(MPDC_E_MESH, err);
@@ -755,6 +756,7 @@ int mpdc_state_create(const mpdc_mesh *m, const mpdc_config *c, void *dev_ws, si
     int rc = check_config(m, c);
     if (rc != MPDC_OK) return rc;
     if (!dev_ws || !out) return fail(MPDC_E_INVAL, "null workspace or output handle");
+    if ((uintptr_t)dev_ws % kAlign) return fail(MPDC_E_INVAL, "state workspace must be 256-byte aligned");
     mpdc_state *st = new_state(m, c);
     size_t need = state_layout(st, nullptr);
     if (ws_bytes < need) {

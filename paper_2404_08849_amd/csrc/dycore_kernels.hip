@@ -569,21 +569,48 @@ k_cell_a(StageArgs a) {
         double mdot_b[L];
         if (cl.valid) {
             const long K1M = (long)(K + 1) * M;
+            // FP32 policies: the FP32 copy for the advective users, and the FP64
+            // flux only where the tracer accumulation reads it
+            const bool st64 = !MDOT32 || a.mdot64;
+            double dps[L];
 #pragma unroll
             for (int j = 0; j < L; j++) {
                 const int mm = v.mm0 + (M1 ? 0 : j);
-                const double dps = -scan[lc * KM + (K - 1) * M + mm];
+                dps[j] = -scan[lc * KM + (K - 1) * M + mm];
                 const double acc = scan[lc * KM + v.k[j] * M + mm];
-                mdot_b[j] = (v.k[j] == K - 1) ? 0.0 : -acc - sgb[j] * dps;
-                // FP32 policies: the FP32 copy for the advective users, and the FP64
-                // flux only where the tracer accumulation reads it
-                const bool st64 = !MDOT32 || a.mdot64;
-                if (st64) a.mdot[(long)i * K1M + (long)(v.k[j] + 1) * M + mm] = mdot_b[j];
-                if constexpr (MDOT32) a.mdot32[(long)i * K1M + (long)(v.k[j] + 1) * M + mm] = (float)mdot_b[j];
-                if (v.k[j] == 0) {
-                    if (st64) a.mdot[(long)i * K1M + mm] = 0.0;
-                    if constexpr (MDOT32) a.mdot32[(long)i * K1M + mm] = 0.0f;
-                    a.dps[(long)i * M + mm] = dps;
+                mdot_b[j] = (v.k[j] == K - 1) ? 0.0 : -acc - sgb[j] * dps[j];
+            }
+            if constexpr (M1) {
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    if (st64) a.mdot[(long)i * K1M + v.k[j] + 1] = mdot_b[j];
+                    if constexpr (MDOT32) a.mdot32[(long)i * K1M + v.k[j] + 1] = (float)mdot_b[j];
+                }
+                if (v.k0 == 0) {
+                    if (st64) a.mdot[(long)i * K1M] = 0.0;
+                    if constexpr (MDOT32) a.mdot32[(long)i * K1M] = 0.0f;
+                    a.dps[i] = dps[0];
+                }
+            } else {
+                // the lane's L members of one interface are consecutive: one
+                // vector store per array
+                Pack<double, L> m64, z64, dp;
+                Pack<float, L> m32, z32;
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    m64.v[j] = mdot_b[j];
+                    m32.v[j] = (float)mdot_b[j];
+                    z64.v[j] = 0.0;
+                    z32.v[j] = 0.0f;
+                    dp.v[j] = dps[j];
+                }
+                const long o = (long)i * K1M + (long)(v.k0 + 1) * M + v.mm0;
+                if (st64) stp<double, L>(a.mdot + o, m64);
+                if constexpr (MDOT32) stp<float, L>(a.mdot32 + o, m32);
+                if (v.k0 == 0) {
+                    if (st64) stp<double, L>(a.mdot + (long)i * K1M + v.mm0, z64);
+                    if constexpr (MDOT32) stp<float, L>(a.mdot32 + (long)i * K1M + v.mm0, z32);
+                    stp<double, L>(a.dps + (long)i * M + v.mm0, dp);
                 }
             }
             // ---- second derivatives of theta ----

@@ -102,6 +102,10 @@ def test_error_paths(mpdc, mesh_cache):
     assert lib.mpdc_state_create(g.h, ctypes.byref(cfg), ctypes.c_void_p(ws.data_ptr()), need - 1,
                                  ctypes.byref(out)) == -3
     assert out.value is None
+    # a workspace that is not 256-byte aligned (checked before anything is written)
+    assert lib.mpdc_state_create(g.h, ctypes.byref(cfg), ctypes.c_void_p(ws.data_ptr() + 64), need,
+                                 ctypes.byref(out)) == -1
+    assert out.value is None
     # steps of the wrong kind
     assert lib.mpdc_dycore_step(trs.h, 1, None) == -7
     assert lib.mpdc_tracer_step(hdc.h, 1, None) == -7

@@ -129,6 +129,14 @@ def test_error_paths(mpdc, mesh_cache):
     assert lib.mpdc_set_kernel_launch(hdc.h, 3, 2, 100) == -1        # not a multiple of 64
     assert lib.mpdc_set_kernel_launch(trs.h, 0, 4, 128) == -1        # 4 does not divide T = 2
     assert lib.mpdc_set_kernel_launch(trs.h, 3, 0, 0) == -1          # the tracer has three kernels
+    # one cell per work-group (tracer): K T / values_per_lane <= 512 threads, also
+    # when only the values per lane change afterwards
+    big = mpdc.State(g, mpdc.MODEL_TRACER, mpdc.POLICY_MIX, K=60, T=16, dt=600.0)
+    assert lib.mpdc_set_kernel_launch(big.h, 0, 1, 1) == -1          # 960 threads
+    assert lib.mpdc_set_kernel_launch(big.h, 0, 2, 1) == 0           # 480 threads
+    assert lib.mpdc_set_kernel_launch(big.h, 0, 1, 0) == -1          # keeps one cell: 960 again
+    assert big.get_kernel_launch(0) == (2, 1)
+    del big
     # the states still step after the rejected calls
     hdc.state_write(mpdc.FIELD_PS, np.full((g.N, 1), 1.0e5))
     hdc.state_write(mpdc.FIELD_THETA, np.full((g.N, K, 1), 300.0 * 9.9e4 / K))
